@@ -1,0 +1,302 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix.
+
+None of these compares the oracle with itself: each checks it against an
+independent construction (brute-force second quantisation of the paper's
+Hamiltonian, closed forms, LAPACK on matrices assembled by hand, or exact
+invariants), chosen so that a dropped term, a wrong sign, a wrong index
+convention or a transposed operand fails at least one of them.
+"""
+import itertools
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2405_10197_amd import synth
+
+
+# ---------------------------------------------------------------------------
+# helpers written independently of the oracle
+# ---------------------------------------------------------------------------
+def _op(mask, kind, P):
+    """One fermionic operator on a spin-orbital occupation mask -> (phase, mask) or None."""
+    below = mask & ((1 << P) - 1)
+    phase = -1 if bin(below).count("1") % 2 else 1
+    if kind == "a":
+        if not (mask >> P) & 1:
+            return None
+        return phase, mask ^ (1 << P)
+    if (mask >> P) & 1:
+        return None
+    return phase, mask | (1 << P)
+
+
+def _apply_string(mask, ops):
+    """ops listed left to right as written; the rightmost acts first."""
+    ph = 1
+    for kind, P in reversed(ops):
+        r = _op(mask, kind, P)
+        if r is None:
+            return None
+        ph *= r[0]
+        mask = r[1]
+    return ph, mask
+
+
+def _second_quantised_h(h, eri, na, nb, ecore):
+    """H of eq. (hamiltonian) applied term by term in the spin-orbital basis.
+
+    Spin orbital P < n is (P, alpha), P >= n is (P-n, beta); the determinant of
+    alpha string a and beta string b is the mask a | b << n, i.e. alpha creators
+    left of beta creators, each ascending. <pq||rs> = <pq|rs> - <pq|sr> with
+    <pq|rs> = (pr|qs) for matching spins.
+    """
+    n = h.shape[0]
+    ns = 2 * n
+
+    def sp(P):
+        return (P // n, P % n)
+
+    def hs(P, Q):
+        (s1, p), (s2, q) = sp(P), sp(Q)
+        return h[p, q] if s1 == s2 else 0.0
+
+    def gs(P, Q, R, S):
+        (sP, p), (sQ, q), (sR, r), (sS, s) = sp(P), sp(Q), sp(R), sp(S)
+        return eri[p, r, q, s] if (sP == sR and sQ == sS) else 0.0
+
+    astr = [sum(1 << p for p in c) for c in itertools.combinations(range(n), na)]
+    bstr = [sum(1 << p for p in c) for c in itertools.combinations(range(n), nb)]
+    astr.sort()
+    bstr.sort()
+    dets = [a | (b << n) for a in astr for b in bstr]
+    idx = {d: k for k, d in enumerate(dets)}
+    nd = len(dets)
+    H = np.zeros((nd, nd))
+    for j, dj in enumerate(dets):
+        H[j, j] += ecore
+        for P in range(ns):
+            for Q in range(ns):
+                v = hs(P, Q)
+                if v == 0.0:
+                    continue
+                r = _apply_string(dj, [("c", P), ("a", Q)])
+                if r is not None:
+                    H[idx[r[1]], j] += v * r[0]
+        for P, Q, R, S in itertools.product(range(ns), repeat=4):
+            v = gs(P, Q, R, S) - gs(P, Q, S, R)
+            if v == 0.0:
+                continue
+            r = _apply_string(dj, [("c", P), ("c", Q), ("a", S), ("a", R)])
+            if r is not None:
+                H[idx[r[1]], j] += 0.25 * v * r[0]
+    return H
+
+
+def _random_ints(n, seed):
+    # generic (non-synthetic) integrals with the 8-fold symmetry, all entries nonzero
+    rng = np.random.default_rng(seed)
+    h = rng.normal(size=(n, n))
+    h = 0.5 * (h + h.T)
+    g = rng.normal(size=(n, n, n, n))
+    g = g + g.transpose(1, 0, 2, 3)
+    g = g + g.transpose(0, 1, 3, 2)
+    g = g + g.transpose(2, 3, 0, 1)
+    return h, 0.125 * g
+
+
+# ---------------------------------------------------------------------------
+# strings and lists
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("n,k", [(1, 0), (1, 1), (4, 2), (6, 3), (7, 2), (10, 5)])
+def test_strings_are_all_subsets_ascending(n, k):
+    s = oracle.strings(n, k)
+    ref = sorted(sum(1 << p for p in c) for c in itertools.combinations(range(n), k))
+    assert [int(x) for x in s] == ref
+    assert s.size == math.comb(n, k)
+    assert int(s[0]) == (1 << k) - 1          # aufbau string first
+
+
+@pytest.mark.parametrize("n,k", [(3, 1), (4, 2), (5, 3), (6, 3), (5, 5), (5, 0)])
+def test_single_list_matches_operator_application(n, k):
+    P, Q, J, S = oracle.single_list(n, k)
+    strs = [int(x) for x in oracle.strings(n, k)]
+    assert P.shape == (len(strs), k * (n - k + 1))
+    for I, mI in enumerate(strs):
+        seen = []
+        for e in range(P.shape[1]):
+            p, q, j, s = int(P[I, e]), int(Q[I, e]), int(J[I, e]), int(S[I, e])
+            r = _apply_string(strs[j], [("c", p), ("a", q)])
+            assert r is not None and r[1] == mI and r[0] == s
+            seen.append((p, q))
+        assert seen == sorted(seen)               # canonical order: p, then q ascending
+        # every nonzero <I|a+_p a_q|J> appears exactly once
+        cnt = 0
+        for p in range(n):
+            for q in range(n):
+                for mJ in strs:
+                    if _apply_string(mJ, [("c", p), ("a", q)]) is not None and \
+                            _apply_string(mJ, [("c", p), ("a", q)])[1] == mI:
+                        cnt += 1
+        assert cnt == P.shape[1]
+
+
+# ---------------------------------------------------------------------------
+# Hamiltonian vs brute-force second quantisation of eq. (hamiltonian)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("n,na,nb", [(2, 1, 1), (3, 2, 1), (3, 1, 2), (4, 2, 2), (4, 3, 1), (3, 3, 0), (4, 0, 2)])
+def test_hamiltonian_equals_second_quantised_definition(n, na, nb):
+    h, eri = _random_ints(n, 100 + 10 * n + na)
+    H = oracle.hamiltonian(h, eri, na, nb, ecore=0.37)
+    Hb = _second_quantised_h(h, eri, na, nb, 0.37)
+    np.testing.assert_allclose(H, Hb, atol=1e-12, rtol=0)
+
+
+def test_hamiltonian_hermitian_and_sigma_rows():
+    h, eri, _ = synth.integrals(6, 1)
+    H = oracle.hamiltonian(h, eri, 3, 3)
+    assert np.abs(H - H.T).max() < 1e-14
+    C = synth.ci_vector(20, 20, 11)[0]
+    sig = oracle.sigma(h, eri, 3, 3, C)
+    np.testing.assert_allclose(sig.reshape(-1), H @ C.reshape(-1), atol=1e-13, rtol=0)
+
+
+# ---------------------------------------------------------------------------
+# closed forms and special cases
+# ---------------------------------------------------------------------------
+def test_two_electrons_two_orbitals_closed_form():
+    """CAS(2,2): singlet block in {|0a0b>, |1a1b>, (|0a1b>+|1a0b>)/sqrt2} and the
+    Ms=0 triplet (|0a1b>-|1a0b>)/sqrt2, worked out by hand from the Slater-Condon rules."""
+    h, eri = _random_ints(2, 7)
+    g = lambda p, q, r, s: eri[p, q, r, s]
+    r2 = math.sqrt(2.0)
+    Hs = np.array([
+        [2 * h[0, 0] + g(0, 0, 0, 0), g(0, 1, 1, 0), r2 * (h[0, 1] + g(0, 1, 0, 0))],
+        [g(0, 1, 1, 0), 2 * h[1, 1] + g(1, 1, 1, 1), r2 * (h[0, 1] + g(0, 1, 1, 1))],
+        [r2 * (h[0, 1] + g(0, 1, 0, 0)), r2 * (h[0, 1] + g(0, 1, 1, 1)),
+         h[0, 0] + h[1, 1] + g(0, 0, 1, 1) + g(0, 1, 1, 0)],
+    ])
+    Et = h[0, 0] + h[1, 1] + g(0, 0, 1, 1) - g(0, 1, 1, 0)
+    ref = np.sort(np.concatenate([np.linalg.eigvalsh(Hs), [Et]]))
+    E = np.linalg.eigvalsh(oracle.hamiltonian(h, eri, 1, 1))
+    np.testing.assert_allclose(E, ref, atol=1e-12, rtol=0)
+    # singlet / triplet assignment
+    Es, _, s2 = oracle.solve(h, eri, 1, 1, nroots=3, spin="singlet")
+    np.testing.assert_allclose(Es, np.linalg.eigvalsh(Hs), atol=1e-12, rtol=0)
+    np.testing.assert_allclose(s2, 0.0, atol=1e-12)
+
+
+def test_two_electrons_two_orbitals_decoupled_roots():
+    """With h01 = (01|00) = (01|11) = 0 the 2x2 block has E = mean +- sqrt(d^2 + K^2)."""
+    h = np.diag([-1.3, 0.4])
+    eri = np.zeros((2, 2, 2, 2))
+    J00, J11, J01, K = 0.7, 0.6, 0.5, 0.15
+    eri[0, 0, 0, 0] = J00
+    eri[1, 1, 1, 1] = J11
+    eri[0, 0, 1, 1] = eri[1, 1, 0, 0] = J01
+    for p, q, r, s in [(0, 1, 0, 1), (1, 0, 1, 0), (0, 1, 1, 0), (1, 0, 0, 1)]:
+        eri[p, q, r, s] = K
+    H11, H22 = 2 * h[0, 0] + J00, 2 * h[1, 1] + J11
+    m, d = 0.5 * (H11 + H22), 0.5 * (H11 - H22)
+    ref = sorted([m - math.hypot(d, K), m + math.hypot(d, K),
+                  h[0, 0] + h[1, 1] + J01 + K, h[0, 0] + h[1, 1] + J01 - K])
+    E = np.linalg.eigvalsh(oracle.hamiltonian(h, eri, 1, 1))
+    np.testing.assert_allclose(E, ref, atol=1e-12, rtol=0)
+
+
+@pytest.mark.parametrize("n", [1, 3, 7])
+def test_one_electron_spectrum_is_h(n):
+    h, eri = _random_ints(n, 40 + n)
+    E = np.linalg.eigvalsh(oracle.hamiltonian(h, eri, 1, 0, ecore=0.2))
+    np.testing.assert_allclose(E, np.linalg.eigvalsh(h) + 0.2, atol=1e-12, rtol=0)
+
+
+@pytest.mark.parametrize("n", [2, 4, 6])
+def test_one_alpha_one_beta_explicit_matrix(n):
+    """nalpha = nbeta = 1: H[(i,k),(j,l)] = h_ij d_kl + d_ij h_kl + (ij|kl) exactly.
+    Pins the chemists' index convention and the alpha-beta coupling sign."""
+    h, eri = _random_ints(n, 60 + n)
+    ref = np.kron(h, np.eye(n)) + np.kron(np.eye(n), h) + eri.transpose(0, 2, 1, 3).reshape(n * n, n * n)
+    H = oracle.hamiltonian(h, eri, 1, 1)
+    np.testing.assert_allclose(H, ref, atol=1e-13, rtol=0)
+
+
+@pytest.mark.parametrize("n,na,nb", [(4, 2, 2), (5, 3, 2), (6, 2, 1)])
+def test_zero_eri_spectrum_is_sums_of_orbital_energies(n, na, nb):
+    h, _ = _random_ints(n, 80 + n)
+    eps = np.linalg.eigvalsh(h)
+    ref = sorted(sum(eps[list(a)]) + sum(eps[list(b)])
+                 for a in itertools.combinations(range(n), na)
+                 for b in itertools.combinations(range(n), nb))
+    E = np.linalg.eigvalsh(oracle.hamiltonian(h, np.zeros((n,) * 4), na, nb))
+    np.testing.assert_allclose(E, ref, atol=1e-12, rtol=0)
+
+
+@pytest.mark.parametrize("n", [1, 3, 5])
+def test_full_occupation_closed_form(n):
+    h, eri = _random_ints(n, 90 + n)
+    J = np.einsum("ppqq->pq", eri)
+    K = np.einsum("pqqp->pq", eri)
+    E_closed = 2 * np.trace(h) + np.sum(2 * J - K)
+    E_hs = np.trace(h) + 0.5 * np.sum(J - K)
+    np.testing.assert_allclose(oracle.hamiltonian(h, eri, n, n)[0, 0], E_closed, atol=1e-12)
+    np.testing.assert_allclose(oracle.hamiltonian(h, eri, n, 0)[0, 0], E_hs, atol=1e-12)
+
+
+# ---------------------------------------------------------------------------
+# invariants
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("n,na,nb", [(4, 2, 2), (5, 3, 2), (6, 3, 3)])
+def test_s2_spectrum_and_commutation(n, na, nb):
+    h, eri, _ = synth.integrals(n, 5 + n)
+    S2 = oracle.s2_matrix(n, na, nb)
+    w = np.linalg.eigvalsh(S2)
+    S = 0.5 * (np.sqrt(1.0 + 4.0 * np.clip(w, 0, None)) - 1.0)
+    np.testing.assert_allclose(2 * S, np.round(2 * S), atol=1e-9)
+    assert np.all(np.round(2 * S) % 2 == (na - nb) % 2)
+    assert np.min(S) >= abs(na - nb) / 2 - 1e-9
+    H = oracle.hamiltonian(h, eri, na, nb)
+    assert np.abs(H @ S2 - S2 @ H).max() < 1e-11
+
+
+def test_transposition_parity_of_spin_states():
+    """For nalpha = nbeta, C -> C^T commutes with H; with alpha-before-beta phases a
+    state of spin S has parity (-1)^S under it."""
+    n = 4
+    h, eri, _ = synth.integrals(n, 3)
+    N = math.comb(n, 2)
+    Pm = np.zeros((N * N, N * N))
+    for a in range(N):
+        for b in range(N):
+            Pm[b * N + a, a * N + b] = 1.0
+    H = oracle.hamiltonian(h, eri, 2, 2)
+    assert np.abs(Pm @ H @ Pm - H).max() < 1e-13
+    E, X, s2 = oracle.solve(h, eri, 2, 2, nroots=N * N)
+    for k in range(N * N):
+        S = int(round(0.5 * (math.sqrt(1 + 4 * s2[k]) - 1)))
+        par = float(np.sum(X[k] * X[k].T))
+        if abs(abs(par) - 1) < 1e-8:           # nondegenerate, definite parity
+            assert round(par) == (-1) ** S
+
+
+def test_spectrum_invariant_under_orbital_rotation():
+    n = 5
+    h, eri, _ = synth.integrals(n, 21)
+    Q = synth.random_orthogonal(n, 22)
+    h2, eri2 = oracle.rotate_integrals(h, eri, Q)
+    E1 = np.linalg.eigvalsh(oracle.hamiltonian(h, eri, 3, 2))
+    E2 = np.linalg.eigvalsh(oracle.hamiltonian(h2, eri2, 3, 2))
+    np.testing.assert_allclose(E1, E2, atol=1e-11, rtol=0)
+    # rotating only the one-electron part is not a change of orbitals: spectrum moves
+    E3 = np.linalg.eigvalsh(oracle.hamiltonian(h2, eri, 3, 2))
+    assert np.abs(E3 - E1).max() > 1e-3
+
+
+def test_singlet_selection_and_ground_state_parity():
+    h, eri, _ = synth.integrals(6, 1)
+    E, X, s2 = oracle.solve(h, eri, 3, 3, nroots=1, spin="singlet")
+    assert abs(s2[0]) < 1e-10
+    np.testing.assert_allclose(X[0], X[0].T, atol=1e-12)
+    Ea = np.linalg.eigvalsh(oracle.hamiltonian(h, eri, 3, 3))
+    assert E[0] >= Ea[0] - 1e-12
