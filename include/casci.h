@@ -1,0 +1,243 @@
+/*
+ * casci.h -- C ABI of the MI355X (gfx950) string-based CASCI library.
+ *
+ * What it computes. The lowest eigenpairs of the fermionic Hamiltonian of
+ * eq. (hamiltonian) (Sec. II of Evangelista et al., "Forte: a suite of
+ * advanced multireference quantum chemistry methods")
+ *
+ *     H = V + sum_pq h_pq a+_p a_q + 1/4 sum_pqrs <pq||rs> a+_p a+_q a_s a_r
+ *
+ * restricted to the complete active space of norb spatial orbitals holding
+ * nalpha alpha and nbeta beta electrons (Sec. II.A.1). Determinants are
+ * products of an alpha string and a beta string, |Ia> (x) |Ib>, and a CI
+ * vector is the matrix C[Ia][Ib] (Sec. II.A.1, string-based CI). The
+ * library computes sigma = H C (the sigma build of Sec. II.A.1) and runs a
+ * Davidson-Liu eigensolver on top of it (Sec. II.A.1).
+ *
+ * Conventions fixed by this header (the paper leaves them open):
+ *  - A string is a 64-bit mask, bit p = orbital p occupied (Sec. III.C).
+ *  - Strings of one spin are numbered 0..N-1 in ascending integer order of
+ *    their masks (a gap-free address, Sec. II.A.1); string 0 is the aufbau
+ *    string 0..n-1.
+ *  - Determinant (Ia, Ib) = a+_{Ia...} a+_{Ib...} |->: all alpha creators to
+ *    the left of all beta creators, each group in ascending orbital order
+ *    (the canonical operator order of Sec. III.C). This fixes the sign of
+ *    every CI coefficient. Its address is Ia*Nb + Ib (C is row-major).
+ *  - Two-electron integrals are passed in chemists' notation (pq|rs), which
+ *    is the paper's <pr|qs> (Sec. III.B), stored at ((p*n+q)*n+r)*n+s.
+ *
+ * Memory. Every pointer argument is accompanied by a `mem` flag: HOST
+ * pointers are copied in/out by the library (the call then synchronises the
+ * context stream), DEVICE pointers must live on the context's device and
+ * are used in place, ordered on the context stream. Inputs are borrowed for
+ * the duration of the call only; the library keeps its own copies.
+ *
+ * Errors. Every call returns a status code (CASCI_OK = 0, warnings > 0,
+ * errors < 0) and never aborts or prints. The message of the last error of
+ * a context is available from casci_last_error. A failed call leaves the
+ * context in its previous valid state unless stated otherwise.
+ *
+ * Threads. A context must not be used from two threads at once; distinct
+ * contexts are independent.
+ */
+#ifndef CASCI_H
+#define CASCI_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define CASCI_OK 0
+#define CASCI_NOCONV 1          /* davidson: max_iter reached; results are filled */
+#define CASCI_E_ARG (-1)        /* invalid argument (sizes, symmetry, null pointer) */
+#define CASCI_E_STATE (-2)      /* call order: integrals / strings missing or mismatched */
+#define CASCI_E_NOMEM (-3)      /* predicted or actual device allocation failure */
+#define CASCI_E_DEVICE (-4)     /* HIP runtime error; message in casci_last_error */
+#define CASCI_E_NONFINITE (-5)  /* NaN or Inf in the input */
+#define CASCI_E_UNSUPPORTED (-6)
+
+/* where a pointer lives */
+#define CASCI_MEM_HOST 0
+#define CASCI_MEM_DEVICE 1
+
+/* element types of CI vectors / arithmetic of the alpha-beta contraction */
+#define CASCI_F64 0
+#define CASCI_F32 1
+#define CASCI_BF16 2
+
+/* Davidson preconditioners */
+#define CASCI_PRECOND_DIAG 0    /* t = -r / (H_II - theta) */
+#define CASCI_PRECOND_OLSEN 1   /* diagonal + Olsen's correction along x */
+#define CASCI_PRECOND_MLP 2     /* learned correction, Olsen fallback */
+
+/* spin targets */
+#define CASCI_SPIN_ANY 0        /* lowest roots of the whole (nalpha, nbeta) space */
+#define CASCI_SPIN_SINGLET 1    /* S = 0 roots (needs nalpha == nbeta) */
+
+#define CASCI_MAX_ROOTS 32
+
+typedef struct casci_ctx casci_ctx;
+
+/*
+ * Create a context on HIP device `device` (>= 0), ordering all work on
+ * `hip_stream` (a hipStream_t; NULL = a stream owned by the context).
+ * device = -1 gives a validate-only context: every call checks its
+ * arguments and state exactly as on a GPU and then returns
+ * CASCI_E_UNSUPPORTED instead of launching work (no HIP call is made).
+ * Returns CASCI_E_ARG for out == NULL, CASCI_E_DEVICE if the device cannot
+ * be used. On error *out is NULL.
+ */
+int casci_create(casci_ctx** out, int device, void* hip_stream);
+
+/* Free every buffer of the context (NULL is a no-op). */
+void casci_destroy(casci_ctx* ctx);
+
+/* Message of the last error on this context ("" if none); owned by ctx. */
+const char* casci_last_error(const casci_ctx* ctx);
+
+/*
+ * set_integrals: h (norb x norb, row-major, symmetric), eri (norb^4,
+ * chemists' (pq|rs), 8-fold symmetric), e_core = the scalar V of
+ * eq. (hamiltonian). mem = CASCI_MEM_HOST or CASCI_MEM_DEVICE for h and
+ * eri. The arrays are copied. Checks: 1 <= norb <= 64, finiteness
+ * (CASCI_E_NONFINITE), symmetry of h and the 8-fold symmetry of eri to
+ * 1e-12 * max|value| (CASCI_E_ARG). If strings for a different norb exist
+ * the call fails with CASCI_E_STATE. Invalidates all integral-dependent
+ * device data (same-spin operators, diagonal, pair-integral matrices).
+ */
+int casci_set_integrals(casci_ctx* ctx, int norb, const double* h, const double* eri,
+                        double e_core, int mem);
+
+/*
+ * build_strings: enumerate the nalpha- and nbeta-electron strings of norb
+ * orbitals and their single-substitution lists (Sec. II.A.1: gap-free
+ * string addresses and precomputed substitution lists), on the device.
+ * Requires 0 <= nalpha, nbeta <= norb <= 64 and fewer than 2^31 strings
+ * per spin; if integrals are set, norb must match (CASCI_E_STATE). The
+ * device memory that sigma/davidson will need for one vector pair is
+ * predicted first; CASCI_E_NOMEM leaves no partial state.
+ */
+int casci_build_strings(casci_ctx* ctx, int nalpha, int nbeta, int norb);
+
+/*
+ * dims[0..7] = {Na, Nb, Ndet, sa, sb, ra, rb, norb}: string counts,
+ * determinant count, single-substitution list length per string
+ * (s = n_e (norb - n_e + 1), diagonal E_pp included) and nonzeros per row
+ * of the same-spin operator (r = 1 + n_e(n-n_e) + C(n_e,2) C(n-n_e,2)).
+ */
+int casci_get_dims(const casci_ctx* ctx, int64_t* dims);
+
+/* Copy the strings of one spin (0 = alpha, 1 = beta) to host out[N]. */
+int casci_get_strings(casci_ctx* ctx, int spin, uint64_t* out);
+
+/*
+ * Copy the single-substitution list of one spin to host arrays of N*s
+ * entries: for string I, entry e = I*s + k holds (p, q, J, sign) with
+ * <I| a+_p a_q |J> = sign != 0; p runs over the occupied orbitals of I in
+ * ascending order and, for each p, q over {unoccupied orbitals of I} U {p}
+ * ascending. Any output pointer may be NULL.
+ */
+int casci_get_single_list(casci_ctx* ctx, int spin, int32_t* J, int8_t* sign, uint8_t* p,
+                          uint8_t* q);
+
+/*
+ * Copy the same-spin operator of one spin to host arrays of N*r entries:
+ * F(I,J) = sum_pq k_pq <I|E_pq|J> + 1/2 sum_pqrs (pq|rs) <I|E_pq E_rs|J>
+ * with k_pq = h_pq - 1/2 sum_r (pr|rq), E restricted to that spin; this is
+ * H of eq. (hamiltonian) for the (n_e, 0) system without V. Row I lists its
+ * r nonzero columns in ascending order (col) with their values (val).
+ * Requires integrals and strings.
+ */
+int casci_get_same_spin_operator(casci_ctx* ctx, int spin, int32_t* col, double* val);
+
+/* Diagonal H_II (V included) of every determinant -> out[Ndet] (host or device). */
+int casci_get_diagonal(casci_ctx* ctx, double* out, int mem);
+
+/*
+ * sigma: sigma = H C for one CI vector (the sigma build of Sec. II.A.1).
+ * C and sigma are Na x Nb row-major arrays of `dtype` (CASCI_F64, or
+ * CASCI_F32 for single-precision storage with FP64 accumulation of the
+ * same-spin terms). ab_prec selects the arithmetic of the alpha-beta
+ * contraction: CASCI_F64 (FP64 MFMA), CASCI_F32 (FP32 MFMA) or CASCI_BF16
+ * (BF16 MFMA, FP32 accumulate); the alpha-alpha / beta-beta terms are
+ * computed in FP64 arithmetic. sigma is overwritten, never accumulated.
+ * C and sigma must not overlap.
+ */
+int casci_sigma(casci_ctx* ctx, const void* C, void* sigma, int dtype, int ab_prec, int mem);
+
+/*
+ * <S^2> of a normalised FP64 CI vector C (Na x Nb): S^2 = Sz^2 + Sz + S- S+.
+ * Result to host *s2.
+ */
+int casci_spin_square(casci_ctx* ctx, const double* C, double* s2, int mem);
+
+typedef struct {
+    int max_iter;           /* 0 -> 200 */
+    int m_max;              /* subspace size before collapse; 0 -> max(8, 8*nroots) */
+    int precond;            /* CASCI_PRECOND_* */
+    int spin;               /* CASCI_SPIN_* */
+    int ab_prec;            /* alpha-beta arithmetic in the first phase (CASCI_F64/F32/BF16) */
+    double refine_rnorm;    /* switch sigma to FP64 once max residual < this (<= 0: 1e-2 BF16, 1e-4 F32) */
+    double r_tol;           /* residual threshold; <= 0 -> max(1e-6, sqrt(tol)/10) */
+    double s2_penalty;      /* lambda of H + lambda S^2 for CASCI_SPIN_SINGLET (< 0 -> 0) */
+    const double* guess;    /* optional [nguess][Ndet] FP64 start vectors (host or device) */
+    int nguess;
+    int guess_mem;
+    int verbose_history;    /* fill info->hist_* when the pointers are set */
+} casci_davidson_opts;
+
+typedef struct {
+    int iterations;
+    int sigma_calls;        /* vectors pushed through sigma, all precisions */
+    int sigma_calls_fp64;
+    int converged;          /* 1 if every root met both thresholds */
+    int switch_iter;        /* iteration at which sigma moved to FP64 (-1 = never/FP64 only) */
+    int mlp_fallbacks;      /* learned corrections replaced by the Olsen fallback */
+    double residual[CASCI_MAX_ROOTS];
+    double s2[CASCI_MAX_ROOTS];
+    double time_total_ms;   /* wall time of the call */
+    double time_sigma_ms;   /* device time spent in sigma builds */
+    double time_setup_ms;   /* operator/diagonal preparation inside the call */
+    /* optional per-iteration history, caller-owned, [hist_len][nroots] */
+    double* hist_energy;
+    double* hist_residual;
+    double* hist_time_ms;   /* [hist_len]: wall time from the start of the call */
+    int hist_len;
+} casci_davidson_info;
+
+/*
+ * davidson: lowest nroots (1..CASCI_MAX_ROOTS) eigenpairs of H in the
+ * (nalpha, nbeta) determinant space (or its S = 0 part), ascending, by the
+ * Davidson-Liu method (Sec. II.A.1). Convergence: every root has
+ * |Delta theta| < tol between iterations and residual norm < r_tol.
+ * energies: host [nroots]. vectors: optional [nroots][Ndet] FP64 (host or
+ * device per mem), normalised, phase: largest-|c| entry positive.
+ * opts and info may be NULL. Returns CASCI_OK, or CASCI_NOCONV (> 0) with
+ * the last Ritz pairs filled in.
+ */
+int casci_davidson(casci_ctx* ctx, int nroots, double tol, const casci_davidson_opts* opts,
+                   double* energies, void* vectors, int mem, casci_davidson_info* info);
+
+/*
+ * Profiling aid: on != 0 resets and starts accumulating the device time of
+ * each part of every sigma build on this context (sigma and davidson),
+ * measured with HIP events recorded on the context stream between the
+ * parts; each build then waits for its last event. on = 0 stops.
+ */
+int casci_profile_enable(casci_ctx* ctx, int on);
+
+/*
+ * out[0..7] = {alpha-alpha gather ms, beta-beta transposes ms, beta-beta
+ * gather ms, alpha-beta contraction ms, sigma builds, of which FP64
+ * alpha-beta, 0, 0}, accumulated since casci_profile_enable(ctx, 1).
+ */
+int casci_profile_read(const casci_ctx* ctx, double* out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CASCI_H */

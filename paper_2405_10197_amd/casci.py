@@ -1,0 +1,294 @@
+"""Thin ctypes binding over libcasci.so (C ABI in include/casci.h).
+
+Argument marshalling only: every step of the computation runs in the HIP
+library. Host arrays are numpy arrays (the library copies them in and out);
+device arrays are torch tensors on the context's GPU, passed by pointer and
+used in place on the context's stream (by default torch's current stream).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libcasci.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "casci.h")
+
+OK, NOCONV = 0, 1
+E_ARG, E_STATE, E_NOMEM, E_DEVICE, E_NONFINITE, E_UNSUPPORTED = -1, -2, -3, -4, -5, -6
+MEM_HOST, MEM_DEVICE = 0, 1
+F64, F32, BF16 = 0, 1, 2
+PRECOND = {"diag": 0, "olsen": 1, "mlp": 2}
+SPIN = {"any": 0, "singlet": 1}
+PREC = {"f64": F64, "f32": F32, "bf16": BF16}
+MAX_ROOTS = 32
+
+_ERRNAMES = {E_ARG: "E_ARG", E_STATE: "E_STATE", E_NOMEM: "E_NOMEM", E_DEVICE: "E_DEVICE",
+             E_NONFINITE: "E_NONFINITE", E_UNSUPPORTED: "E_UNSUPPORTED"}
+
+
+class CasciError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("%s (%d): %s" % (_ERRNAMES.get(code, "?"), code, msg))
+        self.code = code
+
+
+class DavidsonOpts(ctypes.Structure):
+    _fields_ = [("max_iter", ctypes.c_int), ("m_max", ctypes.c_int), ("precond", ctypes.c_int),
+                ("spin", ctypes.c_int), ("ab_prec", ctypes.c_int), ("refine_rnorm", ctypes.c_double),
+                ("r_tol", ctypes.c_double), ("s2_penalty", ctypes.c_double),
+                ("guess", ctypes.c_void_p), ("nguess", ctypes.c_int), ("guess_mem", ctypes.c_int),
+                ("verbose_history", ctypes.c_int)]
+
+
+class DavidsonInfo(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int), ("sigma_calls", ctypes.c_int),
+                ("sigma_calls_fp64", ctypes.c_int), ("converged", ctypes.c_int),
+                ("switch_iter", ctypes.c_int), ("mlp_fallbacks", ctypes.c_int),
+                ("residual", ctypes.c_double * MAX_ROOTS), ("s2", ctypes.c_double * MAX_ROOTS),
+                ("time_total_ms", ctypes.c_double), ("time_sigma_ms", ctypes.c_double),
+                ("time_setup_ms", ctypes.c_double), ("hist_energy", ctypes.c_void_p),
+                ("hist_residual", ctypes.c_void_p), ("hist_time_ms", ctypes.c_void_p),
+                ("hist_len", ctypes.c_int)]
+
+
+_lib = None
+
+
+def header_symbols():
+    """Names of every function declared in include/casci.h."""
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(casci_[a-z0-9_]+)\s*\(", text)))
+
+
+def lib():
+    """Load libcasci.so; raises if it has not been built (there is no fallback)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError("libcasci.so is not built; run `python -m paper_2405_10197_amd.build`")
+    L = ctypes.CDLL(LIB_PATH)
+    P, I, D, I64 = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_int64
+    sig = {
+        "casci_create": (I, [ctypes.POINTER(P), I, P]),
+        "casci_destroy": (None, [P]),
+        "casci_last_error": (ctypes.c_char_p, [P]),
+        "casci_set_integrals": (I, [P, I, P, P, D, I]),
+        "casci_build_strings": (I, [P, I, I, I]),
+        "casci_get_dims": (I, [P, P]),
+        "casci_get_strings": (I, [P, I, P]),
+        "casci_get_single_list": (I, [P, I, P, P, P, P]),
+        "casci_get_same_spin_operator": (I, [P, I, P, P]),
+        "casci_get_diagonal": (I, [P, P, I]),
+        "casci_sigma": (I, [P, P, P, I, I, I]),
+        "casci_spin_square": (I, [P, P, P, I]),
+        "casci_davidson": (I, [P, I, D, P, P, P, I, P]),
+        "casci_profile_enable": (I, [P, I]),
+        "casci_profile_read": (I, [P, P]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = L
+    return L
+
+
+def _ptr(a):
+    """(pointer, mem flag) of a numpy array or a torch tensor."""
+    if isinstance(a, np.ndarray):
+        if not a.flags.c_contiguous:
+            raise ValueError("array must be C-contiguous")
+        return a.ctypes.data, MEM_HOST
+    if hasattr(a, "data_ptr"):
+        if not a.is_contiguous():
+            raise ValueError("tensor must be contiguous")
+        return a.data_ptr(), (MEM_DEVICE if a.is_cuda else MEM_HOST)
+    raise TypeError("expected a numpy array or a torch tensor")
+
+
+class Context:
+    """One CASCI problem on one GPU (device=-1: validate-only, no GPU needed)."""
+
+    def __init__(self, device: int = 0, stream=None):
+        self._L = lib()
+        self.device = device
+        if stream is None and device >= 0:
+            import torch
+            with torch.cuda.device(device):
+                stream = torch.cuda.current_stream().cuda_stream
+        h = ctypes.c_void_p()
+        rc = self._L.casci_create(ctypes.byref(h), int(device), ctypes.c_void_p(stream or 0))
+        if rc != OK:
+            raise CasciError(rc, "casci_create(device=%d) failed" % device)
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._L.casci_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def _check(self, rc, allow=(OK,)):
+        if rc in allow:
+            return rc
+        if rc < 0:
+            raise CasciError(rc, self._L.casci_last_error(self._h).decode())
+        return rc
+
+    # -- problem definition -------------------------------------------------
+    def set_integrals(self, h, eri, e_core: float = 0.0):
+        if isinstance(h, np.ndarray):
+            h = np.ascontiguousarray(h, dtype=np.float64)
+            eri = np.ascontiguousarray(eri, dtype=np.float64)
+        n = h.shape[0]
+        if tuple(h.shape) != (n, n) or tuple(eri.shape) != (n, n, n, n):
+            raise ValueError("h must be [n,n] and eri [n,n,n,n]")
+        ph, mem = _ptr(h)
+        pe, mem2 = _ptr(eri)
+        if mem != mem2:
+            raise ValueError("h and eri must live in the same memory")
+        self._check(self._L.casci_set_integrals(self._h, n, ph, pe, float(e_core), mem))
+        self._keep = (h, eri)
+
+    def build_strings(self, nalpha: int, nbeta: int, norb: int):
+        self._check(self._L.casci_build_strings(self._h, int(nalpha), int(nbeta), int(norb)))
+
+    @property
+    def dims(self):
+        d = np.zeros(8, dtype=np.int64)
+        self._check(self._L.casci_get_dims(self._h, d.ctypes.data))
+        keys = ["Na", "Nb", "Ndet", "sa", "sb", "ra", "rb", "norb"]
+        return {k: int(v) for k, v in zip(keys, d)}
+
+    # -- introspection ------------------------------------------------------
+    def strings(self, spin: int):
+        N = self.dims["Nb" if spin else "Na"]
+        out = np.zeros(N, dtype=np.uint64)
+        self._check(self._L.casci_get_strings(self._h, int(spin), out.ctypes.data))
+        return out
+
+    def single_list(self, spin: int):
+        d = self.dims
+        N, s = (d["Nb"], d["sb"]) if spin else (d["Na"], d["sa"])
+        J = np.zeros(N * s, dtype=np.int32)
+        sg = np.zeros(N * s, dtype=np.int8)
+        p = np.zeros(N * s, dtype=np.uint8)
+        q = np.zeros(N * s, dtype=np.uint8)
+        self._check(self._L.casci_get_single_list(self._h, int(spin), J.ctypes.data, sg.ctypes.data,
+                                                  p.ctypes.data, q.ctypes.data))
+        return tuple(a.reshape(N, s) for a in (p, q, J, sg))
+
+    def same_spin_operator(self, spin: int):
+        d = self.dims
+        N, r = (d["Nb"], d["rb"]) if spin else (d["Na"], d["ra"])
+        col = np.zeros(N * r, dtype=np.int32)
+        val = np.zeros(N * r, dtype=np.float64)
+        self._check(self._L.casci_get_same_spin_operator(self._h, int(spin), col.ctypes.data,
+                                                         val.ctypes.data))
+        return col.reshape(N, r), val.reshape(N, r)
+
+    def diagonal(self, out=None):
+        d = self.dims
+        if out is None:
+            out = np.zeros((d["Na"], d["Nb"]))
+        p, mem = _ptr(out)
+        self._check(self._L.casci_get_diagonal(self._h, p, mem))
+        return out
+
+    # -- compute ------------------------------------------------------------
+    def sigma(self, C, out=None, ab_prec: str = "f64"):
+        """sigma = H C. C: [Na, Nb] float64/float32, numpy (host) or torch (device)."""
+        if out is None:
+            if isinstance(C, np.ndarray):
+                out = np.empty_like(C)
+            else:
+                import torch
+                out = torch.empty_like(C)
+        dt = str(C.dtype)
+        dtype = F64 if dt.endswith("float64") else (F32 if dt.endswith("float32") else None)
+        if dtype is None:
+            raise TypeError("C must be float64 or float32")
+        pc, mem = _ptr(C)
+        ps, mem2 = _ptr(out)
+        if mem != mem2 or str(out.dtype) != dt:
+            raise ValueError("C and out must share memory kind and dtype")
+        self._check(self._L.casci_sigma(self._h, pc, ps, dtype, PREC[ab_prec], mem))
+        return out
+
+    def profile(self, on: bool = True):
+        """Start (reset) or stop per-part device timing of sigma builds."""
+        self._check(self._L.casci_profile_enable(self._h, 1 if on else 0))
+
+    def profile_read(self):
+        out = np.zeros(8)
+        self._check(self._L.casci_profile_read(self._h, out.ctypes.data))
+        keys = ["aa_ms", "bb_transpose_ms", "bb_ms", "ab_ms", "sigma_builds", "sigma_builds_fp64"]
+        return {k: float(v) for k, v in zip(keys, out)}
+
+    def spin_square(self, C):
+        pc, mem = _ptr(C)
+        s2 = ctypes.c_double()
+        self._check(self._L.casci_spin_square(self._h, pc, ctypes.byref(s2), mem))
+        return s2.value
+
+    def davidson(self, nroots: int = 1, tol: float = 1e-10, *, precond: str = "diag", spin: str = "any",
+                 ab_prec: str = "f64", max_iter: int = 0, m_max: int = 0, r_tol: float = 0.0,
+                 refine_rnorm: float = 0.0, s2_penalty: float = 0.0, guess=None, vectors=True,
+                 history: int = 0, vectors_out=None):
+        """Lowest roots by Davidson-Liu. Returns (energies, vectors or None, info dict)."""
+        o = DavidsonOpts()
+        o.max_iter, o.m_max = int(max_iter), int(m_max)
+        o.precond, o.spin, o.ab_prec = PRECOND[precond], SPIN[spin], PREC[ab_prec]
+        o.refine_rnorm, o.r_tol, o.s2_penalty = float(refine_rnorm), float(r_tol), float(s2_penalty)
+        if guess is not None:
+            gp, gm = _ptr(guess)
+            o.guess, o.nguess, o.guess_mem = gp, int(guess.shape[0]), gm
+        info = DavidsonInfo()
+        hist = None
+        if history:
+            hist = (np.zeros((history, nroots)), np.zeros((history, nroots)), np.zeros(history))
+            info.hist_energy, info.hist_residual, info.hist_time_ms = (h.ctypes.data for h in hist)
+            info.hist_len = int(history)
+        E = np.zeros(nroots)
+        vp, vm = 0, MEM_HOST
+        vec = None
+        if vectors_out is not None:
+            vec = vectors_out
+            vp, vm = _ptr(vec)
+        elif vectors:
+            d = self.dims
+            vec = np.zeros((nroots, d["Na"], d["Nb"]))
+            vp, vm = _ptr(vec)
+        rc = self._L.casci_davidson(self._h, int(nroots), float(tol), ctypes.byref(o), E.ctypes.data,
+                                    ctypes.c_void_p(vp or None), vm, ctypes.byref(info))
+        self._check(rc, allow=(OK, NOCONV))
+        out = {
+            "status": rc, "iterations": info.iterations, "sigma_calls": info.sigma_calls,
+            "sigma_calls_fp64": info.sigma_calls_fp64, "converged": bool(info.converged),
+            "switch_iter": info.switch_iter, "mlp_fallbacks": info.mlp_fallbacks,
+            "residual": list(info.residual[:nroots]), "s2": list(info.s2[:nroots]),
+            "time_total_ms": info.time_total_ms, "time_sigma_ms": info.time_sigma_ms,
+            "time_setup_ms": info.time_setup_ms,
+        }
+        if hist is not None:
+            n = min(info.iterations, history)
+            out["hist_energy"], out["hist_residual"], out["hist_time_ms"] = (
+                hist[0][:n], hist[1][:n], hist[2][:n])
+        return E, vec, out

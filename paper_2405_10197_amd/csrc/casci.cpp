@@ -1,0 +1,1253 @@
+// Host runtime behind include/casci.h: argument validation, device memory,
+// integral preparation and the Davidson-Liu driver. Every arithmetic step
+// on CI vectors runs in the HIP kernels of this directory; the host only
+// handles the tiny projected quantities (subspace bookkeeping of at most
+// 64 x 64 numbers) and control flow.
+#include "casci.h"
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <limits>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+
+using namespace casci;
+
+namespace {
+
+struct DBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+    hipError_t ensure(size_t b)
+    {
+        if (b <= bytes && p) return hipSuccess;
+        release();
+        if (b == 0) b = 16;
+        hipError_t e = hipMalloc(&p, b);
+        if (e != hipSuccess) {
+            p = nullptr;
+            bytes = 0;
+            (void)hipGetLastError();
+            return e;
+        }
+        bytes = b;
+        return hipSuccess;
+    }
+    void release()
+    {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        bytes = 0;
+    }
+    template <typename T>
+    T* as() const
+    {
+        return reinterpret_cast<T*>(p);
+    }
+};
+
+struct DeviceGuard {
+    int prev = -1;
+    bool active = false;
+    explicit DeviceGuard(int dev)
+    {
+        if (dev < 0) return;
+        if (hipGetDevice(&prev) == hipSuccess && prev != dev) {
+            active = hipSetDevice(dev) == hipSuccess;
+        }
+    }
+    ~DeviceGuard()
+    {
+        if (active) (void)hipSetDevice(prev);
+    }
+};
+
+int64_t binomial(int n, int k)
+{
+    if (k < 0 || k > n) return 0;
+    long double r = 1;
+    for (int i = 1; i <= k; ++i) r = r * (n - k + i) / i;
+    return (int64_t)llroundl(r);
+}
+
+}  // namespace
+
+struct casci_ctx {
+    int device = -1;
+    bool validate_only = false;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    std::string err;
+
+    // integrals
+    bool has_ints = false;
+    int norb_ints = 0;
+    std::vector<double> h, eri;
+    double ecore = 0.0;
+
+    // strings
+    bool has_strings = false;
+    int norb = 0, na = 0, nb = 0;
+    int64_t Na = 0, Nb = 0, Nd = 0;
+    int sa = 0, sb = 0, ra = 0, rb = 0;
+    std::vector<int64_t> binom;  // (norb+1)^2
+
+    DBuf d_binom, d_astr, d_bstr, d_la_j, d_la_pq, d_lb_j, d_lb_pq;
+
+    // integral-dependent data
+    bool prepared = false;
+    double prepared_lambda = 0.0;
+    DBuf d_h, d_eri, d_fa_col, d_fa_val, d_fb_col, d_fb_val, d_jpq, d_diag;
+    DBuf d_vt_sym, d_pairs_sym, d_vt_full, d_pairs_full, d_vt_s2;
+    int M_sym = 0, Mp_sym = 0, M_full = 0, Mp_full = 0;
+    bool have_full = false, have_s2 = false;
+
+    // workspaces
+    DBuf d_t1, d_t2, d_vin, d_vout, d_work, d_small;
+
+    // optional per-part timing of sigma builds (HIP events on `stream`)
+    bool profiling = false;
+    hipEvent_t pev[6] = {};
+    double prof[8] = {};
+
+    int fail(int code, const std::string& msg)
+    {
+        err = msg;
+        return code;
+    }
+};
+
+#define HIPC(expr)                                                                      \
+    do {                                                                                \
+        hipError_t e_ = (expr);                                                         \
+        if (e_ != hipSuccess) {                                                         \
+            (void)hipGetLastError();                                                    \
+            return ctx->fail(e_ == hipErrorOutOfMemory ? CASCI_E_NOMEM : CASCI_E_DEVICE,  \
+                             std::string(#expr) + ": " + hipGetErrorString(e_));        \
+        }                                                                               \
+    } while (0)
+
+#define CHECK_RC(expr)          \
+    do {                        \
+        int rc_ = (expr);       \
+        if (rc_ < 0) return rc_; \
+    } while (0)
+
+static const char* kValidateOnly = "validate-only context: no device work is launched";
+
+// ---------------------------------------------------------------------------
+// context
+// ---------------------------------------------------------------------------
+extern "C" int casci_create(casci_ctx** out, int device, void* hip_stream)
+{
+    if (!out) return CASCI_E_ARG;
+    *out = nullptr;
+    casci_ctx* ctx = new (std::nothrow) casci_ctx();
+    if (!ctx) return CASCI_E_NOMEM;
+    if (device < -1) {
+        delete ctx;
+        return CASCI_E_ARG;
+    }
+    if (device == -1) {
+        ctx->validate_only = true;
+        *out = ctx;
+        return CASCI_OK;
+    }
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || device >= count) {
+        (void)hipGetLastError();
+        delete ctx;
+        return CASCI_E_DEVICE;
+    }
+    ctx->device = device;
+    DeviceGuard g(device);
+    if (hip_stream) {
+        ctx->stream = (hipStream_t)hip_stream;
+    } else {
+        if (hipStreamCreate(&ctx->stream) != hipSuccess) {
+            delete ctx;
+            return CASCI_E_DEVICE;
+        }
+        ctx->own_stream = true;
+    }
+    *out = ctx;
+    return CASCI_OK;
+}
+
+extern "C" void casci_destroy(casci_ctx* ctx)
+{
+    if (!ctx) return;
+    if (!ctx->validate_only) {
+        DeviceGuard g(ctx->device);
+        (void)hipStreamSynchronize(ctx->stream);
+        DBuf* bufs[] = {&ctx->d_binom, &ctx->d_astr, &ctx->d_bstr, &ctx->d_la_j, &ctx->d_la_pq,
+                        &ctx->d_lb_j, &ctx->d_lb_pq, &ctx->d_h, &ctx->d_eri, &ctx->d_fa_col,
+                        &ctx->d_fa_val, &ctx->d_fb_col, &ctx->d_fb_val, &ctx->d_jpq, &ctx->d_diag,
+                        &ctx->d_vt_sym, &ctx->d_pairs_sym, &ctx->d_vt_full, &ctx->d_pairs_full,
+                        &ctx->d_vt_s2, &ctx->d_t1, &ctx->d_t2, &ctx->d_vin, &ctx->d_vout,
+                        &ctx->d_work, &ctx->d_small};
+        for (DBuf* b : bufs) b->release();
+        for (hipEvent_t& e : ctx->pev)
+            if (e) (void)hipEventDestroy(e);
+        if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
+    }
+    delete ctx;
+}
+
+extern "C" const char* casci_last_error(const casci_ctx* ctx)
+{
+    return ctx ? ctx->err.c_str() : "null context";
+}
+
+// ---------------------------------------------------------------------------
+// integrals
+// ---------------------------------------------------------------------------
+extern "C" int casci_set_integrals(casci_ctx* ctx, int norb, const double* h, const double* eri,
+                                   double e_core, int mem)
+{
+    if (!ctx) return CASCI_E_ARG;
+    if (norb < 1 || norb > 64) return ctx->fail(CASCI_E_ARG, "norb must be in [1, 64]");
+    if (!h || !eri) return ctx->fail(CASCI_E_ARG, "h and eri must not be NULL");
+    if (mem != CASCI_MEM_HOST && mem != CASCI_MEM_DEVICE) return ctx->fail(CASCI_E_ARG, "bad mem flag");
+    if (ctx->has_strings && ctx->norb != norb)
+        return ctx->fail(CASCI_E_STATE, "norb differs from the strings already built");
+    const size_t n = (size_t)norb, n2 = n * n, n4 = n2 * n2;
+    std::vector<double> hh(n2), ee(n4);
+    if (mem == CASCI_MEM_DEVICE) {
+        if (ctx->validate_only) return ctx->fail(CASCI_E_UNSUPPORTED, kValidateOnly);
+        DeviceGuard g(ctx->device);
+        HIPC(hipMemcpyAsync(hh.data(), h, n2 * 8, hipMemcpyDeviceToHost, ctx->stream));
+        HIPC(hipMemcpyAsync(ee.data(), eri, n4 * 8, hipMemcpyDeviceToHost, ctx->stream));
+        HIPC(hipStreamSynchronize(ctx->stream));
+    } else {
+        std::memcpy(hh.data(), h, n2 * 8);
+        std::memcpy(ee.data(), eri, n4 * 8);
+    }
+    if (!std::isfinite(e_core)) return ctx->fail(CASCI_E_NONFINITE, "e_core is not finite");
+    double hmax = 0.0, emax = 0.0;
+    for (double v : hh) {
+        if (!std::isfinite(v)) return ctx->fail(CASCI_E_NONFINITE, "h has a non-finite entry");
+        hmax = std::max(hmax, std::fabs(v));
+    }
+    for (double v : ee) {
+        if (!std::isfinite(v)) return ctx->fail(CASCI_E_NONFINITE, "eri has a non-finite entry");
+        emax = std::max(emax, std::fabs(v));
+    }
+    const double th = 1e-12 * std::max(1.0, hmax), te = 1e-12 * std::max(1.0, emax);
+    for (size_t p = 0; p < n; ++p)
+        for (size_t q = 0; q < n; ++q)
+            if (std::fabs(hh[p * n + q] - hh[q * n + p]) > th)
+                return ctx->fail(CASCI_E_ARG, "h is not symmetric");
+    auto E = [&](size_t p, size_t q, size_t r, size_t s) { return ee[((p * n + q) * n + r) * n + s]; };
+    for (size_t p = 0; p < n; ++p)
+        for (size_t q = 0; q < n; ++q)
+            for (size_t r = 0; r < n; ++r)
+                for (size_t s = 0; s < n; ++s) {
+                    double v = E(p, q, r, s);
+                    if (std::fabs(v - E(q, p, r, s)) > te || std::fabs(v - E(p, q, s, r)) > te ||
+                        std::fabs(v - E(r, s, p, q)) > te)
+                        return ctx->fail(CASCI_E_ARG, "eri lacks the 8-fold (pq|rs) symmetry");
+                }
+    ctx->h.swap(hh);
+    ctx->eri.swap(ee);
+    ctx->ecore = e_core;
+    ctx->norb_ints = norb;
+    ctx->has_ints = true;
+    ctx->prepared = false;
+    ctx->have_full = ctx->have_s2 = false;
+    return CASCI_OK;
+}
+
+// ---------------------------------------------------------------------------
+// strings
+// ---------------------------------------------------------------------------
+static int64_t predicted_bytes(int64_t Na, int64_t Nb, int sa, int sb, int ra, int rb)
+{
+    const int64_t Nd = Na * Nb;
+    int64_t b = 8 * (Na + Nb) + 6 * (Na * (int64_t)sa + Nb * (int64_t)sb);
+    b += 12 * (Na * (int64_t)ra + Nb * (int64_t)rb);
+    b += 8 * Nd * 5;  // diagonal, two sigma temporaries, one C/sigma pair
+    return b;
+}
+
+extern "C" int casci_build_strings(casci_ctx* ctx, int nalpha, int nbeta, int norb)
+{
+    if (!ctx) return CASCI_E_ARG;
+    if (norb < 1 || norb > 64) return ctx->fail(CASCI_E_ARG, "norb must be in [1, 64]");
+    if (nalpha < 0 || nbeta < 0 || nalpha > norb || nbeta > norb)
+        return ctx->fail(CASCI_E_ARG, "need 0 <= nalpha, nbeta <= norb");
+    if (ctx->has_ints && ctx->norb_ints != norb)
+        return ctx->fail(CASCI_E_STATE, "norb differs from the integrals already set");
+    const int64_t Na = binomial(norb, nalpha), Nb = binomial(norb, nbeta);
+    if (Na >= (1LL << 31) || Nb >= (1LL << 31))
+        return ctx->fail(CASCI_E_NOMEM, "more than 2^31 strings per spin");
+    if (Na > 0 && Nb > (int64_t)9e18 / Na) return ctx->fail(CASCI_E_NOMEM, "determinant count overflows");
+    const int sa = nalpha * (norb - nalpha + 1), sb = nbeta * (norb - nbeta + 1);
+    auto rcount = [&](int ne) {
+        return (int)(1 + ne * (norb - ne) + binomial(ne, 2) * binomial(norb - ne, 2));
+    };
+    const int ra = rcount(nalpha), rb = rcount(nbeta);
+    const int64_t need = predicted_bytes(Na, Nb, sa, sb, ra, rb);
+    if (need > (1LL << 40)) return ctx->fail(CASCI_E_NOMEM, "predicted device memory exceeds 1 TiB");
+    std::vector<int64_t> binom((size_t)(norb + 1) * (norb + 1));
+    for (int p = 0; p <= norb; ++p)
+        for (int k = 0; k <= norb; ++k) binom[(size_t)p * (norb + 1) + k] = binomial(p, k);
+
+    if (!ctx->validate_only) {
+        DeviceGuard g(ctx->device);
+        size_t fr = 0, tot = 0;
+        if (hipMemGetInfo(&fr, &tot) == hipSuccess && (size_t)need > fr)
+            return ctx->fail(CASCI_E_NOMEM, "predicted device memory exceeds free memory");
+        (void)hipGetLastError();
+        casci_ctx tmp;  // build into fresh buffers so a failure leaves no partial state
+        HIPC(tmp.d_binom.ensure(binom.size() * 8));
+        HIPC(tmp.d_astr.ensure(Na * 8));
+        HIPC(tmp.d_bstr.ensure(Nb * 8));
+        HIPC(tmp.d_la_j.ensure(Na * (size_t)sa * 4));
+        HIPC(tmp.d_la_pq.ensure(Na * (size_t)sa * 2));
+        HIPC(tmp.d_lb_j.ensure(Nb * (size_t)sb * 4));
+        HIPC(tmp.d_lb_pq.ensure(Nb * (size_t)sb * 2));
+        HIPC(hipMemcpyAsync(tmp.d_binom.p, binom.data(), binom.size() * 8, hipMemcpyHostToDevice,
+                            ctx->stream));
+        HIPC(launch_build_strings(norb, nalpha, Na, tmp.d_binom.as<int64_t>(), tmp.d_astr.as<uint64_t>(),
+                                  ctx->stream));
+        HIPC(launch_build_strings(norb, nbeta, Nb, tmp.d_binom.as<int64_t>(), tmp.d_bstr.as<uint64_t>(),
+                                  ctx->stream));
+        HIPC(launch_single_lists(norb, nalpha, Na, tmp.d_astr.as<uint64_t>(), tmp.d_binom.as<int64_t>(),
+                                 sa, tmp.d_la_j.as<int32_t>(), tmp.d_la_pq.as<uint16_t>(), ctx->stream));
+        HIPC(launch_single_lists(norb, nbeta, Nb, tmp.d_bstr.as<uint64_t>(), tmp.d_binom.as<int64_t>(),
+                                 sb, tmp.d_lb_j.as<int32_t>(), tmp.d_lb_pq.as<uint16_t>(), ctx->stream));
+        HIPC(hipStreamSynchronize(ctx->stream));
+        std::swap(ctx->d_binom, tmp.d_binom);
+        std::swap(ctx->d_astr, tmp.d_astr);
+        std::swap(ctx->d_bstr, tmp.d_bstr);
+        std::swap(ctx->d_la_j, tmp.d_la_j);
+        std::swap(ctx->d_la_pq, tmp.d_la_pq);
+        std::swap(ctx->d_lb_j, tmp.d_lb_j);
+        std::swap(ctx->d_lb_pq, tmp.d_lb_pq);
+        DBuf* old[] = {&tmp.d_binom, &tmp.d_astr, &tmp.d_bstr, &tmp.d_la_j,
+                       &tmp.d_la_pq, &tmp.d_lb_j, &tmp.d_lb_pq};
+        for (DBuf* b : old) b->release();
+    }
+    ctx->binom.swap(binom);
+    ctx->norb = norb;
+    ctx->na = nalpha;
+    ctx->nb = nbeta;
+    ctx->Na = Na;
+    ctx->Nb = Nb;
+    ctx->Nd = Na * Nb;
+    ctx->sa = sa;
+    ctx->sb = sb;
+    ctx->ra = ra;
+    ctx->rb = rb;
+    ctx->has_strings = true;
+    ctx->prepared = false;
+    ctx->have_full = ctx->have_s2 = false;
+    return CASCI_OK;
+}
+
+extern "C" int casci_get_dims(const casci_ctx* ctx, int64_t* dims)
+{
+    if (!ctx || !dims) return CASCI_E_ARG;
+    if (!ctx->has_strings) return CASCI_E_STATE;
+    dims[0] = ctx->Na;
+    dims[1] = ctx->Nb;
+    dims[2] = ctx->Nd;
+    dims[3] = ctx->sa;
+    dims[4] = ctx->sb;
+    dims[5] = ctx->ra;
+    dims[6] = ctx->rb;
+    dims[7] = ctx->norb;
+    return CASCI_OK;
+}
+
+static int need_device(casci_ctx* ctx)
+{
+    if (ctx->validate_only) return ctx->fail(CASCI_E_UNSUPPORTED, kValidateOnly);
+    return CASCI_OK;
+}
+
+extern "C" int casci_get_strings(casci_ctx* ctx, int spin, uint64_t* out)
+{
+    if (!ctx) return CASCI_E_ARG;
+    if (spin != 0 && spin != 1) return ctx->fail(CASCI_E_ARG, "spin must be 0 or 1");
+    if (!out) return ctx->fail(CASCI_E_ARG, "out is NULL");
+    if (!ctx->has_strings) return ctx->fail(CASCI_E_STATE, "build_strings first");
+    CHECK_RC(need_device(ctx));
+    DeviceGuard g(ctx->device);
+    const DBuf& b = spin ? ctx->d_bstr : ctx->d_astr;
+    const int64_t N = spin ? ctx->Nb : ctx->Na;
+    HIPC(hipMemcpyAsync(out, b.p, N * 8, hipMemcpyDeviceToHost, ctx->stream));
+    HIPC(hipStreamSynchronize(ctx->stream));
+    return CASCI_OK;
+}
+
+extern "C" int casci_get_single_list(casci_ctx* ctx, int spin, int32_t* J, int8_t* sign, uint8_t* p,
+                                     uint8_t* q)
+{
+    if (!ctx) return CASCI_E_ARG;
+    if (spin != 0 && spin != 1) return ctx->fail(CASCI_E_ARG, "spin must be 0 or 1");
+    if (!ctx->has_strings) return ctx->fail(CASCI_E_STATE, "build_strings first");
+    CHECK_RC(need_device(ctx));
+    DeviceGuard g(ctx->device);
+    const int64_t N = spin ? ctx->Nb : ctx->Na;
+    const int s = spin ? ctx->sb : ctx->sa;
+    const size_t cnt = (size_t)N * s;
+    std::vector<int32_t> lj(cnt);
+    std::vector<uint16_t> lpq(cnt);
+    if (cnt) {
+        HIPC(hipMemcpyAsync(lj.data(), (spin ? ctx->d_lb_j : ctx->d_la_j).p, cnt * 4,
+                            hipMemcpyDeviceToHost, ctx->stream));
+        HIPC(hipMemcpyAsync(lpq.data(), (spin ? ctx->d_lb_pq : ctx->d_la_pq).p, cnt * 2,
+                            hipMemcpyDeviceToHost, ctx->stream));
+        HIPC(hipStreamSynchronize(ctx->stream));
+    }
+    for (size_t i = 0; i < cnt; ++i) {
+        if (J) J[i] = l1_index(lj[i]);
+        if (sign) sign[i] = (int8_t)l1_sign(lj[i]);
+        if (p) p[i] = (uint8_t)(lpq[i] & 0xff);
+        if (q) q[i] = (uint8_t)(lpq[i] >> 8);
+    }
+    return CASCI_OK;
+}
+
+// ---------------------------------------------------------------------------
+// integral-dependent preparation
+// ---------------------------------------------------------------------------
+static void pair_tables(int n, bool full, std::vector<uint16_t>& pairs, int& M, int& Mp)
+{
+    pairs.clear();
+    for (int r = 0; r < n; ++r)
+        for (int s = full ? 0 : r; s < n; ++s) pairs.push_back((uint16_t)(r | (s << 8)));
+    M = (int)pairs.size();
+    Mp = (M + 15) / 16 * 16;
+    pairs.resize(Mp, 0xffff);
+}
+
+// Vt[pq][m] = (pq|r_m s_m) + coefficient of the S^2 penalty:
+// lambda * S^2 contains -lambda sum_pq E^a_qp E^b_pq, i.e. -lambda on
+// (alpha pair (p,q), beta pair (r,s)) whenever p = s and q = r.
+static void build_vt(const casci_ctx* ctx, const std::vector<uint16_t>& pairs, int M, int Mp,
+                     double eri_scale, double penalty, std::vector<double>& vt)
+{
+    const int n = ctx->norb;
+    vt.assign((size_t)n * n * Mp, 0.0);
+    for (int p = 0; p < n; ++p)
+        for (int q = 0; q < n; ++q)
+            for (int m = 0; m < M; ++m) {
+                const int r = pairs[m] & 0xff, s = pairs[m] >> 8;
+                double v = eri_scale * ctx->eri[(((size_t)p * n + q) * n + r) * n + s];
+                if (p == s && q == r) v -= penalty;
+                vt[((size_t)p * n + q) * Mp + m] = v;
+            }
+}
+
+static int ensure_prepared(casci_ctx* ctx, double lambda)
+{
+    if (!ctx->has_ints) return ctx->fail(CASCI_E_STATE, "set_integrals first");
+    if (!ctx->has_strings) return ctx->fail(CASCI_E_STATE, "build_strings first");
+    if (ctx->norb != ctx->norb_ints) return ctx->fail(CASCI_E_STATE, "norb mismatch");
+    CHECK_RC(need_device(ctx));
+    const int n = ctx->norb;
+    hipStream_t st = ctx->stream;
+    if (!ctx->prepared) {
+        HIPC(ctx->d_h.ensure((size_t)n * n * 8));
+        HIPC(ctx->d_eri.ensure((size_t)n * n * n * n * 8));
+        HIPC(hipMemcpyAsync(ctx->d_h.p, ctx->h.data(), (size_t)n * n * 8, hipMemcpyHostToDevice, st));
+        HIPC(hipMemcpyAsync(ctx->d_eri.p, ctx->eri.data(), (size_t)n * n * n * n * 8,
+                            hipMemcpyHostToDevice, st));
+        HIPC(ctx->d_fa_col.ensure((size_t)ctx->Na * ctx->ra * 4));
+        HIPC(ctx->d_fa_val.ensure((size_t)ctx->Na * ctx->ra * 8));
+        HIPC(launch_same_spin_operator(n, ctx->na, ctx->Na, ctx->d_astr.as<uint64_t>(),
+                                       ctx->d_binom.as<int64_t>(), ctx->d_h.as<double>(),
+                                       ctx->d_eri.as<double>(), ctx->ra, ctx->d_fa_col.as<int32_t>(),
+                                       ctx->d_fa_val.as<double>(), st));
+        if (ctx->nb != ctx->na) {
+            HIPC(ctx->d_fb_col.ensure((size_t)ctx->Nb * ctx->rb * 4));
+            HIPC(ctx->d_fb_val.ensure((size_t)ctx->Nb * ctx->rb * 8));
+            HIPC(launch_same_spin_operator(n, ctx->nb, ctx->Nb, ctx->d_bstr.as<uint64_t>(),
+                                           ctx->d_binom.as<int64_t>(), ctx->d_h.as<double>(),
+                                           ctx->d_eri.as<double>(), ctx->rb,
+                                           ctx->d_fb_col.as<int32_t>(), ctx->d_fb_val.as<double>(), st));
+        } else {
+            ctx->d_fb_col.release();
+            ctx->d_fb_val.release();
+        }
+        std::vector<double> jpq((size_t)n * n);
+        for (int p = 0; p < n; ++p)
+            for (int q = 0; q < n; ++q) jpq[p * n + q] = ctx->eri[(((size_t)p * n + p) * n + q) * n + q];
+        HIPC(ctx->d_jpq.ensure(jpq.size() * 8));
+        HIPC(hipMemcpyAsync(ctx->d_jpq.p, jpq.data(), jpq.size() * 8, hipMemcpyHostToDevice, st));
+        std::vector<uint16_t> pairs;
+        std::vector<double> vt;
+        pair_tables(n, false, pairs, ctx->M_sym, ctx->Mp_sym);
+        build_vt(ctx, pairs, ctx->M_sym, ctx->Mp_sym, 1.0, 0.0, vt);
+        HIPC(ctx->d_pairs_sym.ensure(pairs.size() * 2));
+        HIPC(ctx->d_vt_sym.ensure(vt.size() * 8));
+        HIPC(hipMemcpyAsync(ctx->d_pairs_sym.p, pairs.data(), pairs.size() * 2, hipMemcpyHostToDevice, st));
+        HIPC(hipMemcpyAsync(ctx->d_vt_sym.p, vt.data(), vt.size() * 8, hipMemcpyHostToDevice, st));
+        // pageable host sources: finish before the vectors go out of scope
+        HIPC(hipStreamSynchronize(st));
+        ctx->prepared = true;
+        ctx->have_full = false;
+        ctx->prepared_lambda = std::nan("");
+    }
+    if (!(ctx->prepared_lambda == lambda)) {
+        HIPC(ctx->d_diag.ensure((size_t)ctx->Nd * 8));
+        const bool same = ctx->nb == ctx->na;
+        HIPC(launch_diagonal(n, ctx->Na, ctx->Nb, ctx->d_astr.as<uint64_t>(), ctx->d_bstr.as<uint64_t>(),
+                             ctx->d_fa_val.as<double>(), ctx->ra,
+                             (same ? ctx->d_fa_val : ctx->d_fb_val).as<double>(), ctx->rb,
+                             ctx->d_jpq.as<double>(), ctx->ecore, lambda, ctx->d_diag.as<double>(), st));
+        if (lambda != 0.0) {
+            std::vector<uint16_t> pairs;
+            std::vector<double> vt;
+            pair_tables(n, true, pairs, ctx->M_full, ctx->Mp_full);
+            build_vt(ctx, pairs, ctx->M_full, ctx->Mp_full, 1.0, lambda, vt);
+            HIPC(ctx->d_pairs_full.ensure(pairs.size() * 2));
+            HIPC(ctx->d_vt_full.ensure(vt.size() * 8));
+            HIPC(hipMemcpyAsync(ctx->d_pairs_full.p, pairs.data(), pairs.size() * 2,
+                                hipMemcpyHostToDevice, st));
+            HIPC(hipMemcpyAsync(ctx->d_vt_full.p, vt.data(), vt.size() * 8, hipMemcpyHostToDevice, st));
+            HIPC(hipStreamSynchronize(st));
+            ctx->have_full = true;
+        }
+        ctx->prepared_lambda = lambda;
+    }
+    return CASCI_OK;
+}
+
+static AbParams ab_params(const casci_ctx* ctx, bool full)
+{
+    AbParams p;
+    p.n = ctx->norb;
+    p.nb = ctx->nb;
+    p.Na = ctx->Na;
+    p.Nb = ctx->Nb;
+    p.sa = ctx->sa;
+    p.M = full ? ctx->M_full : ctx->M_sym;
+    p.Mp = full ? ctx->Mp_full : ctx->Mp_sym;
+    p.full = full ? 1 : 0;
+    p.la_j = ctx->d_la_j.as<int32_t>();
+    p.la_pq = ctx->d_la_pq.as<uint16_t>();
+    p.bstr = ctx->d_bstr.as<uint64_t>();
+    p.binom = ctx->d_binom.as<int64_t>();
+    p.pairs = (full ? ctx->d_pairs_full : ctx->d_pairs_sym).as<uint16_t>();
+    return p;
+}
+
+// sigma = (H + lambda S^2) C on device vectors (FP64 storage)
+static int sigma_dev(casci_ctx* ctx, const double* C, double* S, int ab_prec, double lambda)
+{
+    hipStream_t st = ctx->stream;
+    const int64_t Na = ctx->Na, Nb = ctx->Nb, Nd = ctx->Nd;
+    const double ms = 0.5 * (ctx->na - ctx->nb);
+    const double shift = ctx->ecore + lambda * (ms * ms + ms + ctx->nb);
+    const bool prof = ctx->profiling;
+    auto mark = [&](int i) -> int {
+        if (prof) HIPC(hipEventRecord(ctx->pev[i], st));
+        return CASCI_OK;
+    };
+    CHECK_RC(mark(0));
+    HIPC(launch_ss_gather_f64(ctx->d_fa_col.as<int32_t>(), ctx->d_fa_val.as<double>(), ctx->ra, Na, Nb,
+                              C, S, shift, 0, st));
+    CHECK_RC(mark(1));
+    if (ctx->nb > 0) {
+        HIPC(ctx->d_t1.ensure((size_t)Nd * 8));
+        HIPC(ctx->d_t2.ensure((size_t)Nd * 8));
+        const bool same = ctx->nb == ctx->na;
+        const DBuf& fcol = same ? ctx->d_fa_col : ctx->d_fb_col;
+        const DBuf& fval = same ? ctx->d_fa_val : ctx->d_fb_val;
+        HIPC(launch_transpose_f64(C, ctx->d_t1.as<double>(), Na, Nb, 0, 1.0, st));
+        CHECK_RC(mark(2));
+        HIPC(launch_ss_gather_f64(fcol.as<int32_t>(), fval.as<double>(), ctx->rb, Nb, Na,
+                                  ctx->d_t1.as<double>(), ctx->d_t2.as<double>(), 0.0, 0, st));
+        CHECK_RC(mark(3));
+        HIPC(launch_transpose_f64(ctx->d_t2.as<double>(), S, Nb, Na, 1, 1.0, st));
+    } else {
+        CHECK_RC(mark(2));
+        CHECK_RC(mark(3));
+    }
+    CHECK_RC(mark(4));
+    if (ctx->na > 0 && ctx->nb > 0) {
+        const bool full = lambda != 0.0;
+        AbParams p = ab_params(ctx, full);
+        const DBuf& vt = full ? ctx->d_vt_full : ctx->d_vt_sym;
+        if (ab_prec == CASCI_F64) {
+            HIPC(launch_ab_f64(p, vt.as<double>(), C, S, st));
+        } else {
+            return ctx->fail(CASCI_E_UNSUPPORTED, "low-precision alpha-beta arithmetic not built");
+        }
+    }
+    CHECK_RC(mark(5));
+    if (prof) {
+        HIPC(hipEventSynchronize(ctx->pev[5]));
+        float t[5];
+        for (int i = 0; i < 5; ++i) HIPC(hipEventElapsedTime(&t[i], ctx->pev[i], ctx->pev[i + 1]));
+        ctx->prof[0] += t[0];         // alpha-alpha gather
+        ctx->prof[1] += t[1] + t[3];  // the two transposes of the beta-beta term
+        ctx->prof[2] += t[2];         // beta-beta gather
+        ctx->prof[3] += t[4];         // alpha-beta contraction
+        ctx->prof[4] += 1;            // sigma builds
+        ctx->prof[5] += (ab_prec == CASCI_F64) ? 1 : 0;
+    }
+    return CASCI_OK;
+}
+
+extern "C" int casci_profile_enable(casci_ctx* ctx, int on)
+{
+    if (!ctx) return CASCI_E_ARG;
+    CHECK_RC(need_device(ctx));
+    DeviceGuard g(ctx->device);
+    if (on) {
+        for (hipEvent_t& e : ctx->pev)
+            if (!e) HIPC(hipEventCreate(&e));
+        for (double& x : ctx->prof) x = 0.0;
+    }
+    ctx->profiling = on != 0;
+    return CASCI_OK;
+}
+
+extern "C" int casci_profile_read(const casci_ctx* ctx, double* out)
+{
+    if (!ctx || !out) return CASCI_E_ARG;
+    for (int i = 0; i < 8; ++i) out[i] = ctx->prof[i];
+    return CASCI_OK;
+}
+
+extern "C" int casci_get_same_spin_operator(casci_ctx* ctx, int spin, int32_t* col, double* val)
+{
+    if (!ctx) return CASCI_E_ARG;
+    if (spin != 0 && spin != 1) return ctx->fail(CASCI_E_ARG, "spin must be 0 or 1");
+    if (!col || !val) return ctx->fail(CASCI_E_ARG, "col and val must not be NULL");
+    DeviceGuard g(ctx->device);
+    CHECK_RC(ensure_prepared(ctx, 0.0));
+    const bool same = ctx->nb == ctx->na;
+    const int64_t N = spin ? ctx->Nb : ctx->Na;
+    const int r = spin ? ctx->rb : ctx->ra;
+    const DBuf& dc = (spin && !same) ? ctx->d_fb_col : ctx->d_fa_col;
+    const DBuf& dv = (spin && !same) ? ctx->d_fb_val : ctx->d_fa_val;
+    const size_t cnt = (size_t)N * r;
+    std::vector<int32_t> c(cnt);
+    std::vector<double> v(cnt);
+    HIPC(hipMemcpyAsync(c.data(), dc.p, cnt * 4, hipMemcpyDeviceToHost, ctx->stream));
+    HIPC(hipMemcpyAsync(v.data(), dv.p, cnt * 8, hipMemcpyDeviceToHost, ctx->stream));
+    HIPC(hipStreamSynchronize(ctx->stream));
+    std::vector<int> idx(r);
+    for (int64_t I = 0; I < N; ++I) {
+        for (int k = 0; k < r; ++k) idx[k] = k;
+        const int32_t* cr = c.data() + I * r;
+        std::sort(idx.begin(), idx.end(), [&](int a, int b) { return cr[a] < cr[b]; });
+        for (int k = 0; k < r; ++k) {
+            col[I * r + k] = cr[idx[k]];
+            val[I * r + k] = v[I * r + idx[k]];
+        }
+    }
+    return CASCI_OK;
+}
+
+extern "C" int casci_get_diagonal(casci_ctx* ctx, double* out, int mem)
+{
+    if (!ctx) return CASCI_E_ARG;
+    if (!out) return ctx->fail(CASCI_E_ARG, "out is NULL");
+    if (mem != CASCI_MEM_HOST && mem != CASCI_MEM_DEVICE) return ctx->fail(CASCI_E_ARG, "bad mem flag");
+    DeviceGuard g(ctx->device);
+    CHECK_RC(ensure_prepared(ctx, 0.0));
+    HIPC(hipMemcpyAsync(out, ctx->d_diag.p, (size_t)ctx->Nd * 8,
+                        mem == CASCI_MEM_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice,
+                        ctx->stream));
+    if (mem == CASCI_MEM_HOST) HIPC(hipStreamSynchronize(ctx->stream));
+    return CASCI_OK;
+}
+
+static int check_vec_args(casci_ctx* ctx, const void* C, const void* S, int dtype, int ab_prec, int mem)
+{
+    if (!C || !S) return ctx->fail(CASCI_E_ARG, "C and sigma must not be NULL");
+    if (C == S) return ctx->fail(CASCI_E_ARG, "C and sigma must not overlap");
+    if (dtype != CASCI_F64 && dtype != CASCI_F32) return ctx->fail(CASCI_E_ARG, "dtype must be F64 or F32");
+    if (ab_prec != CASCI_F64 && ab_prec != CASCI_F32 && ab_prec != CASCI_BF16)
+        return ctx->fail(CASCI_E_ARG, "ab_prec must be F64, F32 or BF16");
+    if (mem != CASCI_MEM_HOST && mem != CASCI_MEM_DEVICE) return ctx->fail(CASCI_E_ARG, "bad mem flag");
+    return CASCI_OK;
+}
+
+extern "C" int casci_sigma(casci_ctx* ctx, const void* C, void* sigma, int dtype, int ab_prec, int mem)
+{
+    if (!ctx) return CASCI_E_ARG;
+    CHECK_RC(check_vec_args(ctx, C, sigma, dtype, ab_prec, mem));
+    if (!ctx->has_ints) return ctx->fail(CASCI_E_STATE, "set_integrals first");
+    if (!ctx->has_strings) return ctx->fail(CASCI_E_STATE, "build_strings first");
+    CHECK_RC(need_device(ctx));
+    DeviceGuard g(ctx->device);
+    CHECK_RC(ensure_prepared(ctx, 0.0));
+    const size_t Nd = (size_t)ctx->Nd;
+    const size_t esz = dtype == CASCI_F64 ? 8 : 4;
+    hipStream_t st = ctx->stream;
+    const double* cin;
+    double* sout;
+    if (dtype == CASCI_F64 && mem == CASCI_MEM_DEVICE) {
+        cin = (const double*)C;
+        sout = (double*)sigma;
+    } else {
+        HIPC(ctx->d_vin.ensure(Nd * 8));
+        HIPC(ctx->d_vout.ensure(Nd * 8));
+        cin = ctx->d_vin.as<double>();
+        sout = ctx->d_vout.as<double>();
+        if (dtype == CASCI_F64) {
+            HIPC(hipMemcpyAsync(ctx->d_vin.p, C, Nd * 8, hipMemcpyHostToDevice, st));
+        } else {
+            const float* src = (const float*)C;
+            if (mem == CASCI_MEM_HOST) {
+                HIPC(ctx->d_vout.ensure(Nd * 8));
+                HIPC(hipMemcpyAsync(ctx->d_vout.p, C, Nd * esz, hipMemcpyHostToDevice, st));
+                src = ctx->d_vout.as<float>();
+            }
+            HIPC(launch_convert_f32_to_f64(src, ctx->d_vin.as<double>(), (int64_t)Nd, st));
+        }
+    }
+    CHECK_RC(sigma_dev(ctx, cin, sout, ab_prec, 0.0));
+    if (!(dtype == CASCI_F64 && mem == CASCI_MEM_DEVICE)) {
+        if (dtype == CASCI_F64) {
+            HIPC(hipMemcpyAsync(sigma, sout, Nd * 8, hipMemcpyDeviceToHost, st));
+        } else if (mem == CASCI_MEM_DEVICE) {
+            HIPC(launch_convert_f64_to_f32(sout, (float*)sigma, (int64_t)Nd, st));
+        } else {
+            HIPC(launch_convert_f64_to_f32(sout, (float*)ctx->d_vin.p, (int64_t)Nd, st));
+            HIPC(hipMemcpyAsync(sigma, ctx->d_vin.p, Nd * 4, hipMemcpyDeviceToHost, st));
+        }
+        if (mem == CASCI_MEM_HOST) HIPC(hipStreamSynchronize(st));
+    }
+    return CASCI_OK;
+}
+
+// small device scratch: reduction partials + results
+static int ensure_work(casci_ctx* ctx, size_t nout)
+{
+    HIPC(ctx->d_work.ensure(nout * 512 * 8 + 4096));
+    return CASCI_OK;
+}
+
+static int dots(casci_ctx* ctx, const double* A, int na, const double* B, int nb, std::vector<double>& out)
+{
+    const size_t nout = (size_t)na * nb;
+    if (nout == 0) {
+        out.clear();
+        return CASCI_OK;
+    }
+    CHECK_RC(ensure_work(ctx, nout));
+    HIPC(ctx->d_small.ensure(64 * 1024 * 8));
+    double* res = ctx->d_small.as<double>() + 49152;  // dedicated region of the scratch block
+    if (nout > 16384) return ctx->fail(CASCI_E_ARG, "too many dot products in one call");
+    HIPC(launch_block_dot(A, ctx->Nd, na, B, ctx->Nd, nb, ctx->Nd, ctx->d_work.as<double>(), res,
+                          ctx->stream));
+    out.resize(nout);
+    HIPC(hipMemcpyAsync(out.data(), res, nout * 8, hipMemcpyDeviceToHost, ctx->stream));
+    HIPC(hipStreamSynchronize(ctx->stream));
+    return CASCI_OK;
+}
+
+// <S^2> = (Ms^2 + Ms + nb) |C|^2 - <C| sum_pq E^a_qp E^b_pq |C>  (divided by |C|^2)
+static int spin_square_dev(casci_ctx* ctx, const double* C, double* s2)
+{
+    hipStream_t st = ctx->stream;
+    const int n = ctx->norb;
+    const double ms = 0.5 * (ctx->na - ctx->nb);
+    std::vector<double> cc;
+    CHECK_RC(dots(ctx, C, 1, C, 1, cc));
+    double x = 0.0;
+    if (ctx->na > 0 && ctx->nb > 0) {
+        if (!ctx->have_s2) {
+            std::vector<uint16_t> pairs;
+            std::vector<double> vt;
+            int M, Mp;
+            pair_tables(n, true, pairs, M, Mp);
+            build_vt(ctx, pairs, M, Mp, 0.0, 1.0, vt);
+            HIPC(ctx->d_pairs_full.ensure(pairs.size() * 2));
+            HIPC(ctx->d_vt_s2.ensure(vt.size() * 8));
+            HIPC(hipMemcpyAsync(ctx->d_pairs_full.p, pairs.data(), pairs.size() * 2,
+                                hipMemcpyHostToDevice, st));
+            HIPC(hipMemcpyAsync(ctx->d_vt_s2.p, vt.data(), vt.size() * 8, hipMemcpyHostToDevice, st));
+            HIPC(hipStreamSynchronize(st));
+            ctx->M_full = M;
+            ctx->Mp_full = Mp;
+            ctx->have_s2 = true;
+        }
+        HIPC(ctx->d_t2.ensure((size_t)ctx->Nd * 8));
+        HIPC(hipMemsetAsync(ctx->d_t2.p, 0, (size_t)ctx->Nd * 8, st));
+        AbParams p = ab_params(ctx, true);
+        HIPC(launch_ab_f64(p, ctx->d_vt_s2.as<double>(), C, ctx->d_t2.as<double>(), st));
+        std::vector<double> cs;
+        CHECK_RC(dots(ctx, C, 1, ctx->d_t2.as<double>(), 1, cs));
+        x = cs[0];
+    }
+    *s2 = cc[0] > 0 ? ((ms * ms + ms + ctx->nb) * cc[0] + x) / cc[0] : 0.0;
+    return CASCI_OK;
+}
+
+extern "C" int casci_spin_square(casci_ctx* ctx, const double* C, double* s2, int mem)
+{
+    if (!ctx) return CASCI_E_ARG;
+    if (!C || !s2) return ctx->fail(CASCI_E_ARG, "C and s2 must not be NULL");
+    if (mem != CASCI_MEM_HOST && mem != CASCI_MEM_DEVICE) return ctx->fail(CASCI_E_ARG, "bad mem flag");
+    if (!ctx->has_strings) return ctx->fail(CASCI_E_STATE, "build_strings first");
+    if (!ctx->has_ints) return ctx->fail(CASCI_E_STATE, "set_integrals first");
+    CHECK_RC(need_device(ctx));
+    DeviceGuard g(ctx->device);
+    CHECK_RC(ensure_prepared(ctx, ctx->prepared ? ctx->prepared_lambda : 0.0));
+    const double* c = C;
+    if (mem == CASCI_MEM_HOST) {
+        HIPC(ctx->d_vin.ensure((size_t)ctx->Nd * 8));
+        HIPC(hipMemcpyAsync(ctx->d_vin.p, C, (size_t)ctx->Nd * 8, hipMemcpyHostToDevice, ctx->stream));
+        c = ctx->d_vin.as<double>();
+    }
+    return spin_square_dev(ctx, c, s2);
+}
+
+// ---------------------------------------------------------------------------
+// Davidson-Liu
+// ---------------------------------------------------------------------------
+namespace {
+
+struct Timer {
+    std::chrono::steady_clock::time_point t0 = std::chrono::steady_clock::now();
+    double ms() const
+    {
+        return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    }
+};
+
+}  // namespace
+
+extern "C" int casci_davidson(casci_ctx* ctx, int nroots, double tol, const casci_davidson_opts* opts,
+                              double* energies, void* vectors, int mem, casci_davidson_info* info)
+{
+    if (!ctx) return CASCI_E_ARG;
+    Timer wall;
+    casci_davidson_opts o;
+    std::memset(&o, 0, sizeof(o));
+    o.ab_prec = CASCI_F64;
+    if (opts) o = *opts;
+    if (nroots < 1 || nroots > CASCI_MAX_ROOTS) return ctx->fail(CASCI_E_ARG, "nroots must be in [1, 32]");
+    if (!(tol > 0.0) || !std::isfinite(tol)) return ctx->fail(CASCI_E_ARG, "tol must be positive");
+    if (!energies) return ctx->fail(CASCI_E_ARG, "energies must not be NULL");
+    if (mem != CASCI_MEM_HOST && mem != CASCI_MEM_DEVICE) return ctx->fail(CASCI_E_ARG, "bad mem flag");
+    if (o.precond != CASCI_PRECOND_DIAG && o.precond != CASCI_PRECOND_OLSEN && o.precond != CASCI_PRECOND_MLP)
+        return ctx->fail(CASCI_E_ARG, "unknown preconditioner");
+    if (o.spin != CASCI_SPIN_ANY && o.spin != CASCI_SPIN_SINGLET) return ctx->fail(CASCI_E_ARG, "unknown spin target");
+    if (o.ab_prec != CASCI_F64 && o.ab_prec != CASCI_F32 && o.ab_prec != CASCI_BF16)
+        return ctx->fail(CASCI_E_ARG, "ab_prec must be F64, F32 or BF16");
+    if (o.max_iter < 0 || o.m_max < 0) return ctx->fail(CASCI_E_ARG, "negative max_iter or m_max");
+    if (!ctx->has_ints) return ctx->fail(CASCI_E_STATE, "set_integrals first");
+    if (!ctx->has_strings) return ctx->fail(CASCI_E_STATE, "build_strings first");
+    if (o.spin == CASCI_SPIN_SINGLET && ctx->na != ctx->nb)
+        return ctx->fail(CASCI_E_ARG, "a singlet target needs nalpha == nbeta");
+    const int64_t Nd = ctx->Nd;
+    if (nroots > Nd) return ctx->fail(CASCI_E_ARG, "nroots exceeds the number of determinants");
+    if (o.guess && o.nguess < nroots) return ctx->fail(CASCI_E_ARG, "need at least nroots guess vectors");
+    if (o.guess && o.nguess > 64) return ctx->fail(CASCI_E_ARG, "at most 64 guess vectors");
+    if (o.precond == CASCI_PRECOND_MLP) return ctx->fail(CASCI_E_UNSUPPORTED, "MLP preconditioner not built");
+    CHECK_RC(need_device(ctx));
+    DeviceGuard guard(ctx->device);
+
+    const int k = nroots;
+    const int max_iter = o.max_iter > 0 ? o.max_iter : 200;
+    int m_max = o.m_max > 0 ? o.m_max : std::max(8, 8 * k);
+    m_max = std::min<int64_t>(std::min(m_max, 64), Nd);
+    m_max = std::max(m_max, (int)std::min<int64_t>(Nd, 2 * k));
+    const double r_tol = o.r_tol > 0 ? o.r_tol : std::max(1e-6, std::sqrt(tol) / 10.0);
+    const double lambda = (o.spin == CASCI_SPIN_SINGLET && o.s2_penalty > 0) ? o.s2_penalty : 0.0;
+    const bool singlet = o.spin == CASCI_SPIN_SINGLET;
+    int prec = o.ab_prec;  // current alpha-beta arithmetic
+    const double refine_at = o.refine_rnorm > 0 ? o.refine_rnorm : (prec == CASCI_BF16 ? 1e-2 : 1e-4);
+
+    Timer setup_t;
+    CHECK_RC(ensure_prepared(ctx, lambda));
+    hipStream_t st = ctx->stream;
+    HIPC(hipStreamSynchronize(st));
+    const double setup_ms = setup_t.ms();
+
+    // device storage: basis B (m_max + k slots), S (m_max), Ritz X/SX (2k each), temp (1)
+    const size_t vb = (size_t)Nd * 8;
+    DBuf dB, dS, dX, dSX, dT;
+    HIPC(dB.ensure(vb * (m_max + k)));
+    HIPC(dS.ensure(vb * (m_max + k)));
+    HIPC(dX.ensure(vb * 2 * k));
+    HIPC(dSX.ensure(vb * 2 * k));
+    HIPC(dT.ensure(vb));
+    struct Free {
+        DBuf* b[5];
+        ~Free()
+        {
+            for (DBuf* x : b) x->release();
+        }
+    } free_all{{&dB, &dS, &dX, &dSX, &dT}};
+    double* B = dB.as<double>();
+    double* S = dS.as<double>();
+    double* X = dX.as<double>();
+    double* SX = dSX.as<double>();
+    auto vB = [&](int i) { return B + (size_t)i * Nd; };
+    auto vS = [&](int i) { return S + (size_t)i * Nd; };
+    auto vX = [&](int i) { return X + (size_t)i * Nd; };
+    auto vSX = [&](int i) { return SX + (size_t)i * Nd; };
+    HIPC(ctx->d_small.ensure(64 * 1024 * 8));
+    double* dsm = ctx->d_small.as<double>();
+    // d_small layout (doubles): [0, 4096) G, [4096, 8192) Y, [8192, 8256) theta,
+    // [8320, 8320+4096) coefficients, [16384, ...) reduction results (dots)
+    double* dG = dsm;
+    double* dY = dsm + 4096;
+    double* dth = dsm + 8192;
+    double* dcoef = dsm + 8320;
+    double* dres = dsm + 32768;
+    CHECK_RC(ensure_work(ctx, 64 * 64));
+
+    hipEvent_t ev0, ev1;
+    HIPC(hipEventCreate(&ev0));
+    HIPC(hipEventCreate(&ev1));
+    struct EvFree {
+        hipEvent_t a, b;
+        ~EvFree()
+        {
+            (void)hipEventDestroy(a);
+            (void)hipEventDestroy(b);
+        }
+    } evfree{ev0, ev1};
+    double sigma_ms = 0.0;
+    int sigma_calls = 0, sigma64 = 0;
+
+    auto run_sigma = [&](const double* c, double* s) -> int {
+        HIPC(hipEventRecord(ev0, st));
+        CHECK_RC(sigma_dev(ctx, c, s, prec, lambda));
+        HIPC(hipEventRecord(ev1, st));
+        HIPC(hipEventSynchronize(ev1));
+        float ms = 0;
+        HIPC(hipEventElapsedTime(&ms, ev0, ev1));
+        sigma_ms += ms;
+        ++sigma_calls;
+        if (prec == CASCI_F64) ++sigma64;
+        return CASCI_OK;
+    };
+    auto dots_dev = [&](const double* A, int na, const double* Bv, int nb, std::vector<double>& out) {
+        return dots(ctx, A, na, Bv, nb, out);
+    };
+    auto combine = [&](const double* A, int na, const std::vector<double>& coef, int nc, double beta,
+                       double* Yv) -> int {
+        // coef is na x nc row-major
+        HIPC(hipMemcpyAsync(dcoef, coef.data(), coef.size() * 8, hipMemcpyHostToDevice, st));
+        HIPC(launch_combine(A, Nd, na, dcoef, nc, nc, beta, Yv, Nd, Nd, st));
+        HIPC(hipStreamSynchronize(st));  // coef is pageable host memory
+        return CASCI_OK;
+    };
+    auto symmetrize = [&](double* v) -> int {
+        // v <- (v + v^T)/2 for nalpha == nbeta
+        HIPC(launch_transpose_f64(v, dT.as<double>(), ctx->Na, ctx->Nb, 0, 1.0, st));
+        HIPC(launch_axpby_f64(0.5, dT.as<double>(), 0.5, v, Nd, st));
+        return CASCI_OK;
+    };
+
+    // ---- orthonormalise vectors [m, m+cnt) of B against [0, m) and each other;
+    // returns the number kept (compacted to [m, m+kept))
+    auto orthonormalize = [&](int m, int cnt, int& kept) -> int {
+        std::vector<double> c;
+        std::vector<double> before(cnt);
+        for (int j = 0; j < cnt; ++j) {
+            std::vector<double> nn;
+            CHECK_RC(dots_dev(vB(m + j), 1, vB(m + j), 1, nn));
+            before[j] = std::sqrt(nn[0]);
+        }
+        if (m > 0) {
+            for (int pass = 0; pass < 2; ++pass) {
+                CHECK_RC(dots_dev(vB(0), m, vB(m), cnt, c));
+                for (double& x : c) x = -x;
+                CHECK_RC(combine(vB(0), m, c, cnt, 1.0, vB(m)));
+            }
+        }
+        kept = 0;
+        for (int j = 0; j < cnt; ++j) {
+            double* v = vB(m + j);
+            if (kept > 0) {
+                for (int pass = 0; pass < 2; ++pass) {
+                    CHECK_RC(dots_dev(vB(m), kept, v, 1, c));
+                    for (double& x : c) x = -x;
+                    CHECK_RC(combine(vB(m), kept, c, 1, 1.0, v));
+                }
+            }
+            std::vector<double> nn;
+            CHECK_RC(dots_dev(v, 1, v, 1, nn));
+            const double nrm = std::sqrt(nn[0]);
+            if (!(nrm > 1e-8 * std::max(before[j], 1e-300)) || !(nrm > 1e-14)) continue;
+            HIPC(launch_scale(v, 1.0 / nrm, Nd, st));
+            if (kept != j) HIPC(hipMemcpyAsync(vB(m + kept), v, vb, hipMemcpyDeviceToDevice, st));
+            ++kept;
+        }
+        return CASCI_OK;
+    };
+
+    std::vector<double> G((size_t)m_max * m_max, 0.0);  // host copy of B^T (H) B, ld = m_max
+    auto extend_G = [&](int m0, int cnt) -> int {
+        std::vector<double> d;
+        CHECK_RC(dots_dev(vB(0), m0 + cnt, vS(m0), cnt, d));  // (m0+cnt) x cnt
+        for (int i = 0; i < m0 + cnt; ++i)
+            for (int j = 0; j < cnt; ++j) {
+                G[(size_t)i * m_max + m0 + j] = d[(size_t)i * cnt + j];
+                G[(size_t)(m0 + j) * m_max + i] = d[(size_t)i * cnt + j];
+            }
+        return CASCI_OK;
+    };
+
+    // ---- initial guess
+    int m = 0;
+    if (o.guess) {
+        const int ng = std::min(o.nguess, m_max);
+        HIPC(hipMemcpyAsync(B, o.guess, vb * ng,
+                            o.guess_mem == CASCI_MEM_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice,
+                            st));
+        if (singlet)
+            for (int j = 0; j < ng; ++j) CHECK_RC(symmetrize(vB(j)));
+        int kept = 0;
+        CHECK_RC(orthonormalize(0, ng, kept));
+        m = kept;
+    }
+    if (m < k) {
+        // Start vectors from the lowest diagonal elements (ties: lower address).
+        // For nalpha == nbeta the determinants (a,b) and (b,a) are combined into
+        // (e_ab +- e_ba)/sqrt2: transposition commutes with H and with the
+        // diagonal preconditioner, so a space without antisymmetric vectors
+        // would never reach odd-S states. SINGLET keeps the + combinations.
+        std::vector<double> diag(Nd);
+        HIPC(hipMemcpyAsync(diag.data(), ctx->d_diag.p, vb, hipMemcpyDeviceToHost, st));
+        HIPC(hipStreamSynchronize(st));
+        std::vector<int64_t> idx(Nd);
+        for (int64_t i = 0; i < Nd; ++i) idx[i] = i;
+        const int64_t want = std::min<int64_t>(Nd, 8 * k + 16);
+        std::partial_sort(idx.begin(), idx.begin() + want, idx.end(), [&](int64_t a, int64_t b) {
+            return diag[a] < diag[b] || (diag[a] == diag[b] && a < b);
+        });
+        struct Pick {
+            int64_t lo, hi;
+            int sign;
+        };
+        const bool paired = ctx->na == ctx->nb;
+        std::vector<Pick> cand;
+        auto have = [&](const Pick& c) {
+            for (auto& q : cand)
+                if (q.lo == c.lo && q.hi == c.hi && q.sign == c.sign) return true;
+            return false;
+        };
+        for (int64_t t = 0; t < want; ++t) {
+            const int64_t x = idx[t];
+            const int64_t a = x / ctx->Nb, b = x % ctx->Nb;
+            const int64_t y = paired ? b * ctx->Nb + a : x;
+            Pick ps{std::min(x, y), std::max(x, y), 1};
+            if (!have(ps)) cand.push_back(ps);
+            if (paired && !singlet && ps.lo != ps.hi) {
+                Pick pa{ps.lo, ps.hi, -1};
+                if (!have(pa)) cand.push_back(pa);
+            }
+        }
+        std::vector<Pick> picks;
+        for (auto& c : cand)
+            if ((int)picks.size() < k - m) picks.push_back(c);
+        if (paired && !singlet) {
+            bool anti = false;
+            for (auto& p : picks) anti |= p.sign < 0;
+            if (!anti)
+                for (auto& c : cand)
+                    if (c.sign < 0) {
+                        picks.push_back(c);
+                        break;
+                    }
+        }
+        const int start = m;
+        for (auto& pr : picks) {
+            if (m >= m_max) break;
+            double* v = vB(m);
+            HIPC(hipMemsetAsync(v, 0, vb, st));
+            const double one = 1.0, h2 = std::sqrt(0.5), h2s = pr.sign * std::sqrt(0.5);
+            if (pr.lo == pr.hi) {
+                HIPC(hipMemcpyAsync(v + pr.lo, &one, 8, hipMemcpyHostToDevice, st));
+            } else {
+                HIPC(hipMemcpyAsync(v + pr.lo, &h2, 8, hipMemcpyHostToDevice, st));
+                HIPC(hipMemcpyAsync(v + pr.hi, &h2s, 8, hipMemcpyHostToDevice, st));
+            }
+            HIPC(hipStreamSynchronize(st));
+            ++m;
+        }
+        if (start > 0) {
+            int kept = 0;
+            CHECK_RC(orthonormalize(start, m - start, kept));
+            m = start + kept;
+        }
+        if (m < k) return ctx->fail(CASCI_E_ARG, "could not build nroots independent start vectors");
+    }
+    for (int j = 0; j < m; ++j) CHECK_RC(run_sigma(vB(j), vS(j)));
+    CHECK_RC(extend_G(0, m));
+
+    std::vector<double> theta_prev(k, std::numeric_limits<double>::infinity());
+    std::vector<double> theta(64), Y(64 * 64), rn(k, 0.0);
+    bool converged = false, have_prev = false;
+    int it = 0, switch_iter = (prec == CASCI_F64) ? -1 : -2;
+    double last_rmax = std::numeric_limits<double>::infinity();
+    int stall = 0, empty_steps = 0;
+    for (it = 0; it < max_iter; ++it) {
+        // Rayleigh-Ritz on the device
+        std::vector<double> Gc((size_t)m * m);
+        for (int i = 0; i < m; ++i)
+            for (int j = 0; j < m; ++j) Gc[(size_t)i * m + j] = G[(size_t)i * m_max + j];
+        HIPC(hipMemcpyAsync(dG, Gc.data(), Gc.size() * 8, hipMemcpyHostToDevice, st));
+        HIPC(launch_jacobi_eigh(dG, m, m, dth, dY, st));
+        HIPC(hipMemcpyAsync(theta.data(), dth, m * 8, hipMemcpyDeviceToHost, st));
+        HIPC(hipMemcpyAsync(Y.data(), dY, (size_t)m * m * 8, hipMemcpyDeviceToHost, st));
+        HIPC(hipStreamSynchronize(st));
+        // previous Ritz vectors move to slots [k, 2k)
+        if (have_prev) {
+            HIPC(hipMemcpyAsync(vX(k), vX(0), vb * k, hipMemcpyDeviceToDevice, st));
+            HIPC(hipMemcpyAsync(vSX(k), vSX(0), vb * k, hipMemcpyDeviceToDevice, st));
+        }
+        // Ritz vectors X = B Y[:, :k], SX = S Y[:, :k]
+        std::vector<double> yk((size_t)m * k);
+        for (int i = 0; i < m; ++i)
+            for (int j = 0; j < k; ++j) yk[(size_t)i * k + j] = Y[(size_t)i * m + j];
+        CHECK_RC(combine(vB(0), m, yk, k, 0.0, vX(0)));
+        CHECK_RC(combine(vS(0), m, yk, k, 0.0, vSX(0)));
+        HIPC(hipMemcpyAsync(dth, theta.data(), k * 8, hipMemcpyHostToDevice, st));
+        HIPC(launch_residual(X, SX, Nd, k, dth, ctx->d_diag.as<double>(), Nd, ctx->d_work.as<double>(),
+                             dres, st));
+        std::vector<double> rs(4 * k);
+        HIPC(hipMemcpyAsync(rs.data(), dres, 4 * k * 8, hipMemcpyDeviceToHost, st));
+        HIPC(hipStreamSynchronize(st));
+        double rmax = 0.0;
+        std::vector<int> todo;
+        for (int j = 0; j < k; ++j) {
+            rn[j] = std::sqrt(std::max(rs[4 * j], 0.0));
+            rmax = std::max(rmax, rn[j]);
+            const double dth_j = std::fabs(theta[j] - theta_prev[j]);
+            if (!(rn[j] < r_tol && dth_j < tol)) todo.push_back(j);
+        }
+        if (info && info->hist_energy && it < info->hist_len)
+            for (int j = 0; j < k; ++j) info->hist_energy[(size_t)it * k + j] = theta[j];
+        if (info && info->hist_residual && it < info->hist_len)
+            for (int j = 0; j < k; ++j) info->hist_residual[(size_t)it * k + j] = rn[j];
+        if (info && info->hist_time_ms && it < info->hist_len) info->hist_time_ms[it] = wall.ms();
+        for (int j = 0; j < k; ++j) theta_prev[j] = theta[j];
+        if (!std::isfinite(rmax)) return ctx->fail(CASCI_E_NONFINITE, "non-finite residual in Davidson");
+        if (todo.empty() && prec == CASCI_F64) {
+            converged = true;
+            break;
+        }
+        // precision switch: restart from the Ritz vectors with FP64 sigma
+        if (prec != CASCI_F64) {
+            stall = (rmax > 0.5 * last_rmax) ? stall + 1 : 0;
+            if (rmax < refine_at || stall >= 2 || todo.empty()) {
+                prec = CASCI_F64;
+                switch_iter = it;
+                HIPC(hipMemcpyAsync(vB(0), vX(0), vb * k, hipMemcpyDeviceToDevice, st));
+                int kept = 0;
+                CHECK_RC(orthonormalize(0, k, kept));
+                m = kept;
+                for (int j = 0; j < m; ++j) CHECK_RC(run_sigma(vB(j), vS(j)));
+                CHECK_RC(extend_G(0, m));
+                have_prev = false;
+                last_rmax = std::numeric_limits<double>::infinity();
+                for (int j = 0; j < k; ++j) theta_prev[j] = std::numeric_limits<double>::infinity();
+                continue;
+            }
+        }
+        last_rmax = rmax;
+        // collapse: keep current and previous Ritz vectors
+        if (m + (int)todo.size() > m_max) {
+            const int nkeep = (have_prev && 2 * k + (int)todo.size() <= m_max) ? 2 * k : k;
+            HIPC(hipMemcpyAsync(vB(0), vX(0), vb * nkeep, hipMemcpyDeviceToDevice, st));
+            HIPC(hipMemcpyAsync(vS(0), vSX(0), vb * nkeep, hipMemcpyDeviceToDevice, st));
+            // Gram-Schmidt of the previous Ritz vectors against the current ones,
+            // the same combination applied to their sigma vectors
+            int mm = k;
+            for (int j = k; j < nkeep; ++j) {
+                std::vector<double> c;
+                for (int pass = 0; pass < 2; ++pass) {
+                    CHECK_RC(dots_dev(vB(0), mm, vB(j), 1, c));
+                    for (double& x : c) x = -x;
+                    CHECK_RC(combine(vB(0), mm, c, 1, 1.0, vB(j)));
+                    CHECK_RC(combine(vS(0), mm, c, 1, 1.0, vS(j)));
+                }
+                std::vector<double> nn;
+                CHECK_RC(dots_dev(vB(j), 1, vB(j), 1, nn));
+                const double nrm = std::sqrt(nn[0]);
+                if (nrm < 1e-8) continue;
+                HIPC(launch_scale(vB(j), 1.0 / nrm, Nd, st));
+                HIPC(launch_scale(vS(j), 1.0 / nrm, Nd, st));
+                if (mm != j) {
+                    HIPC(hipMemcpyAsync(vB(mm), vB(j), vb, hipMemcpyDeviceToDevice, st));
+                    HIPC(hipMemcpyAsync(vS(mm), vS(j), vb, hipMemcpyDeviceToDevice, st));
+                }
+                ++mm;
+            }
+            m = mm;
+            std::fill(G.begin(), G.end(), 0.0);
+            CHECK_RC(extend_G(0, m));
+        }
+        // corrections for unconverged roots
+        const int cnt = (int)todo.size();
+        for (int t = 0; t < cnt; ++t) {
+            const int j = todo[t];
+            double eps = 0.0;
+            if (o.precond == CASCI_PRECOND_OLSEN && std::fabs(rs[4 * j + 2]) > 1e-300)
+                eps = rs[4 * j + 1] / rs[4 * j + 2];
+            HIPC(launch_precondition(vX(j), vSX(j), theta[j], eps, ctx->d_diag.as<double>(), Nd, vB(m + t), st));
+            if (singlet) CHECK_RC(symmetrize(vB(m + t)));
+        }
+        int kept = 0;
+        CHECK_RC(orthonormalize(m, cnt, kept));
+        if (kept == 0) {
+            // no new direction (e.g. the subspace already spans the space): one more
+            // Rayleigh-Ritz step settles the energy change; a second empty step stops
+            if (++empty_steps >= 2) break;
+            continue;
+        }
+        empty_steps = 0;
+        for (int j = 0; j < kept; ++j) CHECK_RC(run_sigma(vB(m + j), vS(m + j)));
+        CHECK_RC(extend_G(m, kept));
+        m += kept;
+        have_prev = true;
+    }
+
+    // results
+    for (int j = 0; j < k; ++j) energies[j] = theta[j];
+    std::vector<double> s2v(k, 0.0);
+    if (vectors || info) {
+        for (int j = 0; j < k; ++j) {
+            // phase: largest-|c| entry positive (ties: lowest index)
+            std::vector<double> hv(Nd);
+            HIPC(hipMemcpyAsync(hv.data(), vX(j), vb, hipMemcpyDeviceToHost, st));
+            HIPC(hipStreamSynchronize(st));
+            int64_t best = 0;
+            for (int64_t i = 1; i < Nd; ++i)
+                if (std::fabs(hv[i]) > std::fabs(hv[best])) best = i;
+            if (hv[best] < 0) HIPC(launch_scale(vX(j), -1.0, Nd, st));
+            if (info) CHECK_RC(spin_square_dev(ctx, vX(j), &s2v[j]));
+        }
+        if (vectors)
+            HIPC(hipMemcpyAsync(vectors, X, vb * k,
+                                mem == CASCI_MEM_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice, st));
+        HIPC(hipStreamSynchronize(st));
+    }
+    if (info) {
+        info->iterations = it + (converged ? 1 : 0);
+        info->sigma_calls = sigma_calls;
+        info->sigma_calls_fp64 = sigma64;
+        info->converged = converged ? 1 : 0;
+        info->switch_iter = switch_iter < 0 ? -1 : switch_iter;
+        info->mlp_fallbacks = 0;
+        for (int j = 0; j < CASCI_MAX_ROOTS; ++j) {
+            info->residual[j] = j < k ? rn[j] : 0.0;
+            info->s2[j] = j < k ? s2v[j] : 0.0;
+        }
+        info->time_sigma_ms = sigma_ms;
+        info->time_setup_ms = setup_ms;
+        info->time_total_ms = wall.ms();
+    }
+    return converged ? CASCI_OK : CASCI_NOCONV;
+}

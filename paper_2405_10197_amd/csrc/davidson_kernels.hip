@@ -1,0 +1,353 @@
+// Davidson-Liu kernels (Sec. II.A.1 of the paper names the method; the
+// paper gives no algorithmic detail). All reductions are two-stage with a
+// fixed partition and a fixed summation order, so FP64 results are
+// bitwise reproducible from run to run.
+#include "internal.h"
+
+namespace casci {
+
+constexpr int RED_BLOCKS = 512;  // stage-1 partials per output
+constexpr int RED_THREADS = 256;
+
+__device__ inline double block_sum(double v, double* sh)
+{
+    // fixed-order tree over RED_THREADS values
+    sh[threadIdx.x] = v;
+    __syncthreads();
+    for (int s = RED_THREADS / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+        __syncthreads();
+    }
+    double r = sh[0];
+    __syncthreads();
+    return r;
+}
+
+// stage 1: partial[(i*nb + j) * RED_BLOCKS + blockIdx.x] over a 4x4 group of (i, j)
+__global__ __launch_bounds__(RED_THREADS) void k_block_dot(const double* __restrict__ A, int64_t lda,
+                                                           int na, const double* __restrict__ B,
+                                                           int64_t ldb, int nb, int64_t len,
+                                                           double* __restrict__ work)
+{
+    __shared__ double sh[RED_THREADS];
+    const int i0 = blockIdx.y * 4, j0 = blockIdx.z * 4;
+    double acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < len; x += stride) {
+        double a[4], b[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) a[i] = (i0 + i < na) ? A[(int64_t)(i0 + i) * lda + x] : 0.0;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) b[j] = (j0 + j < nb) ? B[(int64_t)(j0 + j) * ldb + x] : 0.0;
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) acc[i][j] += a[i] * b[j];
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            double s = block_sum(acc[i][j], sh);
+            if (threadIdx.x == 0 && i0 + i < na && j0 + j < nb)
+                work[((int64_t)(i0 + i) * nb + (j0 + j)) * RED_BLOCKS + blockIdx.x] = s;
+        }
+}
+
+// stage 2: one thread per output, partials summed in index order
+__global__ void k_reduce_partials(const double* __restrict__ work, int nout, int nparts,
+                                  double* __restrict__ out)
+{
+    int o = blockIdx.x * blockDim.x + threadIdx.x;
+    if (o >= nout) return;
+    double s = 0.0;
+    for (int k = 0; k < nparts; ++k) s += work[(int64_t)o * nparts + k];
+    out[o] = s;
+}
+
+hipError_t launch_block_dot(const double* A, int64_t lda, int na, const double* B, int64_t ldb,
+                            int nb, int64_t len, double* work, double* out, hipStream_t st)
+{
+    if (na <= 0 || nb <= 0) return hipSuccess;
+    dim3 grid(RED_BLOCKS, (na + 3) / 4, (nb + 3) / 4);
+    hipLaunchKernelGGL(k_block_dot, grid, dim3(RED_THREADS), 0, st, A, lda, na, B, ldb, nb, len, work);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    int nout = na * nb;
+    hipLaunchKernelGGL(k_reduce_partials, dim3((nout + 127) / 128), dim3(128), 0, st, work, nout,
+                       RED_BLOCKS, out);
+    return hipGetLastError();
+}
+
+// Y_j = beta Y_j + sum_i A_i coef[i*ldc + j]
+__global__ __launch_bounds__(256) void k_combine(const double* __restrict__ A, int64_t lda, int na,
+                                                 const double* __restrict__ coef, int ldc, int nc,
+                                                 double beta, double* __restrict__ Y, int64_t ldy,
+                                                 int64_t len)
+{
+    __shared__ double sc[64 * 8];
+    for (int t = threadIdx.x; t < na * nc; t += blockDim.x) {
+        int i = t / nc, j = t - i * nc;
+        sc[t] = coef[i * ldc + j];
+    }
+    __syncthreads();
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < len; x += stride) {
+        double acc[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) acc[j] = 0.0;
+        for (int i = 0; i < na; ++i) {
+            const double a = A[(int64_t)i * lda + x];
+#pragma unroll
+            for (int j = 0; j < 8; ++j)
+                if (j < nc) acc[j] += a * sc[i * nc + j];
+        }
+#pragma unroll
+        for (int j = 0; j < 8; ++j)
+            if (j < nc) {
+                double* y = Y + (int64_t)j * ldy + x;
+                *y = (beta == 0.0 ? 0.0 : beta * *y) + acc[j];
+            }
+    }
+}
+
+static unsigned ew_grid(int64_t n)
+{
+    int64_t g = (n + 255) / 256;
+    return (unsigned)(g > 8192 ? 8192 : (g < 1 ? 1 : g));
+}
+
+hipError_t launch_combine(const double* A, int64_t lda, int na, const double* coef, int ldc, int nc,
+                          double beta, double* Y, int64_t ldy, int64_t len, hipStream_t st)
+{
+    if (nc <= 0 || len <= 0) return hipSuccess;
+    if (na > 64) return hipErrorInvalidValue;
+    for (int j0 = 0; j0 < nc; j0 += 8) {
+        int n8 = nc - j0 < 8 ? nc - j0 : 8;
+        hipLaunchKernelGGL(k_combine, dim3(ew_grid(len)), dim3(256), 0, st, A, lda, na, coef + j0,
+                           ldc, n8, beta, Y + (int64_t)j0 * ldy, ldy, len);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+__device__ inline double safe_denominator(double d)
+{
+    // |H_II - theta| clamped to >= 1e-8, sign kept
+    if (fabs(d) < 1e-8) return d < 0 ? -1e-8 : 1e-8;
+    return d;
+}
+
+// stage 1 of residual norms and Olsen dots, one blockIdx.y per root
+__global__ __launch_bounds__(RED_THREADS) void k_residual(const double* __restrict__ X,
+                                                          const double* __restrict__ SX, int64_t ld,
+                                                          const double* __restrict__ theta,
+                                                          const double* __restrict__ diag,
+                                                          int64_t len, double* __restrict__ work)
+{
+    __shared__ double sh[RED_THREADS];
+    const int k = blockIdx.y;
+    const double th = theta[k];
+    const double* x = X + (int64_t)k * ld;
+    const double* sx = SX + (int64_t)k * ld;
+    double rr = 0.0, xr = 0.0, xx = 0.0;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < len; i += stride) {
+        const double xi = x[i];
+        const double r = sx[i] - th * xi;
+        const double inv = 1.0 / safe_denominator(diag[i] - th);
+        rr += r * r;
+        xr += xi * inv * r;
+        xx += xi * inv * xi;
+    }
+    double s0 = block_sum(rr, sh), s1 = block_sum(xr, sh), s2 = block_sum(xx, sh);
+    if (threadIdx.x == 0) {
+        work[((int64_t)k * 4 + 0) * RED_BLOCKS + blockIdx.x] = s0;
+        work[((int64_t)k * 4 + 1) * RED_BLOCKS + blockIdx.x] = s1;
+        work[((int64_t)k * 4 + 2) * RED_BLOCKS + blockIdx.x] = s2;
+        work[((int64_t)k * 4 + 3) * RED_BLOCKS + blockIdx.x] = 0.0;
+    }
+}
+
+hipError_t launch_residual(const double* X, const double* SX, int64_t ld, int k, const double* theta,
+                           const double* diag, int64_t len, double* work, double* out,
+                           hipStream_t st)
+{
+    if (k <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_residual, dim3(RED_BLOCKS, k), dim3(RED_THREADS), 0, st, X, SX, ld, theta,
+                       diag, len, work);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_reduce_partials, dim3((4 * k + 127) / 128), dim3(128), 0, st, work, 4 * k,
+                       RED_BLOCKS, out);
+    return hipGetLastError();
+}
+
+__global__ void k_precondition(const double* __restrict__ X, const double* __restrict__ SX,
+                               double theta, double eps, const double* __restrict__ diag,
+                               int64_t len, double* __restrict__ T)
+{
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < len; i += stride) {
+        const double xi = X[i];
+        const double r = SX[i] - theta * xi;
+        T[i] = (-r + eps * xi) / safe_denominator(diag[i] - theta);
+    }
+}
+
+hipError_t launch_precondition(const double* X, const double* SX, double theta, double eps,
+                               const double* diag, int64_t len, double* T, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_precondition, dim3(ew_grid(len)), dim3(256), 0, st, X, SX, theta, eps, diag,
+                       len, T);
+    return hipGetLastError();
+}
+
+__global__ void k_scale(double* x, double a, int64_t n)
+{
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) x[i] *= a;
+}
+
+hipError_t launch_scale(double* x, double a, int64_t n, hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_scale, dim3(ew_grid(n)), dim3(256), 0, st, x, a, n);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Rayleigh-Ritz: cyclic Jacobi on the projected matrix, one workgroup, FP64.
+// Round-robin ordering: each round rotates mm/2 disjoint (p, q) planes at
+// once (mm = m rounded up to even; the padding index has zero coupling).
+// Rotation zeroing A_pq (A' = J^T A J, J_pp = J_qq = c, J_pq = s, J_qp = -s):
+//   th = (A_qq - A_pp) / (2 A_pq), t = sgn(th) / (|th| + sqrt(th^2 + 1)),
+//   c = 1/sqrt(t^2 + 1), s = t c.
+// ---------------------------------------------------------------------------
+constexpr int JAC_MAX = 64;
+
+__global__ __launch_bounds__(256) void k_jacobi(const double* __restrict__ G, int m, int ldg,
+                                                double* __restrict__ theta, double* __restrict__ Y)
+{
+    __shared__ double A[JAC_MAX][JAC_MAX + 1];
+    __shared__ double V[JAC_MAX][JAC_MAX + 1];
+    __shared__ double cs[JAC_MAX / 2][2];
+    __shared__ int pq[JAC_MAX / 2][2];
+    __shared__ double red[256];
+    __shared__ int order[JAC_MAX];
+    const int tid = threadIdx.x;
+    const int mm = m + (m & 1);
+    for (int t = tid; t < mm * mm; t += 256) {
+        int i = t / mm, j = t - i * mm;
+        double v = 0.0;
+        if (i < m && j < m) v = 0.5 * (G[i * ldg + j] + G[j * ldg + i]);
+        A[i][j] = v;
+        V[i][j] = (i == j) ? 1.0 : 0.0;
+    }
+    __syncthreads();
+    for (int sweep = 0; sweep < 60; ++sweep) {
+        double off = 0.0, dg = 0.0;
+        for (int t = tid; t < mm * mm; t += 256) {
+            int i = t / mm, j = t - i * mm;
+            if (i != j) off += A[i][j] * A[i][j];
+            else dg += A[i][j] * A[i][j];
+        }
+        red[tid] = off;
+        __syncthreads();
+        for (int s = 128; s > 0; s >>= 1) {
+            if (tid < s) red[tid] += red[tid + s];
+            __syncthreads();
+        }
+        const double offn = red[0];
+        __syncthreads();
+        red[tid] = dg;
+        __syncthreads();
+        for (int s = 128; s > 0; s >>= 1) {
+            if (tid < s) red[tid] += red[tid + s];
+            __syncthreads();
+        }
+        const double dgn = red[0];
+        __syncthreads();
+        if (offn <= 1e-32 * dgn || offn == 0.0) break;
+        for (int round = 0; round < mm - 1; ++round) {
+            if (tid < mm / 2) {
+                // player at position k: position 0 fixed, others rotate
+                auto player = [&](int pos) {
+                    return pos == 0 ? 0 : ((pos - 1 + round) % (mm - 1)) + 1;
+                };
+                int p = player(tid), q = player(mm - 1 - tid);
+                if (p > q) { int tt = p; p = q; q = tt; }
+                double c = 1.0, s = 0.0;
+                const double apq = A[p][q];
+                if (apq != 0.0) {
+                    const double th = (A[q][q] - A[p][p]) / (2.0 * apq);
+                    const double t = (th >= 0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
+                    c = 1.0 / sqrt(t * t + 1.0);
+                    s = t * c;
+                }
+                pq[tid][0] = p;
+                pq[tid][1] = q;
+                cs[tid][0] = c;
+                cs[tid][1] = s;
+            }
+            __syncthreads();
+            // rows: A <- J^T A
+            for (int t = tid; t < (mm / 2) * mm; t += 256) {
+                int k = t / mm, j = t - k * mm;
+                int p = pq[k][0], q = pq[k][1];
+                double c = cs[k][0], s = cs[k][1];
+                double ap = A[p][j], aq = A[q][j];
+                A[p][j] = c * ap - s * aq;
+                A[q][j] = s * ap + c * aq;
+            }
+            __syncthreads();
+            // columns: A <- A J, V <- V J
+            for (int t = tid; t < (mm / 2) * mm; t += 256) {
+                int k = t / mm, i = t - k * mm;
+                int p = pq[k][0], q = pq[k][1];
+                double c = cs[k][0], s = cs[k][1];
+                double ap = A[i][p], aq = A[i][q];
+                A[i][p] = c * ap - s * aq;
+                A[i][q] = s * ap + c * aq;
+                double vp = V[i][p], vq = V[i][q];
+                V[i][p] = c * vp - s * vq;
+                V[i][q] = s * vp + c * vq;
+            }
+            __syncthreads();
+        }
+    }
+    if (tid == 0) {
+        // ascending order of the m real eigenvalues (stable selection, ties by index)
+        for (int i = 0; i < m; ++i) order[i] = i;
+        for (int i = 0; i < m; ++i) {
+            int best = i;
+            for (int j = i + 1; j < m; ++j)
+                if (A[order[j]][order[j]] < A[order[best]][order[best]]) best = j;
+            int tt = order[i];
+            order[i] = order[best];
+            order[best] = tt;
+        }
+    }
+    __syncthreads();
+    for (int t = tid; t < m; t += 256) theta[t] = A[order[t]][order[t]];
+    for (int t = tid; t < m * m; t += 256) {
+        int i = t / m, j = t - i * m;  // Y[i][j] = component i of vector j
+        Y[t] = V[i][order[j]];
+    }
+}
+
+hipError_t launch_jacobi_eigh(const double* G, int m, int ldg, double* theta, double* Y,
+                              hipStream_t st)
+{
+    if (m <= 0) return hipSuccess;
+    if (m > JAC_MAX) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_jacobi, dim3(1), dim3(256), 0, st, G, m, ldg, theta, Y);
+    return hipGetLastError();
+}
+
+}  // namespace casci

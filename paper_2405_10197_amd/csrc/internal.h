@@ -1,0 +1,100 @@
+// Internal declarations shared by the host runtime and the HIP kernel files.
+// Not part of the public ABI (include/casci.h is).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace casci {
+
+// ---------------------------------------------------------------------------
+// string bookkeeping shared by host and device code
+// ---------------------------------------------------------------------------
+// A single-substitution list entry is stored as two arrays: int32 J with the
+// sign folded in (J >= 0: sign +1, stored ~J: sign -1) and uint16 pq = p | q<<8.
+__host__ __device__ inline int32_t l1_encode(int32_t J, int sign) { return sign > 0 ? J : ~J; }
+__host__ __device__ inline int32_t l1_index(int32_t v) { return v >= 0 ? v : ~v; }
+__host__ __device__ inline int l1_sign(int32_t v) { return v >= 0 ? 1 : -1; }
+
+// bits strictly between orbitals a and b
+__host__ __device__ inline uint64_t between_mask(int a, int b)
+{
+    int lo = a < b ? a : b, hi = a < b ? b : a;
+    if (hi - lo < 2) return 0;
+    uint64_t upto_hi = (hi >= 64) ? ~0ull : ((1ull << hi) - 1);
+    uint64_t upto_lo1 = (lo + 1 >= 64) ? ~0ull : ((1ull << (lo + 1)) - 1);
+    return upto_hi & ~upto_lo1;
+}
+
+// ---------------------------------------------------------------------------
+// launch wrappers (defined in the .hip files); all enqueue on `st`
+// ---------------------------------------------------------------------------
+// setup_kernels.hip
+hipError_t launch_build_strings(int n, int ne, int64_t N, const int64_t* binom, uint64_t* out,
+                                hipStream_t st);
+hipError_t launch_single_lists(int n, int ne, int64_t N, const uint64_t* strs, const int64_t* binom,
+                               int s, int32_t* lj, uint16_t* lpq, hipStream_t st);
+hipError_t launch_same_spin_operator(int n, int ne, int64_t N, const uint64_t* strs,
+                                     const int64_t* binom, const double* h, const double* eri,
+                                     int r, int32_t* col, double* val, hipStream_t st);
+hipError_t launch_diagonal(int n, int64_t Na, int64_t Nb, const uint64_t* astr,
+                           const uint64_t* bstr, const double* fa, int ra, const double* fb, int rb,
+                           const double* jpq, double shift, double lambda_s2, double* out,
+                           hipStream_t st);
+
+// sigma_kernels.hip
+// Y(I,:) = [acc ? Y(I,:) : 0] + sum_e val[I*r+e] X(col[I*r+e], :) + shift * X(I,:)
+hipError_t launch_ss_gather_f64(const int32_t* col, const double* val, int r, int64_t nrows,
+                                int64_t ncols, const double* X, double* Y, double shift, int acc,
+                                hipStream_t st);
+hipError_t launch_ss_gather_f32(const int32_t* col, const double* val, int r, int64_t nrows,
+                                int64_t ncols, const float* X, float* Y, double shift, int acc,
+                                hipStream_t st);
+// out[j][i] (+)= in[i][j], in: rows x cols
+hipError_t launch_transpose_f64(const double* in, double* out, int64_t rows, int64_t cols, int acc,
+                                double scale, hipStream_t st);
+hipError_t launch_transpose_f32(const float* in, float* out, int64_t rows, int64_t cols, int acc,
+                                hipStream_t st);
+
+struct AbParams {
+    int n, nb;            // orbitals, beta electrons
+    int64_t Na, Nb;       // string counts
+    int sa;               // alpha list length
+    int M, Mp;            // pair rows (real, padded to 16)
+    int full;             // 1: ordered pairs (r,s) r,s < n; 0: r <= s
+    const int32_t* la_j;  // alpha single list
+    const uint16_t* la_pq;
+    const uint64_t* bstr;
+    const int64_t* binom; // (n+1) x (n+1)
+    const uint16_t* pairs;// [Mp] r | s << 8
+};
+// sigma(Ia, :) += alpha-beta term; Vt[pq][Mp] in the arithmetic's type
+hipError_t launch_ab_f64(const AbParams& p, const double* Vt, const double* C, double* sigma,
+                         hipStream_t st);
+hipError_t launch_ab_lowp(const AbParams& p, int prec, const void* Vt, const double* C,
+                          double* sigma, hipStream_t st);
+hipError_t launch_convert_f64_to_f32(const double* in, float* out, int64_t n, hipStream_t st);
+hipError_t launch_convert_f32_to_f64(const float* in, double* out, int64_t n, hipStream_t st);
+hipError_t launch_axpby_f64(double a, const double* x, double b, double* y, int64_t n, hipStream_t st);
+
+// davidson_kernels.hip
+// partial dots: out[i*nb+j] = sum_x A_i[x] B_j[x]; A_i = A + i*lda, B_j = B + j*ldb
+hipError_t launch_block_dot(const double* A, int64_t lda, int na, const double* B, int64_t ldb,
+                            int nb, int64_t len, double* work, double* out, hipStream_t st);
+// Y_j = beta*Y_j + sum_i A_i coef[i*ldc + j], j < nc (coef on device)
+hipError_t launch_combine(const double* A, int64_t lda, int na, const double* coef, int ldc, int nc,
+                          double beta, double* Y, int64_t ldy, int64_t len, hipStream_t st);
+// residual norms / Olsen dots for k roots:
+// r = SX_k - th_k X_k; out[k*4+0] = |r|^2, [1] = x.(D-th)^-1 r, [2] = x.(D-th)^-1 x
+hipError_t launch_residual(const double* X, const double* SX, int64_t ld, int k, const double* theta,
+                           const double* diag, int64_t len, double* work, double* out,
+                           hipStream_t st);
+// t = -(D-th)^-1 r + eps (D-th)^-1 x  (eps = 0 for the diagonal preconditioner)
+hipError_t launch_precondition(const double* X, const double* SX, double theta, double eps,
+                               const double* diag, int64_t len, double* T, hipStream_t st);
+// symmetric eigensolve of G[m x m] (ld = ldg), ascending: theta[m], Y[m x m] column j = vector j
+hipError_t launch_jacobi_eigh(const double* G, int m, int ldg, double* theta, double* Y,
+                              hipStream_t st);
+hipError_t launch_scale(double* x, double a, int64_t n, hipStream_t st);
+
+}  // namespace casci

@@ -1,0 +1,139 @@
+"""C ABI checks that need no GPU: the library loads, exports every symbol the
+header declares, and validates arguments and call order in a validate-only
+context (device = -1) before any device work."""
+import ctypes
+import math
+
+import numpy as np
+import pytest
+
+from paper_2405_10197_amd import casci, synth
+
+
+@pytest.fixture(scope="module")
+def L():
+    return casci.lib()
+
+
+def test_every_header_symbol_is_exported(L):
+    names = casci.header_symbols()
+    assert "casci_sigma" in names and "casci_davidson" in names
+    for n in names:
+        assert hasattr(L, n), n
+
+
+def vctx():
+    return casci.Context(device=-1)
+
+
+def test_create_rejects_bad_device_and_null(L):
+    assert L.casci_create(None, 0, None) == casci.E_ARG
+    h = ctypes.c_void_p()
+    assert L.casci_create(ctypes.byref(h), -7, None) == casci.E_ARG
+
+
+def test_dims_after_build_strings():
+    c = vctx()
+    c.build_strings(8, 8, 16)
+    d = c.dims
+    assert d["Na"] == d["Nb"] == 12870 and d["Ndet"] == 12870 ** 2
+    assert d["sa"] == 8 * 9 and d["ra"] == 1 + 64 + 28 * 28
+    c.build_strings(5, 4, 9)
+    d = c.dims
+    assert (d["Na"], d["Nb"], d["sa"], d["sb"]) == (126, 126, 25, 24)
+    assert d["ra"] == 1 + 5 * 4 + math.comb(5, 2) * math.comb(4, 2)
+
+
+@pytest.mark.parametrize("na,nb,n", [(-1, 0, 4), (5, 1, 4), (1, 1, 0), (1, 1, 65)])
+def test_build_strings_rejects_bad_sizes(na, nb, n):
+    c = vctx()
+    with pytest.raises(casci.CasciError) as e:
+        c.build_strings(na, nb, n)
+    assert e.value.code == casci.E_ARG
+
+
+def test_predicted_out_of_memory():
+    c = vctx()
+    with pytest.raises(casci.CasciError) as e:
+        c.build_strings(20, 20, 40)
+    assert e.value.code == casci.E_NOMEM
+    with pytest.raises(casci.CasciError) as e:
+        c.build_strings(12, 12, 24)  # 7.3e6^2 determinants: petabytes
+    assert e.value.code == casci.E_NOMEM
+
+
+def test_integral_validation():
+    h, eri, _ = synth.integrals(4, 1)
+    c = vctx()
+    c.set_integrals(h, eri)
+    bad = h.copy()
+    bad[0, 1] += 1e-3
+    with pytest.raises(casci.CasciError) as e:
+        c.set_integrals(bad, eri)
+    assert e.value.code == casci.E_ARG
+    bad = eri.copy()
+    bad[0, 1, 2, 3] += 1e-3
+    with pytest.raises(casci.CasciError) as e:
+        c.set_integrals(h, bad)
+    assert e.value.code == casci.E_ARG
+    bad = eri.copy()
+    bad[1, 1, 1, 1] = np.nan
+    with pytest.raises(casci.CasciError) as e:
+        c.set_integrals(h, bad)
+    assert e.value.code == casci.E_NONFINITE
+    with pytest.raises(casci.CasciError) as e:
+        c.set_integrals(h, eri, e_core=float("inf"))
+    assert e.value.code == casci.E_NONFINITE
+
+
+def test_call_order_and_norb_mismatch():
+    h, eri, _ = synth.integrals(4, 1)
+    c = vctx()
+    C = np.zeros((6, 6))
+    with pytest.raises(casci.CasciError) as e:
+        c.sigma(C)
+    assert e.value.code == casci.E_STATE
+    c.build_strings(2, 2, 4)
+    with pytest.raises(casci.CasciError) as e:
+        c.sigma(C)
+    assert e.value.code == casci.E_STATE      # no integrals yet
+    h5, eri5, _ = synth.integrals(5, 1)
+    with pytest.raises(casci.CasciError) as e:
+        c.set_integrals(h5, eri5)
+    assert e.value.code == casci.E_STATE
+    c.set_integrals(h, eri)
+    with pytest.raises(casci.CasciError) as e:
+        c.sigma(C)
+    assert e.value.code == casci.E_UNSUPPORTED  # validate-only: everything valid, no device
+    with pytest.raises(casci.CasciError) as e:
+        c.davidson(1, 1e-8)
+    assert e.value.code == casci.E_UNSUPPORTED
+
+
+def test_davidson_argument_checks():
+    h, eri, _ = synth.integrals(4, 1)
+    c = vctx()
+    c.build_strings(2, 1, 4)
+    c.set_integrals(h, eri)
+    for kw, code in [(dict(nroots=0), casci.E_ARG), (dict(nroots=33), casci.E_ARG),
+                     (dict(tol=-1.0), casci.E_ARG), (dict(spin="singlet"), casci.E_ARG)]:
+        args = dict(nroots=1, tol=1e-8)
+        args.update(kw)
+        with pytest.raises(casci.CasciError) as e:
+            c.davidson(args.pop("nroots"), args.pop("tol"), **args)
+        assert e.value.code == code, kw
+
+
+def test_sigma_argument_checks(L):
+    c = vctx()
+    h, eri, _ = synth.integrals(4, 1)
+    c.build_strings(2, 2, 4)
+    c.set_integrals(h, eri)
+    C = np.zeros((6, 6))
+    assert L.casci_sigma(c._h, None, C.ctypes.data, 0, 0, 0) == casci.E_ARG
+    assert L.casci_sigma(c._h, C.ctypes.data, C.ctypes.data, 0, 0, 0) == casci.E_ARG
+    S = np.zeros((6, 6))
+    assert L.casci_sigma(c._h, C.ctypes.data, S.ctypes.data, 7, 0, 0) == casci.E_ARG
+    assert L.casci_sigma(c._h, C.ctypes.data, S.ctypes.data, 0, 9, 0) == casci.E_ARG
+    assert L.casci_sigma(c._h, C.ctypes.data, S.ctypes.data, 0, 0, 5) == casci.E_ARG
+    assert b"NULL" in L.casci_last_error(c._h) or L.casci_last_error(c._h)
