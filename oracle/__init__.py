@@ -32,6 +32,7 @@ from __future__ import annotations
 
 import ctypes
 import itertools
+import math
 import os
 import subprocess
 
@@ -62,7 +63,8 @@ def _load():
         lib.oracle_dense_h.argtypes = [i, P, P, d, P, l, P, l, P]
         lib.oracle_sigma_rows.argtypes = [i, P, P, d, P, l, P, l, P, P, l, P]
         lib.oracle_dense_s2.argtypes = [i, P, l, P, l, P]
-        for f in (lib.oracle_dense_h, lib.oracle_sigma_rows, lib.oracle_dense_s2):
+        lib.oracle_h_rows.argtypes = [i, P, P, d, P, l, P, l, P, l, l, P, P, P]
+        for f in (lib.oracle_dense_h, lib.oracle_sigma_rows, lib.oracle_dense_s2, lib.oracle_h_rows):
             f.restype = ctypes.c_int
         _lib = lib
     return _lib
@@ -183,6 +185,37 @@ def sigma(h, eri, nalpha: int, nbeta: int, C, ecore: float = 0.0) -> np.ndarray:
     na, nb = strings(n, nalpha).size, strings(n, nbeta).size
     out = sigma_rows(h, eri, nalpha, nbeta, C, np.arange(na * nb), ecore)
     return out.reshape(na, nb)
+
+
+def hamiltonian_csr(h, eri, nalpha: int, nbeta: int, ecore: float = 0.0, block: int = 4096):
+    """H as a scipy CSR matrix (same Slater-Condon elements as ``hamiltonian``),
+    for spaces too large for the dense matrix."""
+    import scipy.sparse as sp
+    n, h, eri = _prep(h, eri)
+    a = strings(n, nalpha)
+    b = strings(n, nbeta)
+    nd = a.size * b.size
+    ne = nalpha + nbeta
+    maxc = 1 + ne * (2 * n - ne) + math.comb(ne, 2) * math.comb(2 * n - ne, 2)
+    L = _load()
+    indptr = [0]
+    cols_all, vals_all = [], []
+    for r0 in range(0, nd, block):
+        rows = np.arange(r0, min(nd, r0 + block), dtype=np.int64)
+        cols = np.empty(rows.size * maxc, dtype=np.int64)
+        vals = np.empty(rows.size * maxc)
+        cnt = np.empty(rows.size, dtype=np.int64)
+        rc = L.oracle_h_rows(n, _ptr(h), _ptr(eri), float(ecore), _ptr(a), a.size, _ptr(b), b.size,
+                             _ptr(rows), rows.size, maxc, _ptr(cols), _ptr(vals), _ptr(cnt))
+        if rc != 0:
+            raise RuntimeError("oracle_h_rows failed: %d" % rc)
+        for t in range(rows.size):
+            cols_all.append(cols[t * maxc:t * maxc + cnt[t]])
+            vals_all.append(vals[t * maxc:t * maxc + cnt[t]])
+        indptr.extend((indptr[-1] + np.cumsum(cnt)).tolist())
+    H = sp.csr_matrix((np.concatenate(vals_all), np.concatenate(cols_all), np.array(indptr)), shape=(nd, nd))
+    H.sort_indices()
+    return H
 
 
 def s2_matrix(norb: int, nalpha: int, nbeta: int) -> np.ndarray:

@@ -236,6 +236,66 @@ int oracle_sigma_rows(int n, const double* h, const double* eri, double ecore,
 }
 
 /*
+ * Rows of H in sparse form: for each determinant index rows[t], every
+ * determinant J reachable by at most two spin-orbital substitutions (same
+ * enumeration as oracle_sigma_rows) and the element H_IJ. Row t writes
+ * count[t] <= maxc pairs into cols[t*maxc ...] and vals[t*maxc ...].
+ */
+int oracle_h_rows(int n, const double* h, const double* eri, double ecore,
+                  const uint64_t* astr, long Na, const uint64_t* bstr, long Nb,
+                  const long* rows, long nrows, long maxc, long* cols, double* vals, long* count)
+{
+    if (n < 1 || 2 * n > 64) return -1;
+    ints_t I = {n, h, eri, ecore};
+    const int nso = 2 * n;
+    det_t amask = (((det_t)1 << n) - 1);
+    int* holes = (int*)malloc(sizeof(int) * nso);
+    int* parts = (int*)malloc(sizeof(int) * nso);
+    if (!holes || !parts) { free(holes); free(parts); return -2; }
+    for (long t = 0; t < nrows; ++t) {
+        long x = rows[t];
+        det_t A = make_det(n, astr[x / Nb], bstr[x % Nb]);
+        int nh = 0, np = 0;
+        for (int P = 0; P < nso; ++P) {
+            if (occ(A, P)) holes[nh++] = P; else parts[np++] = P;
+        }
+        long c = 0;
+        long* cr = cols + t * maxc;
+        double* vr = vals + t * maxc;
+        cr[c] = x; vr[c] = h_element(&I, A, A); ++c;
+        for (int i = 0; i < nh; ++i)
+            for (int a = 0; a < np; ++a) {
+                if (spin_of(&I, holes[i]) != spin_of(&I, parts[a])) continue;
+                det_t B = (A & ~((det_t)1 << holes[i])) | ((det_t)1 << parts[a]);
+                long ia = find_string(astr, Na, B & amask);
+                long ib = find_string(bstr, Nb, B >> n);
+                if (ia < 0 || ib < 0) continue;
+                if (c >= maxc) { free(holes); free(parts); return -3; }
+                cr[c] = ia * Nb + ib; vr[c] = h_element(&I, A, B); ++c;
+            }
+        for (int i = 0; i < nh; ++i)
+            for (int j = i + 1; j < nh; ++j)
+                for (int a = 0; a < np; ++a)
+                    for (int b = a + 1; b < np; ++b) {
+                        int sh = spin_of(&I, holes[i]) + spin_of(&I, holes[j]);
+                        int sp = spin_of(&I, parts[a]) + spin_of(&I, parts[b]);
+                        if (sh != sp) continue;
+                        det_t B = A & ~((det_t)1 << holes[i]) & ~((det_t)1 << holes[j]);
+                        B |= ((det_t)1 << parts[a]) | ((det_t)1 << parts[b]);
+                        long ia = find_string(astr, Na, B & amask);
+                        long ib = find_string(bstr, Nb, B >> n);
+                        if (ia < 0 || ib < 0) continue;
+                        if (c >= maxc) { free(holes); free(parts); return -3; }
+                        cr[c] = ia * Nb + ib; vr[c] = h_element(&I, A, B); ++c;
+                    }
+        count[t] = c;
+    }
+    free(holes);
+    free(parts);
+    return 0;
+}
+
+/*
  * Dense S^2 over the same basis: S^2 = Sz^2 + Sz + S- S+, with
  * S+ = sum_p a+_{p alpha} a_{p beta} and S- = sum_p a+_{p beta} a_{p alpha},
  * each operator applied to the occupation list one at a time.

@@ -1048,9 +1048,13 @@ extern "C" int casci_davidson(casci_ctx* ctx, int nroots, double tol, const casc
                 if (!have(pa)) cand.push_back(pa);
             }
         }
+        // 2k start vectors (at least k+1): Davidson can only converge to states
+        // present in the space, and a space of exactly k vectors easily misses one
+        const int nstart = std::max(k - m, (int)std::min<int64_t>(
+                               {(int64_t)2 * k - m, (int64_t)m_max - k - m, Nd - m}));
         std::vector<Pick> picks;
         for (auto& c : cand)
-            if ((int)picks.size() < k - m) picks.push_back(c);
+            if ((int)picks.size() < nstart) picks.push_back(c);
         if (paired && !singlet) {
             bool anti = false;
             for (auto& p : picks) anti |= p.sign < 0;

@@ -153,6 +153,14 @@ def test_hamiltonian_equals_second_quantised_definition(n, na, nb):
     np.testing.assert_allclose(H, Hb, atol=1e-12, rtol=0)
 
 
+@pytest.mark.parametrize("n,na,nb", [(4, 2, 2), (5, 3, 2), (6, 2, 4)])
+def test_sparse_rows_equal_dense(n, na, nb):
+    h, eri, _ = synth.integrals(n, 30 + n)
+    H = oracle.hamiltonian(h, eri, na, nb, 0.1)
+    Hs = oracle.hamiltonian_csr(h, eri, na, nb, 0.1, block=7).toarray()
+    np.testing.assert_allclose(Hs, H, atol=1e-14, rtol=0)
+
+
 def test_hamiltonian_hermitian_and_sigma_rows():
     h, eri, _ = synth.integrals(6, 1)
     H = oracle.hamiltonian(h, eri, 3, 3)
