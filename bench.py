@@ -39,6 +39,14 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def progress_printer(tag):
+    def f(it, th, rn, ms):
+        log("[%s] iter %3d  %.1f s  E %s  |r| %s" % (tag, it, ms / 1000.0,
+                                                   " ".join("%.10f" % x for x in th),
+                                                   " ".join("%.1e" % x for x in rn)))
+    return f
+
+
 def time_to_threshold(hist_e, hist_t, eref, thr=1e-8):
     """Wall time (s) of the first iteration after which every root stays within thr of eref."""
     err = np.abs(hist_e - eref[None, :]).max(axis=1)
@@ -77,7 +85,8 @@ def main():
     ref = casci.Context(0)
     ref.set_integrals(h, eri)
     ref.build_strings(na, nb, n)
-    Eref, _, iref = ref.davidson(k, 1e-12, r_tol=1e-7, vectors=False, history=400, precond="olsen", **common)
+    Eref, _, iref = ref.davidson(k, 1e-11, r_tol=1e-6, vectors=False, history=400, precond="olsen",
+                                 progress=progress_printer("ref"), **common)
     dims = ref.dims
     log("[bench] Eref", Eref.tolist(), "iters", iref["iterations"], "converged", iref["converged"])
 
@@ -87,7 +96,8 @@ def main():
     bctx.set_integrals(h, eri)
     bctx.build_strings(na, nb, n)
     bctx.profile(True)
-    Eb, _, ib = bctx.davidson(k, 1e-10, vectors=False, history=400, precond="diag", **common)
+    Eb, _, ib = bctx.davidson(k, 1e-10, vectors=False, history=400, precond="diag",
+                              progress=progress_printer("fp64-diag"), **common)
     base_prof = bctx.profile_read()
     t_base, it_base = time_to_threshold(ib["hist_energy"], ib["hist_time_ms"], Eref)
     log("[bench] baseline time-to-1e-8 %.3f s, iters %d" % (t_base, ib["iterations"]))
@@ -103,7 +113,8 @@ def main():
         ctx.set_integrals(h, eri)
         ctx.build_strings(na, nb, n)
         ctx.profile(True)
-        E, _, info = ctx.davidson(k, 1e-10, vectors=False, history=400, **headline, **common)
+        E, _, info = ctx.davidson(k, 1e-10, vectors=False, history=400, progress=progress_printer("step%d" % step),
+                                  **headline, **common)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         prof = ctx.profile_read()

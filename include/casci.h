@@ -186,7 +186,12 @@ typedef struct {
     const double* guess;    /* optional [nguess][Ndet] FP64 start vectors (host or device) */
     int nguess;
     int guess_mem;
-    int verbose_history;    /* fill info->hist_* when the pointers are set */
+    int verbose_history;    /* reserved, set to 0 */
+    /* optional, called once per iteration on the calling thread with the
+       current Ritz values, residual norms and wall time since the call began */
+    void (*progress)(void* user, int iteration, int nroots, const double* theta,
+                     const double* rnorm, double wall_ms);
+    void* progress_user;
 } casci_davidson_opts;
 
 typedef struct {

@@ -41,7 +41,13 @@ class DavidsonOpts(ctypes.Structure):
                 ("spin", ctypes.c_int), ("ab_prec", ctypes.c_int), ("refine_rnorm", ctypes.c_double),
                 ("r_tol", ctypes.c_double), ("s2_penalty", ctypes.c_double),
                 ("guess", ctypes.c_void_p), ("nguess", ctypes.c_int), ("guess_mem", ctypes.c_int),
-                ("verbose_history", ctypes.c_int)]
+                ("verbose_history", ctypes.c_int), ("progress", ctypes.c_void_p),
+                ("progress_user", ctypes.c_void_p)]
+
+
+PROGRESS_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_int, ctypes.c_int,
+                               ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
+                               ctypes.c_double)
 
 
 class DavidsonInfo(ctypes.Structure):
@@ -251,9 +257,19 @@ class Context:
     def davidson(self, nroots: int = 1, tol: float = 1e-10, *, precond: str = "diag", spin: str = "any",
                  ab_prec: str = "f64", max_iter: int = 0, m_max: int = 0, r_tol: float = 0.0,
                  refine_rnorm: float = 0.0, s2_penalty: float = 0.0, guess=None, vectors=True,
-                 history: int = 0, vectors_out=None):
-        """Lowest roots by Davidson-Liu. Returns (energies, vectors or None, info dict)."""
+                 history: int = 0, vectors_out=None, progress=None):
+        """Lowest roots by Davidson-Liu. Returns (energies, vectors or None, info dict).
+
+        progress: optional callable(iteration, theta list, residual list, wall_ms),
+        called by the library once per iteration.
+        """
         o = DavidsonOpts()
+        cb = None
+        if progress is not None:
+            def _cb(user, it, k, th, rn, ms):
+                progress(it, [th[i] for i in range(k)], [rn[i] for i in range(k)], ms)
+            cb = PROGRESS_FN(_cb)
+            o.progress = ctypes.cast(cb, ctypes.c_void_p)
         o.max_iter, o.m_max = int(max_iter), int(m_max)
         o.precond, o.spin, o.ab_prec = PRECOND[precond], SPIN[spin], PREC[ab_prec]
         o.refine_rnorm, o.r_tol, o.s2_penalty = float(refine_rnorm), float(r_tol), float(s2_penalty)

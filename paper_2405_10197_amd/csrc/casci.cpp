@@ -103,11 +103,12 @@ struct casci_ctx {
     double prepared_lambda = 0.0;
     DBuf d_h, d_eri, d_fa_col, d_fa_val, d_fb_col, d_fb_val, d_jpq, d_diag;
     DBuf d_vt_sym, d_pairs_sym, d_vt_full, d_pairs_full, d_vt_s2;
+    DBuf d_vt_sym_lp[2], d_vt_full_lp[2];  // FP32 and BF16 copies (round to nearest even)
     int M_sym = 0, Mp_sym = 0, M_full = 0, Mp_full = 0;
     bool have_full = false, have_s2 = false;
 
     // workspaces
-    DBuf d_t1, d_t2, d_vin, d_vout, d_work, d_small;
+    DBuf d_t1, d_t2, d_vin, d_vout, d_work, d_small, d_clp, d_c32;
 
     // optional per-part timing of sigma builds (HIP events on `stream`)
     bool profiling = false;
@@ -127,7 +128,9 @@ struct casci_ctx {
         if (e_ != hipSuccess) {                                                         \
             (void)hipGetLastError();                                                    \
             return ctx->fail(e_ == hipErrorOutOfMemory ? CASCI_E_NOMEM : CASCI_E_DEVICE,  \
-                             std::string(#expr) + ": " + hipGetErrorString(e_));        \
+                             std::string(#expr) + ": " + hipGetErrorString(e_) +       \
+                                 (*launch_reason() ? std::string(" (") + launch_reason() + ")"  \
+                                                   : std::string()));                   \
         }                                                                               \
     } while (0)
 
@@ -189,7 +192,8 @@ extern "C" void casci_destroy(casci_ctx* ctx)
                         &ctx->d_fa_val, &ctx->d_fb_col, &ctx->d_fb_val, &ctx->d_jpq, &ctx->d_diag,
                         &ctx->d_vt_sym, &ctx->d_pairs_sym, &ctx->d_vt_full, &ctx->d_pairs_full,
                         &ctx->d_vt_s2, &ctx->d_t1, &ctx->d_t2, &ctx->d_vin, &ctx->d_vout,
-                        &ctx->d_work, &ctx->d_small};
+                        &ctx->d_work, &ctx->d_small, &ctx->d_vt_sym_lp[0], &ctx->d_vt_sym_lp[1],
+                        &ctx->d_vt_full_lp[0], &ctx->d_vt_full_lp[1], &ctx->d_clp, &ctx->d_c32};
         for (DBuf* b : bufs) b->release();
         for (hipEvent_t& e : ctx->pev)
             if (e) (void)hipEventDestroy(e);
@@ -446,6 +450,40 @@ static void build_vt(const casci_ctx* ctx, const std::vector<uint16_t>& pairs, i
             }
 }
 
+// FP64 -> BF16 with round-to-nearest-even. The FP64 -> FP32 step is itself
+// RNE and can only mislead the second rounding when it lands exactly on a
+// BF16 tie; then the side of the tie is taken from the FP64 value.
+static uint16_t bf16_rne(double x)
+{
+    const float f = (float)x;
+    uint32_t u;
+    std::memcpy(&u, &f, 4);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40);  // NaN stays NaN
+    if ((u & 0xffffu) == 0x8000u) {
+        const double back = (double)f;
+        if (std::fabs(x) > std::fabs(back)) u += 1;       // above the tie in magnitude
+        else if (std::fabs(x) < std::fabs(back)) u -= 1;  // below it
+    }
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+static int upload_lowp(casci_ctx* ctx, const std::vector<double>& vt, DBuf* lp)
+{
+    std::vector<float> f(vt.size());
+    std::vector<uint16_t> b(vt.size());
+    for (size_t i = 0; i < vt.size(); ++i) {
+        f[i] = (float)vt[i];
+        b[i] = bf16_rne(vt[i]);
+    }
+    HIPC(lp[0].ensure(f.size() * 4));
+    HIPC(lp[1].ensure(b.size() * 2));
+    HIPC(hipMemcpyAsync(lp[0].p, f.data(), f.size() * 4, hipMemcpyHostToDevice, ctx->stream));
+    HIPC(hipMemcpyAsync(lp[1].p, b.data(), b.size() * 2, hipMemcpyHostToDevice, ctx->stream));
+    HIPC(hipStreamSynchronize(ctx->stream));
+    return CASCI_OK;
+}
+
 static int ensure_prepared(casci_ctx* ctx, double lambda)
 {
     if (!ctx->has_ints) return ctx->fail(CASCI_E_STATE, "set_integrals first");
@@ -492,6 +530,7 @@ static int ensure_prepared(casci_ctx* ctx, double lambda)
         HIPC(hipMemcpyAsync(ctx->d_vt_sym.p, vt.data(), vt.size() * 8, hipMemcpyHostToDevice, st));
         // pageable host sources: finish before the vectors go out of scope
         HIPC(hipStreamSynchronize(st));
+        CHECK_RC(upload_lowp(ctx, vt, ctx->d_vt_sym_lp));
         ctx->prepared = true;
         ctx->have_full = false;
         ctx->prepared_lambda = std::nan("");
@@ -514,6 +553,7 @@ static int ensure_prepared(casci_ctx* ctx, double lambda)
                                 hipMemcpyHostToDevice, st));
             HIPC(hipMemcpyAsync(ctx->d_vt_full.p, vt.data(), vt.size() * 8, hipMemcpyHostToDevice, st));
             HIPC(hipStreamSynchronize(st));
+            CHECK_RC(upload_lowp(ctx, vt, ctx->d_vt_full_lp));
             ctx->have_full = true;
         }
         ctx->prepared_lambda = lambda;
@@ -535,28 +575,51 @@ static AbParams ab_params(const casci_ctx* ctx, bool full)
     p.la_j = ctx->d_la_j.as<int32_t>();
     p.la_pq = ctx->d_la_pq.as<uint16_t>();
     p.bstr = ctx->d_bstr.as<uint64_t>();
-    p.binom = ctx->d_binom.as<int64_t>();
+    p.lb_j = ctx->d_lb_j.as<int32_t>();
+    p.sb = ctx->sb;
     p.pairs = (full ? ctx->d_pairs_full : ctx->d_pairs_sym).as<uint16_t>();
     return p;
 }
 
-// sigma = (H + lambda S^2) C on device vectors (FP64 storage)
-static int sigma_dev(casci_ctx* ctx, const double* C, double* S, int ab_prec, double lambda)
+// sigma = (H + lambda S^2) C on device vectors (FP64 storage).
+// parity = +1 / -1 declares C = +-C^T (nalpha = nbeta only): transposition
+// commutes with H, so sigma_bb = parity * sigma_aa^T and one same-spin gather
+// serves both spins. parity = 0: general C. ab_prec != F64 also reads the
+// same-spin gather operand from an FP32 copy of C (accumulation stays FP64).
+static int sigma_dev(casci_ctx* ctx, const double* C, double* S, int ab_prec, double lambda,
+                     int parity = 0)
 {
     hipStream_t st = ctx->stream;
     const int64_t Na = ctx->Na, Nb = ctx->Nb, Nd = ctx->Nd;
     const double ms = 0.5 * (ctx->na - ctx->nb);
     const double shift = ctx->ecore + lambda * (ms * ms + ms + ctx->nb);
     const bool prof = ctx->profiling;
+    const bool lowp = ab_prec != CASCI_F64;
+    if (parity != 0 && ctx->na != ctx->nb) return ctx->fail(CASCI_E_ARG, "parity needs nalpha == nbeta");
+    set_launch_reason("");
     auto mark = [&](int i) -> int {
         if (prof) HIPC(hipEventRecord(ctx->pev[i], st));
         return CASCI_OK;
     };
     CHECK_RC(mark(0));
-    HIPC(launch_ss_gather_f64(ctx->d_fa_col.as<int32_t>(), ctx->d_fa_val.as<double>(), ctx->ra, Na, Nb,
-                              C, S, shift, 0, st));
+    const int64_t ld32 = lowp_ld(1, Nb);
+    if (lowp) {
+        HIPC(ctx->d_c32.ensure((size_t)Na * ld32 * 4));
+        HIPC(launch_convert_lowp(1, C, ctx->d_c32.p, Na, Nb, ld32, st));
+    }
+    const double s_aa = parity != 0 ? 0.5 * shift : shift;  // halved: S + p S^T doubles it
+    if (lowp)
+        HIPC(launch_ss_gather_f32in(ctx->d_fa_col.as<int32_t>(), ctx->d_fa_val.as<double>(), ctx->ra, Na, Nb,
+                                    ctx->d_c32.as<float>(), ld32, S, s_aa, 0, st));
+    else
+        HIPC(launch_ss_gather_f64(ctx->d_fa_col.as<int32_t>(), ctx->d_fa_val.as<double>(), ctx->ra, Na, Nb,
+                                  C, S, s_aa, 0, st));
     CHECK_RC(mark(1));
-    if (ctx->nb > 0) {
+    if (parity != 0) {
+        CHECK_RC(mark(2));
+        CHECK_RC(mark(3));
+        HIPC(launch_sym_add(S, Na, parity, 1.0, st));
+    } else if (ctx->nb > 0) {
         HIPC(ctx->d_t1.ensure((size_t)Nd * 8));
         HIPC(ctx->d_t2.ensure((size_t)Nd * 8));
         const bool same = ctx->nb == ctx->na;
@@ -577,10 +640,18 @@ static int sigma_dev(casci_ctx* ctx, const double* C, double* S, int ab_prec, do
         const bool full = lambda != 0.0;
         AbParams p = ab_params(ctx, full);
         const DBuf& vt = full ? ctx->d_vt_full : ctx->d_vt_sym;
-        if (ab_prec == CASCI_F64) {
+        if (!lowp) {
             HIPC(launch_ab_f64(p, vt.as<double>(), C, S, st));
         } else {
-            return ctx->fail(CASCI_E_UNSUPPORTED, "low-precision alpha-beta arithmetic not built");
+            const DBuf* lp = full ? ctx->d_vt_full_lp : ctx->d_vt_sym_lp;
+            if (ab_prec == CASCI_F32) {
+                HIPC(launch_ab_lowp(p, 1, lp[0].p, ctx->d_c32.p, ld32, S, st));
+            } else {
+                const int64_t ld = lowp_ld(2, Nb);
+                HIPC(ctx->d_clp.ensure((size_t)Na * ld * 2));
+                HIPC(launch_convert_lowp(2, C, ctx->d_clp.p, Na, Nb, ld, st));
+                HIPC(launch_ab_lowp(p, 2, lp[1].p, ctx->d_clp.p, ld, S, st));
+            }
         }
     }
     CHECK_RC(mark(5));
@@ -588,12 +659,12 @@ static int sigma_dev(casci_ctx* ctx, const double* C, double* S, int ab_prec, do
         HIPC(hipEventSynchronize(ctx->pev[5]));
         float t[5];
         for (int i = 0; i < 5; ++i) HIPC(hipEventElapsedTime(&t[i], ctx->pev[i], ctx->pev[i + 1]));
-        ctx->prof[0] += t[0];         // alpha-alpha gather
-        ctx->prof[1] += t[1] + t[3];  // the two transposes of the beta-beta term
+        ctx->prof[0] += t[0];         // alpha-alpha gather (with the FP32 conversion if any)
+        ctx->prof[1] += t[1] + t[3];  // transposes / parity symmetrisation of the beta-beta term
         ctx->prof[2] += t[2];         // beta-beta gather
-        ctx->prof[3] += t[4];         // alpha-beta contraction
+        ctx->prof[3] += t[4];         // alpha-beta contraction (with its input conversion)
         ctx->prof[4] += 1;            // sigma builds
-        ctx->prof[5] += (ab_prec == CASCI_F64) ? 1 : 0;
+        ctx->prof[5] += lowp ? 0 : 1;
     }
     return CASCI_OK;
 }
@@ -918,9 +989,13 @@ extern "C" int casci_davidson(casci_ctx* ctx, int nroots, double tol, const casc
     double sigma_ms = 0.0;
     int sigma_calls = 0, sigma64 = 0;
 
-    auto run_sigma = [&](const double* c, double* s) -> int {
+    // transposition parity of every basis / Ritz vector (nalpha == nbeta): kept
+    // exact by projecting each new vector, so sigma needs one same-spin gather
+    const bool use_par = ctx->na == ctx->nb && (singlet || !o.guess);
+    std::vector<int> par(m_max + k, 0), xpar(2 * k, 0);
+    auto run_sigma = [&](const double* c, double* s, int parity) -> int {
         HIPC(hipEventRecord(ev0, st));
-        CHECK_RC(sigma_dev(ctx, c, s, prec, lambda));
+        CHECK_RC(sigma_dev(ctx, c, s, prec, lambda, use_par ? parity : 0));
         HIPC(hipEventRecord(ev1, st));
         HIPC(hipEventSynchronize(ev1));
         float ms = 0;
@@ -941,10 +1016,9 @@ extern "C" int casci_davidson(casci_ctx* ctx, int nroots, double tol, const casc
         HIPC(hipStreamSynchronize(st));  // coef is pageable host memory
         return CASCI_OK;
     };
-    auto symmetrize = [&](double* v) -> int {
-        // v <- (v + v^T)/2 for nalpha == nbeta
-        HIPC(launch_transpose_f64(v, dT.as<double>(), ctx->Na, ctx->Nb, 0, 1.0, st));
-        HIPC(launch_axpby_f64(0.5, dT.as<double>(), 0.5, v, Nd, st));
+    auto symmetrize = [&](double* v, int p) -> int {
+        // v <- (v + p v^T)/2 for nalpha == nbeta
+        HIPC(launch_sym_add(v, ctx->Na, p, 0.5, st));
         return CASCI_OK;
     };
 
@@ -975,12 +1049,18 @@ extern "C" int casci_davidson(casci_ctx* ctx, int nroots, double tol, const casc
                     CHECK_RC(combine(vB(m), kept, c, 1, 1.0, v));
                 }
             }
+            // Re-project onto the vector's parity before normalising: what is left
+            // after Gram-Schmidt can be small, and normalising it would amplify
+            // rounding-level components of the other parity. The projection
+            // keeps orthogonality to a basis of pure-parity vectors.
+            if (use_par && par[m + j] != 0) CHECK_RC(symmetrize(v, par[m + j]));
             std::vector<double> nn;
             CHECK_RC(dots_dev(v, 1, v, 1, nn));
             const double nrm = std::sqrt(nn[0]);
             if (!(nrm > 1e-8 * std::max(before[j], 1e-300)) || !(nrm > 1e-14)) continue;
             HIPC(launch_scale(v, 1.0 / nrm, Nd, st));
             if (kept != j) HIPC(hipMemcpyAsync(vB(m + kept), v, vb, hipMemcpyDeviceToDevice, st));
+            par[m + kept] = par[m + j];
             ++kept;
         }
         return CASCI_OK;
@@ -1006,7 +1086,10 @@ extern "C" int casci_davidson(casci_ctx* ctx, int nroots, double tol, const casc
                             o.guess_mem == CASCI_MEM_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice,
                             st));
         if (singlet)
-            for (int j = 0; j < ng; ++j) CHECK_RC(symmetrize(vB(j)));
+            for (int j = 0; j < ng; ++j) {
+                CHECK_RC(symmetrize(vB(j), 1));
+                par[j] = 1;
+            }
         int kept = 0;
         CHECK_RC(orthonormalize(0, ng, kept));
         m = kept;
@@ -1078,6 +1161,7 @@ extern "C" int casci_davidson(casci_ctx* ctx, int nroots, double tol, const casc
                 HIPC(hipMemcpyAsync(v + pr.hi, &h2s, 8, hipMemcpyHostToDevice, st));
             }
             HIPC(hipStreamSynchronize(st));
+            par[m] = pr.sign;
             ++m;
         }
         if (start > 0) {
@@ -1087,7 +1171,7 @@ extern "C" int casci_davidson(casci_ctx* ctx, int nroots, double tol, const casc
         }
         if (m < k) return ctx->fail(CASCI_E_ARG, "could not build nroots independent start vectors");
     }
-    for (int j = 0; j < m; ++j) CHECK_RC(run_sigma(vB(j), vS(j)));
+    for (int j = 0; j < m; ++j) CHECK_RC(run_sigma(vB(j), vS(j), par[j]));
     CHECK_RC(extend_G(0, m));
 
     std::vector<double> theta_prev(k, std::numeric_limits<double>::infinity());
@@ -1098,9 +1182,13 @@ extern "C" int casci_davidson(casci_ctx* ctx, int nroots, double tol, const casc
     int stall = 0, empty_steps = 0;
     for (it = 0; it < max_iter; ++it) {
         // Rayleigh-Ritz on the device
+        // With parity, B^T H B is block diagonal (the two parities are orthogonal
+        // and H preserves them); its off-block entries are rounding noise and are
+        // set to zero, so every Ritz vector lies exactly in one parity block.
         std::vector<double> Gc((size_t)m * m);
         for (int i = 0; i < m; ++i)
-            for (int j = 0; j < m; ++j) Gc[(size_t)i * m + j] = G[(size_t)i * m_max + j];
+            for (int j = 0; j < m; ++j)
+                Gc[(size_t)i * m + j] = (use_par && par[i] != par[j]) ? 0.0 : G[(size_t)i * m_max + j];
         HIPC(hipMemcpyAsync(dG, Gc.data(), Gc.size() * 8, hipMemcpyHostToDevice, st));
         HIPC(launch_jacobi_eigh(dG, m, m, dth, dY, st));
         HIPC(hipMemcpyAsync(theta.data(), dth, m * 8, hipMemcpyDeviceToHost, st));
@@ -1110,6 +1198,15 @@ extern "C" int casci_davidson(casci_ctx* ctx, int nroots, double tol, const casc
         if (have_prev) {
             HIPC(hipMemcpyAsync(vX(k), vX(0), vb * k, hipMemcpyDeviceToDevice, st));
             HIPC(hipMemcpyAsync(vSX(k), vSX(0), vb * k, hipMemcpyDeviceToDevice, st));
+            for (int j = 0; j < k; ++j) xpar[k + j] = xpar[j];
+        }
+        // parity of each Ritz vector: the projected matrix is block diagonal in
+        // parity, so each eigenvector lives (up to rounding) in one block
+        for (int j = 0; j < k; ++j) {
+            double wp = 0.0;
+            for (int i = 0; i < m; ++i)
+                if (par[i] > 0) wp += Y[(size_t)i * m + j] * Y[(size_t)i * m + j];
+            xpar[j] = use_par ? (wp >= 0.5 ? 1 : -1) : 0;
         }
         // Ritz vectors X = B Y[:, :k], SX = S Y[:, :k]
         std::vector<double> yk((size_t)m * k);
@@ -1137,6 +1234,7 @@ extern "C" int casci_davidson(casci_ctx* ctx, int nroots, double tol, const casc
             for (int j = 0; j < k; ++j) info->hist_residual[(size_t)it * k + j] = rn[j];
         if (info && info->hist_time_ms && it < info->hist_len) info->hist_time_ms[it] = wall.ms();
         for (int j = 0; j < k; ++j) theta_prev[j] = theta[j];
+        if (o.progress) o.progress(o.progress_user, it, k, theta.data(), rn.data(), wall.ms());
         if (!std::isfinite(rmax)) return ctx->fail(CASCI_E_NONFINITE, "non-finite residual in Davidson");
         if (todo.empty() && prec == CASCI_F64) {
             converged = true;
@@ -1149,10 +1247,11 @@ extern "C" int casci_davidson(casci_ctx* ctx, int nroots, double tol, const casc
                 prec = CASCI_F64;
                 switch_iter = it;
                 HIPC(hipMemcpyAsync(vB(0), vX(0), vb * k, hipMemcpyDeviceToDevice, st));
+                for (int j = 0; j < k; ++j) par[j] = xpar[j];
                 int kept = 0;
                 CHECK_RC(orthonormalize(0, k, kept));
                 m = kept;
-                for (int j = 0; j < m; ++j) CHECK_RC(run_sigma(vB(j), vS(j)));
+                for (int j = 0; j < m; ++j) CHECK_RC(run_sigma(vB(j), vS(j), par[j]));
                 CHECK_RC(extend_G(0, m));
                 have_prev = false;
                 last_rmax = std::numeric_limits<double>::infinity();
@@ -1166,6 +1265,7 @@ extern "C" int casci_davidson(casci_ctx* ctx, int nroots, double tol, const casc
             const int nkeep = (have_prev && 2 * k + (int)todo.size() <= m_max) ? 2 * k : k;
             HIPC(hipMemcpyAsync(vB(0), vX(0), vb * nkeep, hipMemcpyDeviceToDevice, st));
             HIPC(hipMemcpyAsync(vS(0), vSX(0), vb * nkeep, hipMemcpyDeviceToDevice, st));
+            for (int j = 0; j < nkeep; ++j) par[j] = xpar[j];
             // Gram-Schmidt of the previous Ritz vectors against the current ones,
             // the same combination applied to their sigma vectors
             int mm = k;
@@ -1180,13 +1280,17 @@ extern "C" int casci_davidson(casci_ctx* ctx, int nroots, double tol, const casc
                 std::vector<double> nn;
                 CHECK_RC(dots_dev(vB(j), 1, vB(j), 1, nn));
                 const double nrm = std::sqrt(nn[0]);
-                if (nrm < 1e-8) continue;
+                // a nearly dependent previous Ritz vector is dropped: normalising a
+                // small remainder would amplify rounding (and, with parity, its
+                // other-parity part, which its sigma vector does not follow)
+                if (nrm < 1e-4) continue;
                 HIPC(launch_scale(vB(j), 1.0 / nrm, Nd, st));
                 HIPC(launch_scale(vS(j), 1.0 / nrm, Nd, st));
                 if (mm != j) {
                     HIPC(hipMemcpyAsync(vB(mm), vB(j), vb, hipMemcpyDeviceToDevice, st));
                     HIPC(hipMemcpyAsync(vS(mm), vS(j), vb, hipMemcpyDeviceToDevice, st));
                 }
+                par[mm] = par[j];
                 ++mm;
             }
             m = mm;
@@ -1201,7 +1305,8 @@ extern "C" int casci_davidson(casci_ctx* ctx, int nroots, double tol, const casc
             if (o.precond == CASCI_PRECOND_OLSEN && std::fabs(rs[4 * j + 2]) > 1e-300)
                 eps = rs[4 * j + 1] / rs[4 * j + 2];
             HIPC(launch_precondition(vX(j), vSX(j), theta[j], eps, ctx->d_diag.as<double>(), Nd, vB(m + t), st));
-            if (singlet) CHECK_RC(symmetrize(vB(m + t)));
+            par[m + t] = xpar[j];
+            if (use_par) CHECK_RC(symmetrize(vB(m + t), xpar[j]));
         }
         int kept = 0;
         CHECK_RC(orthonormalize(m, cnt, kept));
@@ -1212,7 +1317,7 @@ extern "C" int casci_davidson(casci_ctx* ctx, int nroots, double tol, const casc
             continue;
         }
         empty_steps = 0;
-        for (int j = 0; j < kept; ++j) CHECK_RC(run_sigma(vB(m + j), vS(m + j)));
+        for (int j = 0; j < kept; ++j) CHECK_RC(run_sigma(vB(m + j), vS(m + j), par[m + j]));
         CHECK_RC(extend_G(m, kept));
         m += kept;
         have_prev = true;

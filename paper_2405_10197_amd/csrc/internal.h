@@ -26,6 +26,11 @@ __host__ __device__ inline uint64_t between_mask(int a, int b)
     return upto_hi & ~upto_lo1;
 }
 
+// Reason of the last hipErrorInvalidValue returned by a launch wrapper of
+// this library on the calling thread ("" if the error came from HIP itself).
+const char* launch_reason();
+void set_launch_reason(const char* why);
+
 // ---------------------------------------------------------------------------
 // launch wrappers (defined in the .hip files); all enqueue on `st`
 // ---------------------------------------------------------------------------
@@ -47,6 +52,12 @@ hipError_t launch_diagonal(int n, int64_t Na, int64_t Nb, const uint64_t* astr,
 hipError_t launch_ss_gather_f64(const int32_t* col, const double* val, int r, int64_t nrows,
                                 int64_t ncols, const double* X, double* Y, double shift, int acc,
                                 hipStream_t st);
+// same gather reading an FP32 copy of X with row stride ldx, FP64 output
+hipError_t launch_ss_gather_f32in(const int32_t* col, const double* val, int r, int64_t nrows,
+                                  int64_t ncols, const float* X, int64_t ldx, double* Y, double shift,
+                                  int acc, hipStream_t st);
+// S <- scale (S + p S^T), S square n x n, in place
+hipError_t launch_sym_add(double* S, int64_t n, int p, double scale, hipStream_t st);
 hipError_t launch_ss_gather_f32(const int32_t* col, const double* val, int r, int64_t nrows,
                                 int64_t ncols, const float* X, float* Y, double shift, int acc,
                                 hipStream_t st);
@@ -65,14 +76,20 @@ struct AbParams {
     const int32_t* la_j;  // alpha single list
     const uint16_t* la_pq;
     const uint64_t* bstr;
-    const int64_t* binom; // (n+1) x (n+1)
+    const int32_t* lb_j;  // beta single list (targets of the scatter)
+    int sb;               // beta list length
     const uint16_t* pairs;// [Mp] r | s << 8
 };
 // sigma(Ia, :) += alpha-beta term; Vt[pq][Mp] in the arithmetic's type
+// (prec 1: float, FP32 MFMA; prec 2: bf16, BF16 MFMA; both accumulate in FP32)
 hipError_t launch_ab_f64(const AbParams& p, const double* Vt, const double* C, double* sigma,
                          hipStream_t st);
-hipError_t launch_ab_lowp(const AbParams& p, int prec, const void* Vt, const double* C,
+hipError_t launch_ab_lowp(const AbParams& p, int prec, const void* Vt, const void* Cs, int64_t ldc,
                           double* sigma, hipStream_t st);
+// padded row stride of the low-precision copy of C, and the conversion itself
+int64_t lowp_ld(int prec, int64_t cols);
+hipError_t launch_convert_lowp(int prec, const double* C, void* out, int64_t rows, int64_t cols,
+                               int64_t ld, hipStream_t st);
 hipError_t launch_convert_f64_to_f32(const double* in, float* out, int64_t n, hipStream_t st);
 hipError_t launch_convert_f32_to_f64(const float* in, double* out, int64_t n, hipStream_t st);
 hipError_t launch_axpby_f64(double a, const double* x, double b, double* y, int64_t n, hipStream_t st);

@@ -14,7 +14,19 @@
 // signs factorise, so no extra phase appears in sigma_ab.
 #include "internal.h"
 
+#include <climits>
+
 namespace casci {
+
+static thread_local const char* g_launch_reason = "";
+const char* launch_reason() { return g_launch_reason; }
+void set_launch_reason(const char* why) { g_launch_reason = why; }
+
+static hipError_t invalid(const char* why)
+{
+    g_launch_reason = why;
+    return hipErrorInvalidValue;
+}
 
 // ---------------------------------------------------------------------------
 // same-spin gather: Y(I,:) = [acc ? Y : 0] + sum_e val(I,e) X(col(I,e),:) + shift X(I,:)
@@ -35,13 +47,13 @@ __device__ inline double bcast_f64(double v, int lane)
     return *reinterpret_cast<double*>(&u);
 }
 
-template <typename T, int LPE>
+template <typename TX, typename TY, int LPE>
 __global__ __launch_bounds__(256) void k_ss_gather(const int32_t* __restrict__ col,
                                                    const double* __restrict__ val, int r,
                                                    int64_t nrows, int64_t ncols,
-                                                   const T* __restrict__ X, T* __restrict__ Y,
-                                                   double shift, int acc, int64_t nrowblk,
-                                                   int64_t nitems)
+                                                   const TX* __restrict__ X, int64_t ldx,
+                                                   TY* __restrict__ Y, double shift, int acc,
+                                                   int64_t nrowblk, int64_t nitems)
 {
     constexpr int G = 64 / LPE;
     const int64_t per_xcd = gridDim.x / 8;
@@ -79,8 +91,8 @@ __global__ __launch_bounds__(256) void k_ss_gather(const int32_t* __restrict__ c
             }
             // entries past r carry v = 0 and J = 0 (a valid row): no branch needed
             if (cok) {
-                a0 += v0 * (double)X[(int64_t)J0 * ncols + c];
-                a1 += v1 * (double)X[(int64_t)J1 * ncols + c];
+                a0 += v0 * (double)X[(int64_t)J0 * ldx + c];
+                a1 += v1 * (double)X[(int64_t)J1 * ldx + c];
             }
         }
     }
@@ -89,24 +101,25 @@ __global__ __launch_bounds__(256) void k_ss_gather(const int32_t* __restrict__ c
     for (int off = LPE; off < 64; off <<= 1) a += __shfl_xor(a, off);
     if (g == 0 && cok) {
         const int64_t o = I * ncols + c;
-        double y = a + shift * (double)X[o];
+        double y = a + shift * (double)X[I * ldx + c];
         if (acc) y += (double)Y[o];
-        Y[o] = (T)y;
+        Y[o] = (TY)y;
     }
 }
 
-template <typename T, int LPE>
+template <typename TX, typename TY, int LPE>
 static hipError_t ss_gather(const int32_t* col, const double* val, int r, int64_t nrows,
-                            int64_t ncols, const T* X, T* Y, double shift, int acc, hipStream_t st)
+                            int64_t ncols, const TX* X, int64_t ldx, TY* Y, double shift, int acc,
+                            hipStream_t st)
 {
     if (nrows <= 0 || ncols <= 0) return hipSuccess;
     const int64_t nrowblk = (nrows + 3) / 4;
     const int64_t nstrip = (ncols + LPE - 1) / LPE;
     const int64_t nitems = nrowblk * nstrip;
     const int64_t grid = (nitems + 7) / 8 * 8;
-    if (grid > 0x7fffffffLL) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((k_ss_gather<T, LPE>), dim3((unsigned)grid), dim3(256), 0, st, col, val, r,
-                       nrows, ncols, X, Y, shift, acc, nrowblk, nitems);
+    if (grid > 0x7fffffffLL) return invalid("same-spin gather: grid too large");
+    hipLaunchKernelGGL((k_ss_gather<TX, TY, LPE>), dim3((unsigned)grid), dim3(256), 0, st, col, val, r,
+                       nrows, ncols, X, ldx, Y, shift, acc, nrowblk, nitems);
     return hipGetLastError();
 }
 
@@ -114,14 +127,67 @@ hipError_t launch_ss_gather_f64(const int32_t* col, const double* val, int r, in
                                 int64_t ncols, const double* X, double* Y, double shift, int acc,
                                 hipStream_t st)
 {
-    return ss_gather<double, 32>(col, val, r, nrows, ncols, X, Y, shift, acc, st);
+    return ss_gather<double, double, 32>(col, val, r, nrows, ncols, X, ncols, Y, shift, acc, st);
+}
+
+hipError_t launch_ss_gather_f32in(const int32_t* col, const double* val, int r, int64_t nrows,
+                                  int64_t ncols, const float* X, int64_t ldx, double* Y, double shift,
+                                  int acc, hipStream_t st)
+{
+    return ss_gather<float, double, 64>(col, val, r, nrows, ncols, X, ldx, Y, shift, acc, st);
 }
 
 hipError_t launch_ss_gather_f32(const int32_t* col, const double* val, int r, int64_t nrows,
                                 int64_t ncols, const float* X, float* Y, double shift, int acc,
                                 hipStream_t st)
 {
-    return ss_gather<float, 64>(col, val, r, nrows, ncols, X, Y, shift, acc, st);
+    return ss_gather<float, float, 64>(col, val, r, nrows, ncols, X, ncols, Y, shift, acc, st);
+}
+
+// ---------------------------------------------------------------------------
+// S <- scale * (S + p S^T) in place for a square matrix (p = +-1): the tile
+// pair (bi, bj) / (bj, bi) is read into LDS by one block before either is
+// written, so every output uses the original values.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_sym_add(double* __restrict__ S, int64_t n, double p,
+                                                 double scale, int64_t nb)
+{
+    __shared__ double A[32][33];
+    __shared__ double B[32][33];
+    // blockIdx.x enumerates pairs bi <= bj
+    int64_t k = blockIdx.x, bi = 0;
+    while (k >= nb - bi) {
+        k -= nb - bi;
+        ++bi;
+    }
+    const int64_t bj = bi + k;
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+    const int64_t r0 = bi * 32, c0 = bj * 32;
+    for (int i = ty; i < 32; i += 8) {
+        const int64_t ra = r0 + i, ca = c0 + tx;
+        A[i][tx] = (ra < n && ca < n) ? S[ra * n + ca] : 0.0;
+        const int64_t rb = c0 + i, cb = r0 + tx;
+        B[i][tx] = (rb < n && cb < n) ? S[rb * n + cb] : 0.0;
+    }
+    __syncthreads();
+    for (int i = ty; i < 32; i += 8) {
+        const int64_t ra = r0 + i, ca = c0 + tx;
+        if (ra < n && ca < n) S[ra * n + ca] = scale * (A[i][tx] + p * B[tx][i]);
+        if (bi != bj) {
+            const int64_t rb = c0 + i, cb = r0 + tx;
+            if (rb < n && cb < n) S[rb * n + cb] = scale * (B[i][tx] + p * A[tx][i]);
+        }
+    }
+}
+
+hipError_t launch_sym_add(double* S, int64_t n, int p, double scale, hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    const int64_t nb = (n + 31) / 32;
+    const int64_t pairs = nb * (nb + 1) / 2;
+    if (pairs > 0x7fffffffLL) return invalid("sym_add: matrix too large");
+    hipLaunchKernelGGL(k_sym_add, dim3((unsigned)pairs), dim3(256), 0, st, S, n, (double)p, scale, nb);
+    return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
@@ -171,63 +237,121 @@ hipError_t launch_transpose_f32(const float* in, float* out, int64_t rows, int64
 // alpha-beta contraction on MFMA
 // ---------------------------------------------------------------------------
 // One workgroup owns one alpha string Ia (and one chunk [lo, lo+chunk) of
-// the sigma row, kept in LDS). For every tile of TN beta strings Jb:
+// the sigma row, accumulated in LDS). For every tile of TN beta strings Jb:
 //   D(e, Jb)  = C(J_e, Jb),  e in L1(Ia)           (row gathers -> LDS)
 //   T(m, Jb)  = sum_e A(m, e) D(e, Jb),             A(m,e) = s_e (p_e q_e|r_m s_m)
-//             (one 16-row M tile per wave, 16x16x4 FP64 MFMA)
+//             (one 16-row M tile per wave, 16x16xK MFMA, four N sub-tiles
+//              as independent accumulator chains)
 //   sigma(Ia, Ib) += sign * T(m, Jb) for Ib = E_{r s} Jb, scattered from the
 //             accumulator registers into the LDS row with atomic adds.
 // Pair rows m: r <= s when the integrals are symmetric in rs (T(rs) = T(sr);
 // the one of E_rs / E_sr that does not vanish on Jb is applied), or all
 // ordered (r, s) when an S^2 penalty (not rs-symmetric) is folded in.
+// Scatter targets and signs are read from the beta single-substitution list
+// of Jb: the entry (p=a, q=b) of L1(Jb) is the string Jb - a + b.
+// The next tile of C is loaded into registers while the current one is
+// multiplied, so the gather latency hides behind the MFMA work.
 typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 
 constexpr int AB_TN = 64;
-constexpr int AB_LDD = AB_TN + 2;
 
-__device__ inline int rank32(uint64_t mask, const int* __restrict__ b32, int ldb)
-{
-    int r = 0, k = 1;
-    while (mask) {
-        int p = __builtin_ctzll(mask);
-        r += b32[p * ldb + k];
-        ++k;
-        mask &= mask - 1;
+struct MfmaF64 {
+    using elem = double;   // element stored in the D tile
+    using frag = double;   // MFMA operand of one lane
+    using acc = d4;
+    using lacc = double;   // LDS accumulator
+    static constexpr int K = 4;
+    static constexpr bool kmajor_tile = false;
+    __device__ static acc mma(frag a, frag b, acc c)
+    {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
     }
-    return r;
-}
+    // accumulator element v of a lane holds row 4*v + lane/16, column lane%16
+    __device__ static int row(int v, int lane) { return 4 * v + (lane >> 4); }
+    __device__ static elem cvt(double x) { return x; }
+};
 
-// scatter target of pair (r, s) acting on Jb; returns -1 if the operator vanishes
-__device__ inline int ab_target(uint64_t jb, int r, int s, int full, const int* b32, int ldb,
-                                int jb_index, int* sign)
+struct MfmaF32 {
+    using elem = float;
+    using frag = float;
+    using acc = f4;
+    using lacc = float;
+    static constexpr int K = 4;
+    static constexpr bool kmajor_tile = false;
+    __device__ static acc mma(frag a, frag b, acc c)
+    {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+    __device__ static int row(int v, int lane) { return 4 * (lane >> 4) + v; }
+    __device__ static elem cvt(double x) { return (float)x; }
+};
+
+struct MfmaBF16 {
+    using elem = __bf16;
+    using frag = bf8;
+    using acc = f4;
+    using lacc = float;
+    static constexpr int K = 32;
+    static constexpr bool kmajor_tile = true;  // tile stored [column][k]: 8 k per lane in one read
+    __device__ static acc mma(frag a, frag b, acc c)
+    {
+        return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+    }
+    __device__ static int row(int v, int lane) { return 4 * (lane >> 4) + v; }
+    __device__ static elem cvt(double x) { return (__bf16)(float)x; }
+};
+
+template <typename MF>
+struct TileLayout {
+    // D tile of Kp rows (k) x TN columns
+    __host__ __device__ static int ld(int Kp) { return MF::kmajor_tile ? Kp + 8 : AB_TN + 2; }
+    __host__ __device__ static int size(int Kp) { return MF::kmajor_tile ? AB_TN * (Kp + 8) : Kp * (AB_TN + 2); }
+    __device__ static int at(int k, int c, int Kp) { return MF::kmajor_tile ? c * (Kp + 8) + k : k * (AB_TN + 2) + c; }
+};
+
+// target and sign of the pair (r, s) acting on the beta string jb (column jcol)
+__device__ inline int ab_lookup(uint64_t jb, int r, int s, int full, int n, int nb_el, int sb,
+                                const int32_t* __restrict__ lb_j, int64_t jcol, int* sign)
 {
-    const int orr = (jb >> r) & 1, oss = (jb >> s) & 1;
     *sign = 1;
-    if (r == s) return orr ? jb_index : -1;
+    const int orr = (jb >> r) & 1, oss = (jb >> s) & 1;
+    if (r == s) return orr ? (int)jcol : -1;
+    int a, b;
     if (full) {
         if (!oss || orr) return -1;  // E_rs needs s occupied, r empty
+        a = s;
+        b = r;
     } else {
         if (orr == oss) return -1;   // exactly one of r, s occupied
+        a = oss ? s : r;
+        b = oss ? r : s;
     }
-    if (__popcll(jb & between_mask(r, s)) & 1) *sign = -1;
-    return rank32(jb ^ (1ull << r) ^ (1ull << s), b32, ldb);
+    const uint64_t nmask = (n >= 64) ? ~0ull : ((1ull << n) - 1);
+    const int pos = __popcll(jb & ((1ull << a) - 1)) * (n - nb_el + 1) +
+                    __popcll(~jb & nmask & ((1ull << b) - 1)) + (a < b ? 1 : 0);
+    const int32_t enc = lb_j[jcol * sb + pos];
+    *sign = l1_sign(enc);
+    return l1_index(enc);
 }
 
-template <int KBMAX, int MT>
-__global__ __launch_bounds__(1024) void k_ab_f64(AbParams p, const double* __restrict__ Vt,
-                                                 const double* __restrict__ C,
-                                                 double* __restrict__ sigma, int kb_count,
-                                                 int64_t chunk, int nchunks)
-{
-    extern __shared__ __align__(16) unsigned char smem[];
-    const int Kp = kb_count * 4;
-    const int ldb = p.nb + 2;
-    double* sig = reinterpret_cast<double*>(smem);
-    double* Dt = sig + chunk;
-    int* sJ = reinterpret_cast<int*>(Dt + (int64_t)Kp * AB_LDD);
-    int* b32 = sJ + Kp;
+constexpr int AB_MAX_WAVES = 12;
 
-    // XCD-aware order: consecutive alpha strings share most of their L1 rows
+template <typename MF, int KBMAX, int MT, int PF>
+__global__ __launch_bounds__(64 * AB_MAX_WAVES) void k_ab(AbParams p, const typename MF::elem* __restrict__ Vt,
+                                             const double* __restrict__ C, double* __restrict__ sigma,
+                                             int kb_count, int64_t chunk, int nchunks)
+{
+    using elem = typename MF::elem;
+    using lacc = typename MF::lacc;
+    using acc_t = typename MF::acc;
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int Kp = kb_count * MF::K;
+    lacc* sig = reinterpret_cast<lacc*>(smem);
+    elem* Dt = reinterpret_cast<elem*>(smem + ((chunk * sizeof(lacc) + 15) / 16) * 16);
+    int* sJ = reinterpret_cast<int*>(Dt + ((TileLayout<MF>::size(Kp) * (int)sizeof(elem) + 15) / 16) * 16 / sizeof(elem));
+
     const int64_t per_xcd = gridDim.x / 8;
     const int64_t t = (int64_t)(blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
     const int64_t nitems = p.Na * nchunks;
@@ -240,133 +364,559 @@ __global__ __launch_bounds__(1024) void k_ab_f64(AbParams p, const double* __res
     const int wave = tid >> 6, lane = tid & 63;
     const int nwaves = nth >> 6;
 
-    for (int64_t i = tid; i < hi - lo; i += nth) sig[i] = 0.0;
+    for (int64_t i = tid; i < hi - lo; i += nth) sig[i] = (lacc)0;
     for (int i = tid; i < Kp; i += nth) sJ[i] = i < p.sa ? l1_index(p.la_j[ia * p.sa + i]) : 0;
-    for (int i = tid; i < p.n * ldb; i += nth) {
-        int pp = i / ldb, kk = i - pp * ldb;
-        b32[i] = kk <= p.nb ? (int)p.binom[pp * (p.n + 1) + kk] : 0;
-    }
 
-    // 16x16x4 FP64 MFMA operands: lane holds A(m0 + lane%16, 4*kb + lane/16) and
-    // B(4*kb + lane/16, lane%16)
-    double afr[MT][KBMAX];
-    int pr_r[MT][4], pr_s[MT][4];
+    // A fragments and the pair (r, s) of each accumulator row this lane owns
+    typename MF::frag afr[MT][KBMAX];
+    int pr[MT][4];  // r | s << 8, or -1
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt) {
         const int m0 = (wave + mt * nwaves) * 16;
         const int m = m0 + (lane & 15);
 #pragma unroll
         for (int kb = 0; kb < KBMAX; ++kb) {
-            double v = 0.0;
-            const int e = kb * 4 + (lane >> 4);
-            if (kb < kb_count && e < p.sa && m < p.M) {
-                const int32_t enc = p.la_j[ia * p.sa + e];
-                const int pq = p.la_pq[ia * p.sa + e];
-                const int pqi = (pq & 0xff) * p.n + (pq >> 8);
-                v = Vt[(int64_t)pqi * p.Mp + m] * l1_sign(enc);
+            typename MF::frag f;
+            constexpr int PER = MF::K / 4;  // operand elements per lane
+#pragma unroll
+            for (int q = 0; q < PER; ++q) {
+                const int e = kb * MF::K + (lane >> 4) * PER + q;
+                elem v = MF::cvt(0.0);
+                if (kb < kb_count && e < p.sa && m < p.M) {
+                    const int32_t enc = p.la_j[ia * p.sa + e];
+                    const int pq = p.la_pq[ia * p.sa + e];
+                    const int pqi = (pq & 0xff) * p.n + (pq >> 8);
+                    v = Vt[(int64_t)pqi * p.Mp + m];
+                    if (l1_sign(enc) < 0) v = -v;
+                }
+                if constexpr (PER == 1) f = v; else f[q] = v;
             }
-            afr[mt][kb] = v;
+            afr[mt][kb] = f;
         }
-        // accumulator element v of a lane holds row 4*v + lane/16, column lane%16
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-            const int mm = m0 + 4 * v + (lane >> 4);
-            const int code = mm < p.M ? p.pairs[mm] : 0xffff;
-            pr_r[mt][v] = mm < p.M ? (code & 0xff) : -1;
-            pr_s[mt][v] = code >> 8;
+            const int mm = m0 + MF::row(v, lane);
+            pr[mt][v] = mm < p.M ? (int)p.pairs[mm] : -1;
         }
     }
     __syncthreads();
 
-    for (int64_t j0 = 0; j0 < p.Nb; j0 += AB_TN) {
-        // gather D tile: rows J_e of C, columns [j0, j0+TN)
-        for (int i = tid; i < Kp * AB_TN; i += nth) {
-            const int k = i / AB_TN, cidx = i - k * AB_TN;
-            const int64_t jb = j0 + cidx;
+    const int tile_elems = Kp * AB_TN;
+    double pf[PF];
+    auto load_tile = [&](int64_t j0) {
+#pragma unroll
+        for (int i = 0; i < PF; ++i) {
+            const int idx = tid + i * nth;
+            const int k = idx / AB_TN, c = idx - k * AB_TN;
             double v = 0.0;
-            if (k < p.sa && jb < p.Nb) v = C[(int64_t)sJ[k] * p.Nb + jb];
-            Dt[k * AB_LDD + cidx] = v;
+            if (idx < tile_elems && k < p.sa && j0 + c < p.Nb) v = C[(int64_t)sJ[k] * p.Nb + j0 + c];
+            pf[i] = v;
         }
-        __syncthreads();
+    };
+    auto store_tile = [&]() {
+#pragma unroll
+        for (int i = 0; i < PF; ++i) {
+            const int idx = tid + i * nth;
+            if (idx < tile_elems) {
+                const int k = idx / AB_TN, c = idx - k * AB_TN;
+                Dt[TileLayout<MF>::at(k, c, Kp)] = MF::cvt(pf[i]);
+            }
+        }
+    };
+    load_tile(0);
+    store_tile();
+    __syncthreads();
+
+    for (int64_t j0 = 0; j0 < p.Nb; j0 += AB_TN) {
+        const bool more = j0 + AB_TN < p.Nb;
+        if (more) load_tile(j0 + AB_TN);
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt) {
             const int mtile = wave + mt * nwaves;
             if (mtile * 16 >= p.Mp) continue;
-            for (int ns = 0; ns < AB_TN / 16; ++ns) {
-                const int64_t jcol = j0 + ns * 16 + (lane & 15);
-                if (j0 + ns * 16 >= p.Nb) break;
-                d4 acc = {0.0, 0.0, 0.0, 0.0};
+            acc_t acc[4];
 #pragma unroll
-                for (int kb = 0; kb < KBMAX; ++kb) {
-                    if (kb < kb_count) {
-                        const double b = Dt[(kb * 4 + (lane >> 4)) * AB_LDD + ns * 16 + (lane & 15)];
-                        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(afr[mt][kb], b, acc, 0, 0, 0);
+            for (int ns = 0; ns < 4; ++ns)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) acc[ns][v] = 0;
+#pragma unroll
+            for (int kb = 0; kb < KBMAX; ++kb) {
+                if (kb < kb_count) {
+#pragma unroll
+                    for (int ns = 0; ns < 4; ++ns) {
+                        typename MF::frag b;
+                        const int c = ns * 16 + (lane & 15);
+                        if constexpr (MF::kmajor_tile) {
+                            b = *reinterpret_cast<const typename MF::frag*>(
+                                &Dt[TileLayout<MF>::at(kb * MF::K + (lane >> 4) * (MF::K / 4), c, Kp)]);
+                        } else {
+                            b = Dt[TileLayout<MF>::at(kb * MF::K + (lane >> 4), c, Kp)];
+                        }
+                        acc[ns] = MF::mma(afr[mt][kb], b, acc[ns]);
                     }
                 }
-                if (jcol < p.Nb) {
-                    const uint64_t jb = p.bstr[jcol];
+            }
+            // scatter: target string and sign from the beta list of column Jb
 #pragma unroll
-                    for (int v = 0; v < 4; ++v) {
-                        if (pr_r[mt][v] < 0) continue;
-                        int sg;
-                        const int tgt = ab_target(jb, pr_r[mt][v], pr_s[mt][v], p.full, b32, ldb,
-                                                  (int)jcol, &sg);
-                        if (tgt >= lo && tgt < hi) atomicAdd(&sig[tgt - lo], sg * acc[v]);
+            for (int ns = 0; ns < 4; ++ns) {
+                const int64_t jcol = j0 + ns * 16 + (lane & 15);
+                if (jcol >= p.Nb) continue;
+                const uint64_t jb = p.bstr[jcol];
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int code = pr[mt][v];
+                    if (code < 0) continue;
+                    int sg;
+                    const int tg = ab_lookup(jb, code & 0xff, code >> 8, p.full, p.n, p.nb, p.sb, p.lb_j,
+                                             jcol, &sg);
+                    if (tg >= lo && tg < hi) {
+                        const lacc x = (lacc)acc[ns][v];
+                        atomicAdd(&sig[tg - lo], sg > 0 ? x : -x);
                     }
                 }
             }
         }
         __syncthreads();
+        if (more) store_tile();
+        __syncthreads();
     }
     double* srow = sigma + ia * p.Nb;
-    for (int64_t i = tid; i < hi - lo; i += nth) srow[lo + i] += sig[i];
+    for (int64_t i = tid; i < hi - lo; i += nth) srow[lo + i] += (double)sig[i];
 }
 
-static int64_t ab_lds_bytes(const AbParams& p, int kb_count, int64_t chunk, int elt)
+// ---------------------------------------------------------------------------
+// low-precision alpha-beta contraction (FP32 or BF16 MFMA, FP32 accumulate)
+// ---------------------------------------------------------------------------
+// Same algorithm as k_ab, tuned for the case where the MFMA work is cheap:
+// C is first converted once per sigma to the MFMA input type with its rows
+// padded to a multiple of 16 bytes, so D tiles are gathered with 16-byte
+// loads (a BF16 tile row of 64 columns is one 128-byte line); the tiles are
+// double-buffered in LDS and the sigma row is accumulated in FP32, which
+// keeps one workgroup under 80 KB of LDS so that two share a CU and hide each
+// other's gather and scatter latency.
+constexpr int ABL_MAX_WAVES = 12;
+
+// scatter target from an LDS copy of the tile's beta list rows (row = column cl)
+__device__ inline int ab_lookup_lds(uint64_t jb, int r, int s, int full, int n, int nb_el, int sb,
+                                    const int32_t* __restrict__ Lt, int cl, int64_t jcol, int* sign)
 {
-    return chunk * elt + (int64_t)kb_count * 4 * AB_LDD * 8 + kb_count * 4 * 4 +
-           (int64_t)p.n * (p.nb + 2) * 4 + 64;
+    *sign = 1;
+    const int orr = (jb >> r) & 1, oss = (jb >> s) & 1;
+    if (r == s) return orr ? (int)jcol : -1;
+    int a, b;
+    if (full) {
+        if (!oss || orr) return -1;
+        a = s;
+        b = r;
+    } else {
+        if (orr == oss) return -1;
+        a = oss ? s : r;
+        b = oss ? r : s;
+    }
+    const uint64_t nmask = (n >= 64) ? ~0ull : ((1ull << n) - 1);
+    const int pos = __popcll(jb & ((1ull << a) - 1)) * (n - nb_el + 1) +
+                    __popcll(~jb & nmask & ((1ull << b) - 1)) + (a < b ? 1 : 0);
+    const int32_t enc = Lt[cl * sb + pos];
+    *sign = l1_sign(enc);
+    return l1_index(enc);
+}
+
+template <typename MF, int KBMAX, int MT, int SPT>
+__global__ __launch_bounds__(64 * ABL_MAX_WAVES) void k_ab_lp(
+    AbParams p, const typename MF::elem* __restrict__ Vt, const typename MF::elem* __restrict__ Cs,
+    int64_t ldc, double* __restrict__ sigma, int kb_count, int64_t chunk, int nchunks)
+{
+    using elem = typename MF::elem;
+    using acc_t = typename MF::acc;
+    using vec_t = uint4;  // 16 bytes
+    constexpr int VEC = 16 / sizeof(elem);
+    constexpr int SEGS = AB_TN / VEC;  // 16-byte segments per tile row
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int Kp = kb_count * MF::K;
+    const int tsz = ((TileLayout<MF>::size(Kp) * (int)sizeof(elem) + 15) / 16) * 16;
+    const int lsz = AB_TN * p.sb * 4;  // list rows of one tile (multiple of 256 bytes)
+    float* sig = reinterpret_cast<float*>(smem);
+    unsigned char* base = smem + ((chunk * 4 + 15) / 16) * 16;
+    elem* Dt0 = reinterpret_cast<elem*>(base);
+    elem* Dt1 = reinterpret_cast<elem*>(base + tsz);
+    int32_t* Lt0 = reinterpret_cast<int32_t*>(base + 2 * tsz);
+    int32_t* Lt1 = reinterpret_cast<int32_t*>(base + 2 * tsz + lsz);
+    uint64_t* sB = reinterpret_cast<uint64_t*>(base + 2 * tsz + 2 * lsz);  // [2][TN]
+    int* sJ = reinterpret_cast<int*>(sB + 2 * AB_TN);
+
+    const int64_t per_xcd = gridDim.x / 8;
+    const int64_t t = (int64_t)(blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
+    const int64_t nitems = p.Na * nchunks;
+    if (t >= nitems) return;
+    const int64_t ia = t / nchunks;
+    const int64_t lo = (t - ia * nchunks) * chunk;
+    const int64_t hi = min(lo + chunk, p.Nb);
+    const int tid = threadIdx.x, nth = blockDim.x;
+    const int wave = tid >> 6, lane = tid & 63;
+    const int nwaves = nth >> 6;
+
+    for (int64_t i = tid; i < hi - lo; i += nth) sig[i] = 0.f;
+    for (int i = tid; i < Kp; i += nth) sJ[i] = i < p.sa ? l1_index(p.la_j[ia * p.sa + i]) : -1;
+
+    typename MF::frag afr[MT][KBMAX];
+    int pr[MT][4];
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) {
+        const int m0 = (wave + mt * nwaves) * 16;
+        const int m = m0 + (lane & 15);
+#pragma unroll
+        for (int kb = 0; kb < KBMAX; ++kb) {
+            typename MF::frag f;
+            constexpr int PER = MF::K / 4;
+#pragma unroll
+            for (int q = 0; q < PER; ++q) {
+                const int e = kb * MF::K + (lane >> 4) * PER + q;
+                elem v = MF::cvt(0.0);
+                if (kb < kb_count && e < p.sa && m < p.M) {
+                    const int32_t enc = p.la_j[ia * p.sa + e];
+                    const int pq = p.la_pq[ia * p.sa + e];
+                    v = Vt[(int64_t)((pq & 0xff) * p.n + (pq >> 8)) * p.Mp + m];
+                    if (l1_sign(enc) < 0) v = -v;
+                }
+                if constexpr (PER == 1) f = v; else f[q] = v;
+            }
+            afr[mt][kb] = f;
+        }
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int mm = m0 + MF::row(v, lane);
+            pr[mt][v] = mm < p.M ? (int)p.pairs[mm] : -1;
+        }
+    }
+    __syncthreads();
+
+    // One tile: Kp x SEGS segments of C plus the TN list rows (contiguous in
+    // memory). issue() starts the global loads into registers, commit() stores
+    // them to the idle LDS buffers after this tile's MFMA work.
+    const int nseg = Kp * SEGS;
+    const int nlseg = lsz / 16;
+    const int ntot = nseg + nlseg;
+    vec_t pf[SPT];
+    uint64_t pfb = 0;
+    const int64_t list_end = p.Nb * (int64_t)p.sb;  // in int32
+    auto issue = [&](int64_t j0) {
+#pragma unroll
+        for (int q = 0; q < SPT; ++q) {
+            const int sidx = tid + q * nth;
+            vec_t v = {0u, 0u, 0u, 0u};
+            if (sidx < nseg) {
+                const int k = sidx / SEGS, sg = sidx - k * SEGS;
+                const int64_t col = j0 + sg * VEC;
+                const int J = sJ[k];
+                if (J >= 0 && col < ldc) v = *reinterpret_cast<const vec_t*>(Cs + J * ldc + col);
+            } else if (sidx < ntot) {
+                const int64_t off = j0 * p.sb + (int64_t)(sidx - nseg) * 4;
+                if (off < list_end) v = *reinterpret_cast<const vec_t*>(p.lb_j + off);
+            }
+            pf[q] = v;
+        }
+        pfb = (tid < AB_TN && j0 + tid < p.Nb) ? p.bstr[j0 + tid] : 0ull;
+    };
+    auto commit = [&](elem* Dt, int32_t* Lt, uint64_t* sb) {
+#pragma unroll
+        for (int q = 0; q < SPT; ++q) {
+            const int sidx = tid + q * nth;
+            if (sidx < nseg) {
+                const int k = sidx / SEGS, sg = sidx - k * SEGS;
+                const elem* ve = reinterpret_cast<const elem*>(&pf[q]);
+#pragma unroll
+                for (int e = 0; e < VEC; ++e) Dt[TileLayout<MF>::at(k, sg * VEC + e, Kp)] = ve[e];
+            } else if (sidx < ntot) {
+                *reinterpret_cast<vec_t*>(Lt + (sidx - nseg) * 4) = pf[q];
+            }
+        }
+        if (tid < AB_TN) sb[tid] = pfb;
+    };
+    issue(0);
+    commit(Dt0, Lt0, sB);
+    __syncthreads();
+
+    int buf = 0;
+    for (int64_t j0 = 0; j0 < p.Nb; j0 += AB_TN) {
+        elem* Dt = buf ? Dt1 : Dt0;
+        const int32_t* Lt = buf ? Lt1 : Lt0;
+        const uint64_t* sb = sB + buf * AB_TN;
+        const bool more = j0 + AB_TN < p.Nb;
+        if (more) issue(j0 + AB_TN);
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) {
+            const int mtile = wave + mt * nwaves;
+            if (mtile * 16 >= p.Mp) continue;
+            acc_t acc[4];
+#pragma unroll
+            for (int ns = 0; ns < 4; ++ns)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) acc[ns][v] = 0.f;
+#pragma unroll
+            for (int kb = 0; kb < KBMAX; ++kb) {
+                if (kb < kb_count) {
+#pragma unroll
+                    for (int ns = 0; ns < 4; ++ns) {
+                        typename MF::frag b;
+                        const int c = ns * 16 + (lane & 15);
+                        if constexpr (MF::kmajor_tile) {
+                            b = *reinterpret_cast<const typename MF::frag*>(
+                                &Dt[TileLayout<MF>::at(kb * MF::K + (lane >> 4) * (MF::K / 4), c, Kp)]);
+                        } else {
+                            b = Dt[TileLayout<MF>::at(kb * MF::K + (lane >> 4), c, Kp)];
+                        }
+                        acc[ns] = MF::mma(afr[mt][kb], b, acc[ns]);
+                    }
+                }
+            }
+#pragma unroll
+            for (int ns = 0; ns < 4; ++ns) {
+                const int cl = ns * 16 + (lane & 15);
+                const int64_t jcol = j0 + cl;
+                if (jcol >= p.Nb) continue;
+                const uint64_t jb = sb[cl];
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int code = pr[mt][v];
+                    if (code < 0) continue;
+                    int sg;
+                    const int tg = ab_lookup_lds(jb, code & 0xff, code >> 8, p.full, p.n, p.nb, p.sb, Lt, cl,
+                                                 jcol, &sg);
+                    if (tg >= lo && tg < hi) {
+                        const float x = acc[ns][v];
+                        atomicAdd(&sig[tg - lo], sg > 0 ? x : -x);
+                    }
+                }
+            }
+        }
+        if (more) commit(buf ? Dt0 : Dt1, buf ? Lt0 : Lt1, sB + (1 - buf) * AB_TN);
+        __syncthreads();
+        buf ^= 1;
+    }
+    double* srow = sigma + ia * p.Nb;
+    for (int64_t i = tid; i < hi - lo; i += nth) srow[lo + i] += (double)sig[i];
+}
+
+template <typename MF>
+static int64_t abl_lds_bytes(int kb_count, int sb, int64_t chunk)
+{
+    const int Kp = kb_count * MF::K;
+    int64_t b = (chunk * 4 + 15) / 16 * 16;
+    b += 2 * (((int64_t)TileLayout<MF>::size(Kp) * sizeof(typename MF::elem) + 15) / 16 * 16);
+    b += 2 * (int64_t)AB_TN * sb * 4;
+    b += 2 * AB_TN * 8 + (int64_t)Kp * 4 + 64;
+    return b;
+}
+
+template <typename MF>
+static hipError_t abl_launch(const AbParams& p, const void* Vt, const void* Cs, int64_t ldc,
+                             double* sigma, hipStream_t st)
+{
+    if (p.Na <= 0 || p.Nb <= 0 || p.sa <= 0 || p.M <= 0) return hipSuccess;
+    const int kb_count = (p.sa + MF::K - 1) / MF::K;
+    const int mtiles = p.Mp / 16;
+    const int MT = mtiles <= ABL_MAX_WAVES ? 1 : 2;
+    int nwaves = (mtiles + MT - 1) / MT;
+    if (nwaves > ABL_MAX_WAVES) return invalid("alpha-beta: too many pair rows (norb too large)");
+    if (nwaves < 2) nwaves = 2;  // more loaders for tiny pair counts
+    // two workgroups per CU when the sigma row allows it
+    const int64_t fixed = abl_lds_bytes<MF>(kb_count, p.sb, 0);
+    int64_t cap = 80 * 1024 - 256;
+    if (fixed + p.Nb * 4 > cap) cap = 160 * 1024 - 512;
+    int64_t chunk = (cap - fixed) / 4;
+    if (chunk < 256) return invalid("alpha-beta: LDS too small for the sigma row chunk");
+    int nchunks = (int)((p.Nb + chunk - 1) / chunk);
+    chunk = (p.Nb + nchunks - 1) / nchunks;
+    const size_t lds = (size_t)abl_lds_bytes<MF>(kb_count, p.sb, chunk);
+    const int nseg = kb_count * MF::K * (AB_TN * (int)sizeof(typename MF::elem) / 16) + AB_TN * p.sb / 4;
+    const int spt = (nseg + 64 * nwaves - 1) / (64 * nwaves);
+    if (spt > 8) return invalid("alpha-beta: tile larger than the prefetch registers");
+    const int64_t items = p.Na * nchunks;
+    const int64_t grid = (items + 7) / 8 * 8;
+    dim3 blk(64 * nwaves);
+#define ABL_GO(KBV, MTV, SPTV)                                                                      \
+    {                                                                                               \
+        auto kern = k_ab_lp<MF, KBV, MTV, SPTV>;                                                    \
+        hipError_t e = hipFuncSetAttribute((const void*)kern,                                       \
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);   \
+        if (e != hipSuccess) {                                                                      \
+            g_launch_reason = "hipFuncSetAttribute(max dynamic LDS) failed";                        \
+            return e;                                                                               \
+        }                                                                                           \
+        hipLaunchKernelGGL(kern, dim3((unsigned)grid), blk, lds, st, p,                             \
+                           (const typename MF::elem*)Vt, (const typename MF::elem*)Cs, ldc, sigma,  \
+                           kb_count, chunk, nchunks);                                               \
+        return hipGetLastError();                                                                   \
+    }
+#define ABL_KB(KBV, MTV)                                                                            \
+    if (kb_count <= KBV && MT == MTV) {                                                             \
+        if (spt <= 2) ABL_GO(KBV, MTV, 2)                                                           \
+        if (spt <= 4) ABL_GO(KBV, MTV, 4)                                                           \
+        ABL_GO(KBV, MTV, 8)                                                                         \
+    }
+    if constexpr (MF::K == 4) {
+        ABL_KB(3, 1)
+        ABL_KB(5, 1)
+        ABL_KB(8, 1)
+        ABL_KB(11, 1)
+        ABL_KB(14, 1)
+        ABL_KB(18, 1)
+        ABL_KB(23, 1)
+        ABL_KB(14, 2)
+        ABL_KB(18, 2)
+        ABL_KB(23, 2)
+    } else {
+        ABL_KB(1, 1)
+        ABL_KB(2, 1)
+        ABL_KB(3, 1)
+        ABL_KB(4, 1)
+        ABL_KB(3, 2)
+        ABL_KB(4, 2)
+    }
+#undef ABL_KB
+#undef ABL_GO
+    return invalid("alpha-beta: no kernel variant for this K-block count");
+}
+
+// C (FP64, rows x cols) -> padded copy in the MFMA input type, row stride ld
+template <typename T>
+__global__ void k_convert_pad(const double* __restrict__ C, T* __restrict__ out, int64_t rows,
+                              int64_t cols, int64_t ld)
+{
+    const int64_t total = rows * ld;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t r = i / ld, c = i - r * ld;
+        out[i] = c < cols ? (T)(float)C[r * cols + c] : (T)0.f;
+    }
+}
+
+template <typename MF>
+static int64_t ab_lds_bytes(int kb_count, int64_t chunk)
+{
+    const int Kp = kb_count * MF::K;
+    int64_t b = (chunk * (int64_t)sizeof(typename MF::lacc) + 15) / 16 * 16;
+    b += ((int64_t)TileLayout<MF>::size(Kp) * sizeof(typename MF::elem) + 15) / 16 * 16;
+    b += (int64_t)Kp * 4 + 64;
+    return b;
+}
+
+template <typename MF, int KB, int MTV>
+static hipError_t ab_launch_pf(const AbParams& p, const void* Vt, const double* C, double* sigma,
+                               int kb_count, int64_t chunk, int nchunks, int nwaves, int pf,
+                               hipStream_t st)
+{
+    const size_t lds = (size_t)ab_lds_bytes<MF>(kb_count, chunk);
+    const int64_t items = p.Na * nchunks;
+    const int64_t grid = (items + 7) / 8 * 8;
+    dim3 blk(64 * nwaves);
+#define AB_PF(PFV)                                                                                  \
+    if (pf <= PFV) {                                                                                \
+        auto kern = k_ab<MF, KB, MTV, PFV>;                                                         \
+        hipError_t e = hipFuncSetAttribute((const void*)kern,                                       \
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);   \
+        if (e != hipSuccess) {                                                                      \
+            g_launch_reason = "hipFuncSetAttribute(max dynamic LDS) failed";                        \
+            return e;                                                                               \
+        }                                                                                           \
+        hipLaunchKernelGGL(kern, dim3((unsigned)grid), blk, lds, st, p,                             \
+                           (const typename MF::elem*)Vt, C, sigma, kb_count, chunk, nchunks);       \
+        return hipGetLastError();                                                                   \
+    }
+    AB_PF(4)
+    AB_PF(8)
+    AB_PF(12)
+    AB_PF(16)
+#undef AB_PF
+    return invalid("alpha-beta: prefetch depth above 16");
+}
+
+template <typename MF>
+static hipError_t ab_launch(const AbParams& p, const void* Vt, const double* C, double* sigma,
+                            hipStream_t st)
+{
+    if (p.Na <= 0 || p.Nb <= 0 || p.sa <= 0 || p.M <= 0) return hipSuccess;
+    const int kb_count = (p.sa + MF::K - 1) / MF::K;
+    const int mtiles = p.Mp / 16;
+    const int MT = mtiles > AB_MAX_WAVES ? 2 : 1;
+    const int nwaves = (mtiles + MT - 1) / MT;
+    if (nwaves > AB_MAX_WAVES) return invalid("alpha-beta: too many pair rows (norb too large)");
+    const int64_t lds_cap = 160 * 1024 - 512;
+    const int64_t fixed = ab_lds_bytes<MF>(kb_count, 0);
+    int64_t chunk = (lds_cap - fixed) / (int64_t)sizeof(typename MF::lacc);
+    if (chunk < 256) return invalid("alpha-beta: LDS too small for the sigma row chunk");
+    int nchunks = (int)((p.Nb + chunk - 1) / chunk);
+    chunk = (p.Nb + nchunks - 1) / nchunks;
+    const int nth = 64 * nwaves;
+    const int pf = (kb_count * MF::K * AB_TN + nth - 1) / nth;
+    if (pf > 16) return invalid("alpha-beta: prefetch depth above 16");
+    constexpr int KS = MF::K;
+#define AB_KB(KBV, MTV)                                                                             \
+    if (kb_count <= KBV && MT == MTV)                                                               \
+        return ab_launch_pf<MF, KBV, MTV>(p, Vt, C, sigma, kb_count, chunk, nchunks, nwaves, pf, st);
+    if constexpr (KS == 4) {
+        // exact K-block counts of the common active spaces (n = 6..18) keep
+        // the A fragments in registers without dead slots
+        AB_KB(3, 1)
+        AB_KB(5, 1)
+        AB_KB(8, 1)
+        AB_KB(11, 1)
+        AB_KB(14, 1)
+        AB_KB(18, 1)
+        AB_KB(23, 1)
+        AB_KB(28, 1)
+        AB_KB(32, 1)
+        AB_KB(8, 2)
+        AB_KB(14, 2)
+        AB_KB(18, 2)
+        AB_KB(23, 2)
+    } else {
+        AB_KB(1, 1)
+        AB_KB(2, 1)
+        AB_KB(3, 1)
+        AB_KB(4, 1)
+        AB_KB(2, 2)
+        AB_KB(3, 2)
+        AB_KB(4, 2)
+    }
+#undef AB_KB
+    return invalid("alpha-beta: no kernel variant for this K-block count");
 }
 
 hipError_t launch_ab_f64(const AbParams& p, const double* Vt, const double* C, double* sigma,
                          hipStream_t st)
 {
-    if (p.Na <= 0 || p.Nb <= 0 || p.sa <= 0 || p.M <= 0) return hipSuccess;
-    const int kb_count = (p.sa + 3) / 4;
-    const int mtiles = p.Mp / 16;
-    const int MT = mtiles > 16 ? 2 : 1;
-    const int nwaves = (mtiles + MT - 1) / MT;
-    if (nwaves > 16) return hipErrorInvalidValue;
-    const int64_t lds_cap = 160 * 1024 - 1024;
-    int64_t fixed = ab_lds_bytes(p, kb_count, 0, 8);
-    int64_t chunk = (lds_cap - fixed) / 8;
-    if (chunk < 256) return hipErrorInvalidValue;
-    int nchunks = (int)((p.Nb + chunk - 1) / chunk);
-    chunk = (p.Nb + nchunks - 1) / nchunks;
-    const size_t lds = (size_t)ab_lds_bytes(p, kb_count, chunk, 8);
-    const int64_t items = p.Na * nchunks;
-    const int64_t grid = (items + 7) / 8 * 8;
-    dim3 blk(64 * nwaves);
-#define AB_CASE(KB, MTV)                                                                         \
-    if (kb_count <= KB && MT == MTV) {                                                           \
-        hipFuncSetAttribute((const void*)k_ab_f64<KB, MTV>,                                      \
-                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);               \
-        hipLaunchKernelGGL((k_ab_f64<KB, MTV>), dim3((unsigned)grid), blk, lds, st, p, Vt, C,    \
-                           sigma, kb_count, chunk, nchunks);                                     \
-        return hipGetLastError();                                                                \
-    }
-    AB_CASE(4, 1)
-    AB_CASE(8, 1)
-    AB_CASE(12, 1)
-    AB_CASE(16, 1)
-    AB_CASE(24, 1)
-    AB_CASE(32, 1)
-    AB_CASE(8, 2)
-    AB_CASE(16, 2)
-    AB_CASE(24, 2)
-    AB_CASE(32, 2)
-#undef AB_CASE
-    return hipErrorInvalidValue;
+    return ab_launch<MfmaF64>(p, Vt, C, sigma, st);
+}
+
+hipError_t launch_ab_lowp(const AbParams& p, int prec, const void* Vt, const void* Cs, int64_t ldc,
+                          double* sigma, hipStream_t st)
+{
+    if (prec == 1) return abl_launch<MfmaF32>(p, Vt, Cs, ldc, sigma, st);
+    if (prec == 2) return abl_launch<MfmaBF16>(p, Vt, Cs, ldc, sigma, st);
+    return invalid("alpha-beta: unknown precision");
+}
+
+int64_t lowp_ld(int prec, int64_t cols)
+{
+    const int64_t v = prec == 1 ? 4 : 8;  // elements per 16 bytes
+    return (cols + v - 1) / v * v;
+}
+
+hipError_t launch_convert_lowp(int prec, const double* C, void* out, int64_t rows, int64_t cols,
+                               int64_t ld, hipStream_t st)
+{
+    const int64_t total = rows * ld;
+    if (total <= 0) return hipSuccess;
+    int64_t g = (total + 255) / 256;
+    if (g > 16384) g = 16384;
+    if (prec == 1)
+        hipLaunchKernelGGL(k_convert_pad<float>, dim3((unsigned)g), dim3(256), 0, st, C, (float*)out, rows,
+                           cols, ld);
+    else
+        hipLaunchKernelGGL(k_convert_pad<__bf16>, dim3((unsigned)g), dim3(256), 0, st, C, (__bf16*)out, rows,
+                           cols, ld);
+    return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
@@ -417,9 +967,5 @@ hipError_t launch_axpby_f64(double a, const double* x, double b, double* y, int6
     return hipGetLastError();
 }
 
-hipError_t launch_ab_lowp(const AbParams&, int, const void*, const double*, double*, hipStream_t)
-{
-    return hipErrorNotSupported;
-}
 
 }  // namespace casci

@@ -261,3 +261,55 @@ def test_spin_square_of_oracle_vectors(torch):
     E, X, s2 = oracle_roots(h, eri, na, nb, 6)
     for k in range(6):
         assert abs(c.spin_square(np.ascontiguousarray(X[k])) - s2[k]) < 1e-10
+
+
+# --------------------------------------------------------------------------
+# mixed precision
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("n,na,nb", [(2, 1, 1), (4, 2, 2), (6, 3, 3), (7, 4, 3), (9, 5, 4), (10, 5, 5),
+                                     (12, 1, 1), (6, 6, 5)])
+def test_sigma_low_precision_error_bounds(torch, n, na, nb):
+    """FP32 / BF16 alpha-beta arithmetic (FP32 accumulation): the error against
+    the FP64 oracle stays within what the input rounding allows (unit roundoff
+    2^-24 and 2^-8 times the accumulated magnitudes)."""
+    c, h, eri = make(n, na, nb, 100 + n + na)
+    d = c.dims
+    C = synth.ci_vector(d["Na"], d["Nb"], 5)[0]
+    ref = oracle.sigma(h, eri, na, nb, C)
+    Ct = torch.from_numpy(C).cuda()
+    e32 = rel_err(c.sigma(Ct, ab_prec="f32").cpu().numpy(), ref)
+    e16 = rel_err(c.sigma(Ct, ab_prec="bf16").cpu().numpy(), ref)
+    assert e32 < 2e-6, e32
+    assert e16 < 2e-2, e16
+    if n > 1:
+        assert e16 > e32  # the BF16 path really is a different arithmetic
+
+
+@pytest.mark.parametrize("prec", ["f32", "bf16"])
+def test_mixed_precision_davidson_reaches_fp64_energies(torch, prec):
+    """Low-precision sigma first, FP64 sigma in the final iterations: the
+    reported energies are FP64 Rayleigh quotients and match LAPACK."""
+    n, na, nb, k = 8, 4, 4, 3
+    c, h, eri = make(n, na, nb, 3000)
+    Eo, _, _ = oracle_roots(h, eri, na, nb, k)
+    E, _, info = c.davidson(k, 1e-11, ab_prec=prec, r_tol=1e-7, vectors=False)
+    assert info["converged"]
+    assert info["switch_iter"] >= 0
+    assert info["sigma_calls_fp64"] < info["sigma_calls"]
+    assert np.abs(E - Eo).max() < 1e-10
+
+
+def test_davidson_parity_path_cas10_vs_eigsh(torch):
+    """nalpha = nbeta with spin ANY: every basis vector carries a transposition
+    parity and sigma uses one same-spin gather; energies of both parities match."""
+    import scipy.sparse.linalg as sla
+    n = 10
+    c, h, eri = make(n, 5, 5, 77)
+    Hs = oracle.hamiltonian_csr(h, eri, 5, 5)
+    Eo = np.sort(sla.eigsh(Hs, k=5, which="SA", tol=1e-13)[0])
+    E, X, info = c.davidson(5, 1e-11, r_tol=1e-7)
+    assert info["converged"]
+    assert np.abs(E - Eo).max() < 1e-10
+    pars = [float(np.sum(x * x.T)) for x in X]
+    assert all(abs(abs(p) - 1) < 1e-8 for p in pars)
+    assert any(p < 0 for p in pars) and any(p > 0 for p in pars)
