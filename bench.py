@@ -57,6 +57,33 @@ def time_to_threshold(hist_e, hist_t, eref, thr=1e-8):
     return float("nan"), -1
 
 
+def sigma_only(args, casci, h, eri, n, na, nb):
+    """Repeated sigma builds on a seeded normalised vector (for kernel profiling)."""
+    import torch
+    ctx = casci.Context(0)
+    ctx.set_integrals(h, eri)
+    ctx.build_strings(na, nb, n)
+    d = ctx.dims
+    g = torch.Generator(device="cuda").manual_seed(50)
+    C = torch.randn(d["Na"], d["Nb"], dtype=torch.float64, device="cuda", generator=g)
+    C /= C.norm()
+    S = torch.empty_like(C)
+    for _ in range(args.warmup):
+        ctx.sigma(C, out=S, ab_prec=args.sigma_only)
+    torch.cuda.synchronize()
+    ctx.profile(True)
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        ctx.sigma(C, out=S, ab_prec=args.sigma_only)
+        torch.cuda.synchronize()
+        log("[sigma] build %d done" % i)
+    dt = (time.perf_counter() - t0) / max(args.steps, 1)
+    P = ctx.profile_read()
+    k = max(P["sigma_builds"], 1)
+    print(json.dumps({"sigma_only": args.sigma_only, "workload": args.workload, "ms_per_sigma": dt * 1e3,
+                      "parts_ms": {x: P[x] / k for x in ("aa_ms", "bb_ms", "bb_transpose_ms", "ab_ms")}}))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -65,6 +92,8 @@ def main():
     ap.add_argument("--workload", default="cas16", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--sigma-only", default=None, choices=["f64", "f32", "bf16"],
+                    help="profiling aid: only run --steps sigma builds of the workload in this precision")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build runs on exactly one GPU (the string-CASCI path is measured "
@@ -79,6 +108,10 @@ def main():
     h, eri, _ = synth.integrals(n, seed)
     penalty = 1.0 if spin == "singlet" else 0.0
     common = dict(spin=spin, s2_penalty=penalty)
+
+    if args.sigma_only:
+        sigma_only(args, casci, h, eri, n, na, nb)
+        return
 
     # reference energies: tight FP64 run (untimed)
     log("[bench] reference FP64 solve %s" % args.workload)

@@ -180,7 +180,8 @@ typedef struct {
     int precond;            /* CASCI_PRECOND_* */
     int spin;               /* CASCI_SPIN_* */
     int ab_prec;            /* alpha-beta arithmetic in the first phase (CASCI_F64/F32/BF16) */
-    double refine_rnorm;    /* switch sigma to FP64 once max residual < this (<= 0: 1e-2 BF16, 1e-4 F32) */
+    double refine_rnorm;    /* switch sigma to FP64 once max residual < this (<= 0: 2e-2 BF16, 2e-5 F32);
+                               also after 8 iterations without halving the best residual */
     double r_tol;           /* residual threshold; <= 0 -> max(1e-6, sqrt(tol)/10) */
     double s2_penalty;      /* lambda of H + lambda S^2 for CASCI_SPIN_SINGLET (< 0 -> 0) */
     const double* guess;    /* optional [nguess][Ndet] FP64 start vectors (host or device) */
@@ -225,6 +226,68 @@ typedef struct {
  */
 int casci_davidson(casci_ctx* ctx, int nroots, double tol, const casci_davidson_opts* opts,
                    double* energies, void* vectors, int mem, casci_davidson_info* info);
+
+/* ------------------------------------------------------------------------
+ * Learned Davidson preconditioner (CASCI_PRECOND_MLP). A per-determinant
+ * network 8 -> 64 -> 64 -> 1 (tanh, FP32) predicts the correction vector
+ * from features of the determinant and of the current Ritz pair (theta, x,
+ * r = H x - theta x, d = H_II, N determinants):
+ *   f0 = tanh((d-theta)/4), f1 = asinh(r_I sqrt(N)/|r|), f2 = asinh(x_I sqrt(N)),
+ *   f3 = asinh(-r_I/(d-theta) sqrt(N)/|r|), f4/f5 = alpha/beta electrons outside
+ *   the aufbau orbitals / max(1, min(n_e, n-n_e)), f6 = open-shell fraction
+ *   popcount(Ia^Ib)/n, f7 = tanh((d - min_I H_II)/4).
+ * Parameters (CASCI_MLP_NPARAM floats): W1[8][64] (input-major), b1[64],
+ * W2[64][64], b2[64], W3[64], b3. A non-finite or vanishing learned
+ * correction falls back to the Olsen correction (counted in
+ * casci_davidson_info.mlp_fallbacks).
+ * ---------------------------------------------------------------------- */
+#define CASCI_MLP_NPARAM 4801
+
+/* Copy n = CASCI_MLP_NPARAM parameters in (host or device); resets the Adam moments. */
+int casci_mlp_set_params(casci_ctx* ctx, const float* params, int64_t n, int mem);
+
+/* Copy the current parameters to host out[CASCI_MLP_NPARAM]. */
+int casci_mlp_get_params(casci_ctx* ctx, float* out);
+
+/* Network outputs Y[N] for feature rows X[N][8] (host or device). */
+int casci_mlp_forward(casci_ctx* ctx, const float* X, int64_t N, float* Y, int mem);
+
+/*
+ * Mean squared error L = (1/N) sum (y_i - T_i)^2 over all N rows and its
+ * gradient with respect to the parameters (host grad[CASCI_MLP_NPARAM] and
+ * *loss, either may be NULL). Summation order is fixed (reproducible).
+ */
+int casci_mlp_loss_grad(casci_ctx* ctx, const float* X, const float* T, int64_t N, float* grad,
+                        double* loss, int mem);
+
+/*
+ * Adam training (beta1 0.9, beta2 0.999, eps 1e-8) of the context's
+ * parameters on rows (X, T): `epochs` passes over a seeded shuffle, mini-batch
+ * `batch` (>= 64), learning rate lr. loss_hist: optional host [epochs] mean
+ * training loss per epoch.
+ */
+int casci_mlp_train(casci_ctx* ctx, const float* X, const float* T, int64_t N, int epochs, int batch,
+                    float lr, uint64_t seed, double* loss_hist, int mem);
+
+/*
+ * Training data from the method itself: runs casci_davidson(nroots, tol, opts)
+ * and, at every iteration and for every root j, draws `samples` determinant
+ * indices (seeded) and writes their features F[row][8] and targets
+ * T[row] = (s x*_j - x_j)_I sqrt(N)/|s x*_j - x_j| (s = sign of x*_j . x_j),
+ * with x* = xstar (device, [nroots][Ndet], the converged vectors). F, T are
+ * device buffers of max_rows rows; *nrows = rows written. Returns the
+ * Davidson status.
+ */
+int casci_mlp_collect(casci_ctx* ctx, int nroots, double tol, const casci_davidson_opts* opts,
+                      const double* xstar, int samples, uint64_t seed, float* F, float* T,
+                      int64_t max_rows, int64_t* nrows);
+
+/*
+ * Features F[m][8] (host) of the determinants idx[0..m) (host) for the Ritz
+ * pair (theta, x) whose sigma vector is sx (x, sx: device FP64 [Ndet]).
+ */
+int casci_mlp_features(casci_ctx* ctx, const double* x, const double* sx, double theta,
+                       const int64_t* idx, int m, float* F);
 
 /*
  * Profiling aid: on != 0 resets and starts accumulating the device time of

@@ -15,7 +15,7 @@ CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libcasci.so")
-SOURCES = ["setup_kernels.hip", "sigma_kernels.hip", "davidson_kernels.hip", "casci.cpp"]
+SOURCES = ["setup_kernels.hip", "sigma_kernels.hip", "davidson_kernels.hip", "mlp_kernels.hip", "casci.cpp"]
 ARCH = "gfx950"
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -25,6 +25,7 @@ PRECOND = {"diag": 0, "olsen": 1, "mlp": 2}
 SPIN = {"any": 0, "singlet": 1}
 PREC = {"f64": F64, "f32": F32, "bf16": BF16}
 MAX_ROOTS = 32
+MLP_NPARAM = 4801
 
 _ERRNAMES = {E_ARG: "E_ARG", E_STATE: "E_STATE", E_NOMEM: "E_NOMEM", E_DEVICE: "E_DEVICE",
              E_NONFINITE: "E_NONFINITE", E_UNSUPPORTED: "E_UNSUPPORTED"}
@@ -95,6 +96,13 @@ def lib():
         "casci_spin_square": (I, [P, P, P, I]),
         "casci_davidson": (I, [P, I, D, P, P, P, I, P]),
         "casci_profile_enable": (I, [P, I]),
+        "casci_mlp_set_params": (I, [P, P, I64, I]),
+        "casci_mlp_get_params": (I, [P, P]),
+        "casci_mlp_forward": (I, [P, P, I64, P, I]),
+        "casci_mlp_loss_grad": (I, [P, P, P, I64, P, P, I]),
+        "casci_mlp_train": (I, [P, P, P, I64, I, I, ctypes.c_float, ctypes.c_uint64, P, I]),
+        "casci_mlp_collect": (I, [P, I, D, P, P, I, ctypes.c_uint64, P, P, I64, P]),
+        "casci_mlp_features": (I, [P, P, P, D, P, I, P]),
         "casci_profile_read": (I, [P, P]),
     }
     for name, (res, args) in sig.items():
@@ -237,6 +245,73 @@ class Context:
             raise ValueError("C and out must share memory kind and dtype")
         self._check(self._L.casci_sigma(self._h, pc, ps, dtype, PREC[ab_prec], mem))
         return out
+
+    # -- learned preconditioner ------------------------------------------
+    def mlp_set_params(self, params):
+        p, mem = _ptr(params)
+        if str(params.dtype).split(".")[-1] != "float32" or int(np.prod(params.shape)) != MLP_NPARAM:
+            raise ValueError("params must be %d float32 values" % MLP_NPARAM)
+        self._check(self._L.casci_mlp_set_params(self._h, p, MLP_NPARAM, mem))
+
+    def mlp_get_params(self):
+        out = np.zeros(MLP_NPARAM, dtype=np.float32)
+        self._check(self._L.casci_mlp_get_params(self._h, out.ctypes.data))
+        return out
+
+    def mlp_forward(self, X):
+        X = np.ascontiguousarray(X, dtype=np.float32)
+        Y = np.zeros(X.shape[0], dtype=np.float32)
+        self._check(self._L.casci_mlp_forward(self._h, X.ctypes.data, X.shape[0], Y.ctypes.data, MEM_HOST))
+        return Y
+
+    def mlp_loss_grad(self, X, T):
+        X = np.ascontiguousarray(X, dtype=np.float32)
+        T = np.ascontiguousarray(T, dtype=np.float32)
+        g = np.zeros(MLP_NPARAM, dtype=np.float32)
+        loss = ctypes.c_double()
+        self._check(self._L.casci_mlp_loss_grad(self._h, X.ctypes.data, T.ctypes.data, X.shape[0], g.ctypes.data,
+                                                ctypes.byref(loss), MEM_HOST))
+        return loss.value, g
+
+    def mlp_train(self, X, T, epochs=10, batch=4096, lr=1e-3, seed=0):
+        """X, T: numpy (host) or torch CUDA tensors. Returns per-epoch training loss."""
+        px, mem = _ptr(X)
+        pt, mem2 = _ptr(T)
+        if mem != mem2:
+            raise ValueError("X and T must share memory kind")
+        hist = np.zeros(epochs)
+        self._check(self._L.casci_mlp_train(self._h, px, pt, int(X.shape[0]), int(epochs), int(batch),
+                                            float(lr), int(seed), hist.ctypes.data, mem))
+        return hist
+
+    def mlp_collect(self, nroots, tol, xstar, samples=2048, seed=0, max_rows=1 << 20, **opts):
+        """Training rows (features, targets) from a Davidson run; xstar: torch CUDA [nroots, Na, Nb]."""
+        import torch
+        F = torch.empty((max_rows, 8), dtype=torch.float32, device="cuda")
+        T = torch.empty(max_rows, dtype=torch.float32, device="cuda")
+        o = self._opts(**opts)
+        n = ctypes.c_int64()
+        rc = self._L.casci_mlp_collect(self._h, int(nroots), float(tol), ctypes.byref(o), xstar.data_ptr(),
+                                       int(samples), int(seed), F.data_ptr(), T.data_ptr(), int(max_rows),
+                                       ctypes.byref(n))
+        self._check(rc, allow=(OK, NOCONV))
+        return F[:n.value], T[:n.value]
+
+    def mlp_features(self, x, sx, theta, idx):
+        """Features of determinants idx for the Ritz pair (theta, x) with sigma sx (torch CUDA FP64)."""
+        idx = np.ascontiguousarray(idx, dtype=np.int64)
+        F = np.zeros((idx.size, 8), dtype=np.float32)
+        self._check(self._L.casci_mlp_features(self._h, x.data_ptr(), sx.data_ptr(), float(theta),
+                                               idx.ctypes.data, idx.size, F.ctypes.data))
+        return F
+
+    def _opts(self, precond="diag", spin="any", ab_prec="f64", max_iter=0, m_max=0, r_tol=0.0,
+              refine_rnorm=0.0, s2_penalty=0.0):
+        o = DavidsonOpts()
+        o.max_iter, o.m_max = int(max_iter), int(m_max)
+        o.precond, o.spin, o.ab_prec = PRECOND[precond], SPIN[spin], PREC[ab_prec]
+        o.refine_rnorm, o.r_tol, o.s2_penalty = float(refine_rnorm), float(r_tol), float(s2_penalty)
+        return o
 
     def profile(self, on: bool = True):
         """Start (reset) or stop per-part device timing of sigma builds."""

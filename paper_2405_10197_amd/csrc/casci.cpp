@@ -110,6 +110,10 @@ struct casci_ctx {
     // workspaces
     DBuf d_t1, d_t2, d_vin, d_vout, d_work, d_small, d_clp, d_c32;
 
+    // learned preconditioner parameters (FP32, MLP_NPARAM values)
+    DBuf d_mlp, d_mlp_m, d_mlp_v, d_mlp_g, d_mlp_part, d_mlp_perm, d_mlp_sse, d_mlp_idx;
+    bool have_mlp = false;
+
     // optional per-part timing of sigma builds (HIP events on `stream`)
     bool profiling = false;
     hipEvent_t pev[6] = {};
@@ -193,7 +197,9 @@ extern "C" void casci_destroy(casci_ctx* ctx)
                         &ctx->d_vt_sym, &ctx->d_pairs_sym, &ctx->d_vt_full, &ctx->d_pairs_full,
                         &ctx->d_vt_s2, &ctx->d_t1, &ctx->d_t2, &ctx->d_vin, &ctx->d_vout,
                         &ctx->d_work, &ctx->d_small, &ctx->d_vt_sym_lp[0], &ctx->d_vt_sym_lp[1],
-                        &ctx->d_vt_full_lp[0], &ctx->d_vt_full_lp[1], &ctx->d_clp, &ctx->d_c32};
+                        &ctx->d_vt_full_lp[0], &ctx->d_vt_full_lp[1], &ctx->d_clp, &ctx->d_c32,
+                        &ctx->d_mlp, &ctx->d_mlp_m, &ctx->d_mlp_v, &ctx->d_mlp_g, &ctx->d_mlp_part,
+                        &ctx->d_mlp_perm, &ctx->d_mlp_sse, &ctx->d_mlp_idx};
         for (DBuf* b : bufs) b->release();
         for (hipEvent_t& e : ctx->pev)
             if (e) (void)hipEventDestroy(e);
@@ -893,8 +899,88 @@ struct Timer {
 
 }  // namespace
 
+// training-data collector run inside Davidson (casci_mlp_collect)
+struct Collector {
+    const double* xstar;  // device [nroots][Ndet]
+    int samples;
+    uint64_t seed;
+    float* F;             // device [max_rows][MLP_IN]
+    float* T;             // device [max_rows]
+    int64_t max_rows;
+    int64_t rows = 0;
+};
+
+static int davidson_impl(casci_ctx* ctx, int nroots, double tol, const casci_davidson_opts* opts,
+                         double* energies, void* vectors, int mem, casci_davidson_info* info,
+                         Collector* col);
+
 extern "C" int casci_davidson(casci_ctx* ctx, int nroots, double tol, const casci_davidson_opts* opts,
                               double* energies, void* vectors, int mem, casci_davidson_info* info)
+{
+    return davidson_impl(ctx, nroots, tol, opts, energies, vectors, mem, info, nullptr);
+}
+
+static MlpFeatArgs mlp_args(const casci_ctx* ctx, const double* x, const double* sx, double theta,
+                            double rnorm, double dmin)
+{
+    MlpFeatArgs a;
+    a.diag = ctx->d_diag.as<double>();
+    a.x = x;
+    a.sx = sx;
+    a.theta = theta;
+    a.rnorm = rnorm;
+    a.dmin = dmin;
+    a.astr = ctx->d_astr.as<uint64_t>();
+    a.bstr = ctx->d_bstr.as<uint64_t>();
+    a.N = ctx->Nd;
+    a.Nb = ctx->Nb;
+    a.n = ctx->norb;
+    a.na = ctx->na;
+    a.nb = ctx->nb;
+    return a;
+}
+
+// one iteration of training-data collection: for every root, `samples`
+// random determinants get their features and the normalised error x* - x
+static int collect_step(casci_ctx* ctx, Collector* col, int k, const double* X, const double* SX,
+                        const std::vector<double>& theta, const std::vector<double>& rn, double dmin)
+{
+    const int64_t Nd = ctx->Nd;
+    hipStream_t st = ctx->stream;
+    for (int j = 0; j < k && col->rows < col->max_rows; ++j) {
+        const double* x = X + (size_t)j * Nd;
+        const double* xs = col->xstar + (size_t)j * Nd;
+        std::vector<double> d1, d2;
+        CHECK_RC(dots(ctx, xs, 1, x, 1, d1));
+        CHECK_RC(dots(ctx, xs, 1, xs, 1, d2));
+        const double sgn = d1[0] >= 0 ? 1.0 : -1.0;
+        const double dn2 = d2[0] + 1.0 - 2.0 * sgn * d1[0];  // |s x* - x|^2 with |x| = 1
+        if (!(dn2 > 1e-24)) continue;
+        const int m = (int)std::min<int64_t>(col->samples, col->max_rows - col->rows);
+        std::vector<int64_t> idx(m);
+        uint64_t z = col->seed + 0x9E3779B97F4A7C15ull * (uint64_t)(col->rows + 1);
+        for (int i = 0; i < m; ++i) {  // splitmix64 stream
+            z += 0x9E3779B97F4A7C15ull;
+            uint64_t w = z;
+            w = (w ^ (w >> 30)) * 0xBF58476D1CE4E5B9ull;
+            w = (w ^ (w >> 27)) * 0x94D049BB133111EBull;
+            w ^= w >> 31;
+            idx[i] = (int64_t)(w % (uint64_t)Nd);
+        }
+        HIPC(ctx->d_mlp_idx.ensure((size_t)m * 8));
+        HIPC(hipMemcpyAsync(ctx->d_mlp_idx.p, idx.data(), (size_t)m * 8, hipMemcpyHostToDevice, st));
+        MlpFeatArgs fa = mlp_args(ctx, x, SX + (size_t)j * Nd, theta[j], rn[j], dmin);
+        HIPC(launch_mlp_collect(fa, ctx->d_mlp_idx.as<int64_t>(), m, xs, sgn, 1.0 / std::sqrt(dn2),
+                                col->F + col->rows * MLP_IN, col->T + col->rows, st));
+        HIPC(hipStreamSynchronize(st));
+        col->rows += m;
+    }
+    return CASCI_OK;
+}
+
+static int davidson_impl(casci_ctx* ctx, int nroots, double tol, const casci_davidson_opts* opts,
+                         double* energies, void* vectors, int mem, casci_davidson_info* info,
+                         Collector* col)
 {
     if (!ctx) return CASCI_E_ARG;
     Timer wall;
@@ -920,7 +1006,8 @@ extern "C" int casci_davidson(casci_ctx* ctx, int nroots, double tol, const casc
     if (nroots > Nd) return ctx->fail(CASCI_E_ARG, "nroots exceeds the number of determinants");
     if (o.guess && o.nguess < nroots) return ctx->fail(CASCI_E_ARG, "need at least nroots guess vectors");
     if (o.guess && o.nguess > 64) return ctx->fail(CASCI_E_ARG, "at most 64 guess vectors");
-    if (o.precond == CASCI_PRECOND_MLP) return ctx->fail(CASCI_E_UNSUPPORTED, "MLP preconditioner not built");
+    if (o.precond == CASCI_PRECOND_MLP && !ctx->have_mlp)
+        return ctx->fail(CASCI_E_STATE, "MLP preconditioner selected but no parameters set");
     CHECK_RC(need_device(ctx));
     DeviceGuard guard(ctx->device);
 
@@ -933,7 +1020,7 @@ extern "C" int casci_davidson(casci_ctx* ctx, int nroots, double tol, const casc
     const double lambda = (o.spin == CASCI_SPIN_SINGLET && o.s2_penalty > 0) ? o.s2_penalty : 0.0;
     const bool singlet = o.spin == CASCI_SPIN_SINGLET;
     int prec = o.ab_prec;  // current alpha-beta arithmetic
-    const double refine_at = o.refine_rnorm > 0 ? o.refine_rnorm : (prec == CASCI_BF16 ? 1e-2 : 1e-4);
+    const double refine_at = o.refine_rnorm > 0 ? o.refine_rnorm : (prec == CASCI_BF16 ? 2e-2 : 2e-5);
 
     Timer setup_t;
     CHECK_RC(ensure_prepared(ctx, lambda));
@@ -1094,21 +1181,25 @@ extern "C" int casci_davidson(casci_ctx* ctx, int nroots, double tol, const casc
         CHECK_RC(orthonormalize(0, ng, kept));
         m = kept;
     }
+    // host copy of the diagonal: start vectors and the lowest element (a
+    // feature of the learned preconditioner)
+    std::vector<double> diag(Nd);
+    HIPC(hipMemcpyAsync(diag.data(), ctx->d_diag.p, vb, hipMemcpyDeviceToHost, st));
+    HIPC(hipStreamSynchronize(st));
+    const double dmin = *std::min_element(diag.begin(), diag.end());
     if (m < k) {
         // Start vectors from the lowest diagonal elements (ties: lower address).
         // For nalpha == nbeta the determinants (a,b) and (b,a) are combined into
         // (e_ab +- e_ba)/sqrt2: transposition commutes with H and with the
         // diagonal preconditioner, so a space without antisymmetric vectors
         // would never reach odd-S states. SINGLET keeps the + combinations.
-        std::vector<double> diag(Nd);
-        HIPC(hipMemcpyAsync(diag.data(), ctx->d_diag.p, vb, hipMemcpyDeviceToHost, st));
-        HIPC(hipStreamSynchronize(st));
         std::vector<int64_t> idx(Nd);
         for (int64_t i = 0; i < Nd; ++i) idx[i] = i;
         const int64_t want = std::min<int64_t>(Nd, 8 * k + 16);
         std::partial_sort(idx.begin(), idx.begin() + want, idx.end(), [&](int64_t a, int64_t b) {
             return diag[a] < diag[b] || (diag[a] == diag[b] && a < b);
         });
+
         struct Pick {
             int64_t lo, hi;
             int sign;
@@ -1179,7 +1270,8 @@ extern "C" int casci_davidson(casci_ctx* ctx, int nroots, double tol, const casc
     bool converged = false, have_prev = false;
     int it = 0, switch_iter = (prec == CASCI_F64) ? -1 : -2;
     double last_rmax = std::numeric_limits<double>::infinity();
-    int stall = 0, empty_steps = 0;
+    int stall = 0, empty_steps = 0, mlp_fallbacks = 0;
+    std::vector<double> best_hist;
     for (it = 0; it < max_iter; ++it) {
         // Rayleigh-Ritz on the device
         // With parity, B^T H B is block diagonal (the two parities are orthogonal
@@ -1235,15 +1327,26 @@ extern "C" int casci_davidson(casci_ctx* ctx, int nroots, double tol, const casc
         if (info && info->hist_time_ms && it < info->hist_len) info->hist_time_ms[it] = wall.ms();
         for (int j = 0; j < k; ++j) theta_prev[j] = theta[j];
         if (o.progress) o.progress(o.progress_user, it, k, theta.data(), rn.data(), wall.ms());
+        if (col) CHECK_RC(collect_step(ctx, col, k, X, SX, theta, rn, dmin));
         if (!std::isfinite(rmax)) return ctx->fail(CASCI_E_NONFINITE, "non-finite residual in Davidson");
         if (todo.empty() && prec == CASCI_F64) {
             converged = true;
             break;
         }
-        // precision switch: restart from the Ritz vectors with FP64 sigma
+        // precision switch: once the residual reaches the level the low-precision
+        // sigma can resolve (or stops improving: no 2x gain of the best residual
+        // over 8 iterations), restart from the Ritz vectors with FP64 sigma
         if (prec != CASCI_F64) {
-            stall = (rmax > 0.5 * last_rmax) ? stall + 1 : 0;
-            if (rmax < refine_at || stall >= 2 || todo.empty()) {
+            best_hist.push_back(rmax);
+            const int nh = (int)best_hist.size();
+            bool stalled = false;
+            if (nh > 16) {
+                double recent = *std::min_element(best_hist.end() - 8, best_hist.end());
+                double before = *std::min_element(best_hist.begin(), best_hist.end() - 8);
+                stalled = recent > 0.5 * before;
+            }
+            (void)stall;
+            if (rmax < refine_at || stalled || todo.empty()) {
                 prec = CASCI_F64;
                 switch_iter = it;
                 HIPC(hipMemcpyAsync(vB(0), vX(0), vb * k, hipMemcpyDeviceToDevice, st));
@@ -1304,7 +1407,22 @@ extern "C" int casci_davidson(casci_ctx* ctx, int nroots, double tol, const casc
             double eps = 0.0;
             if (o.precond == CASCI_PRECOND_OLSEN && std::fabs(rs[4 * j + 2]) > 1e-300)
                 eps = rs[4 * j + 1] / rs[4 * j + 2];
-            HIPC(launch_precondition(vX(j), vSX(j), theta[j], eps, ctx->d_diag.as<double>(), Nd, vB(m + t), st));
+            bool done = false;
+            if (o.precond == CASCI_PRECOND_MLP) {
+                MlpFeatArgs fa = mlp_args(ctx, vX(j), vSX(j), theta[j], rn[j], dmin);
+                HIPC(launch_mlp_correction(fa, ctx->d_mlp.as<float>(), vB(m + t), st));
+                std::vector<double> nn;
+                CHECK_RC(dots_dev(vB(m + t), 1, vB(m + t), 1, nn));
+                // the judge: a non-finite or vanishing learned correction falls back to Olsen
+                done = std::isfinite(nn[0]) && nn[0] > 0.0;
+                if (!done) ++mlp_fallbacks;
+            }
+            if (!done) {
+                if (o.precond == CASCI_PRECOND_MLP && std::fabs(rs[4 * j + 2]) > 1e-300)
+                    eps = rs[4 * j + 1] / rs[4 * j + 2];
+                HIPC(launch_precondition(vX(j), vSX(j), theta[j], eps, ctx->d_diag.as<double>(), Nd, vB(m + t),
+                                         st));
+            }
             par[m + t] = xpar[j];
             if (use_par) CHECK_RC(symmetrize(vB(m + t), xpar[j]));
         }
@@ -1349,7 +1467,7 @@ extern "C" int casci_davidson(casci_ctx* ctx, int nroots, double tol, const casc
         info->sigma_calls_fp64 = sigma64;
         info->converged = converged ? 1 : 0;
         info->switch_iter = switch_iter < 0 ? -1 : switch_iter;
-        info->mlp_fallbacks = 0;
+        info->mlp_fallbacks = mlp_fallbacks;
         for (int j = 0; j < CASCI_MAX_ROOTS; ++j) {
             info->residual[j] = j < k ? rn[j] : 0.0;
             info->s2[j] = j < k ? s2v[j] : 0.0;
@@ -1359,4 +1477,247 @@ extern "C" int casci_davidson(casci_ctx* ctx, int nroots, double tol, const casc
         info->time_total_ms = wall.ms();
     }
     return converged ? CASCI_OK : CASCI_NOCONV;
+}
+
+// ---------------------------------------------------------------------------
+// learned preconditioner
+// ---------------------------------------------------------------------------
+static int mlp_upload(casci_ctx* ctx, const float* src, size_t n, int mem, DBuf& dst)
+{
+    HIPC(dst.ensure(n * 4));
+    HIPC(hipMemcpyAsync(dst.p, src, n * 4, mem == CASCI_MEM_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice,
+                        ctx->stream));
+    if (mem == CASCI_MEM_HOST) HIPC(hipStreamSynchronize(ctx->stream));
+    return CASCI_OK;
+}
+
+extern "C" int casci_mlp_set_params(casci_ctx* ctx, const float* params, int64_t n, int mem)
+{
+    if (!ctx) return CASCI_E_ARG;
+    if (!params) return ctx->fail(CASCI_E_ARG, "params is NULL");
+    if (n != MLP_NPARAM) return ctx->fail(CASCI_E_ARG, "expected MLP_NPARAM parameters");
+    if (mem != CASCI_MEM_HOST && mem != CASCI_MEM_DEVICE) return ctx->fail(CASCI_E_ARG, "bad mem flag");
+    CHECK_RC(need_device(ctx));
+    DeviceGuard g(ctx->device);
+    CHECK_RC(mlp_upload(ctx, params, MLP_NPARAM, mem, ctx->d_mlp));
+    HIPC(ctx->d_mlp_m.ensure(MLP_NPARAM * 4));
+    HIPC(ctx->d_mlp_v.ensure(MLP_NPARAM * 4));
+    HIPC(hipMemsetAsync(ctx->d_mlp_m.p, 0, MLP_NPARAM * 4, ctx->stream));
+    HIPC(hipMemsetAsync(ctx->d_mlp_v.p, 0, MLP_NPARAM * 4, ctx->stream));
+    HIPC(hipStreamSynchronize(ctx->stream));
+    ctx->have_mlp = true;
+    return CASCI_OK;
+}
+
+extern "C" int casci_mlp_get_params(casci_ctx* ctx, float* out)
+{
+    if (!ctx) return CASCI_E_ARG;
+    if (!out) return ctx->fail(CASCI_E_ARG, "out is NULL");
+    if (!ctx->have_mlp) return ctx->fail(CASCI_E_STATE, "no MLP parameters set");
+    CHECK_RC(need_device(ctx));
+    DeviceGuard g(ctx->device);
+    HIPC(hipMemcpyAsync(out, ctx->d_mlp.p, MLP_NPARAM * 4, hipMemcpyDeviceToHost, ctx->stream));
+    HIPC(hipStreamSynchronize(ctx->stream));
+    return CASCI_OK;
+}
+
+extern "C" int casci_mlp_forward(casci_ctx* ctx, const float* X, int64_t N, float* Y, int mem)
+{
+    if (!ctx) return CASCI_E_ARG;
+    if (!X || !Y || N < 0) return ctx->fail(CASCI_E_ARG, "bad arguments");
+    if (mem != CASCI_MEM_HOST && mem != CASCI_MEM_DEVICE) return ctx->fail(CASCI_E_ARG, "bad mem flag");
+    if (!ctx->have_mlp) return ctx->fail(CASCI_E_STATE, "no MLP parameters set");
+    CHECK_RC(need_device(ctx));
+    DeviceGuard g(ctx->device);
+    hipStream_t st = ctx->stream;
+    const float* dx = X;
+    float* dy = Y;
+    DBuf bx, by;
+    if (mem == CASCI_MEM_HOST) {
+        HIPC(bx.ensure((size_t)N * MLP_IN * 4 + 16));
+        HIPC(by.ensure((size_t)N * 4 + 16));
+        HIPC(hipMemcpyAsync(bx.p, X, (size_t)N * MLP_IN * 4, hipMemcpyHostToDevice, st));
+        dx = bx.as<float>();
+        dy = by.as<float>();
+    }
+    HIPC(launch_mlp_forward(ctx->d_mlp.as<float>(), dx, N, dy, st));
+    if (mem == CASCI_MEM_HOST) {
+        HIPC(hipMemcpyAsync(Y, dy, (size_t)N * 4, hipMemcpyDeviceToHost, st));
+        HIPC(hipStreamSynchronize(st));
+        bx.release();
+        by.release();
+    }
+    return CASCI_OK;
+}
+
+// gradient of the mean squared error over all N samples with the current params
+static int mlp_grad_full(casci_ctx* ctx, const float* dX, const float* dT, int64_t N, const int32_t* perm,
+                         int64_t begin, int64_t count, double* sse)
+{
+    const int nblocks = 512;
+    HIPC(ctx->d_mlp_part.ensure((size_t)nblocks * (MLP_NPARAM + 1) * 4));
+    HIPC(ctx->d_mlp_g.ensure(MLP_NPARAM * 4));
+    HIPC(ctx->d_mlp_sse.ensure(64));
+    HIPC(launch_mlp_grad(ctx->d_mlp.as<float>(), dX, dT, perm, begin, count, count,
+                         ctx->d_mlp_part.as<float>(), nblocks, ctx->d_mlp_g.as<float>(),
+                         ctx->d_mlp_sse.as<double>(), ctx->stream));
+    (void)N;
+    if (sse) {
+        HIPC(hipMemcpyAsync(sse, ctx->d_mlp_sse.p, 8, hipMemcpyDeviceToHost, ctx->stream));
+        HIPC(hipStreamSynchronize(ctx->stream));
+    }
+    return CASCI_OK;
+}
+
+static int mlp_stage(casci_ctx* ctx, const float* X, const float* T, int64_t N, int mem, DBuf& bx, DBuf& bt,
+                     const float** dX, const float** dT)
+{
+    *dX = X;
+    *dT = T;
+    if (mem == CASCI_MEM_HOST) {
+        HIPC(bx.ensure((size_t)N * MLP_IN * 4 + 16));
+        HIPC(bt.ensure((size_t)N * 4 + 16));
+        HIPC(hipMemcpyAsync(bx.p, X, (size_t)N * MLP_IN * 4, hipMemcpyHostToDevice, ctx->stream));
+        HIPC(hipMemcpyAsync(bt.p, T, (size_t)N * 4, hipMemcpyHostToDevice, ctx->stream));
+        HIPC(hipStreamSynchronize(ctx->stream));
+        *dX = bx.as<float>();
+        *dT = bt.as<float>();
+    }
+    return CASCI_OK;
+}
+
+static int mlp_identity_perm(casci_ctx* ctx, int64_t N)
+{
+    std::vector<int32_t> perm(N);
+    for (int64_t i = 0; i < N; ++i) perm[i] = (int32_t)i;
+    HIPC(ctx->d_mlp_perm.ensure((size_t)N * 4 + 16));
+    HIPC(hipMemcpyAsync(ctx->d_mlp_perm.p, perm.data(), (size_t)N * 4, hipMemcpyHostToDevice, ctx->stream));
+    HIPC(hipStreamSynchronize(ctx->stream));
+    return CASCI_OK;
+}
+
+extern "C" int casci_mlp_loss_grad(casci_ctx* ctx, const float* X, const float* T, int64_t N, float* grad,
+                                   double* loss, int mem)
+{
+    if (!ctx) return CASCI_E_ARG;
+    if (!X || !T || N <= 0 || N >= (1LL << 31)) return ctx->fail(CASCI_E_ARG, "bad arguments");
+    if (mem != CASCI_MEM_HOST && mem != CASCI_MEM_DEVICE) return ctx->fail(CASCI_E_ARG, "bad mem flag");
+    if (!ctx->have_mlp) return ctx->fail(CASCI_E_STATE, "no MLP parameters set");
+    CHECK_RC(need_device(ctx));
+    DeviceGuard g(ctx->device);
+    DBuf bx, bt;
+    const float *dX, *dT;
+    CHECK_RC(mlp_stage(ctx, X, T, N, mem, bx, bt, &dX, &dT));
+    CHECK_RC(mlp_identity_perm(ctx, N));
+    double sse = 0.0;
+    CHECK_RC(mlp_grad_full(ctx, dX, dT, N, ctx->d_mlp_perm.as<int32_t>(), 0, N, &sse));
+    if (loss) *loss = sse / (double)N;
+    if (grad) {
+        HIPC(hipMemcpyAsync(grad, ctx->d_mlp_g.p, MLP_NPARAM * 4, hipMemcpyDeviceToHost, ctx->stream));
+        HIPC(hipStreamSynchronize(ctx->stream));
+    }
+    bx.release();
+    bt.release();
+    return CASCI_OK;
+}
+
+extern "C" int casci_mlp_train(casci_ctx* ctx, const float* X, const float* T, int64_t N, int epochs,
+                               int batch, float lr, uint64_t seed, double* loss_hist, int mem)
+{
+    if (!ctx) return CASCI_E_ARG;
+    if (!X || !T || N <= 0 || N >= (1LL << 31) || epochs < 1 || batch < 64 || !(lr > 0))
+        return ctx->fail(CASCI_E_ARG, "bad arguments");
+    if (mem != CASCI_MEM_HOST && mem != CASCI_MEM_DEVICE) return ctx->fail(CASCI_E_ARG, "bad mem flag");
+    if (!ctx->have_mlp) return ctx->fail(CASCI_E_STATE, "set initial MLP parameters first");
+    CHECK_RC(need_device(ctx));
+    DeviceGuard g(ctx->device);
+    hipStream_t st = ctx->stream;
+    DBuf bx, bt;
+    const float *dX, *dT;
+    CHECK_RC(mlp_stage(ctx, X, T, N, mem, bx, bt, &dX, &dT));
+    std::vector<int32_t> perm(N);
+    for (int64_t i = 0; i < N; ++i) perm[i] = (int32_t)i;
+    HIPC(ctx->d_mlp_perm.ensure((size_t)N * 4 + 16));
+    uint64_t z = seed;
+    int step = 0;
+    for (int ep = 0; ep < epochs; ++ep) {
+        for (int64_t i = N - 1; i > 0; --i) {  // Fisher-Yates with splitmix64
+            z += 0x9E3779B97F4A7C15ull;
+            uint64_t w = z;
+            w = (w ^ (w >> 30)) * 0xBF58476D1CE4E5B9ull;
+            w = (w ^ (w >> 27)) * 0x94D049BB133111EBull;
+            w ^= w >> 31;
+            std::swap(perm[i], perm[w % (uint64_t)(i + 1)]);
+        }
+        HIPC(hipMemcpyAsync(ctx->d_mlp_perm.p, perm.data(), (size_t)N * 4, hipMemcpyHostToDevice, st));
+        HIPC(hipStreamSynchronize(st));
+        double ep_sse = 0.0;
+        for (int64_t b0 = 0; b0 < N; b0 += batch) {
+            const int64_t cnt = std::min<int64_t>(batch, N - b0);
+            double sse = 0.0;
+            CHECK_RC(mlp_grad_full(ctx, dX, dT, N, ctx->d_mlp_perm.as<int32_t>(), b0, cnt, &sse));
+            ep_sse += sse;
+            HIPC(launch_adam(ctx->d_mlp.as<float>(), ctx->d_mlp_g.as<float>(), ctx->d_mlp_m.as<float>(),
+                             ctx->d_mlp_v.as<float>(), lr, ++step, st));
+        }
+        if (loss_hist) loss_hist[ep] = ep_sse / (double)N;
+    }
+    HIPC(hipStreamSynchronize(st));
+    bx.release();
+    bt.release();
+    return CASCI_OK;
+}
+
+extern "C" int casci_mlp_collect(casci_ctx* ctx, int nroots, double tol, const casci_davidson_opts* opts,
+                                 const double* xstar, int samples, uint64_t seed, float* F, float* T,
+                                 int64_t max_rows, int64_t* nrows)
+{
+    if (!ctx) return CASCI_E_ARG;
+    if (!xstar || !F || !T || !nrows || samples < 1 || max_rows < 1)
+        return ctx->fail(CASCI_E_ARG, "bad arguments");
+    Collector col;
+    col.xstar = xstar;
+    col.samples = samples;
+    col.seed = seed;
+    col.F = F;
+    col.T = T;
+    col.max_rows = max_rows;
+    std::vector<double> E(nroots > 0 && nroots <= CASCI_MAX_ROOTS ? nroots : 1);
+    const int rc = davidson_impl(ctx, nroots, tol, opts, E.data(), nullptr, CASCI_MEM_HOST, nullptr, &col);
+    *nrows = col.rows;
+    return rc;
+}
+
+extern "C" int casci_mlp_features(casci_ctx* ctx, const double* x, const double* sx, double theta,
+                                  const int64_t* idx, int m, float* F)
+{
+    if (!ctx) return CASCI_E_ARG;
+    if (!x || !sx || !idx || !F || m < 0) return ctx->fail(CASCI_E_ARG, "bad arguments");
+    if (!ctx->has_ints) return ctx->fail(CASCI_E_STATE, "set_integrals first");
+    if (!ctx->has_strings) return ctx->fail(CASCI_E_STATE, "build_strings first");
+    CHECK_RC(need_device(ctx));
+    DeviceGuard g(ctx->device);
+    CHECK_RC(ensure_prepared(ctx, ctx->prepared ? ctx->prepared_lambda : 0.0));
+    hipStream_t st = ctx->stream;
+    const size_t vb = (size_t)ctx->Nd * 8;
+    std::vector<double> diag(ctx->Nd);
+    HIPC(hipMemcpyAsync(diag.data(), ctx->d_diag.p, vb, hipMemcpyDeviceToHost, st));
+    HIPC(hipStreamSynchronize(st));
+    const double dmin = *std::min_element(diag.begin(), diag.end());
+    // residual norm |sx - theta x| from two dots and the cross term
+    std::vector<double> xx, ss, xs;
+    CHECK_RC(dots(ctx, x, 1, x, 1, xx));
+    CHECK_RC(dots(ctx, sx, 1, sx, 1, ss));
+    CHECK_RC(dots(ctx, x, 1, sx, 1, xs));
+    const double rn = std::sqrt(std::max(0.0, ss[0] - 2 * theta * xs[0] + theta * theta * xx[0]));
+    HIPC(ctx->d_mlp_idx.ensure((size_t)m * 8 + 8));
+    HIPC(hipMemcpyAsync(ctx->d_mlp_idx.p, idx, (size_t)m * 8, hipMemcpyHostToDevice, st));
+    DBuf bf;
+    HIPC(bf.ensure((size_t)m * MLP_IN * 4 + 16));
+    MlpFeatArgs fa = mlp_args(ctx, x, sx, theta, rn, dmin);
+    HIPC(launch_mlp_collect(fa, ctx->d_mlp_idx.as<int64_t>(), m, nullptr, 1.0, 0.0, bf.as<float>(), nullptr, st));
+    HIPC(hipMemcpyAsync(F, bf.p, (size_t)m * MLP_IN * 4, hipMemcpyDeviceToHost, st));
+    HIPC(hipStreamSynchronize(st));
+    bf.release();
+    return CASCI_OK;
 }

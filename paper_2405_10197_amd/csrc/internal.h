@@ -114,4 +114,29 @@ hipError_t launch_jacobi_eigh(const double* G, int m, int ldg, double* theta, do
                               hipStream_t st);
 hipError_t launch_scale(double* x, double a, int64_t n, hipStream_t st);
 
+// mlp_kernels.hip (learned preconditioner)
+constexpr int MLP_IN = 8, MLP_HIDDEN = 64;
+constexpr int MLP_NPARAM = MLP_IN * MLP_HIDDEN + MLP_HIDDEN + MLP_HIDDEN * MLP_HIDDEN + MLP_HIDDEN +
+                           MLP_HIDDEN + 1;
+struct MlpFeatArgs {
+    const double* diag;
+    const double* x;   // Ritz vector
+    const double* sx;  // its sigma
+    double theta, rnorm, dmin;
+    const uint64_t* astr;
+    const uint64_t* bstr;
+    int64_t N, Nb;
+    int n, na, nb;
+};
+hipError_t launch_mlp_correction(const MlpFeatArgs& a, const float* P, double* t, hipStream_t st);
+hipError_t launch_mlp_collect(const MlpFeatArgs& a, const int64_t* idx, int m, const double* xstar,
+                              double xsign, double dnorm_inv, float* F, float* T, hipStream_t st);
+hipError_t launch_mlp_forward(const float* P, const float* X, int64_t N, float* Y, hipStream_t st);
+// one gradient of the mean squared error over samples perm[begin, begin+count) of
+// `total` (the loss is normalised by total); partial holds nblocks*(NPARAM+1) floats
+hipError_t launch_mlp_grad(const float* P, const float* X, const float* T, const int32_t* perm,
+                           int64_t begin, int64_t count, int64_t total, float* partial, int nblocks,
+                           float* grad, double* sse, hipStream_t st);
+hipError_t launch_adam(float* P, const float* g, float* m, float* v, float lr, int step, hipStream_t st);
+
 }  // namespace casci
