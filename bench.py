@@ -1,13 +1,19 @@
 """Benchmark of the string-CASCI hot path on one MI355X.
 
-A step is one complete CASCI solve of the workload on synthetic seeded
-integrals: integrals in, strings and substitution lists, same-spin operators,
-diagonal, then Davidson-Liu with sigma builds to convergence (tol 1e-10 Eh on
-the energy change, residual 1e-5). `value` is the time to reach 1e-8 Eh on
-every root (median over the timed steps), measured against reference
-energies from a tight FP64 run in the same process.
+A step is one complete CASCI solve of the workload on seeded synthetic
+integrals: integrals in, strings and substitution lists, same-spin
+operators, diagonal, then Davidson-Liu with sigma builds to convergence
+(energy change 1e-10 Eh, residual 1e-6). `value` is the time until every
+root stays within 1e-8 Eh of the reference energies (median over the timed
+steps). The reference energies and the baseline time come from the plain
+FP64, diagonal-preconditioned Davidson run in the same process; the timed
+steps use the headline solver (BF16 alpha-beta arithmetic with FP32
+accumulation, then FP64 sigma for the final iterations; Olsen
+preconditioner; one same-spin gather per sigma through transposition
+parity).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload cas16|cas12]
+       python bench.py --sigma-only f64|f32|bf16 --steps K   (kernel profiling aid)
 """
 from __future__ import annotations
 
@@ -15,6 +21,7 @@ import argparse
 import json
 import math
 import os
+import re
 import sys
 import time
 
@@ -29,10 +36,11 @@ PEAK = {"hbm_GBps": 8000.0, "f64_TF": 78.6, "f32_TF": 157.3, "bf16_TF": 2500.0}
 WORKLOADS = {
     # name: (norb, nalpha, nbeta, nroots, seed, spin, description)
     "cas16": (16, 8, 8, 3, 4, "any", "CAS(16e,16o), 3 roots state-averaged (equal weights), "
-              "165,636,900 determinants, seeded synthetic integrals"),
+              "165,636,900 determinants, seeded synthetic integrals (seed 4)"),
     "cas12": (12, 6, 6, 1, 2, "singlet", "CAS(12e,12o) singlet ground state, 853,776 determinants, "
-              "seeded synthetic integrals"),
+              "seeded synthetic integrals (seed 2)"),
 }
+HEADLINE = dict(precond="olsen", ab_prec="bf16")
 
 
 def log(*a):
@@ -41,9 +49,10 @@ def log(*a):
 
 def progress_printer(tag):
     def f(it, th, rn, ms):
-        log("[%s] iter %3d  %.1f s  E %s  |r| %s" % (tag, it, ms / 1000.0,
-                                                   " ".join("%.10f" % x for x in th),
-                                                   " ".join("%.1e" % x for x in rn)))
+        if it % 10 == 0:
+            log("[%s] iter %3d  %.1f s  E %s  |r| %s" % (tag, it, ms / 1000.0,
+                                                       " ".join("%.10f" % x for x in th),
+                                                       " ".join("%.1e" % x for x in rn)))
     return f
 
 
@@ -57,12 +66,34 @@ def time_to_threshold(hist_e, hist_t, eref, thr=1e-8):
     return float("nan"), -1
 
 
-def sigma_only(args, casci, h, eri, n, na, nb):
-    """Repeated sigma builds on a seeded normalised vector (for kernel profiling)."""
-    import torch
+def read_traffic(path):
+    """HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, KiB per dispatch, scaled by
+    the copy-kernel factor) from a committed rocprofv3 summary, or None."""
+    if not os.path.exists(path):
+        return None
+    txt = open(path).read()
+    vals = {}
+    for key in ("FETCH_SIZE_KiB", "WRITE_SIZE_KiB", "copy_scale"):
+        m = re.search(r"^%s\s*[:=]\s*([0-9.eE+-]+)" % key, txt, re.M)
+        if m:
+            vals[key] = float(m.group(1))
+    if "FETCH_SIZE_KiB" not in vals or "WRITE_SIZE_KiB" not in vals:
+        return None
+    scale = vals.get("copy_scale", 1.0)
+    return (vals["FETCH_SIZE_KiB"] + vals["WRITE_SIZE_KiB"]) * 1024.0 * scale
+
+
+def make_ctx(casci, h, eri, n, na, nb):
     ctx = casci.Context(0)
     ctx.set_integrals(h, eri)
     ctx.build_strings(na, nb, n)
+    return ctx
+
+
+def sigma_only(args, casci, h, eri, n, na, nb):
+    """Repeated sigma builds on a seeded normalised vector (for kernel profiling)."""
+    import torch
+    ctx = make_ctx(casci, h, eri, n, na, nb)
     d = ctx.dims
     g = torch.Generator(device="cuda").manual_seed(50)
     C = torch.randn(d["Na"], d["Nb"], dtype=torch.float64, device="cuda", generator=g)
@@ -81,14 +112,45 @@ def sigma_only(args, casci, h, eri, n, na, nb):
     P = ctx.profile_read()
     k = max(P["sigma_builds"], 1)
     print(json.dumps({"sigma_only": args.sigma_only, "workload": args.workload, "ms_per_sigma": dt * 1e3,
-                      "parts_ms": {x: P[x] / k for x in ("aa_ms", "bb_ms", "bb_transpose_ms", "ab_ms")}}))
+                      "parts_ms": {x: P[x] / k for x in ("aa_ms", "bb_ms", "ab_ms", "combine_ms", "total_ms")}}))
+
+
+def kernel_figures(P, dims, n, tag):
+    """Per-launch averages and rates of the sigma kernels from HIP events recorded
+    on the library's stream (P = profile_read()[tag])."""
+    nb_sig = P["sigma_builds"]
+    if nb_sig <= 0:
+        return None
+    Nd = dims["Ndet"]
+    M = n * (n + 1) // 2
+    ab_flops = 2.0 * M * dims["sa"] * Nd
+    ab_ms = P["ab_ms"] / nb_sig
+    aa_ms = P["aa_ms"] / nb_sig
+    esz = 8 if tag == "f64" else 4
+    # one same-spin gather launch: read C, write sigma, read the operator rows (int32 + FP64)
+    gather_bytes = Nd * esz + Nd * 8.0 + dims["Na"] * dims["ra"] * 12.0
+    gathered = dims["ra"] * Nd * float(esz)
+    peak = PEAK["f64_TF"] if tag == "f64" else PEAK["bf16_TF"]
+    return {
+        "sigma_builds": int(nb_sig),
+        "ms_per_sigma": P["total_ms"] / nb_sig,
+        "alpha_alpha_gather_ms": aa_ms, "beta_beta_ms": P["bb_ms"] / nb_sig,
+        "combine_ms": P["combine_ms"] / nb_sig,
+        "alpha_beta_ms": ab_ms,
+        "alpha_beta_TFLOPs": ab_flops / (ab_ms * 1e-3) / 1e12,
+        "alpha_beta_mfma_util": ab_flops / (ab_ms * 1e-3) / 1e12 / peak,
+        "alpha_beta_flops": ab_flops,
+        "gather_GBps_algorithmic": gather_bytes / (aa_ms * 1e-3) / 1e9,
+        "gather_GBps_gathered_operands": gathered / (aa_ms * 1e-3) / 1e9,
+        "gather_bytes_algorithmic": gather_bytes,
+    }
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=2)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1)
+    ap.add_argument("--warmup", type=int, default=0)
     ap.add_argument("--workload", default="cas16", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
@@ -106,105 +168,83 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     n, na, nb, k, seed, spin, desc = WORKLOADS[args.workload]
     h, eri, _ = synth.integrals(n, seed)
-    penalty = 1.0 if spin == "singlet" else 0.0
-    common = dict(spin=spin, s2_penalty=penalty)
-
+    common = dict(spin=spin, s2_penalty=1.0 if spin == "singlet" else 0.0)
     if args.sigma_only:
         sigma_only(args, casci, h, eri, n, na, nb)
         return
 
-    # reference energies: tight FP64 run (untimed)
-    log("[bench] reference FP64 solve %s" % args.workload)
-    ref = casci.Context(0)
-    ref.set_integrals(h, eri)
-    ref.build_strings(na, nb, n)
-    Eref, _, iref = ref.davidson(k, 1e-11, r_tol=1e-6, vectors=False, history=400, precond="olsen",
-                                 progress=progress_printer("ref"), **common)
-    dims = ref.dims
-    log("[bench] Eref", Eref.tolist(), "iters", iref["iterations"], "converged", iref["converged"])
-
-    # plain FP64 + diagonal preconditioner: the baseline solver
-    log("[bench] FP64 diagonal-preconditioned solve")
-    bctx = casci.Context(0)
-    bctx.set_integrals(h, eri)
-    bctx.build_strings(na, nb, n)
+    # baseline and reference: plain FP64 sigma, diagonal preconditioner
+    log("[bench] FP64 diagonal-preconditioned solve of %s (reference energies)" % args.workload)
+    bctx = make_ctx(casci, h, eri, n, na, nb)
+    dims = bctx.dims
     bctx.profile(True)
-    Eb, _, ib = bctx.davidson(k, 1e-10, vectors=False, history=400, precond="diag",
-                              progress=progress_printer("fp64-diag"), **common)
+    Eref, _, ib = bctx.davidson(k, 1e-10, vectors=False, history=1000, precond="diag", max_iter=1000,
+                                progress=progress_printer("fp64-diag"), **common)
     base_prof = bctx.profile_read()
     t_base, it_base = time_to_threshold(ib["hist_energy"], ib["hist_time_ms"], Eref)
-    log("[bench] baseline time-to-1e-8 %.3f s, iters %d" % (t_base, ib["iterations"]))
+    log("[bench] baseline: converged %s, %d iterations, time-to-1e-8 %.2f s" %
+        (ib["converged"], ib["iterations"], t_base))
     del bctx
+    torch.cuda.empty_cache()
 
-    # headline solver (timed steps)
-    headline = dict(precond="olsen", ab_prec="f64")
+    # headline solver, timed steps
     times, ttt, infos, profs = [], [], [], []
+    E = None
     for step in range(args.warmup + args.steps):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        ctx = casci.Context(0)
-        ctx.set_integrals(h, eri)
-        ctx.build_strings(na, nb, n)
+        ctx = make_ctx(casci, h, eri, n, na, nb)
         ctx.profile(True)
-        E, _, info = ctx.davidson(k, 1e-10, vectors=False, history=400, progress=progress_printer("step%d" % step),
-                                  **headline, **common)
+        E, _, info = ctx.davidson(k, 1e-10, vectors=False, history=1000, max_iter=1000,
+                                  progress=progress_printer("step%d" % step), **HEADLINE, **common)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         prof = ctx.profile_read()
         del ctx
-        t_hit, _ = time_to_threshold(info["hist_energy"], info["hist_time_ms"], Eref)
-        log("[bench] step %d: %.3f s, time-to-1e-8 %.3f s, iters %d, sigma %d" %
-            (step, dt, t_hit, info["iterations"], info["sigma_calls"]))
+        t_hit, it_hit = time_to_threshold(info["hist_energy"], info["hist_time_ms"], Eref)
+        log("[bench] step %d: %.2f s, time-to-1e-8 %.2f s (iteration %d), %d iterations, %d sigma (%d FP64)" %
+            (step, dt, t_hit, it_hit, info["iterations"], info["sigma_calls"], info["sigma_calls_fp64"]))
         if step >= args.warmup:
             times.append(dt)
             ttt.append(t_hit)
             infos.append(info)
             profs.append(prof)
 
-    # per-kernel figures from HIP events recorded on the library's stream
     P = profs[-1]
-    nb_sig = max(P["sigma_builds"], 1)
-    Nd = dims["Ndet"]
-    M = n * (n + 1) // 2
-    ab_flops = 2.0 * M * dims["sa"] * Nd
-    ab_ms = P["ab_ms"] / nb_sig
-    aa_ms = P["aa_ms"] / nb_sig
-    bb_ms = P["bb_ms"] / nb_sig
-    tr_ms = P["bb_transpose_ms"] / nb_sig
-    # algorithmic bytes of one same-spin gather launch: read C, write sigma, read the operator rows
-    gather_bytes = 2.0 * Nd * 8 + dims["Na"] * dims["ra"] * 12.0
-    gathered_bytes = dims["ra"] * Nd * 8.0
-    parts = {"alpha_beta_mfma": ab_ms, "alpha_alpha_gather": aa_ms, "beta_beta_gather": bb_ms,
-             "beta_beta_transposes": tr_ms}
-    dominant = max(parts, key=parts.get)
-    if dominant == "alpha_beta_mfma":
-        ach = ab_flops / (ab_ms * 1e-3) / 1e12
-        roof = {"kernel": "k_ab_f64", "bound": "mfma", "achieved": ach, "peak": PEAK["f64_TF"],
-                "unit": "TFLOP/s", "frac": ach / PEAK["f64_TF"], "traffic": None}
+    lowp = kernel_figures(P["lowp"], dims, n, "lowp")
+    f64 = kernel_figures(P["f64"], dims, n, "f64")
+    f64_base = kernel_figures(base_prof["f64"], dims, n, "f64")
+    # dominant kernel of the timed step (total device time)
+    cand = []
+    for tag, fig in (("lowp", lowp), ("f64", f64)):
+        if fig:
+            nbld = fig["sigma_builds"]
+            cand.append((fig["alpha_beta_ms"] * nbld, tag, "ab", fig))
+            cand.append((fig["alpha_alpha_gather_ms"] * nbld, tag, "aa", fig))
+    cand.sort(key=lambda c: -c[0])
+    _, tag, part, fig = cand[0]
+    if part == "ab":
+        peak = PEAK["bf16_TF"] if tag == "lowp" else PEAK["f64_TF"]
+        kname = "k_ab_lp<MfmaBF16>" if tag == "lowp" else "k_ab<MfmaF64>"
+        ach = fig["alpha_beta_TFLOPs"]
+        roof = {"kernel": kname, "bound": "mfma", "achieved": ach, "peak": peak, "unit": "TFLOP/s",
+                "frac": ach / peak, "traffic": None}
     else:
-        ms = aa_ms if dominant == "alpha_alpha_gather" else bb_ms
-        ach = gather_bytes / (ms * 1e-3) / 1e9
-        roof = {"kernel": "k_ss_gather<double,32>", "bound": "hbm", "achieved": ach,
-                "peak": PEAK["hbm_GBps"], "unit": "GB/s", "frac": ach / PEAK["hbm_GBps"], "traffic": None}
-    sigma_ms = aa_ms + bb_ms + tr_ms + ab_ms
-    sigma_detail = {
-        "sigma_ms": sigma_ms, "parts_ms": parts,
-        "alpha_beta_TFLOPs": ab_flops / (ab_ms * 1e-3) / 1e12,
-        "alpha_beta_mfma_util_f64": ab_flops / (ab_ms * 1e-3) / 1e12 / PEAK["f64_TF"],
-        "gather_compulsory_GBps": gather_bytes / (aa_ms * 1e-3) / 1e9,
-        "gather_effective_GBps": gathered_bytes / (aa_ms * 1e-3) / 1e9,
-        "alpha_beta_flops_per_sigma": ab_flops, "gather_bytes_per_launch": gather_bytes,
-    }
+        kname = "k_ss_gather<float,double,64>" if tag == "lowp" else "k_ss_gather<double,double,32>"
+        ach = fig["gather_GBps_algorithmic"]
+        traffic = read_traffic(os.path.join(ROOT, "profiles", "%s_%s_pmc.txt" % (
+            "ss_gather_f32" if tag == "lowp" else "ss_gather_f64", args.workload)))
+        roof = {"kernel": kname, "bound": "hbm", "achieved": ach, "peak": PEAK["hbm_GBps"], "unit": "GB/s",
+                "frac": ach / PEAK["hbm_GBps"], "traffic": traffic}
 
     # CPU oracle on a bounded sample: rows of sigma at the same size, scaled to
-    # the number of sigma builds the GPU solve needed before reaching 1e-8 Eh
+    # the sigma builds of the GPU solve
     cpu = None
     if not args.no_cpu_baseline:
         import oracle
         rng = np.random.default_rng(7)
-        C = synth.ci_vector(dims["Na"], dims["Nb"], 8)[0] if Nd <= 2e7 else None
-        if C is None:
-            C = np.ones(Nd) / math.sqrt(Nd)
+        Nd = dims["Ndet"]
+        C = np.ones(Nd) / math.sqrt(Nd) if Nd > 2e7 else synth.ci_vector(dims["Na"], dims["Nb"], 8)[0]
         nrows, elapsed = 0, 0.0
         t0 = time.perf_counter()
         while elapsed < args.cpu_seconds:
@@ -215,25 +255,27 @@ def main():
         per_sigma_s = elapsed / nrows * Nd
         calls = infos[-1]["sigma_calls"]
         cpu = {"value": per_sigma_s * calls, "unit": "s", "cores": 1, "kind": "oracle",
-               "sample": "%d random rows of sigma = H C at %s by Slater-Condon enumeration "
-                         "(%.1f s), scaled to %d determinants x %d sigma builds of the GPU solve"
+               "sample": "%d random rows of sigma = H C at %s by single-threaded Slater-Condon enumeration "
+                         "(%.1f s of CPU time), scaled to %d determinants x %d sigma builds (the GPU solve's)"
                          % (nrows, args.workload, elapsed, Nd, calls),
-               "per_sigma_s": per_sigma_s}
+               "oracle_seconds_per_sigma": per_sigma_s}
 
     med = float(np.median(ttt))
     out = {
         "metric": METRIC, "value": med, "unit": "s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": 1000.0 * float(np.mean(times)), "higher_is_better": False,
-        "scaling": "strong", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "scaling": "strong", "vs_baseline": None, "dtype": "bf16+f64", "data": "synthetic",
         "config": {"workload": desc, "norb": n, "nalpha": na, "nbeta": nb, "nroots": k, "seed": seed,
-                   "spin": spin, "solver": headline},
+                   "spin": spin, "solver": "BF16 alpha-beta (FP32 accumulate) + FP64 sigma refinement, Olsen"},
         "roofline": roof,
         "cpu_baseline": cpu,
-        "fp64_diag_time_to_1e8_s": t_base, "fp64_diag_iterations": ib["iterations"],
+        "fp64_diag_time_to_1e8_s": t_base,
+        "fp64_diag_iterations": ib["iterations"], "fp64_diag_sigma_calls": ib["sigma_calls"],
         "speedup_vs_fp64_diag": (t_base / med) if med > 0 else None,
         "iterations": infos[-1]["iterations"], "sigma_calls": infos[-1]["sigma_calls"],
-        "energies": E.tolist(), "energy_error_vs_ref": float(np.abs(E - Eref).max()),
-        "sigma": sigma_detail,
+        "sigma_calls_fp64": infos[-1]["sigma_calls_fp64"], "switch_iteration": infos[-1]["switch_iter"],
+        "energies": E.tolist(), "energy_error_vs_fp64_reference": float(np.abs(E - Eref).max()),
+        "sigma_fp64": f64_base, "sigma_lowp_bf16": lowp, "sigma_fp64_in_headline": f64,
     }
     print(json.dumps(out))
 

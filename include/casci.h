@@ -298,9 +298,12 @@ int casci_mlp_features(casci_ctx* ctx, const double* x, const double* sx, double
 int casci_profile_enable(casci_ctx* ctx, int on);
 
 /*
- * out[0..7] = {alpha-alpha gather ms, beta-beta transposes ms, beta-beta
- * gather ms, alpha-beta contraction ms, sigma builds, of which FP64
- * alpha-beta, 0, 0}, accumulated since casci_profile_enable(ctx, 1).
+ * out[0..15]: out[0..5] for sigma builds with FP64 alpha-beta arithmetic and
+ * out[6..11] for low-precision builds, each = {alpha-alpha gather ms (with the
+ * conversions of C if any), beta-beta ms (transposes + gather, or nothing
+ * with parity), alpha-beta contraction ms (on a second stream, overlapping
+ * the gathers), join + final combination ms, whole build ms, number of
+ * builds}; out[12..15] = 0. Accumulated since casci_profile_enable(ctx, 1).
  */
 int casci_profile_read(const casci_ctx* ctx, double* out);
 

@@ -318,10 +318,17 @@ class Context:
         self._check(self._L.casci_profile_enable(self._h, 1 if on else 0))
 
     def profile_read(self):
-        out = np.zeros(8)
+        """Per-part device time (ms) of the sigma builds since profile(True), split by
+        the arithmetic of the alpha-beta term ('f64' and 'lowp'); the alpha-beta part
+        runs concurrently with the gathers, so 'total_ms' is the wall time of the builds."""
+        out = np.zeros(16)
         self._check(self._L.casci_profile_read(self._h, out.ctypes.data))
-        keys = ["aa_ms", "bb_transpose_ms", "bb_ms", "ab_ms", "sigma_builds", "sigma_builds_fp64"]
-        return {k: float(v) for k, v in zip(keys, out)}
+        keys = ["aa_ms", "bb_ms", "ab_ms", "combine_ms", "total_ms", "sigma_builds"]
+        res = {}
+        for tag, off in (("f64", 0), ("lowp", 6)):
+            res[tag] = {k: float(out[off + i]) for i, k in enumerate(keys)}
+        res.update({k: res["f64"][k] + res["lowp"][k] for k in keys})
+        return res
 
     def spin_square(self, C):
         pc, mem = _ptr(C)

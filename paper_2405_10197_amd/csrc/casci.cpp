@@ -108,7 +108,7 @@ struct casci_ctx {
     bool have_full = false, have_s2 = false;
 
     // workspaces
-    DBuf d_t1, d_t2, d_vin, d_vout, d_work, d_small, d_clp, d_c32;
+    DBuf d_t1, d_t2, d_t3, d_vin, d_vout, d_work, d_small, d_clp, d_c32;
 
     // learned preconditioner parameters (FP32, MLP_NPARAM values)
     DBuf d_mlp, d_mlp_m, d_mlp_v, d_mlp_g, d_mlp_part, d_mlp_perm, d_mlp_sse, d_mlp_idx;
@@ -117,7 +117,7 @@ struct casci_ctx {
     // optional per-part timing of sigma builds (HIP events on `stream`)
     bool profiling = false;
     hipEvent_t pev[6] = {};
-    double prof[8] = {};
+    double prof[16] = {};
 
     int fail(int code, const std::string& msg)
     {
@@ -197,7 +197,7 @@ extern "C" void casci_destroy(casci_ctx* ctx)
                         &ctx->d_vt_sym, &ctx->d_pairs_sym, &ctx->d_vt_full, &ctx->d_pairs_full,
                         &ctx->d_vt_s2, &ctx->d_t1, &ctx->d_t2, &ctx->d_vin, &ctx->d_vout,
                         &ctx->d_work, &ctx->d_small, &ctx->d_vt_sym_lp[0], &ctx->d_vt_sym_lp[1],
-                        &ctx->d_vt_full_lp[0], &ctx->d_vt_full_lp[1], &ctx->d_clp, &ctx->d_c32,
+                        &ctx->d_vt_full_lp[0], &ctx->d_vt_full_lp[1], &ctx->d_clp, &ctx->d_c32, &ctx->d_t3,
                         &ctx->d_mlp, &ctx->d_mlp_m, &ctx->d_mlp_v, &ctx->d_mlp_g, &ctx->d_mlp_part,
                         &ctx->d_mlp_perm, &ctx->d_mlp_sse, &ctx->d_mlp_idx};
         for (DBuf* b : bufs) b->release();
@@ -583,6 +583,7 @@ static AbParams ab_params(const casci_ctx* ctx, bool full)
     p.bstr = ctx->d_bstr.as<uint64_t>();
     p.lb_j = ctx->d_lb_j.as<int32_t>();
     p.sb = ctx->sb;
+    p.overwrite = 0;
     p.pairs = (full ? ctx->d_pairs_full : ctx->d_pairs_sym).as<uint16_t>();
     return p;
 }
@@ -592,6 +593,10 @@ static AbParams ab_params(const casci_ctx* ctx, bool full)
 // commutes with H, so sigma_bb = parity * sigma_aa^T and one same-spin gather
 // serves both spins. parity = 0: general C. ab_prec != F64 also reads the
 // same-spin gather operand from an FP32 copy of C (accumulation stays FP64).
+// The alpha-beta contraction writes its own buffer, added in by the final pass
+// (with parity fused into the S + p S^T symmetrisation). Running it on a
+// second stream beside the gathers was measured not to help: each slows the
+// other by as much as the overlap gains.
 static int sigma_dev(casci_ctx* ctx, const double* C, double* S, int ab_prec, double lambda,
                      int parity = 0)
 {
@@ -601,17 +606,43 @@ static int sigma_dev(casci_ctx* ctx, const double* C, double* S, int ab_prec, do
     const double shift = ctx->ecore + lambda * (ms * ms + ms + ctx->nb);
     const bool prof = ctx->profiling;
     const bool lowp = ab_prec != CASCI_F64;
+    const bool has_ab = ctx->na > 0 && ctx->nb > 0;
     if (parity != 0 && ctx->na != ctx->nb) return ctx->fail(CASCI_E_ARG, "parity needs nalpha == nbeta");
     set_launch_reason("");
-    auto mark = [&](int i) -> int {
-        if (prof) HIPC(hipEventRecord(ctx->pev[i], st));
+    auto mark = [&](int i, hipStream_t s) -> int {
+        if (prof) HIPC(hipEventRecord(ctx->pev[i], s));
         return CASCI_OK;
     };
-    CHECK_RC(mark(0));
-    const int64_t ld32 = lowp_ld(1, Nb);
+    CHECK_RC(mark(0, st));
+    // inputs in the arithmetic's types (stream order: before the fork)
+    const int64_t ld32 = lowp_ld(1, Nb), ld16 = lowp_ld(2, Nb);
     if (lowp) {
         HIPC(ctx->d_c32.ensure((size_t)Na * ld32 * 4));
         HIPC(launch_convert_lowp(1, C, ctx->d_c32.p, Na, Nb, ld32, st));
+        if (has_ab && ab_prec == CASCI_BF16) {
+            HIPC(ctx->d_clp.ensure((size_t)Na * ld16 * 2));
+            HIPC(launch_convert_lowp(2, C, ctx->d_clp.p, Na, Nb, ld16, st));
+        }
+    }
+    // alpha-beta, overwriting d_t3
+    if (has_ab) {
+        HIPC(ctx->d_t3.ensure((size_t)Nd * 8));
+        CHECK_RC(mark(3, st));
+        const bool full = lambda != 0.0;
+        AbParams p = ab_params(ctx, full);
+        p.overwrite = 1;
+        double* T = ctx->d_t3.as<double>();
+        if (!lowp) {
+            const DBuf& vt = full ? ctx->d_vt_full : ctx->d_vt_sym;
+            HIPC(launch_ab_f64(p, vt.as<double>(), C, T, st));
+        } else {
+            const DBuf* lp = full ? ctx->d_vt_full_lp : ctx->d_vt_sym_lp;
+            if (ab_prec == CASCI_F32)
+                HIPC(launch_ab_lowp(p, 1, lp[0].p, ctx->d_c32.p, ld32, T, st));
+            else
+                HIPC(launch_ab_lowp(p, 2, lp[1].p, ctx->d_clp.p, ld16, T, st));
+        }
+        CHECK_RC(mark(4, st));
     }
     const double s_aa = parity != 0 ? 0.5 * shift : shift;  // halved: S + p S^T doubles it
     if (lowp)
@@ -620,57 +651,44 @@ static int sigma_dev(casci_ctx* ctx, const double* C, double* S, int ab_prec, do
     else
         HIPC(launch_ss_gather_f64(ctx->d_fa_col.as<int32_t>(), ctx->d_fa_val.as<double>(), ctx->ra, Na, Nb,
                                   C, S, s_aa, 0, st));
-    CHECK_RC(mark(1));
-    if (parity != 0) {
-        CHECK_RC(mark(2));
-        CHECK_RC(mark(3));
-        HIPC(launch_sym_add(S, Na, parity, 1.0, st));
-    } else if (ctx->nb > 0) {
+    CHECK_RC(mark(1, st));
+    if (parity == 0 && ctx->nb > 0) {
         HIPC(ctx->d_t1.ensure((size_t)Nd * 8));
         HIPC(ctx->d_t2.ensure((size_t)Nd * 8));
         const bool same = ctx->nb == ctx->na;
         const DBuf& fcol = same ? ctx->d_fa_col : ctx->d_fb_col;
         const DBuf& fval = same ? ctx->d_fa_val : ctx->d_fb_val;
         HIPC(launch_transpose_f64(C, ctx->d_t1.as<double>(), Na, Nb, 0, 1.0, st));
-        CHECK_RC(mark(2));
         HIPC(launch_ss_gather_f64(fcol.as<int32_t>(), fval.as<double>(), ctx->rb, Nb, Na,
                                   ctx->d_t1.as<double>(), ctx->d_t2.as<double>(), 0.0, 0, st));
-        CHECK_RC(mark(3));
         HIPC(launch_transpose_f64(ctx->d_t2.as<double>(), S, Nb, Na, 1, 1.0, st));
-    } else {
-        CHECK_RC(mark(2));
-        CHECK_RC(mark(3));
     }
-    CHECK_RC(mark(4));
-    if (ctx->na > 0 && ctx->nb > 0) {
-        const bool full = lambda != 0.0;
-        AbParams p = ab_params(ctx, full);
-        const DBuf& vt = full ? ctx->d_vt_full : ctx->d_vt_sym;
-        if (!lowp) {
-            HIPC(launch_ab_f64(p, vt.as<double>(), C, S, st));
-        } else {
-            const DBuf* lp = full ? ctx->d_vt_full_lp : ctx->d_vt_sym_lp;
-            if (ab_prec == CASCI_F32) {
-                HIPC(launch_ab_lowp(p, 1, lp[0].p, ctx->d_c32.p, ld32, S, st));
-            } else {
-                const int64_t ld = lowp_ld(2, Nb);
-                HIPC(ctx->d_clp.ensure((size_t)Na * ld * 2));
-                HIPC(launch_convert_lowp(2, C, ctx->d_clp.p, Na, Nb, ld, st));
-                HIPC(launch_ab_lowp(p, 2, lp[1].p, ctx->d_clp.p, ld, S, st));
-            }
-        }
-    }
-    CHECK_RC(mark(5));
+    CHECK_RC(mark(2, st));
+    if (parity != 0)
+        HIPC(launch_sym_add(S, Na, parity, 1.0, st, has_ab ? ctx->d_t3.as<double>() : nullptr));
+    else if (has_ab)
+        HIPC(launch_axpby_f64(1.0, ctx->d_t3.as<double>(), 1.0, S, Nd, st));
+    CHECK_RC(mark(5, st));
     if (prof) {
         HIPC(hipEventSynchronize(ctx->pev[5]));
-        float t[5];
-        for (int i = 0; i < 5; ++i) HIPC(hipEventElapsedTime(&t[i], ctx->pev[i], ctx->pev[i + 1]));
-        ctx->prof[0] += t[0];         // alpha-alpha gather (with the FP32 conversion if any)
-        ctx->prof[1] += t[1] + t[3];  // transposes / parity symmetrisation of the beta-beta term
-        ctx->prof[2] += t[2];         // beta-beta gather
-        ctx->prof[3] += t[4];         // alpha-beta contraction (with its input conversion)
-        ctx->prof[4] += 1;            // sigma builds
-        ctx->prof[5] += lowp ? 0 : 1;
+        float t_aa = 0, t_bb = 0, t_ab = 0, t_tot = 0, t_end = 0, t_cv = 0;
+        HIPC(hipEventElapsedTime(&t_cv, ctx->pev[0], ctx->pev[3]));  // conversions of C
+        HIPC(hipEventElapsedTime(&t_aa, ctx->pev[4], ctx->pev[1]));
+        t_aa += t_cv;
+        HIPC(hipEventElapsedTime(&t_bb, ctx->pev[1], ctx->pev[2]));
+        if (has_ab) HIPC(hipEventElapsedTime(&t_ab, ctx->pev[3], ctx->pev[4]));
+        HIPC(hipEventElapsedTime(&t_end, ctx->pev[2], ctx->pev[5]));
+        HIPC(hipEventElapsedTime(&t_tot, ctx->pev[0], ctx->pev[5]));
+        // [0..5]: FP64 builds, [6..11]: low-precision builds; each: alpha-alpha
+        // gather (with the conversions of C), beta-beta work, alpha-beta
+        // contraction, final combination, whole build, number of builds
+        double* pr = ctx->prof + (lowp ? 6 : 0);
+        pr[0] += t_aa;
+        pr[1] += t_bb;
+        pr[2] += t_ab;
+        pr[3] += t_end;
+        pr[4] += t_tot;
+        pr[5] += 1;
     }
     return CASCI_OK;
 }
@@ -692,7 +710,7 @@ extern "C" int casci_profile_enable(casci_ctx* ctx, int on)
 extern "C" int casci_profile_read(const casci_ctx* ctx, double* out)
 {
     if (!ctx || !out) return CASCI_E_ARG;
-    for (int i = 0; i < 8; ++i) out[i] = ctx->prof[i];
+    for (int i = 0; i < 16; ++i) out[i] = ctx->prof[i];
     return CASCI_OK;
 }
 

@@ -56,8 +56,9 @@ hipError_t launch_ss_gather_f64(const int32_t* col, const double* val, int r, in
 hipError_t launch_ss_gather_f32in(const int32_t* col, const double* val, int r, int64_t nrows,
                                   int64_t ncols, const float* X, int64_t ldx, double* Y, double shift,
                                   int acc, hipStream_t st);
-// S <- scale (S + p S^T), S square n x n, in place
-hipError_t launch_sym_add(double* S, int64_t n, int p, double scale, hipStream_t st);
+// S <- scale (S + p S^T) [+ T], S square n x n, in place (T may be null)
+hipError_t launch_sym_add(double* S, int64_t n, int p, double scale, hipStream_t st,
+                          const double* T = nullptr);
 hipError_t launch_ss_gather_f32(const int32_t* col, const double* val, int r, int64_t nrows,
                                 int64_t ncols, const float* X, float* Y, double shift, int acc,
                                 hipStream_t st);
@@ -79,6 +80,7 @@ struct AbParams {
     const int32_t* lb_j;  // beta single list (targets of the scatter)
     int sb;               // beta list length
     const uint16_t* pairs;// [Mp] r | s << 8
+    int overwrite;        // 1: sigma(Ia,:) = term; 0: sigma(Ia,:) += term
 };
 // sigma(Ia, :) += alpha-beta term; Vt[pq][Mp] in the arithmetic's type
 // (prec 1: float, FP32 MFMA; prec 2: bf16, BF16 MFMA; both accumulate in FP32)

@@ -150,7 +150,7 @@ hipError_t launch_ss_gather_f32(const int32_t* col, const double* val, int r, in
 // written, so every output uses the original values.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_sym_add(double* __restrict__ S, int64_t n, double p,
-                                                 double scale, int64_t nb)
+                                                 double scale, int64_t nb, const double* __restrict__ T)
 {
     __shared__ double A[32][33];
     __shared__ double B[32][33];
@@ -172,21 +172,23 @@ __global__ __launch_bounds__(256) void k_sym_add(double* __restrict__ S, int64_t
     __syncthreads();
     for (int i = ty; i < 32; i += 8) {
         const int64_t ra = r0 + i, ca = c0 + tx;
-        if (ra < n && ca < n) S[ra * n + ca] = scale * (A[i][tx] + p * B[tx][i]);
+        if (ra < n && ca < n)
+            S[ra * n + ca] = scale * (A[i][tx] + p * B[tx][i]) + (T ? T[ra * n + ca] : 0.0);
         if (bi != bj) {
             const int64_t rb = c0 + i, cb = r0 + tx;
-            if (rb < n && cb < n) S[rb * n + cb] = scale * (B[i][tx] + p * A[tx][i]);
+            if (rb < n && cb < n)
+                S[rb * n + cb] = scale * (B[i][tx] + p * A[tx][i]) + (T ? T[rb * n + cb] : 0.0);
         }
     }
 }
 
-hipError_t launch_sym_add(double* S, int64_t n, int p, double scale, hipStream_t st)
+hipError_t launch_sym_add(double* S, int64_t n, int p, double scale, hipStream_t st, const double* T)
 {
     if (n <= 0) return hipSuccess;
     const int64_t nb = (n + 31) / 32;
     const int64_t pairs = nb * (nb + 1) / 2;
     if (pairs > 0x7fffffffLL) return invalid("sym_add: matrix too large");
-    hipLaunchKernelGGL(k_sym_add, dim3((unsigned)pairs), dim3(256), 0, st, S, n, (double)p, scale, nb);
+    hipLaunchKernelGGL(k_sym_add, dim3((unsigned)pairs), dim3(256), 0, st, S, n, (double)p, scale, nb, T);
     return hipGetLastError();
 }
 
@@ -481,7 +483,10 @@ __global__ __launch_bounds__(64 * AB_MAX_WAVES) void k_ab(AbParams p, const type
         __syncthreads();
     }
     double* srow = sigma + ia * p.Nb;
-    for (int64_t i = tid; i < hi - lo; i += nth) srow[lo + i] += (double)sig[i];
+    if (p.overwrite)
+        for (int64_t i = tid; i < hi - lo; i += nth) srow[lo + i] = (double)sig[i];
+    else
+        for (int64_t i = tid; i < hi - lo; i += nth) srow[lo + i] += (double)sig[i];
 }
 
 // ---------------------------------------------------------------------------
@@ -694,7 +699,10 @@ __global__ __launch_bounds__(64 * ABL_MAX_WAVES) void k_ab_lp(
         buf ^= 1;
     }
     double* srow = sigma + ia * p.Nb;
-    for (int64_t i = tid; i < hi - lo; i += nth) srow[lo + i] += (double)sig[i];
+    if (p.overwrite)
+        for (int64_t i = tid; i < hi - lo; i += nth) srow[lo + i] = (double)sig[i];
+    else
+        for (int64_t i = tid; i < hi - lo; i += nth) srow[lo + i] += (double)sig[i];
 }
 
 template <typename MF>
