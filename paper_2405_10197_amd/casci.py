@@ -319,8 +319,9 @@ class Context:
 
     def profile_read(self):
         """Per-part device time (ms) of the sigma builds since profile(True), split by
-        the arithmetic of the alpha-beta term ('f64' and 'lowp'); the alpha-beta part
-        runs concurrently with the gathers, so 'total_ms' is the wall time of the builds."""
+        the arithmetic of the alpha-beta term ('f64' and 'lowp'): alpha-alpha gather
+        (with the conversions of C), beta-beta work, alpha-beta contraction, final
+        combination and whole build, all from events on the library's stream."""
         out = np.zeros(16)
         self._check(self._L.casci_profile_read(self._h, out.ctypes.data))
         keys = ["aa_ms", "bb_ms", "ab_ms", "combine_ms", "total_ms", "sigma_builds"]

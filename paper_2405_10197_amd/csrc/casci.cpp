@@ -103,9 +103,16 @@ struct casci_ctx {
     double prepared_lambda = 0.0;
     DBuf d_h, d_eri, d_fa_col, d_fa_val, d_fb_col, d_fb_val, d_jpq, d_diag;
     DBuf d_vt_sym, d_pairs_sym, d_vt_full, d_pairs_full, d_vt_s2;
+    DBuf d_tg_sym, d_tg_full;  // alpha-beta scatter targets per (beta string, pair row)
+    struct Reduce {            // target-grouped scatter table (AbReduce) of one pair set
+        DBuf tab, tinfo;
+        int max_nseg = 0, ldT = 0;
+        bool have = false;
+    } red_sym, red_full;
     DBuf d_vt_sym_lp[2], d_vt_full_lp[2];  // FP32 and BF16 copies (round to nearest even)
     int M_sym = 0, Mp_sym = 0, M_full = 0, Mp_full = 0;
     bool have_full = false, have_s2 = false;
+    bool have_tg_sym = false, have_tg_full = false;
 
     // workspaces
     DBuf d_t1, d_t2, d_t3, d_vin, d_vout, d_work, d_small, d_clp, d_c32;
@@ -194,7 +201,8 @@ extern "C" void casci_destroy(casci_ctx* ctx)
         DBuf* bufs[] = {&ctx->d_binom, &ctx->d_astr, &ctx->d_bstr, &ctx->d_la_j, &ctx->d_la_pq,
                         &ctx->d_lb_j, &ctx->d_lb_pq, &ctx->d_h, &ctx->d_eri, &ctx->d_fa_col,
                         &ctx->d_fa_val, &ctx->d_fb_col, &ctx->d_fb_val, &ctx->d_jpq, &ctx->d_diag,
-                        &ctx->d_vt_sym, &ctx->d_pairs_sym, &ctx->d_vt_full, &ctx->d_pairs_full,
+                        &ctx->d_vt_sym, &ctx->d_pairs_sym, &ctx->d_vt_full, &ctx->d_pairs_full, &ctx->d_tg_sym, &ctx->d_tg_full,
+                        &ctx->red_sym.tab, &ctx->red_sym.tinfo, &ctx->red_full.tab, &ctx->red_full.tinfo,
                         &ctx->d_vt_s2, &ctx->d_t1, &ctx->d_t2, &ctx->d_vin, &ctx->d_vout,
                         &ctx->d_work, &ctx->d_small, &ctx->d_vt_sym_lp[0], &ctx->d_vt_sym_lp[1],
                         &ctx->d_vt_full_lp[0], &ctx->d_vt_full_lp[1], &ctx->d_clp, &ctx->d_c32, &ctx->d_t3,
@@ -269,6 +277,8 @@ extern "C" int casci_set_integrals(casci_ctx* ctx, int norb, const double* h, co
     ctx->has_ints = true;
     ctx->prepared = false;
     ctx->have_full = ctx->have_s2 = false;
+    ctx->have_tg_sym = ctx->have_tg_full = false;
+    ctx->red_sym.have = ctx->red_full.have = false;
     return CASCI_OK;
 }
 
@@ -357,6 +367,8 @@ extern "C" int casci_build_strings(casci_ctx* ctx, int nalpha, int nbeta, int no
     ctx->has_strings = true;
     ctx->prepared = false;
     ctx->have_full = ctx->have_s2 = false;
+    ctx->have_tg_sym = ctx->have_tg_full = false;
+    ctx->red_sym.have = ctx->red_full.have = false;
     return CASCI_OK;
 }
 
@@ -539,6 +551,8 @@ static int ensure_prepared(casci_ctx* ctx, double lambda)
         CHECK_RC(upload_lowp(ctx, vt, ctx->d_vt_sym_lp));
         ctx->prepared = true;
         ctx->have_full = false;
+        ctx->have_tg_sym = ctx->have_tg_full = false;
+        ctx->red_sym.have = ctx->red_full.have = false;
         ctx->prepared_lambda = std::nan("");
     }
     if (!(ctx->prepared_lambda == lambda)) {
@@ -585,7 +599,152 @@ static AbParams ab_params(const casci_ctx* ctx, bool full)
     p.sb = ctx->sb;
     p.overwrite = 0;
     p.pairs = (full ? ctx->d_pairs_full : ctx->d_pairs_sym).as<uint16_t>();
+    p.tg = (full ? ctx->d_tg_full : ctx->d_tg_sym).as<int32_t>();
     return p;
+}
+
+// scatter-target table of the pair set (needs the strings, lists and pairs on device)
+static int ensure_targets(casci_ctx* ctx, bool full)
+{
+    bool& have = full ? ctx->have_tg_full : ctx->have_tg_sym;
+    if (have) return CASCI_OK;
+    DBuf& tg = full ? ctx->d_tg_full : ctx->d_tg_sym;
+    AbParams p = ab_params(ctx, full);
+    HIPC(tg.ensure((size_t)ctx->Nb * p.Mp * 4));
+    p.tg = tg.as<int32_t>();
+    HIPC(launch_ab_targets(p, tg.as<int32_t>(), ctx->stream));
+    have = true;
+    return CASCI_OK;
+}
+
+// Target-grouped table of the low-precision alpha-beta kernel (layout in
+// internal.h, AbReduce), built on the host from the target table.
+static int ensure_reduce(casci_ctx* ctx, bool full, AbReduce* out)
+{
+    casci_ctx::Reduce& R = full ? ctx->red_full : ctx->red_sym;
+    if (!R.have) {
+        CHECK_RC(ensure_targets(ctx, full));
+        const int Mp = full ? ctx->Mp_full : ctx->Mp_sym;
+        const int64_t Nb = ctx->Nb;
+        const int TN = 64;
+        const int ldT = Mp + 4;
+        const int zslot = TN * ldT;
+        if (zslot + 1 > 0x7fff)
+            return ctx->fail(CASCI_E_UNSUPPORTED, "alpha-beta: too many pair rows for the low-precision table");
+        if (Nb >= 0xffff)
+            return ctx->fail(CASCI_E_UNSUPPORTED, "alpha-beta: more than 65534 beta strings for the low-precision table");
+        std::vector<int32_t> tg((size_t)Nb * Mp);
+        HIPC(hipMemcpyAsync(tg.data(), (full ? ctx->d_tg_full : ctx->d_tg_sym).p, tg.size() * 4,
+                            hipMemcpyDeviceToHost, ctx->stream));
+        HIPC(hipStreamSynchronize(ctx->stream));
+        const int64_t ntiles = (Nb + TN - 1) / TN;
+        const int W = abl_waves(Mp);
+        std::vector<uint32_t> words;
+        std::vector<int32_t> tinfo((size_t)ntiles * 2);
+        std::vector<std::pair<int32_t, uint16_t>> con;
+        struct Group {
+            int32_t target;
+            int begin, count;
+        };
+        std::vector<Group> grp;
+        std::vector<uint16_t> off;
+        int max_nseg = 0;
+        for (int64_t t = 0; t < ntiles; ++t) {
+            con.clear();
+            for (int jl = 0; jl < TN && t * TN + jl < Nb; ++jl)
+                for (int m = 0; m < Mp; ++m) {
+                    const int32_t e = tg[(size_t)(t * TN + jl) * Mp + m];
+                    if (e == INT32_MIN) continue;
+                    con.push_back({l1_index(e), (uint16_t)((jl * ldT + m) | (e < 0 ? 0x8000 : 0))});
+                }
+            std::stable_sort(con.begin(), con.end(),
+                             [](const std::pair<int32_t, uint16_t>& a, const std::pair<int32_t, uint16_t>& b) {
+                                 return a.first < b.first;
+                             });
+            grp.clear();
+            for (size_t i = 0; i < con.size();) {
+                size_t j = i;
+                while (j < con.size() && con[j].first == con[i].first) ++j;
+                grp.push_back({con[i].first, (int)i, (int)(j - i)});
+                i = j;
+            }
+            std::stable_sort(grp.begin(), grp.end(), [](const Group& a, const Group& b) { return a.count > b.count; });
+            // chunks of 64 groups, largest first; blocks of 4 contributions
+            const int nreal = (int)((grp.size() + 63) / 64);
+            std::vector<int> cblocks(nreal);
+            for (int q = 0; q < nreal; ++q) cblocks[q] = (grp[(size_t)q * 64].count + 3) / 4;
+            // longest-first assignment to the least loaded wave; the chunks of
+            // wave w are stored contiguously, wave by wave
+            std::vector<std::vector<int>> per_wave(W);
+            std::vector<int64_t> load(W, 0);
+            for (int q = 0; q < nreal; ++q) {
+                const int w = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+                per_wave[w].push_back(q);
+                load[w] += cblocks[q] + 1;
+            }
+            std::vector<int> order;
+            std::vector<uint16_t> wb(((size_t)W + 1 + 7) / 8 * 8, 0);
+            for (int w = 0; w < W; ++w) {
+                order.insert(order.end(), per_wave[w].begin(), per_wave[w].end());
+                wb[w + 1] = (uint16_t)order.size();
+            }
+            const int nch = (int)order.size();
+            const int dsegs = (nch + 3) / 4;
+            const size_t seg0 = words.size() / 4;
+            for (size_t i = 0; i < wb.size(); i += 2) words.push_back((uint32_t)wb[i] | ((uint32_t)wb[i + 1] << 16));
+            std::vector<uint32_t> desc((size_t)dsegs * 4, 0u);
+            int blocks = 0;
+            for (int q = 0; q < nch; ++q) {
+                const int nb = cblocks[order[q]];
+                if (nb >= 4096 || blocks + nb >= (1 << 20))
+                    return ctx->fail(CASCI_E_UNSUPPORTED, "alpha-beta: scatter table tile too large");
+                desc[q] = (uint32_t)blocks | ((uint32_t)nb << 20);
+                blocks += nb;
+            }
+            words.insert(words.end(), desc.begin(), desc.end());
+            for (int q = 0; q < nch; ++q)
+                for (int lane = 0; lane < 64; lane += 2) {
+                    uint32_t pr = 0;
+                    for (int h = 0; h < 2; ++h) {
+                        const size_t g = (size_t)order[q] * 64 + lane + h;
+                        const uint32_t v = g < grp.size() ? (uint32_t)grp[g].target : 0xffffu;
+                        pr |= v << (16 * h);
+                    }
+                    words.push_back(pr);
+                }
+            off.assign((size_t)blocks * 256, (uint16_t)zslot);
+            for (int q = 0; q < nch; ++q) {
+                const int cb = (int)(desc[q] & 0xfffff);
+                for (int lane = 0; lane < 64; ++lane) {
+                    const size_t g = (size_t)order[q] * 64 + lane;
+                    if (g >= grp.size()) continue;
+                    for (int c = 0; c < grp[g].count; ++c)
+                        off[((size_t)(cb + c / 4) * 64 + lane) * 4 + c % 4] = con[grp[g].begin + c].second;
+                }
+            }
+            for (size_t i = 0; i < off.size(); i += 2) words.push_back((uint32_t)off[i] | ((uint32_t)off[i + 1] << 16));
+            const size_t nseg = words.size() / 4 - seg0;
+            if (seg0 > 0x7fffffff || nseg >= (1u << 20))
+                return ctx->fail(CASCI_E_UNSUPPORTED, "alpha-beta: scatter table too large");
+            tinfo[(size_t)t * 2] = (int32_t)seg0;
+            tinfo[(size_t)t * 2 + 1] = (int32_t)(nseg | ((size_t)nch << 20));
+            max_nseg = std::max(max_nseg, (int)nseg);
+        }
+        if (words.empty()) words.assign(4, 0u);
+        HIPC(R.tab.ensure(words.size() * 4));
+        HIPC(R.tinfo.ensure(tinfo.size() * 4 + 8));
+        HIPC(hipMemcpyAsync(R.tab.p, words.data(), words.size() * 4, hipMemcpyHostToDevice, ctx->stream));
+        HIPC(hipMemcpyAsync(R.tinfo.p, tinfo.data(), tinfo.size() * 4, hipMemcpyHostToDevice, ctx->stream));
+        HIPC(hipStreamSynchronize(ctx->stream));
+        R.max_nseg = max_nseg;
+        R.ldT = ldT;
+        R.have = true;
+    }
+    out->tab = R.tab.as<uint4>();
+    out->tinfo = R.tinfo.as<int2>();
+    out->max_nseg = R.max_nseg;
+    out->ldT = R.ldT;
+    return CASCI_OK;
 }
 
 // sigma = (H + lambda S^2) C on device vectors (FP64 storage).
@@ -629,6 +788,7 @@ static int sigma_dev(casci_ctx* ctx, const double* C, double* S, int ab_prec, do
         HIPC(ctx->d_t3.ensure((size_t)Nd * 8));
         CHECK_RC(mark(3, st));
         const bool full = lambda != 0.0;
+        CHECK_RC(ensure_targets(ctx, full));
         AbParams p = ab_params(ctx, full);
         p.overwrite = 1;
         double* T = ctx->d_t3.as<double>();
@@ -637,10 +797,12 @@ static int sigma_dev(casci_ctx* ctx, const double* C, double* S, int ab_prec, do
             HIPC(launch_ab_f64(p, vt.as<double>(), C, T, st));
         } else {
             const DBuf* lp = full ? ctx->d_vt_full_lp : ctx->d_vt_sym_lp;
+            AbReduce red;
+            CHECK_RC(ensure_reduce(ctx, full, &red));
             if (ab_prec == CASCI_F32)
-                HIPC(launch_ab_lowp(p, 1, lp[0].p, ctx->d_c32.p, ld32, T, st));
+                HIPC(launch_ab_lowp(p, red, 1, lp[0].p, ctx->d_c32.p, ld32, T, st));
             else
-                HIPC(launch_ab_lowp(p, 2, lp[1].p, ctx->d_clp.p, ld16, T, st));
+                HIPC(launch_ab_lowp(p, red, 2, lp[1].p, ctx->d_clp.p, ld16, T, st));
         }
         CHECK_RC(mark(4, st));
     }
@@ -873,6 +1035,7 @@ static int spin_square_dev(casci_ctx* ctx, const double* C, double* s2)
         }
         HIPC(ctx->d_t2.ensure((size_t)ctx->Nd * 8));
         HIPC(hipMemsetAsync(ctx->d_t2.p, 0, (size_t)ctx->Nd * 8, st));
+        CHECK_RC(ensure_targets(ctx, true));
         AbParams p = ab_params(ctx, true);
         HIPC(launch_ab_f64(p, ctx->d_vt_s2.as<double>(), C, ctx->d_t2.as<double>(), st));
         std::vector<double> cs;

@@ -80,14 +80,41 @@ struct AbParams {
     const int32_t* lb_j;  // beta single list (targets of the scatter)
     int sb;               // beta list length
     const uint16_t* pairs;// [Mp] r | s << 8
+    const int32_t* tg;    // [Nb][Mp] scatter targets (launch_ab_targets)
     int overwrite;        // 1: sigma(Ia,:) = term; 0: sigma(Ia,:) += term
 };
+// tg[Jb][m] = E_{r_m s_m} Jb as a list entry (index, sign folded), INT32_MIN where it vanishes
+hipError_t launch_ab_targets(const AbParams& p, int32_t* tg, hipStream_t st);
+// Target-grouped scatter table of the low-precision alpha-beta kernel. For
+// each 64-column tile of beta strings Jb, the contributions (m, Jb) -> Ib of
+// that tile are grouped by target Ib; the groups, sorted by size (largest
+// first), are packed 64 to a chunk (one group per lane), and the chunks are
+// dealt to the W waves of the workgroup, longest first to the least loaded
+// one. A tile's block of 16-byte segments holds, each section padded to 16
+// bytes:
+//   wb[W+1]           uint16: wave w reduces chunks wb[w] .. wb[w+1]-1
+//   desc[nchunk]      uint32: first block | blocks << 20
+//   tgt[nchunk*64]    uint16: target Ib of each lane's group (0xffff: none)
+//   off[blocks*64*4]  uint16: T-tile offset (Jb_local * ldT + m) | sign << 15;
+//                             block b, lane l holds the lane's contributions
+//                             4b..4b+3 at [(b*64 + l)*4 + 0..3]; unused slots
+//                             point to the zero slot 64 * ldT
+// tinfo[t] = {first segment, nseg | nchunk << 20}. Targets fit 16 bits, so
+// the table needs Nb < 65535.
+struct AbReduce {
+    const uint4* tab;
+    const int2* tinfo;
+    int max_nseg;  // largest tile block, in segments
+    int ldT;       // row stride (floats) of the LDS T tile: Mp + 4
+};
+// waves per workgroup of the low-precision alpha-beta kernel for Mp pair rows
+int abl_waves(int Mp);
 // sigma(Ia, :) += alpha-beta term; Vt[pq][Mp] in the arithmetic's type
 // (prec 1: float, FP32 MFMA; prec 2: bf16, BF16 MFMA; both accumulate in FP32)
 hipError_t launch_ab_f64(const AbParams& p, const double* Vt, const double* C, double* sigma,
                          hipStream_t st);
-hipError_t launch_ab_lowp(const AbParams& p, int prec, const void* Vt, const void* Cs, int64_t ldc,
-                          double* sigma, hipStream_t st);
+hipError_t launch_ab_lowp(const AbParams& p, const AbReduce& r, int prec, const void* Vt, const void* Cs,
+                          int64_t ldc, double* sigma, hipStream_t st);
 // padded row stride of the low-precision copy of C, and the conversion itself
 int64_t lowp_ld(int prec, int64_t cols);
 hipError_t launch_convert_lowp(int prec, const double* C, void* out, int64_t rows, int64_t cols,

@@ -249,13 +249,20 @@ hipError_t launch_transpose_f32(const float* in, float* out, int64_t rows, int64
 // Pair rows m: r <= s when the integrals are symmetric in rs (T(rs) = T(sr);
 // the one of E_rs / E_sr that does not vanish on Jb is applied), or all
 // ordered (r, s) when an S^2 penalty (not rs-symmetric) is folded in.
-// Scatter targets and signs are read from the beta single-substitution list
-// of Jb: the entry (p=a, q=b) of L1(Jb) is the string Jb - a + b.
-// The next tile of C is loaded into registers while the current one is
-// multiplied, so the gather latency hides behind the MFMA work.
+// The scatter target of (m, Jb) does not depend on Ia, so it is tabulated once
+// per string set: tg[Jb][m] = Ib with the sign folded in as in the lists
+// (Ib or ~Ib), AB_NONE where E_rs Jb vanishes. Each lane reads the entries of
+// exactly the accumulator elements it owns: the A rows are ordered so that a
+// lane's four accumulator elements are four consecutive pair rows, i.e. one
+// 16-byte load per 16-column sub-tile.
+// The next tile of C and its targets are loaded into registers while the
+// current one is multiplied, so the gather latency hides behind the MFMA work.
 typedef double d4 __attribute__((ext_vector_type(4)));
 typedef float f4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+typedef int i4 __attribute__((ext_vector_type(4)));
+
+constexpr int32_t AB_NONE = INT32_MIN;  // tabulated target of a vanishing E_rs Jb
 
 constexpr int AB_TN = 64;
 
@@ -270,8 +277,10 @@ struct MfmaF64 {
     {
         return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
     }
-    // accumulator element v of a lane holds row 4*v + lane/16, column lane%16
-    __device__ static int row(int v, int lane) { return 4 * v + (lane >> 4); }
+    // accumulator element v of a lane holds row 4*v + lane/16, column lane%16;
+    // A row r carries pair row 4*(r%4) + r/4 so that element v of a lane holds
+    // pair row 4*(lane/16) + v
+    __device__ static int arow(int r) { return 4 * (r & 3) + (r >> 2); }
     __device__ static elem cvt(double x) { return x; }
 };
 
@@ -286,7 +295,8 @@ struct MfmaF32 {
     {
         return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
     }
-    __device__ static int row(int v, int lane) { return 4 * (lane >> 4) + v; }
+    // accumulator element v of a lane holds row 4*(lane/16) + v
+    __device__ static int arow(int r) { return r; }
     __device__ static elem cvt(double x) { return (float)x; }
 };
 
@@ -301,7 +311,7 @@ struct MfmaBF16 {
     {
         return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
     }
-    __device__ static int row(int v, int lane) { return 4 * (lane >> 4) + v; }
+    __device__ static int arow(int r) { return r; }
     __device__ static elem cvt(double x) { return (__bf16)(float)x; }
 };
 
@@ -338,6 +348,73 @@ __device__ inline int ab_lookup(uint64_t jb, int r, int s, int full, int n, int 
     return l1_index(enc);
 }
 
+// tg[j * Mp + m] for every beta string j and pair row m < Mp
+__global__ __launch_bounds__(256) void k_ab_targets(AbParams p, int32_t* __restrict__ tg)
+{
+    const int64_t total = p.Nb * p.Mp;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t j = i / p.Mp;
+        const int m = (int)(i - j * p.Mp);
+        int32_t out = AB_NONE;
+        if (m < p.M) {
+            const int code = p.pairs[m];
+            int sg;
+            const int t = ab_lookup(p.bstr[j], code & 0xff, code >> 8, p.full, p.n, p.nb, p.sb, p.lb_j, j, &sg);
+            if (t >= 0) out = l1_encode(t, sg);
+        }
+        tg[i] = out;
+    }
+}
+
+hipError_t launch_ab_targets(const AbParams& p, int32_t* tg, hipStream_t st)
+{
+    if (p.Nb <= 0 || p.Mp <= 0) return hipSuccess;
+    if (p.Mp % 16 != 0) return invalid("alpha-beta targets: pair rows not padded to 16");
+    int64_t g = (p.Nb * p.Mp + 255) / 256;
+    if (g > 65536) g = 65536;
+    hipLaunchKernelGGL(k_ab_targets, dim3((unsigned)g), dim3(256), 0, st, p, tg);
+    return hipGetLastError();
+}
+
+// targets of the accumulator elements a lane owns in one 64-column tile
+template <int MT>
+__device__ inline void ab_load_targets(const AbParams& p, int64_t j0, int wave, int nwaves, int lane,
+                                       i4 (&dst)[MT][4])
+{
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) {
+        const int m0 = (wave + mt * nwaves) * 16;
+#pragma unroll
+        for (int ns = 0; ns < 4; ++ns) {
+            const int64_t jc = j0 + ns * 16 + (lane & 15);
+            i4 v = {AB_NONE, AB_NONE, AB_NONE, AB_NONE};
+            if (m0 < p.Mp && jc < p.Nb) v = *reinterpret_cast<const i4*>(p.tg + jc * p.Mp + m0 + 4 * (lane >> 4));
+            dst[mt][ns] = v;
+        }
+    }
+}
+
+// scatter-add of one 16x64 accumulator block into the LDS row chunk [lo, hi)
+template <typename LACC, typename ACC>
+__device__ inline void ab_scatter(LACC* sig, const ACC (&acc)[4], const i4 (&tgt)[4], int64_t lo, int64_t hi)
+{
+#pragma unroll
+    for (int ns = 0; ns < 4; ++ns) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int32_t e = tgt[ns][v];
+            if (e != AB_NONE) {
+                const int64_t tgi = l1_index(e);
+                if (tgi >= lo && tgi < hi) {
+                    const LACC x = (LACC)acc[ns][v];
+                    atomicAdd(&sig[tgi - lo], e >= 0 ? x : -x);
+                }
+            }
+        }
+    }
+}
+
 constexpr int AB_MAX_WAVES = 12;
 
 template <typename MF, int KBMAX, int MT, int PF>
@@ -369,13 +446,12 @@ __global__ __launch_bounds__(64 * AB_MAX_WAVES) void k_ab(AbParams p, const type
     for (int64_t i = tid; i < hi - lo; i += nth) sig[i] = (lacc)0;
     for (int i = tid; i < Kp; i += nth) sJ[i] = i < p.sa ? l1_index(p.la_j[ia * p.sa + i]) : 0;
 
-    // A fragments and the pair (r, s) of each accumulator row this lane owns
+    // A fragments (row lane%16 of each M tile carries pair row arow(lane%16))
     typename MF::frag afr[MT][KBMAX];
-    int pr[MT][4];  // r | s << 8, or -1
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt) {
         const int m0 = (wave + mt * nwaves) * 16;
-        const int m = m0 + (lane & 15);
+        const int m = m0 + MF::arow(lane & 15);
 #pragma unroll
         for (int kb = 0; kb < KBMAX; ++kb) {
             typename MF::frag f;
@@ -394,11 +470,6 @@ __global__ __launch_bounds__(64 * AB_MAX_WAVES) void k_ab(AbParams p, const type
                 if constexpr (PER == 1) f = v; else f[q] = v;
             }
             afr[mt][kb] = f;
-        }
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const int mm = m0 + MF::row(v, lane);
-            pr[mt][v] = mm < p.M ? (int)p.pairs[mm] : -1;
         }
     }
     __syncthreads();
@@ -431,6 +502,9 @@ __global__ __launch_bounds__(64 * AB_MAX_WAVES) void k_ab(AbParams p, const type
 
     for (int64_t j0 = 0; j0 < p.Nb; j0 += AB_TN) {
         const bool more = j0 + AB_TN < p.Nb;
+        // this tile's targets: their latency hides behind the FP64 MFMA chain
+        i4 tgc[MT][4];
+        ab_load_targets<MT>(p, j0, wave, nwaves, lane, tgc);
         if (more) load_tile(j0 + AB_TN);
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt) {
@@ -458,25 +532,7 @@ __global__ __launch_bounds__(64 * AB_MAX_WAVES) void k_ab(AbParams p, const type
                     }
                 }
             }
-            // scatter: target string and sign from the beta list of column Jb
-#pragma unroll
-            for (int ns = 0; ns < 4; ++ns) {
-                const int64_t jcol = j0 + ns * 16 + (lane & 15);
-                if (jcol >= p.Nb) continue;
-                const uint64_t jb = p.bstr[jcol];
-#pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    const int code = pr[mt][v];
-                    if (code < 0) continue;
-                    int sg;
-                    const int tg = ab_lookup(jb, code & 0xff, code >> 8, p.full, p.n, p.nb, p.sb, p.lb_j,
-                                             jcol, &sg);
-                    if (tg >= lo && tg < hi) {
-                        const lacc x = (lacc)acc[ns][v];
-                        atomicAdd(&sig[tg - lo], sg > 0 ? x : -x);
-                    }
-                }
-            }
+            ab_scatter<lacc, acc_t>(sig, acc, tgc[mt], lo, hi);
         }
         __syncthreads();
         if (more) store_tile();
@@ -492,44 +548,25 @@ __global__ __launch_bounds__(64 * AB_MAX_WAVES) void k_ab(AbParams p, const type
 // ---------------------------------------------------------------------------
 // low-precision alpha-beta contraction (FP32 or BF16 MFMA, FP32 accumulate)
 // ---------------------------------------------------------------------------
-// Same algorithm as k_ab, tuned for the case where the MFMA work is cheap:
-// C is first converted once per sigma to the MFMA input type with its rows
-// padded to a multiple of 16 bytes, so D tiles are gathered with 16-byte
-// loads (a BF16 tile row of 64 columns is one 128-byte line); the tiles are
-// double-buffered in LDS and the sigma row is accumulated in FP32, which
-// keeps one workgroup under 80 KB of LDS so that two share a CU and hide each
-// other's gather and scatter latency.
+// Same contraction as k_ab, with the scatter done without atomics. C is first
+// converted once per sigma to the MFMA input type with its rows padded to a
+// multiple of 16 bytes, so D tiles are gathered with 16-byte loads (a BF16
+// tile row of 64 columns is one 128-byte line). Per 64-column tile:
+//   1. MFMA: T(m, Jb) for all pair rows, written to an LDS tile Ts[Jb][m];
+//   2. reduce: each lane owns one target Ib of the tile (from the grouped
+//      table, see AbReduce) and adds the signed T entries of its group into
+//      the FP32 sigma row in LDS with a plain read-add-write. A target occurs
+//      once per tile, so no two lanes touch the same word, and every sum is
+//      taken in a fixed order (the result is bitwise reproducible).
+// The next tile's C segments and table block are loaded into registers while
+// the current tile is multiplied and reduced.
 constexpr int ABL_MAX_WAVES = 12;
-
-// scatter target from an LDS copy of the tile's beta list rows (row = column cl)
-__device__ inline int ab_lookup_lds(uint64_t jb, int r, int s, int full, int n, int nb_el, int sb,
-                                    const int32_t* __restrict__ Lt, int cl, int64_t jcol, int* sign)
-{
-    *sign = 1;
-    const int orr = (jb >> r) & 1, oss = (jb >> s) & 1;
-    if (r == s) return orr ? (int)jcol : -1;
-    int a, b;
-    if (full) {
-        if (!oss || orr) return -1;
-        a = s;
-        b = r;
-    } else {
-        if (orr == oss) return -1;
-        a = oss ? s : r;
-        b = oss ? r : s;
-    }
-    const uint64_t nmask = (n >= 64) ? ~0ull : ((1ull << n) - 1);
-    const int pos = __popcll(jb & ((1ull << a) - 1)) * (n - nb_el + 1) +
-                    __popcll(~jb & nmask & ((1ull << b) - 1)) + (a < b ? 1 : 0);
-    const int32_t enc = Lt[cl * sb + pos];
-    *sign = l1_sign(enc);
-    return l1_index(enc);
-}
 
 template <typename MF, int KBMAX, int MT, int SPT>
 __global__ __launch_bounds__(64 * ABL_MAX_WAVES) void k_ab_lp(
-    AbParams p, const typename MF::elem* __restrict__ Vt, const typename MF::elem* __restrict__ Cs,
-    int64_t ldc, double* __restrict__ sigma, int kb_count, int64_t chunk, int nchunks)
+    AbParams p, AbReduce r, const typename MF::elem* __restrict__ Vt,
+    const typename MF::elem* __restrict__ Cs, int64_t ldc, double* __restrict__ sigma, int kb_count,
+    int64_t chunk, int nchunks)
 {
     using elem = typename MF::elem;
     using acc_t = typename MF::acc;
@@ -539,15 +576,14 @@ __global__ __launch_bounds__(64 * ABL_MAX_WAVES) void k_ab_lp(
     extern __shared__ __align__(16) unsigned char smem[];
     const int Kp = kb_count * MF::K;
     const int tsz = ((TileLayout<MF>::size(Kp) * (int)sizeof(elem) + 15) / 16) * 16;
-    const int lsz = AB_TN * p.sb * 4;  // list rows of one tile (multiple of 256 bytes)
+    const int ldT = r.ldT;
+    const int zslot = AB_TN * ldT;
     float* sig = reinterpret_cast<float*>(smem);
     unsigned char* base = smem + ((chunk * 4 + 15) / 16) * 16;
-    elem* Dt0 = reinterpret_cast<elem*>(base);
-    elem* Dt1 = reinterpret_cast<elem*>(base + tsz);
-    int32_t* Lt0 = reinterpret_cast<int32_t*>(base + 2 * tsz);
-    int32_t* Lt1 = reinterpret_cast<int32_t*>(base + 2 * tsz + lsz);
-    uint64_t* sB = reinterpret_cast<uint64_t*>(base + 2 * tsz + 2 * lsz);  // [2][TN]
-    int* sJ = reinterpret_cast<int*>(sB + 2 * AB_TN);
+    elem* Dt = reinterpret_cast<elem*>(base);
+    float* Ts = reinterpret_cast<float*>(base + tsz);
+    unsigned char* Tab = base + tsz + (((int64_t)zslot + 4) * 4 + 15) / 16 * 16;
+    int* sJ = reinterpret_cast<int*>(Tab + (int64_t)r.max_nseg * 16);
 
     const int64_t per_xcd = gridDim.x / 8;
     const int64_t t = (int64_t)(blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
@@ -562,13 +598,13 @@ __global__ __launch_bounds__(64 * ABL_MAX_WAVES) void k_ab_lp(
 
     for (int64_t i = tid; i < hi - lo; i += nth) sig[i] = 0.f;
     for (int i = tid; i < Kp; i += nth) sJ[i] = i < p.sa ? l1_index(p.la_j[ia * p.sa + i]) : -1;
+    if (tid == 0) Ts[zslot] = 0.f;
 
     typename MF::frag afr[MT][KBMAX];
-    int pr[MT][4];
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt) {
         const int m0 = (wave + mt * nwaves) * 16;
-        const int m = m0 + (lane & 15);
+        const int m = m0 + MF::arow(lane & 15);
 #pragma unroll
         for (int kb = 0; kb < KBMAX; ++kb) {
             typename MF::frag f;
@@ -587,24 +623,20 @@ __global__ __launch_bounds__(64 * ABL_MAX_WAVES) void k_ab_lp(
             }
             afr[mt][kb] = f;
         }
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const int mm = m0 + MF::row(v, lane);
-            pr[mt][v] = mm < p.M ? (int)p.pairs[mm] : -1;
-        }
     }
     __syncthreads();
 
-    // One tile: Kp x SEGS segments of C plus the TN list rows (contiguous in
-    // memory). issue() starts the global loads into registers, commit() stores
-    // them to the idle LDS buffers after this tile's MFMA work.
+    // Segments of one tile: nseg of C (Kp rows x SEGS), then the tile's table
+    // block. issue() starts the global loads into a register set; commit_d()
+    // and commit_t() store a set to LDS once the current tile no longer needs
+    // the buffer. Two register sets keep the loads of the next two tiles in
+    // flight while the current one is multiplied and reduced.
     const int nseg = Kp * SEGS;
-    const int nlseg = lsz / 16;
-    const int ntot = nseg + nlseg;
-    vec_t pf[SPT];
-    uint64_t pfb = 0;
-    const int64_t list_end = p.Nb * (int64_t)p.sb;  // in int32
-    auto issue = [&](int64_t j0) {
+    const int64_t ntiles = (p.Nb + AB_TN - 1) / AB_TN;
+    auto issue = [&](vec_t (&pf)[SPT], int64_t tile) {
+        const int2 ti = r.tinfo[tile];
+        const int64_t j0 = tile * AB_TN;
+        const int tseg0 = ti.x, tnseg = ti.y & 0xfffff;
 #pragma unroll
         for (int q = 0; q < SPT; ++q) {
             const int sidx = tid + q * nth;
@@ -614,15 +646,13 @@ __global__ __launch_bounds__(64 * ABL_MAX_WAVES) void k_ab_lp(
                 const int64_t col = j0 + sg * VEC;
                 const int J = sJ[k];
                 if (J >= 0 && col < ldc) v = *reinterpret_cast<const vec_t*>(Cs + J * ldc + col);
-            } else if (sidx < ntot) {
-                const int64_t off = j0 * p.sb + (int64_t)(sidx - nseg) * 4;
-                if (off < list_end) v = *reinterpret_cast<const vec_t*>(p.lb_j + off);
+            } else if (sidx - nseg < tnseg) {
+                v = r.tab[tseg0 + (sidx - nseg)];
             }
             pf[q] = v;
         }
-        pfb = (tid < AB_TN && j0 + tid < p.Nb) ? p.bstr[j0 + tid] : 0ull;
     };
-    auto commit = [&](elem* Dt, int32_t* Lt, uint64_t* sb) {
+    auto commit_d = [&](const vec_t (&pf)[SPT]) {
 #pragma unroll
         for (int q = 0; q < SPT; ++q) {
             const int sidx = tid + q * nth;
@@ -631,23 +661,19 @@ __global__ __launch_bounds__(64 * ABL_MAX_WAVES) void k_ab_lp(
                 const elem* ve = reinterpret_cast<const elem*>(&pf[q]);
 #pragma unroll
                 for (int e = 0; e < VEC; ++e) Dt[TileLayout<MF>::at(k, sg * VEC + e, Kp)] = ve[e];
-            } else if (sidx < ntot) {
-                *reinterpret_cast<vec_t*>(Lt + (sidx - nseg) * 4) = pf[q];
             }
         }
-        if (tid < AB_TN) sb[tid] = pfb;
     };
-    issue(0);
-    commit(Dt0, Lt0, sB);
-    __syncthreads();
-
-    int buf = 0;
-    for (int64_t j0 = 0; j0 < p.Nb; j0 += AB_TN) {
-        elem* Dt = buf ? Dt1 : Dt0;
-        const int32_t* Lt = buf ? Lt1 : Lt0;
-        const uint64_t* sb = sB + buf * AB_TN;
-        const bool more = j0 + AB_TN < p.Nb;
-        if (more) issue(j0 + AB_TN);
+    auto commit_t = [&](const vec_t (&pf)[SPT], int tnseg) {
+#pragma unroll
+        for (int q = 0; q < SPT; ++q) {
+            const int sidx = tid + q * nth;
+            if (sidx >= nseg && sidx - nseg < tnseg)
+                reinterpret_cast<vec_t*>(Tab)[sidx - nseg] = pf[q];
+        }
+    };
+    // multiply and reduce the tile held in LDS; then commit the next one (in pfn)
+    auto step = [&](int64_t tile, int nch, const vec_t (&pfn)[SPT], bool has_next, int nseg_next) {
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt) {
             const int mtile = wave + mt * nwaves;
@@ -674,30 +700,75 @@ __global__ __launch_bounds__(64 * ABL_MAX_WAVES) void k_ab_lp(
                     }
                 }
             }
+            // element v of this lane: pair row mtile*16 + 4*(lane/16) + v, column ns*16 + lane%16
 #pragma unroll
-            for (int ns = 0; ns < 4; ++ns) {
-                const int cl = ns * 16 + (lane & 15);
-                const int64_t jcol = j0 + cl;
-                if (jcol >= p.Nb) continue;
-                const uint64_t jb = sb[cl];
+            for (int ns = 0; ns < 4; ++ns)
+                *reinterpret_cast<f4*>(&Ts[(ns * 16 + (lane & 15)) * ldT + mtile * 16 + 4 * (lane >> 4)]) = acc[ns];
+        }
+        __syncthreads();
+        if (has_next) commit_d(pfn);
+        {
+            const uint16_t* wb = reinterpret_cast<const uint16_t*>(Tab);
+            const int hsegs = (nwaves + 1 + 7) >> 3;
+            const int dsegs = (nch + 3) >> 2;
+            const uint32_t* dsc = reinterpret_cast<const uint32_t*>(Tab + hsegs * 16);
+            const uint16_t* tgt = reinterpret_cast<const uint16_t*>(Tab + (hsegs + dsegs) * 16);
+            const uint2* off = reinterpret_cast<const uint2*>(Tab + (hsegs + dsegs + nch * 8) * 16);
+            const int qe = wb[wave + 1];
+            for (int q = wb[wave]; q < qe; ++q) {
+                const uint32_t d = dsc[q];
+                const int cb = (int)(d & 0xfffff), nbk = (int)(d >> 20);
+                const int tg = tgt[q * 64 + lane];
+                float s = 0.f;
+                for (int b = 0; b < nbk; ++b) {
+                    const uint2 w = off[(cb + b) * 64 + lane];
+                    const uint32_t o[4] = {w.x & 0xffffu, w.x >> 16, w.y & 0xffffu, w.y >> 16};
+                    float v[4];
 #pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    const int code = pr[mt][v];
-                    if (code < 0) continue;
-                    int sg;
-                    const int tg = ab_lookup_lds(jb, code & 0xff, code >> 8, p.full, p.n, p.nb, p.sb, Lt, cl,
-                                                 jcol, &sg);
-                    if (tg >= lo && tg < hi) {
-                        const float x = acc[ns][v];
-                        atomicAdd(&sig[tg - lo], sg > 0 ? x : -x);
-                    }
+                    for (int u = 0; u < 4; ++u) v[u] = Ts[o[u] & 0x7fff];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) s += (o[u] & 0x8000) ? -v[u] : v[u];
                 }
+                if (tg != 0xffff && tg >= lo && tg < hi) sig[tg - lo] += s;
             }
         }
-        if (more) commit(buf ? Dt0 : Dt1, buf ? Lt0 : Lt1, sB + (1 - buf) * AB_TN);
         __syncthreads();
-        buf ^= 1;
+        if (has_next) commit_t(pfn, nseg_next);
+        (void)tile;
+    };
+
+    vec_t pfa[SPT], pfb[SPT];
+    int2 ti0 = r.tinfo[0];
+    int2 ti1 = {0, 0};
+    issue(pfa, 0);
+    if (ntiles > 1) {
+        ti1 = r.tinfo[1];
+        issue(pfb, 1);
     }
+    commit_d(pfa);
+    commit_t(pfa, ti0.y & 0xfffff);
+    __syncthreads();
+    int nch = ti0.y >> 20;
+    // invariant at the top: tile t in LDS, tile t+1 in pfb (described by ti1)
+    for (int64_t t = 0; t < ntiles; t += 2) {
+        int2 ti2 = {0, 0};
+        if (t + 2 < ntiles) {
+            ti2 = r.tinfo[t + 2];
+            issue(pfa, t + 2);
+        }
+        step(t, nch, pfb, t + 1 < ntiles, ti1.y & 0xfffff);
+        if (t + 1 >= ntiles) break;
+        nch = ti1.y >> 20;
+        int2 ti3 = {0, 0};
+        if (t + 3 < ntiles) {
+            ti3 = r.tinfo[t + 3];
+            issue(pfb, t + 3);
+        }
+        step(t + 1, nch, pfa, t + 2 < ntiles, ti2.y & 0xfffff);
+        nch = ti2.y >> 20;
+        ti1 = ti3;
+    }
+    __syncthreads();
     double* srow = sigma + ia * p.Nb;
     if (p.overwrite)
         for (int64_t i = tid; i < hi - lo; i += nth) srow[lo + i] = (double)sig[i];
@@ -705,38 +776,47 @@ __global__ __launch_bounds__(64 * ABL_MAX_WAVES) void k_ab_lp(
         for (int64_t i = tid; i < hi - lo; i += nth) srow[lo + i] += (double)sig[i];
 }
 
+int abl_waves(int Mp)
+{
+    const int mtiles = Mp / 16;
+    const int MT = mtiles <= ABL_MAX_WAVES ? 1 : 2;
+    const int w = (mtiles + MT - 1) / MT;
+    return w < 4 ? 4 : w;  // more loaders and reducers for small pair counts
+}
+
 template <typename MF>
-static int64_t abl_lds_bytes(int kb_count, int sb, int64_t chunk)
+static int64_t abl_lds_bytes(int kb_count, int ldT, int max_nseg, int64_t chunk)
 {
     const int Kp = kb_count * MF::K;
     int64_t b = (chunk * 4 + 15) / 16 * 16;
-    b += 2 * (((int64_t)TileLayout<MF>::size(Kp) * sizeof(typename MF::elem) + 15) / 16 * 16);
-    b += 2 * (int64_t)AB_TN * sb * 4;
-    b += 2 * AB_TN * 8 + (int64_t)Kp * 4 + 64;
+    b += ((int64_t)TileLayout<MF>::size(Kp) * sizeof(typename MF::elem) + 15) / 16 * 16;
+    b += (((int64_t)AB_TN * ldT + 4) * 4 + 15) / 16 * 16;
+    b += (int64_t)max_nseg * 16;
+    b += (int64_t)Kp * 4 + 64;
     return b;
 }
 
 template <typename MF>
-static hipError_t abl_launch(const AbParams& p, const void* Vt, const void* Cs, int64_t ldc,
+static hipError_t abl_launch(const AbParams& p, const AbReduce& r, const void* Vt, const void* Cs, int64_t ldc,
                              double* sigma, hipStream_t st)
 {
     if (p.Na <= 0 || p.Nb <= 0 || p.sa <= 0 || p.M <= 0) return hipSuccess;
+    if (r.ldT < p.Mp + 4 || (int64_t)AB_TN * r.ldT + 1 > 0x7fff || r.ldT % 4 != 0)
+        return invalid("alpha-beta: T tile stride does not fit the table's 15-bit offsets");
+    if (p.Nb >= 0xffff) return invalid("alpha-beta: more than 65534 beta strings for the low-precision table");
     const int kb_count = (p.sa + MF::K - 1) / MF::K;
     const int mtiles = p.Mp / 16;
     const int MT = mtiles <= ABL_MAX_WAVES ? 1 : 2;
-    int nwaves = (mtiles + MT - 1) / MT;
+    const int nwaves = abl_waves(p.Mp);
     if (nwaves > ABL_MAX_WAVES) return invalid("alpha-beta: too many pair rows (norb too large)");
-    if (nwaves < 2) nwaves = 2;  // more loaders for tiny pair counts
-    // two workgroups per CU when the sigma row allows it
-    const int64_t fixed = abl_lds_bytes<MF>(kb_count, p.sb, 0);
-    int64_t cap = 80 * 1024 - 256;
-    if (fixed + p.Nb * 4 > cap) cap = 160 * 1024 - 512;
+    const int64_t fixed = abl_lds_bytes<MF>(kb_count, r.ldT, r.max_nseg, 0);
+    const int64_t cap = 160 * 1024 - 512;
     int64_t chunk = (cap - fixed) / 4;
     if (chunk < 256) return invalid("alpha-beta: LDS too small for the sigma row chunk");
     int nchunks = (int)((p.Nb + chunk - 1) / chunk);
     chunk = (p.Nb + nchunks - 1) / nchunks;
-    const size_t lds = (size_t)abl_lds_bytes<MF>(kb_count, p.sb, chunk);
-    const int nseg = kb_count * MF::K * (AB_TN * (int)sizeof(typename MF::elem) / 16) + AB_TN * p.sb / 4;
+    const size_t lds = (size_t)abl_lds_bytes<MF>(kb_count, r.ldT, r.max_nseg, chunk);
+    const int nseg = kb_count * MF::K * (AB_TN * (int)sizeof(typename MF::elem) / 16) + r.max_nseg;
     const int spt = (nseg + 64 * nwaves - 1) / (64 * nwaves);
     if (spt > 8) return invalid("alpha-beta: tile larger than the prefetch registers");
     const int64_t items = p.Na * nchunks;
@@ -751,7 +831,7 @@ static hipError_t abl_launch(const AbParams& p, const void* Vt, const void* Cs, 
             g_launch_reason = "hipFuncSetAttribute(max dynamic LDS) failed";                        \
             return e;                                                                               \
         }                                                                                           \
-        hipLaunchKernelGGL(kern, dim3((unsigned)grid), blk, lds, st, p,                             \
+        hipLaunchKernelGGL(kern, dim3((unsigned)grid), blk, lds, st, p, r,                          \
                            (const typename MF::elem*)Vt, (const typename MF::elem*)Cs, ldc, sigma,  \
                            kb_count, chunk, nchunks);                                               \
         return hipGetLastError();                                                                   \
@@ -897,11 +977,11 @@ hipError_t launch_ab_f64(const AbParams& p, const double* Vt, const double* C, d
     return ab_launch<MfmaF64>(p, Vt, C, sigma, st);
 }
 
-hipError_t launch_ab_lowp(const AbParams& p, int prec, const void* Vt, const void* Cs, int64_t ldc,
-                          double* sigma, hipStream_t st)
+hipError_t launch_ab_lowp(const AbParams& p, const AbReduce& r, int prec, const void* Vt, const void* Cs,
+                          int64_t ldc, double* sigma, hipStream_t st)
 {
-    if (prec == 1) return abl_launch<MfmaF32>(p, Vt, Cs, ldc, sigma, st);
-    if (prec == 2) return abl_launch<MfmaBF16>(p, Vt, Cs, ldc, sigma, st);
+    if (prec == 1) return abl_launch<MfmaF32>(p, r, Vt, Cs, ldc, sigma, st);
+    if (prec == 2) return abl_launch<MfmaBF16>(p, r, Vt, Cs, ldc, sigma, st);
     return invalid("alpha-beta: unknown precision");
 }
 
