@@ -179,9 +179,13 @@ typedef struct {
     int m_max;              /* subspace size before collapse; 0 -> max(8, 8*nroots) */
     int precond;            /* CASCI_PRECOND_* */
     int spin;               /* CASCI_SPIN_* */
-    int ab_prec;            /* alpha-beta arithmetic in the first phase (CASCI_F64/F32/BF16) */
-    double refine_rnorm;    /* switch sigma to FP64 once max residual < this (<= 0: 2e-2 BF16, 2e-5 F32);
-                               also after 8 iterations without halving the best residual */
+    int ab_prec;            /* alpha-beta arithmetic of the correction vectors (CASCI_F64/F32/BF16).
+                               F32/BF16: mixed precision -- at every collapse the sigma of the
+                               current Ritz vectors is recomputed in FP64, and convergence is only
+                               accepted on FP64 sigma (a low-precision 'converged' triggers that
+                               refinement first) */
+    double refine_rnorm;    /* > 0: every sigma in FP64 once max residual < this; also after 40
+                               iterations without halving the best residual (<= 0: no threshold) */
     double r_tol;           /* residual threshold; <= 0 -> max(1e-6, sqrt(tol)/10) */
     double s2_penalty;      /* lambda of H + lambda S^2 for CASCI_SPIN_SINGLET (< 0 -> 0) */
     const double* guess;    /* optional [nguess][Ndet] FP64 start vectors (host or device) */
@@ -200,8 +204,9 @@ typedef struct {
     int sigma_calls;        /* vectors pushed through sigma, all precisions */
     int sigma_calls_fp64;
     int converged;          /* 1 if every root met both thresholds */
-    int switch_iter;        /* iteration at which sigma moved to FP64 (-1 = never/FP64 only) */
+    int switch_iter;        /* iteration at which every sigma moved to FP64 (-1 = never/FP64 only) */
     int mlp_fallbacks;      /* learned corrections replaced by the Olsen fallback */
+    int refinements;        /* mixed precision: restarts with FP64 sigma of the Ritz vectors */
     double residual[CASCI_MAX_ROOTS];
     double s2[CASCI_MAX_ROOTS];
     double time_total_ms;   /* wall time of the call */
@@ -226,6 +231,14 @@ typedef struct {
  */
 int casci_davidson(casci_ctx* ctx, int nroots, double tol, const casci_davidson_opts* opts,
                    double* energies, void* vectors, int mem, casci_davidson_info* info);
+
+/*
+ * Layout check for bindings: out[0..5] = sizeof(casci_davidson_opts),
+ * sizeof(casci_davidson_info), offsetof(opts, progress), offsetof(info,
+ * residual), offsetof(info, hist_energy), offsetof(info, hist_len). n >= 6.
+ * Works on a validate-only build (no device needed).
+ */
+int casci_abi_layout(int64_t* out, int n);
 
 /* ------------------------------------------------------------------------
  * Learned Davidson preconditioner (CASCI_PRECOND_MLP). A per-determinant

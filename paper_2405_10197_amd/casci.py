@@ -55,6 +55,7 @@ class DavidsonInfo(ctypes.Structure):
     _fields_ = [("iterations", ctypes.c_int), ("sigma_calls", ctypes.c_int),
                 ("sigma_calls_fp64", ctypes.c_int), ("converged", ctypes.c_int),
                 ("switch_iter", ctypes.c_int), ("mlp_fallbacks", ctypes.c_int),
+                ("refinements", ctypes.c_int),
                 ("residual", ctypes.c_double * MAX_ROOTS), ("s2", ctypes.c_double * MAX_ROOTS),
                 ("time_total_ms", ctypes.c_double), ("time_sigma_ms", ctypes.c_double),
                 ("time_setup_ms", ctypes.c_double), ("hist_energy", ctypes.c_void_p),
@@ -104,11 +105,19 @@ def lib():
         "casci_mlp_collect": (I, [P, I, D, P, P, I, ctypes.c_uint64, P, P, I64, P]),
         "casci_mlp_features": (I, [P, P, P, D, P, I, P]),
         "casci_profile_read": (I, [P, P]),
+        "casci_abi_layout": (I, [P, I]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
         f.restype = res
         f.argtypes = args
+    lay = (ctypes.c_int64 * 6)()
+    if L.casci_abi_layout(lay, 6) != 0:
+        raise RuntimeError("casci_abi_layout failed")
+    mine = [ctypes.sizeof(DavidsonOpts), ctypes.sizeof(DavidsonInfo), DavidsonOpts.progress.offset,
+            DavidsonInfo.residual.offset, DavidsonInfo.hist_energy.offset, DavidsonInfo.hist_len.offset]
+    if list(lay) != mine:
+        raise RuntimeError("libcasci.so struct layout %s differs from the binding's %s" % (list(lay), mine))
     _lib = L
     return L
 
@@ -382,6 +391,7 @@ class Context:
             "status": rc, "iterations": info.iterations, "sigma_calls": info.sigma_calls,
             "sigma_calls_fp64": info.sigma_calls_fp64, "converged": bool(info.converged),
             "switch_iter": info.switch_iter, "mlp_fallbacks": info.mlp_fallbacks,
+            "refinements": info.refinements,
             "residual": list(info.residual[:nroots]), "s2": list(info.s2[:nroots]),
             "time_total_ms": info.time_total_ms, "time_sigma_ms": info.time_sigma_ms,
             "time_setup_ms": info.time_setup_ms,

@@ -6,6 +6,7 @@
 #include "casci.h"
 
 #include <algorithm>
+#include <cstddef>
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -855,6 +856,19 @@ static int sigma_dev(casci_ctx* ctx, const double* C, double* S, int ab_prec, do
     return CASCI_OK;
 }
 
+// sizes and offsets of the option / info structs (for bindings to check their layout)
+extern "C" int casci_abi_layout(int64_t* out, int n)
+{
+    if (!out || n < 6) return CASCI_E_ARG;
+    out[0] = (int64_t)sizeof(casci_davidson_opts);
+    out[1] = (int64_t)sizeof(casci_davidson_info);
+    out[2] = (int64_t)offsetof(casci_davidson_opts, progress);
+    out[3] = (int64_t)offsetof(casci_davidson_info, residual);
+    out[4] = (int64_t)offsetof(casci_davidson_info, hist_energy);
+    out[5] = (int64_t)offsetof(casci_davidson_info, hist_len);
+    return CASCI_OK;
+}
+
 extern "C" int casci_profile_enable(casci_ctx* ctx, int on)
 {
     if (!ctx) return CASCI_E_ARG;
@@ -1159,6 +1173,58 @@ static int collect_step(casci_ctx* ctx, Collector* col, int k, const double* X, 
     return CASCI_OK;
 }
 
+// Eigenpairs of a small symmetric host matrix A (P x P, row-major; destroyed)
+// by cyclic Jacobi rotations: w ascending, V column j = eigenvector j.
+static void host_eigh(std::vector<double>& A, int P, std::vector<double>& w, std::vector<double>& V)
+{
+    V.assign((size_t)P * P, 0.0);
+    for (int i = 0; i < P; ++i) V[(size_t)i * P + i] = 1.0;
+    for (int sweep = 0; sweep < 60; ++sweep) {
+        double off = 0.0, tot = 0.0;
+        for (int i = 0; i < P; ++i)
+            for (int j = 0; j < P; ++j) {
+                const double x = A[(size_t)i * P + j] * A[(size_t)i * P + j];
+                tot += x;
+                if (i != j) off += x;
+            }
+        if (off <= 1e-30 * tot) break;
+        for (int p = 0; p < P - 1; ++p)
+            for (int q = p + 1; q < P; ++q) {
+                const double apq = A[(size_t)p * P + q];
+                if (std::fabs(apq) < 1e-300) continue;
+                const double th = (A[(size_t)q * P + q] - A[(size_t)p * P + p]) / (2.0 * apq);
+                const double t = (th >= 0 ? 1.0 : -1.0) / (std::fabs(th) + std::sqrt(th * th + 1.0));
+                const double c = 1.0 / std::sqrt(t * t + 1.0), sn = t * c;
+                for (int r = 0; r < P; ++r) {  // A <- A J
+                    const double a = A[(size_t)r * P + p], b = A[(size_t)r * P + q];
+                    A[(size_t)r * P + p] = c * a - sn * b;
+                    A[(size_t)r * P + q] = sn * a + c * b;
+                }
+                for (int r = 0; r < P; ++r) {  // A <- J^T A
+                    const double a = A[(size_t)p * P + r], b = A[(size_t)q * P + r];
+                    A[(size_t)p * P + r] = c * a - sn * b;
+                    A[(size_t)q * P + r] = sn * a + c * b;
+                }
+                for (int r = 0; r < P; ++r) {  // V <- V J
+                    const double a = V[(size_t)r * P + p], b = V[(size_t)r * P + q];
+                    V[(size_t)r * P + p] = c * a - sn * b;
+                    V[(size_t)r * P + q] = sn * a + c * b;
+                }
+            }
+    }
+    std::vector<int> ord(P);
+    for (int i = 0; i < P; ++i) ord[i] = i;
+    std::stable_sort(ord.begin(), ord.end(),
+                     [&](int a, int b) { return A[(size_t)a * P + a] < A[(size_t)b * P + b]; });
+    std::vector<double> V2((size_t)P * P);
+    w.resize(P);
+    for (int j = 0; j < P; ++j) {
+        w[j] = A[(size_t)ord[j] * P + ord[j]];
+        for (int i = 0; i < P; ++i) V2[(size_t)i * P + j] = V[(size_t)i * P + ord[j]];
+    }
+    V.swap(V2);
+}
+
 static int davidson_impl(casci_ctx* ctx, int nroots, double tol, const casci_davidson_opts* opts,
                          double* energies, void* vectors, int mem, casci_davidson_info* info,
                          Collector* col)
@@ -1200,8 +1266,17 @@ static int davidson_impl(casci_ctx* ctx, int nroots, double tol, const casci_dav
     const double r_tol = o.r_tol > 0 ? o.r_tol : std::max(1e-6, std::sqrt(tol) / 10.0);
     const double lambda = (o.spin == CASCI_SPIN_SINGLET && o.s2_penalty > 0) ? o.s2_penalty : 0.0;
     const bool singlet = o.spin == CASCI_SPIN_SINGLET;
-    int prec = o.ab_prec;  // current alpha-beta arithmetic
-    const double refine_at = o.refine_rnorm > 0 ? o.refine_rnorm : (prec == CASCI_BF16 ? 2e-2 : 2e-5);
+    // Mixed precision (ab_prec F32/BF16): sigma of every new correction vector
+    // uses the low-precision alpha-beta arithmetic, and at every collapse the
+    // sigma of the current Ritz vectors is recomputed in FP64. A correction
+    // enters the Ritz vector with a coefficient of the size of the residual,
+    // so its sigma error only perturbs the next residual by a relative amount;
+    // the refined Ritz vectors carry the FP64 energy. Convergence is declared
+    // only on a residual computed from FP64 sigma. `prec` becomes F64 for good
+    // if the low-precision phase stalls or the residual drops below
+    // refine_rnorm.
+    int prec = o.ab_prec;  // alpha-beta arithmetic of new correction vectors
+    const double refine_at = o.refine_rnorm > 0 ? o.refine_rnorm : 0.0;
 
     Timer setup_t;
     CHECK_RC(ensure_prepared(ctx, lambda));
@@ -1261,18 +1336,19 @@ static int davidson_impl(casci_ctx* ctx, int nroots, double tol, const casci_dav
     // exact by projecting each new vector, so sigma needs one same-spin gather
     const bool use_par = ctx->na == ctx->nb && (singlet || !o.guess);
     std::vector<int> par(m_max + k, 0), xpar(2 * k, 0);
-    auto run_sigma = [&](const double* c, double* s, int parity) -> int {
+    auto run_sigma_p = [&](const double* c, double* s, int parity, int p) -> int {
         HIPC(hipEventRecord(ev0, st));
-        CHECK_RC(sigma_dev(ctx, c, s, prec, lambda, use_par ? parity : 0));
+        CHECK_RC(sigma_dev(ctx, c, s, p, lambda, use_par ? parity : 0));
         HIPC(hipEventRecord(ev1, st));
         HIPC(hipEventSynchronize(ev1));
         float ms = 0;
         HIPC(hipEventElapsedTime(&ms, ev0, ev1));
         sigma_ms += ms;
         ++sigma_calls;
-        if (prec == CASCI_F64) ++sigma64;
+        if (p == CASCI_F64) ++sigma64;
         return CASCI_OK;
     };
+    auto run_sigma = [&](const double* c, double* s, int parity) { return run_sigma_p(c, s, parity, prec); };
     auto dots_dev = [&](const double* A, int na, const double* Bv, int nb, std::vector<double>& out) {
         return dots(ctx, A, na, Bv, nb, out);
     };
@@ -1335,13 +1411,19 @@ static int davidson_impl(casci_ctx* ctx, int nroots, double tol, const casci_dav
     };
 
     std::vector<double> G((size_t)m_max * m_max, 0.0);  // host copy of B^T (H) B, ld = m_max
+    // basis vectors [0, nexact) have FP64 sigma: their entries of G are taken
+    // as (H b_i)^T b_j, which stays exact when b_j's sigma is low precision
+    int nexact = 0;
     auto extend_G = [&](int m0, int cnt) -> int {
-        std::vector<double> d;
+        std::vector<double> d, e;
         CHECK_RC(dots_dev(vB(0), m0 + cnt, vS(m0), cnt, d));  // (m0+cnt) x cnt
+        const int ne = std::min(nexact, m0 + cnt);
+        if (ne > 0 && prec != CASCI_F64) CHECK_RC(dots_dev(vS(0), ne, vB(m0), cnt, e));  // ne x cnt
         for (int i = 0; i < m0 + cnt; ++i)
             for (int j = 0; j < cnt; ++j) {
-                G[(size_t)i * m_max + m0 + j] = d[(size_t)i * cnt + j];
-                G[(size_t)(m0 + j) * m_max + i] = d[(size_t)i * cnt + j];
+                const double g = (i < ne && !e.empty()) ? e[(size_t)i * cnt + j] : d[(size_t)i * cnt + j];
+                G[(size_t)i * m_max + m0 + j] = g;
+                G[(size_t)(m0 + j) * m_max + i] = g;
             }
         return CASCI_OK;
     };
@@ -1368,6 +1450,76 @@ static int davidson_impl(casci_ctx* ctx, int nroots, double tol, const casci_dav
     HIPC(hipMemcpyAsync(diag.data(), ctx->d_diag.p, vb, hipMemcpyDeviceToHost, st));
     HIPC(hipStreamSynchronize(st));
     const double dmin = *std::min_element(diag.begin(), diag.end());
+    if (m < k && !singlet) {
+        // Start space: eigenvectors of H in the P-space of the lowest-diagonal
+        // determinants (with their transposition partners when nalpha == nbeta,
+        // so that both parities are there). Starting from single determinants
+        // instead lets Davidson settle on the lowest states of one symmetry
+        // and never see a lower state of another.
+        const int Pt = (int)std::min<int64_t>(Nd, 240);
+        std::vector<int64_t> idx(Nd);
+        for (int64_t i = 0; i < Nd; ++i) idx[i] = i;
+        const int64_t want = std::min<int64_t>(Nd, 2 * (int64_t)Pt);
+        std::partial_sort(idx.begin(), idx.begin() + want, idx.end(), [&](int64_t a, int64_t b) {
+            return diag[a] < diag[b] || (diag[a] == diag[b] && a < b);
+        });
+        const bool paired = ctx->na == ctx->nb;
+        std::vector<int64_t> dets;
+        auto has = [&](int64_t x) { return std::find(dets.begin(), dets.end(), x) != dets.end(); };
+        for (int64_t t = 0; t < want && (int)dets.size() < Pt; ++t) {
+            const int64_t x = idx[t];
+            if (has(x)) continue;
+            dets.push_back(x);
+            if (paired) {
+                const int64_t y = (x % ctx->Nb) * ctx->Nb + x / ctx->Nb;
+                if (y != x && !has(y)) dets.push_back(y);
+            }
+        }
+        const int P = (int)dets.size();
+        DBuf dd, dh;
+        HIPC(dd.ensure((size_t)P * 8));
+        HIPC(dh.ensure((size_t)P * P * 8));
+        HIPC(hipMemcpyAsync(dd.p, dets.data(), (size_t)P * 8, hipMemcpyHostToDevice, st));
+        const bool same = ctx->nb == ctx->na;
+        HIPC(launch_pspace_h(ctx->norb, P, dd.as<int64_t>(), ctx->Nb, ctx->d_astr.as<uint64_t>(),
+                             ctx->d_bstr.as<uint64_t>(), ctx->d_fa_col.as<int32_t>(), ctx->d_fa_val.as<double>(),
+                             ctx->ra, (same ? ctx->d_fa_col : ctx->d_fb_col).as<int32_t>(),
+                             (same ? ctx->d_fa_val : ctx->d_fb_val).as<double>(), ctx->rb, ctx->d_eri.as<double>(),
+                             ctx->d_diag.as<double>(), dh.as<double>(), st));
+        std::vector<double> Hp((size_t)P * P), wp, Vp;
+        HIPC(hipMemcpyAsync(Hp.data(), dh.p, Hp.size() * 8, hipMemcpyDeviceToHost, st));
+        HIPC(hipStreamSynchronize(st));
+        for (int i = 0; i < P; ++i)  // symmetric by construction up to rounding of the sums
+            for (int j = 0; j < i; ++j) Hp[(size_t)i * P + j] = Hp[(size_t)j * P + i];
+        host_eigh(Hp, P, wp, Vp);
+        std::vector<int> partner(P, -1);
+        if (paired)
+            for (int i = 0; i < P; ++i) {
+                const int64_t y = (dets[i] % ctx->Nb) * ctx->Nb + dets[i] / ctx->Nb;
+                const auto it2 = std::find(dets.begin(), dets.end(), y);
+                partner[i] = it2 == dets.end() ? -1 : (int)(it2 - dets.begin());
+            }
+        const int nstart = (int)std::min<int64_t>({(int64_t)2 * k, (int64_t)m_max - k, (int64_t)P});
+        std::vector<double> y(P);
+        for (int j = 0; j < nstart && m < m_max; ++j) {
+            double pr = 0.0;
+            for (int i = 0; i < P; ++i) {
+                y[i] = Vp[(size_t)i * P + j];
+                if (partner[i] >= 0) pr += Vp[(size_t)i * P + j] * Vp[(size_t)partner[i] * P + j];
+            }
+            double* v = vB(m);
+            HIPC(hipMemsetAsync(v, 0, vb, st));
+            HIPC(hipMemcpyAsync(dh.p, y.data(), (size_t)P * 8, hipMemcpyHostToDevice, st));
+            HIPC(launch_scatter_values(dd.as<int64_t>(), dh.as<double>(), P, v, st));
+            HIPC(hipStreamSynchronize(st));
+            par[m] = paired ? (pr >= 0 ? 1 : -1) : 0;
+            if (use_par) CHECK_RC(symmetrize(v, par[m]));
+            ++m;
+        }
+        int kept = 0;
+        CHECK_RC(orthonormalize(0, m, kept));
+        m = kept;
+    }
     if (m < k) {
         // Start vectors from the lowest diagonal elements (ties: lower address).
         // For nalpha == nbeta the determinants (a,b) and (b,a) are combined into
@@ -1443,15 +1595,19 @@ static int davidson_impl(casci_ctx* ctx, int nroots, double tol, const casci_dav
         }
         if (m < k) return ctx->fail(CASCI_E_ARG, "could not build nroots independent start vectors");
     }
-    for (int j = 0; j < m; ++j) CHECK_RC(run_sigma(vB(j), vS(j), par[j]));
+    // the start space gets FP64 sigma in every mode: its vectors dominate the
+    // first Ritz vectors, and a low-precision error there can reorder nearby
+    // states so that a root is lost for good
+    for (int j = 0; j < m; ++j) CHECK_RC(run_sigma_p(vB(j), vS(j), par[j], CASCI_F64));
+    nexact = m;
     CHECK_RC(extend_G(0, m));
 
     std::vector<double> theta_prev(k, std::numeric_limits<double>::infinity());
     std::vector<double> theta(64), Y(64 * 64), rn(k, 0.0);
     bool converged = false, have_prev = false;
-    int it = 0, switch_iter = (prec == CASCI_F64) ? -1 : -2;
+    int it = 0, switch_iter = -1;
     double last_rmax = std::numeric_limits<double>::infinity();
-    int stall = 0, empty_steps = 0, mlp_fallbacks = 0;
+    int stall = 0, empty_steps = 0, mlp_fallbacks = 0, refinements = 0;
     std::vector<double> best_hist;
     for (it = 0; it < max_iter; ++it) {
         // Rayleigh-Ritz on the device
@@ -1510,46 +1666,17 @@ static int davidson_impl(casci_ctx* ctx, int nroots, double tol, const casci_dav
         if (o.progress) o.progress(o.progress_user, it, k, theta.data(), rn.data(), wall.ms());
         if (col) CHECK_RC(collect_step(ctx, col, k, X, SX, theta, rn, dmin));
         if (!std::isfinite(rmax)) return ctx->fail(CASCI_E_NONFINITE, "non-finite residual in Davidson");
-        if (todo.empty() && prec == CASCI_F64) {
-            converged = true;
-            break;
-        }
-        // precision switch: once the residual reaches the level the low-precision
-        // sigma can resolve (or stops improving: no 2x gain of the best residual
-        // over 8 iterations), restart from the Ritz vectors with FP64 sigma
-        if (prec != CASCI_F64) {
-            best_hist.push_back(rmax);
-            const int nh = (int)best_hist.size();
-            bool stalled = false;
-            if (nh > 16) {
-                double recent = *std::min_element(best_hist.end() - 8, best_hist.end());
-                double before = *std::min_element(best_hist.begin(), best_hist.end() - 8);
-                stalled = recent > 0.5 * before;
-            }
-            (void)stall;
-            if (rmax < refine_at || stalled || todo.empty()) {
-                prec = CASCI_F64;
-                switch_iter = it;
-                HIPC(hipMemcpyAsync(vB(0), vX(0), vb * k, hipMemcpyDeviceToDevice, st));
-                for (int j = 0; j < k; ++j) par[j] = xpar[j];
-                int kept = 0;
-                CHECK_RC(orthonormalize(0, k, kept));
-                m = kept;
-                for (int j = 0; j < m; ++j) CHECK_RC(run_sigma(vB(j), vS(j), par[j]));
-                CHECK_RC(extend_G(0, m));
-                have_prev = false;
-                last_rmax = std::numeric_limits<double>::infinity();
-                for (int j = 0; j < k; ++j) theta_prev[j] = std::numeric_limits<double>::infinity();
-                continue;
-            }
-        }
-        last_rmax = rmax;
-        // collapse: keep current and previous Ritz vectors
-        if (m + (int)todo.size() > m_max) {
-            const int nkeep = (have_prev && 2 * k + (int)todo.size() <= m_max) ? 2 * k : k;
+        // collapse: keep current and previous Ritz vectors (room for ncorr new ones)
+        auto collapse = [&](int ncorr) -> int {
+            const int nkeep = (have_prev && 2 * k + ncorr <= m_max) ? 2 * k : k;
+            const bool refine = prec != CASCI_F64;
             HIPC(hipMemcpyAsync(vB(0), vX(0), vb * nkeep, hipMemcpyDeviceToDevice, st));
             HIPC(hipMemcpyAsync(vS(0), vSX(0), vb * nkeep, hipMemcpyDeviceToDevice, st));
             for (int j = 0; j < nkeep; ++j) par[j] = xpar[j];
+            if (refine) {  // FP64 sigma of the current Ritz vectors
+                for (int j = 0; j < k; ++j) CHECK_RC(run_sigma_p(vB(j), vS(j), par[j], CASCI_F64));
+                ++refinements;
+            }
             // Gram-Schmidt of the previous Ritz vectors against the current ones,
             // the same combination applied to their sigma vectors
             int mm = k;
@@ -1575,12 +1702,87 @@ static int davidson_impl(casci_ctx* ctx, int nroots, double tol, const casci_dav
                     HIPC(hipMemcpyAsync(vS(mm), vS(j), vb, hipMemcpyDeviceToDevice, st));
                 }
                 par[mm] = par[j];
+                // in mixed mode the combined sigma of this small remainder would
+                // carry the accumulated low-precision error, amplified by the
+                // normalisation: recompute it instead
+                if (refine) CHECK_RC(run_sigma(vB(mm), vS(mm), par[mm]));
                 ++mm;
             }
             m = mm;
+            nexact = refine ? k : m;
             std::fill(G.begin(), G.end(), 0.0);
             CHECK_RC(extend_G(0, m));
+            return CASCI_OK;
+        };
+        // the Ritz data is exact when every vector with a nonzero coefficient
+        // has FP64 sigma (always in FP64 mode; in mixed mode right after a
+        // refinement that kept only the Ritz vectors)
+        const bool exact_now = prec == CASCI_F64 || nexact >= m;
+        if (todo.empty() && exact_now) {
+            converged = true;
+            break;
         }
+        if (prec != CASCI_F64) {
+            // stalled low-precision phase (no 2x gain of the best residual over
+            // 40 iterations), or the optional threshold: FP64 from here on
+            best_hist.push_back(rmax);
+            const int nh = (int)best_hist.size();
+            bool stalled = false;
+            if (nh > 80) {
+                double recent = *std::min_element(best_hist.end() - 40, best_hist.end());
+                double before = *std::min_element(best_hist.begin(), best_hist.end() - 40);
+                stalled = recent > 0.5 * before;
+            }
+            (void)stall;
+            const bool to_f64 = stalled || (refine_at > 0 && rmax < refine_at);
+            if (to_f64) {
+                // FP64 from here on: restart from the Ritz vectors
+                prec = CASCI_F64;
+                switch_iter = it;
+                HIPC(hipMemcpyAsync(vB(0), vX(0), vb * k, hipMemcpyDeviceToDevice, st));
+                for (int j = 0; j < k; ++j) par[j] = xpar[j];
+                int kept = 0;
+                CHECK_RC(orthonormalize(0, k, kept));
+                m = kept;
+                for (int j = 0; j < m; ++j) CHECK_RC(run_sigma_p(vB(j), vS(j), par[j], CASCI_F64));
+                nexact = m;
+                ++refinements;
+                std::fill(G.begin(), G.end(), 0.0);
+                CHECK_RC(extend_G(0, m));
+                have_prev = false;
+                last_rmax = std::numeric_limits<double>::infinity();
+                for (int j = 0; j < k; ++j) theta_prev[j] = std::numeric_limits<double>::infinity();
+                continue;
+            }
+            if (todo.empty()) {
+                // converged on low-precision data: collapse with FP64 sigma of the
+                // Ritz vectors and test their exact Rayleigh quotients and residuals
+                CHECK_RC(collapse(0));
+                std::vector<double> th(k);
+                for (int j = 0; j < k; ++j) th[j] = G[(size_t)j * m_max + j];
+                HIPC(hipMemcpyAsync(dth, th.data(), k * 8, hipMemcpyHostToDevice, st));
+                HIPC(launch_residual(B, S, Nd, k, dth, ctx->d_diag.as<double>(), Nd, ctx->d_work.as<double>(),
+                                     dres, st));
+                std::vector<double> rx(4 * k);
+                HIPC(hipMemcpyAsync(rx.data(), dres, 4 * k * 8, hipMemcpyDeviceToHost, st));
+                HIPC(hipStreamSynchronize(st));
+                bool ok = true;
+                for (int j = 0; j < k; ++j) {
+                    const double r = std::sqrt(std::max(rx[4 * j], 0.0));
+                    ok = ok && r < r_tol && std::fabs(th[j] - theta[j]) < tol;
+                    rn[j] = r;
+                }
+                if (ok) {
+                    HIPC(hipMemcpyAsync(vX(0), vB(0), vb * k, hipMemcpyDeviceToDevice, st));
+                    for (int j = 0; j < k; ++j) theta[j] = th[j];
+                    converged = true;
+                    break;
+                }
+                continue;
+            }
+        }
+        last_rmax = rmax;
+        if (m + (int)todo.size() > m_max) CHECK_RC(collapse((int)todo.size()));
         // corrections for unconverged roots
         const int cnt = (int)todo.size();
         for (int t = 0; t < cnt; ++t) {
@@ -1617,6 +1819,7 @@ static int davidson_impl(casci_ctx* ctx, int nroots, double tol, const casci_dav
         }
         empty_steps = 0;
         for (int j = 0; j < kept; ++j) CHECK_RC(run_sigma(vB(m + j), vS(m + j), par[m + j]));
+        if (prec == CASCI_F64) nexact = m + kept;
         CHECK_RC(extend_G(m, kept));
         m += kept;
         have_prev = true;
@@ -1649,6 +1852,7 @@ static int davidson_impl(casci_ctx* ctx, int nroots, double tol, const casci_dav
         info->converged = converged ? 1 : 0;
         info->switch_iter = switch_iter < 0 ? -1 : switch_iter;
         info->mlp_fallbacks = mlp_fallbacks;
+        info->refinements = refinements;
         for (int j = 0; j < CASCI_MAX_ROOTS; ++j) {
             info->residual[j] = j < k ? rn[j] : 0.0;
             info->s2[j] = j < k ? s2v[j] : 0.0;

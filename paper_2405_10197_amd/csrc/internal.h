@@ -46,6 +46,13 @@ hipError_t launch_diagonal(int n, int64_t Na, int64_t Nb, const uint64_t* astr,
                            const uint64_t* bstr, const double* fa, int ra, const double* fb, int rb,
                            const double* jpq, double shift, double lambda_s2, double* out,
                            hipStream_t st);
+// H_IJ over a small set of determinants dets[P] (row-major P x P)
+hipError_t launch_pspace_h(int n, int P, const int64_t* dets, int64_t Nb, const uint64_t* astr,
+                           const uint64_t* bstr, const int32_t* fa_col, const double* fa_val, int ra,
+                           const int32_t* fb_col, const double* fb_val, int rb, const double* eri,
+                           const double* diag, double* H, hipStream_t st);
+// out[idx[i]] = v[i]
+hipError_t launch_scatter_values(const int64_t* idx, const double* v, int P, double* out, hipStream_t st);
 
 // sigma_kernels.hip
 // Y(I,:) = [acc ? Y(I,:) : 0] + sum_e val[I*r+e] X(col[I*r+e], :) + shift * X(I,:)

@@ -215,4 +215,96 @@ hipError_t launch_diagonal(int n, int64_t Na, int64_t Nb, const uint64_t* astr,
     return hipGetLastError();
 }
 
+// H_IJ between the determinants I = dets[i], J = dets[j] of a small set (the
+// start space of the eigensolver): diagonal from H_II; a same-spin
+// difference from the same-spin operator row (plus, for a single
+// substitution p <- q, the opposite-spin Coulomb part sign * sum_k (pq|kk));
+// one substitution in each spin: sign_a sign_b (pq|rs); more: zero.
+__global__ __launch_bounds__(256) void k_pspace_h(int n, int P, const int64_t* __restrict__ dets, int64_t Nb,
+                                                  const uint64_t* __restrict__ astr,
+                                                  const uint64_t* __restrict__ bstr,
+                                                  const int32_t* __restrict__ fa_col,
+                                                  const double* __restrict__ fa_val, int ra,
+                                                  const int32_t* __restrict__ fb_col,
+                                                  const double* __restrict__ fb_val, int rb,
+                                                  const double* __restrict__ eri,
+                                                  const double* __restrict__ diag, double* __restrict__ H)
+{
+    const int i = blockIdx.y;
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= P || i >= P) return;
+    const int64_t I = dets[i], J = dets[j];
+    const int64_t Ia = I / Nb, Ib = I - Ia * Nb, Ja = J / Nb, Jb = J - Ja * Nb;
+    const uint64_t ia = astr[Ia], ib = bstr[Ib], ja = astr[Ja], jb = bstr[Jb];
+    const int da = __popcll(ia ^ ja) / 2, db = __popcll(ib ^ jb) / 2;
+    auto row_value = [&](const int32_t* col, const double* val, int r, int64_t row, int64_t c) {
+        double x = 0.0;
+        for (int e = 0; e < r; ++e)
+            if (col[row * r + e] == (int32_t)c) x = val[row * r + e];
+        return x;
+    };
+    // bra x = ket y - q + p: returns <x| a+_p a_q |y>
+    auto single = [&](uint64_t x, uint64_t y, int& p, int& q) {
+        p = __builtin_ctzll(x & ~y);
+        q = __builtin_ctzll(y & ~x);
+        return (__popcll(y & between_mask(p, q)) & 1) ? -1.0 : 1.0;
+    };
+    double v = 0.0;
+    if (I == J) {
+        v = diag[I];
+    } else if (da + db > 2) {
+        v = 0.0;
+    } else if (db == 0) {
+        v = row_value(fa_col, fa_val, ra, Ia, Ja);
+        if (da == 1) {
+            int p, q;
+            const double sg = single(ia, ja, p, q);
+            double c = 0.0;
+            for (uint64_t bb = ib; bb; bb &= bb - 1) c += eri4(eri, n, p, q, __builtin_ctzll(bb), __builtin_ctzll(bb));
+            v += sg * c;
+        }
+    } else if (da == 0) {
+        v = row_value(fb_col, fb_val, rb, Ib, Jb);
+        if (db == 1) {
+            int p, q;
+            const double sg = single(ib, jb, p, q);
+            double c = 0.0;
+            for (uint64_t aa = ia; aa; aa &= aa - 1) c += eri4(eri, n, p, q, __builtin_ctzll(aa), __builtin_ctzll(aa));
+            v += sg * c;
+        }
+    } else {
+        int p, q, r, t;
+        const double sa = single(ia, ja, p, q);
+        const double sb = single(ib, jb, r, t);
+        v = sa * sb * eri4(eri, n, p, q, r, t);
+    }
+    H[(int64_t)i * P + j] = v;
+}
+
+hipError_t launch_pspace_h(int n, int P, const int64_t* dets, int64_t Nb, const uint64_t* astr,
+                           const uint64_t* bstr, const int32_t* fa_col, const double* fa_val, int ra,
+                           const int32_t* fb_col, const double* fb_val, int rb, const double* eri,
+                           const double* diag, double* H, hipStream_t st)
+{
+    if (P <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_pspace_h, dim3((P + 255) / 256, P), dim3(256), 0, st, n, P, dets, Nb, astr, bstr, fa_col,
+                       fa_val, ra, fb_col, fb_val, rb, eri, diag, H);
+    return hipGetLastError();
+}
+
+// out[idx[i]] = v[i] (out zeroed by the caller)
+__global__ void k_scatter_values(const int64_t* __restrict__ idx, const double* __restrict__ v, int P,
+                                 double* __restrict__ out)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < P) out[idx[i]] = v[i];
+}
+
+hipError_t launch_scatter_values(const int64_t* idx, const double* v, int P, double* out, hipStream_t st)
+{
+    if (P <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_scatter_values, dim3((P + 255) / 256), dim3(256), 0, st, idx, v, P, out);
+    return hipGetLastError();
+}
+
 }  // namespace casci

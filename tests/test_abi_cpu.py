@@ -137,3 +137,13 @@ def test_sigma_argument_checks(L):
     assert L.casci_sigma(c._h, C.ctypes.data, S.ctypes.data, 0, 9, 0) == casci.E_ARG
     assert L.casci_sigma(c._h, C.ctypes.data, S.ctypes.data, 0, 0, 5) == casci.E_ARG
     assert b"NULL" in L.casci_last_error(c._h) or L.casci_last_error(c._h)
+
+
+def test_struct_layout_matches_binding(L):
+    """The ctypes mirrors of the option / info structs agree with the library."""
+    import ctypes
+    lay = (ctypes.c_int64 * 6)()
+    assert L.casci_abi_layout(lay, 6) == 0
+    assert list(lay) == [ctypes.sizeof(casci.DavidsonOpts), ctypes.sizeof(casci.DavidsonInfo),
+                         casci.DavidsonOpts.progress.offset, casci.DavidsonInfo.residual.offset,
+                         casci.DavidsonInfo.hist_energy.offset, casci.DavidsonInfo.hist_len.offset]

@@ -287,16 +287,40 @@ def test_sigma_low_precision_error_bounds(torch, n, na, nb):
 
 @pytest.mark.parametrize("prec", ["f32", "bf16"])
 def test_mixed_precision_davidson_reaches_fp64_energies(torch, prec):
-    """Low-precision sigma first, FP64 sigma in the final iterations: the
-    reported energies are FP64 Rayleigh quotients and match LAPACK."""
+    """Low-precision sigma for the correction vectors, FP64 sigma of the Ritz
+    vectors at every collapse and for the final check: the reported energies
+    are FP64 Rayleigh quotients and match LAPACK."""
     n, na, nb, k = 8, 4, 4, 3
     c, h, eri = make(n, na, nb, 3000)
     Eo, _, _ = oracle_roots(h, eri, na, nb, k)
-    E, _, info = c.davidson(k, 1e-11, ab_prec=prec, r_tol=1e-7, vectors=False)
+    E, _, info = c.davidson(k, 1e-11, ab_prec=prec, r_tol=1e-7, vectors=False, m_max=12)
     assert info["converged"]
-    assert info["switch_iter"] >= 0
-    assert info["sigma_calls_fp64"] < info["sigma_calls"]
+    assert info["switch_iter"] == -1
+    assert 0 < info["sigma_calls_fp64"] < info["sigma_calls"] / 2
     assert np.abs(E - Eo).max() < 1e-10
+    assert max(info["residual"][:k]) < 1e-7
+
+
+def test_mixed_precision_threshold_switch(torch):
+    """refine_rnorm > 0: below that residual every sigma is FP64."""
+    n, na, nb, k = 8, 4, 4, 3
+    c, h, eri = make(n, na, nb, 3000)
+    Eo, _, _ = oracle_roots(h, eri, na, nb, k)
+    E, _, info = c.davidson(k, 1e-11, ab_prec="bf16", r_tol=1e-7, vectors=False, refine_rnorm=1e-3)
+    assert info["converged"] and info["switch_iter"] >= 0
+    assert np.abs(E - Eo).max() < 1e-10
+
+
+def test_mixed_precision_singlet_cas10(torch):
+    """Mixed BF16 solve of a singlet (S^2 penalty, full-pair alpha-beta table)
+    against the FP64 solve of the same problem."""
+    n, na, nb = 10, 5, 5
+    c, h, eri = make(n, na, nb, 3002)
+    E64, _, i64 = c.davidson(2, 1e-11, spin="singlet", s2_penalty=1.0, r_tol=1e-7, vectors=False)
+    E16, _, i16 = c.davidson(2, 1e-11, spin="singlet", s2_penalty=1.0, r_tol=1e-7, vectors=False, ab_prec="bf16")
+    assert i64["converged"] and i16["converged"]
+    assert np.abs(E16 - E64).max() < 1e-9
+    assert i16["sigma_calls_fp64"] < i16["sigma_calls"] / 2
 
 
 def test_davidson_parity_path_cas10_vs_eigsh(torch):
