@@ -7,13 +7,15 @@ operators, diagonal, then Davidson-Liu with sigma builds to convergence
 root stays within 1e-8 Eh of the reference energies (median over the timed
 steps). The reference energies and the baseline time come from the plain
 FP64, diagonal-preconditioned Davidson run in the same process; the timed
-steps use the headline solver (BF16 alpha-beta arithmetic with FP32
-accumulation, then FP64 sigma for the final iterations; Olsen
-preconditioner; one same-spin gather per sigma through transposition
-parity).
+steps use the headline solver: BF16 alpha-beta arithmetic (FP32
+accumulation) for the sigma of every correction vector, FP64 sigma of the
+Ritz vectors at every collapse (48-vector subspace) and for the convergence
+check; Olsen preconditioner; one same-spin gather per sigma through
+transposition parity.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload cas16|cas12]
        python bench.py --sigma-only f64|f32|bf16 --steps K   (kernel profiling aid)
+       python bench.py --copy-probe GIB                       (counter calibration: one plain copy)
 """
 from __future__ import annotations
 
@@ -40,7 +42,7 @@ WORKLOADS = {
     "cas12": (12, 6, 6, 1, 2, "singlet", "CAS(12e,12o) singlet ground state, 853,776 determinants, "
               "seeded synthetic integrals (seed 2)"),
 }
-HEADLINE = dict(precond="olsen", ab_prec="bf16")
+HEADLINE = dict(precond="olsen", ab_prec="bf16", m_max=48)
 
 
 def log(*a):
@@ -67,20 +69,20 @@ def time_to_threshold(hist_e, hist_t, eref, thr=1e-8):
 
 
 def read_traffic(path):
-    """HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, KiB per dispatch, scaled by
-    the copy-kernel factor) from a committed rocprofv3 summary, or None."""
+    """HBM bytes per launch from a committed rocprofv3 counter summary: FETCH_SIZE
+    and WRITE_SIZE (KiB per dispatch), each scaled by what the same counter
+    reads for a plain copy of known size (fetch_scale, write_scale), or None."""
     if not os.path.exists(path):
         return None
     txt = open(path).read()
     vals = {}
-    for key in ("FETCH_SIZE_KiB", "WRITE_SIZE_KiB", "copy_scale"):
+    for key in ("FETCH_SIZE_KiB", "WRITE_SIZE_KiB", "fetch_scale", "write_scale"):
         m = re.search(r"^%s\s*[:=]\s*([0-9.eE+-]+)" % key, txt, re.M)
         if m:
             vals[key] = float(m.group(1))
-    if "FETCH_SIZE_KiB" not in vals or "WRITE_SIZE_KiB" not in vals:
+    if len(vals) < 4:
         return None
-    scale = vals.get("copy_scale", 1.0)
-    return (vals["FETCH_SIZE_KiB"] + vals["WRITE_SIZE_KiB"]) * 1024.0 * scale
+    return 1024.0 * (vals["FETCH_SIZE_KiB"] * vals["fetch_scale"] + vals["WRITE_SIZE_KiB"] * vals["write_scale"])
 
 
 def make_ctx(casci, h, eri, n, na, nb):
@@ -156,7 +158,18 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--sigma-only", default=None, choices=["f64", "f32", "bf16"],
                     help="profiling aid: only run --steps sigma builds of the workload in this precision")
+    ap.add_argument("--copy-probe", type=float, default=None,
+                    help="counter calibration: copy GIB gibibytes once with a plain device copy")
     args = ap.parse_args()
+    if args.copy_probe:
+        import torch
+        nb = int(args.copy_probe * (1 << 30))
+        a = torch.ones(nb // 8, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes_read": nb, "copy_probe_bytes_written": nb}))
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build runs on exactly one GPU (the string-CASCI path is measured "
               "on one MI355X); --gpus %d is not supported" % args.gpus, file=sys.stderr)
@@ -223,6 +236,7 @@ def main():
             cand.append((fig["alpha_alpha_gather_ms"] * nbld, tag, "aa", fig))
     cand.sort(key=lambda c: -c[0])
     _, tag, part, fig = cand[0]
+    device_time_s = {"%s_%s" % (t, p): round(ms / 1000.0, 3) for ms, t, p, _ in cand}
     if part == "ab":
         peak = PEAK["bf16_TF"] if tag == "lowp" else PEAK["f64_TF"]
         kname = "k_ab_lp<MfmaBF16>" if tag == "lowp" else "k_ab<MfmaF64>"
@@ -266,7 +280,8 @@ def main():
         "warmup": args.warmup, "ms_per_step": 1000.0 * float(np.mean(times)), "higher_is_better": False,
         "scaling": "strong", "vs_baseline": None, "dtype": "bf16+f64", "data": "synthetic",
         "config": {"workload": desc, "norb": n, "nalpha": na, "nbeta": nb, "nroots": k, "seed": seed,
-                   "spin": spin, "solver": "BF16 alpha-beta (FP32 accumulate) + FP64 sigma refinement, Olsen"},
+                   "spin": spin, "solver": "BF16 alpha-beta (FP32 accumulate) for corrections + FP64 sigma "
+                                           "of the Ritz vectors at each collapse, Olsen, m_max 48"},
         "roofline": roof,
         "cpu_baseline": cpu,
         "fp64_diag_time_to_1e8_s": t_base,
@@ -276,6 +291,8 @@ def main():
         "sigma_calls_fp64": infos[-1]["sigma_calls_fp64"], "switch_iteration": infos[-1]["switch_iter"],
         "energies": E.tolist(), "energy_error_vs_fp64_reference": float(np.abs(E - Eref).max()),
         "sigma_fp64": f64_base, "sigma_lowp_bf16": lowp, "sigma_fp64_in_headline": f64,
+        "headline_device_time_s": device_time_s, "refinements": infos[-1]["refinements"],
+        "m_max": HEADLINE["m_max"],
     }
     print(json.dumps(out))
 
