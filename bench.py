@@ -16,6 +16,7 @@ transposition parity.
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload cas16|cas12]
        python bench.py --sigma-only f64|f32|bf16 --steps K   (kernel profiling aid)
        python bench.py --copy-probe GIB                       (counter calibration: one plain copy)
+       python bench.py --batch [--batch-count 64]             (64 uneven CAS(8..10) solves, 4 roots)
 """
 from __future__ import annotations
 
@@ -117,6 +118,58 @@ def sigma_only(args, casci, h, eri, n, na, nb):
                       "parts_ms": {x: P[x] / k for x in ("aa_ms", "bb_ms", "ab_ms", "combine_ms", "total_ms")}}))
 
 
+def batch_mode(args):
+    """64 independent solves, CAS(n,n) with n drawn uniformly from {8, 9, 10}
+    (seeded), integrals seed 3000 + i, 4 roots each, spin ANY: concurrent
+    batched solves (graph-replayed sigma) in FP64, FP32 and BF16 alpha-beta
+    arithmetic, against the same solves run one after another."""
+    import torch
+    from paper_2405_10197_amd import casci, synth
+    rng = np.random.default_rng(3)
+    ns = rng.integers(8, 11, args.batch_count)
+    k = 4
+    def contexts():
+        out = []
+        for i, n in enumerate(ns):
+            h, eri, _ = synth.integrals(int(n), 3000 + i)
+            c = casci.Context(0, own_stream=True)
+            c.set_integrals(h, eri)
+            c.build_strings((int(n) + 1) // 2, int(n) // 2, int(n))
+            out.append(c)
+        return out
+    res = {}
+    ref = None
+    for prec in ("f64", "f32", "bf16"):
+        ctxs = contexts()
+        kw = dict(r_tol=1e-7, graph=True, ab_prec=prec, precond="olsen" if prec != "f64" else "diag")
+        casci.batch_davidson(ctxs[:4], k, 1e-11, **kw)  # warm-up: kernels loaded, autotuner filled
+        ctxs = contexts()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        E, infos = casci.batch_davidson(ctxs, k, 1e-11, **kw)
+        dt = time.perf_counter() - t0
+        log("[batch] %s: %.2f s for %d solves" % (prec, dt, len(ctxs)))
+        if ref is None:
+            ref = E
+        res[prec] = {"seconds": dt, "solves_per_s": len(ctxs) / dt, "converged": sum(x["converged"] for x in infos),
+                     "max_energy_error_vs_fp64": float(np.abs(E - ref).max()),
+                     "sigma_calls": sum(x["sigma_calls"] for x in infos),
+                     "sigma_calls_fp64": sum(x["sigma_calls_fp64"] for x in infos)}
+    ctxs = contexts()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for c in ctxs:
+        c.davidson(k, 1e-11, r_tol=1e-7, vectors=False)
+    seq = time.perf_counter() - t0
+    log("[batch] sequential FP64: %.2f s" % seq)
+    print(json.dumps({"metric": "batched uneven CASCI solves", "value": res["bf16"]["solves_per_s"],
+                      "unit": "solves/s", "n_gpus": 1, "higher_is_better": True, "dtype": "bf16+f64",
+                      "data": "synthetic",
+                      "config": {"workload": "%d instances CAS(8..10), 4 roots, spin any" % len(ns),
+                                 "sizes": {str(n): int((ns == n).sum()) for n in (8, 9, 10)}},
+                      "batched": res, "sequential_fp64_seconds": seq}))
+
+
 def kernel_figures(P, dims, n, tag):
     """Per-launch averages and rates of the sigma kernels from HIP events recorded
     on the library's stream (P = profile_read()[tag])."""
@@ -158,6 +211,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--sigma-only", default=None, choices=["f64", "f32", "bf16"],
                     help="profiling aid: only run --steps sigma builds of the workload in this precision")
+    ap.add_argument("--batch", action="store_true", help="run the batched small-active-space workload instead")
+    ap.add_argument("--batch-count", type=int, default=64)
     ap.add_argument("--copy-probe", type=float, default=None,
                     help="counter calibration: copy GIB gibibytes once with a plain device copy")
     args = ap.parse_args()
@@ -179,6 +234,9 @@ def main():
     from paper_2405_10197_amd import casci, synth
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.batch:
+        batch_mode(args)
+        return
     n, na, nb, k, seed, spin, desc = WORKLOADS[args.workload]
     h, eri, _ = synth.integrals(n, seed)
     common = dict(spin=spin, s2_penalty=1.0 if spin == "singlet" else 0.0)

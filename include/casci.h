@@ -197,6 +197,10 @@ typedef struct {
     void (*progress)(void* user, int iteration, int nroots, const double* theta,
                      const double* rnorm, double wall_ms);
     void* progress_user;
+    int graph;              /* 1: replay each sigma build from a captured HIP graph (one launch
+                               per build; the vector is staged through a context buffer) */
+    int buffer_roots;       /* roots followed above the requested ones (they keep a higher state
+                               from replacing the highest requested root): 0 -> 1, < 0 -> none */
 } casci_davidson_opts;
 
 typedef struct {
@@ -231,6 +235,34 @@ typedef struct {
  */
 int casci_davidson(casci_ctx* ctx, int nroots, double tol, const casci_davidson_opts* opts,
                    double* energies, void* vectors, int mem, casci_davidson_info* info);
+
+/*
+ * batch_davidson: independent solves of `count` contexts (each with its own
+ * strings, integrals and stream; no context may appear twice), nroots
+ * roots each, with the same tol and options, run concurrently on up to
+ * nthreads host threads (<= 0: min(count, 16)); their device work overlaps
+ * on the contexts' streams. This is the many-small-active-spaces workload
+ * (Sec. II.A.1's solver applied to a set of CASCI problems of uneven size):
+ * set opts->graph = 1 to replay every sigma build from a captured graph.
+ * energies: host [count][nroots]; infos: optional [count]. A progress
+ * callback in opts is called from the worker threads. Returns the first
+ * negative status of any solve (its message in that context), else
+ * CASCI_NOCONV if any solve did not converge, else CASCI_OK.
+ */
+int casci_batch_davidson(casci_ctx* const* ctxs, int count, int nroots, double tol,
+                         const casci_davidson_opts* opts, double* energies, casci_davidson_info* infos,
+                         int nthreads);
+
+/*
+ * Autotuner choice of the same-spin gather for this context's string space:
+ * out[0] / out[1] = lanes per gathered entry (16, 32 or 64) of the FP64 and
+ * of the FP32-input gather; 0 until the first sigma build in that precision.
+ */
+int casci_get_tuning(casci_ctx* ctx, int* out);
+
+/* Override the autotuner: lanes per gathered entry (16, 32 or 64; 0 = autotune)
+ * of the FP64 and of the FP32-input gather for this context. */
+int casci_set_tuning(casci_ctx* ctx, int f64_lpe, int f32in_lpe);
 
 /*
  * Layout check for bindings: out[0..5] = sizeof(casci_davidson_opts),

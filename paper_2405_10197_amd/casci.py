@@ -43,12 +43,42 @@ class DavidsonOpts(ctypes.Structure):
                 ("r_tol", ctypes.c_double), ("s2_penalty", ctypes.c_double),
                 ("guess", ctypes.c_void_p), ("nguess", ctypes.c_int), ("guess_mem", ctypes.c_int),
                 ("verbose_history", ctypes.c_int), ("progress", ctypes.c_void_p),
-                ("progress_user", ctypes.c_void_p)]
+                ("progress_user", ctypes.c_void_p), ("graph", ctypes.c_int), ("buffer_roots", ctypes.c_int)]
 
 
 PROGRESS_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_int, ctypes.c_int,
                                ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
                                ctypes.c_double)
+
+
+def _make_opts(precond="diag", spin="any", ab_prec="f64", max_iter=0, m_max=0, r_tol=0.0, refine_rnorm=0.0,
+               s2_penalty=0.0, progress=None, graph=False, buffer_roots=0):
+    """Option struct (and the ctypes callback object, which must stay alive during the call)."""
+    o = DavidsonOpts()
+    cb = None
+    if progress is not None:
+        def _cb(user, it, k, th, rn, ms):
+            progress(it, [th[i] for i in range(k)], [rn[i] for i in range(k)], ms)
+        cb = PROGRESS_FN(_cb)
+        o.progress = ctypes.cast(cb, ctypes.c_void_p)
+    o.max_iter, o.m_max = int(max_iter), int(m_max)
+    o.precond, o.spin, o.ab_prec = PRECOND[precond], SPIN[spin], PREC[ab_prec]
+    o.refine_rnorm, o.r_tol, o.s2_penalty = float(refine_rnorm), float(r_tol), float(s2_penalty)
+    o.graph = 1 if graph else 0
+    o.buffer_roots = int(buffer_roots)
+    return o, cb
+
+
+def _info_dict(info, nroots):
+    return {
+        "iterations": info.iterations, "sigma_calls": info.sigma_calls,
+        "sigma_calls_fp64": info.sigma_calls_fp64, "converged": bool(info.converged),
+        "switch_iter": info.switch_iter, "mlp_fallbacks": info.mlp_fallbacks,
+        "refinements": info.refinements,
+        "residual": list(info.residual[:nroots]), "s2": list(info.s2[:nroots]),
+        "time_total_ms": info.time_total_ms, "time_sigma_ms": info.time_sigma_ms,
+        "time_setup_ms": info.time_setup_ms,
+    }
 
 
 class DavidsonInfo(ctypes.Structure):
@@ -106,6 +136,9 @@ def lib():
         "casci_mlp_features": (I, [P, P, P, D, P, I, P]),
         "casci_profile_read": (I, [P, P]),
         "casci_abi_layout": (I, [P, I]),
+        "casci_batch_davidson": (I, [P, I, I, D, P, P, P, I]),
+        "casci_get_tuning": (I, [P, P]),
+        "casci_set_tuning": (I, [P, I, I]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -138,10 +171,14 @@ def _ptr(a):
 class Context:
     """One CASCI problem on one GPU (device=-1: validate-only, no GPU needed)."""
 
-    def __init__(self, device: int = 0, stream=None):
+    def __init__(self, device: int = 0, stream=None, own_stream: bool = False):
+        """device -1: validate-only context (no GPU work). stream: HIP stream
+        handle for the library's work (default: torch's current stream);
+        own_stream=True: the library creates a stream of its own (for
+        concurrent solves, e.g. batch_davidson)."""
         self._L = lib()
         self.device = device
-        if stream is None and device >= 0:
+        if stream is None and device >= 0 and not own_stream:
             import torch
             with torch.cuda.device(device):
                 stream = torch.cuda.current_stream().cuda_stream
@@ -172,8 +209,23 @@ class Context:
         if rc in allow:
             return rc
         if rc < 0:
-            raise CasciError(rc, self._L.casci_last_error(self._h).decode())
+            raise CasciError(rc, self.last_error())
         return rc
+
+    def last_error(self) -> str:
+        m = self._L.casci_last_error(self._h)
+        return m.decode() if m else ""
+
+    def set_tuning(self, f64: int = 0, f32in: int = 0):
+        """Force the lanes per gathered entry (16, 32 or 64; 0: autotune)."""
+        self._check(self._L.casci_set_tuning(self._h, int(f64), int(f32in)))
+
+    def tuning(self):
+        """Autotuned lanes per gathered entry of the same-spin gathers:
+        {'f64': 16|32|64 or 0, 'f32in': ...} (0: not tuned yet)."""
+        out = (ctypes.c_int * 2)()
+        self._check(self._L.casci_get_tuning(self._h, out))
+        return {"f64": out[0], "f32in": out[1]}
 
     # -- problem definition -------------------------------------------------
     def set_integrals(self, h, eri, e_core: float = 0.0):
@@ -349,22 +401,17 @@ class Context:
     def davidson(self, nroots: int = 1, tol: float = 1e-10, *, precond: str = "diag", spin: str = "any",
                  ab_prec: str = "f64", max_iter: int = 0, m_max: int = 0, r_tol: float = 0.0,
                  refine_rnorm: float = 0.0, s2_penalty: float = 0.0, guess=None, vectors=True,
-                 history: int = 0, vectors_out=None, progress=None):
+                 history: int = 0, vectors_out=None, progress=None, graph: bool = False,
+                 buffer_roots: int = 0):
         """Lowest roots by Davidson-Liu. Returns (energies, vectors or None, info dict).
 
         progress: optional callable(iteration, theta list, residual list, wall_ms),
-        called by the library once per iteration.
+        called by the library once per iteration. graph: replay every sigma build
+        from a captured HIP graph.
         """
-        o = DavidsonOpts()
-        cb = None
-        if progress is not None:
-            def _cb(user, it, k, th, rn, ms):
-                progress(it, [th[i] for i in range(k)], [rn[i] for i in range(k)], ms)
-            cb = PROGRESS_FN(_cb)
-            o.progress = ctypes.cast(cb, ctypes.c_void_p)
-        o.max_iter, o.m_max = int(max_iter), int(m_max)
-        o.precond, o.spin, o.ab_prec = PRECOND[precond], SPIN[spin], PREC[ab_prec]
-        o.refine_rnorm, o.r_tol, o.s2_penalty = float(refine_rnorm), float(r_tol), float(s2_penalty)
+        o, cb = _make_opts(precond=precond, spin=spin, ab_prec=ab_prec, max_iter=max_iter, m_max=m_max,
+                           r_tol=r_tol, refine_rnorm=refine_rnorm, s2_penalty=s2_penalty, progress=progress,
+                           graph=graph, buffer_roots=buffer_roots)
         if guess is not None:
             gp, gm = _ptr(guess)
             o.guess, o.nguess, o.guess_mem = gp, int(guess.shape[0]), gm
@@ -387,17 +434,36 @@ class Context:
         rc = self._L.casci_davidson(self._h, int(nroots), float(tol), ctypes.byref(o), E.ctypes.data,
                                     ctypes.c_void_p(vp or None), vm, ctypes.byref(info))
         self._check(rc, allow=(OK, NOCONV))
-        out = {
-            "status": rc, "iterations": info.iterations, "sigma_calls": info.sigma_calls,
-            "sigma_calls_fp64": info.sigma_calls_fp64, "converged": bool(info.converged),
-            "switch_iter": info.switch_iter, "mlp_fallbacks": info.mlp_fallbacks,
-            "refinements": info.refinements,
-            "residual": list(info.residual[:nroots]), "s2": list(info.s2[:nroots]),
-            "time_total_ms": info.time_total_ms, "time_sigma_ms": info.time_sigma_ms,
-            "time_setup_ms": info.time_setup_ms,
-        }
+        out = _info_dict(info, nroots)
+        out["status"] = rc
         if hist is not None:
             n = min(info.iterations, history)
             out["hist_energy"], out["hist_residual"], out["hist_time_ms"] = (
                 hist[0][:n], hist[1][:n], hist[2][:n])
         return E, vec, out
+
+
+def batch_davidson(contexts, nroots: int = 1, tol: float = 1e-10, *, nthreads: int = 0, **kw):
+    """Independent solves of several contexts, run concurrently by the library
+    (casci_batch_davidson). kw: the option keywords of Context.davidson (no
+    guess / vectors). Returns (energies [count][nroots], list of info dicts)."""
+    ctxs = list(contexts)
+    if len(set(id(c) for c in ctxs)) != len(ctxs):
+        raise ValueError("a context appears twice")
+    L = lib()
+    o, cb = _make_opts(**kw)
+    n = len(ctxs)
+    arr = (ctypes.c_void_p * max(n, 1))(*[c._h for c in ctxs])
+    E = np.zeros((n, nroots))
+    infos = (DavidsonInfo * max(n, 1))()
+    rc = L.casci_batch_davidson(arr, n, int(nroots), float(tol), ctypes.byref(o), E.ctypes.data, infos,
+                                int(nthreads))
+    if rc < 0:
+        msgs = [c.last_error() for c in ctxs]
+        raise CasciError(rc, "; ".join(m for m in msgs if m) or "batch_davidson failed")
+    out = []
+    for i in range(n):
+        d = _info_dict(infos[i], nroots)
+        d["status"] = OK if infos[i].converged else NOCONV
+        out.append(d)
+    return E, out

@@ -6,6 +6,11 @@
 #include "casci.h"
 
 #include <algorithm>
+#include <array>
+#include <atomic>
+#include <map>
+#include <mutex>
+#include <thread>
 #include <cstddef>
 #include <chrono>
 #include <cmath>
@@ -127,6 +132,22 @@ struct casci_ctx {
     hipEvent_t pev[6] = {};
     double prof[16] = {};
 
+    // state generation: bumped whenever strings, integrals or the prepared
+    // operators change (captured sigma graphs of an older generation are stale)
+    uint64_t gen = 1;
+    // captured sigma builds (graph mode): inputs staged through d_gin/d_gout
+    struct Graph {
+        int prec, parity;
+        double lambda;
+        uint64_t gen;
+        std::vector<void*> sig;  // device buffers the captured kernels use
+        hipGraphExec_t exec;
+    };
+    std::vector<Graph> graphs;
+    DBuf d_gin, d_gout;
+    // lanes per entry chosen by the autotuner for the FP64 and FP32-input gathers (0: not yet)
+    int tune_lpe[2] = {0, 0};
+
     int fail(int code, const std::string& msg)
     {
         err = msg;
@@ -209,6 +230,10 @@ extern "C" void casci_destroy(casci_ctx* ctx)
                         &ctx->d_vt_full_lp[0], &ctx->d_vt_full_lp[1], &ctx->d_clp, &ctx->d_c32, &ctx->d_t3,
                         &ctx->d_mlp, &ctx->d_mlp_m, &ctx->d_mlp_v, &ctx->d_mlp_g, &ctx->d_mlp_part,
                         &ctx->d_mlp_perm, &ctx->d_mlp_sse, &ctx->d_mlp_idx};
+        for (auto& gr : ctx->graphs) (void)hipGraphExecDestroy(gr.exec);
+        ctx->graphs.clear();
+        ctx->d_gin.release();
+        ctx->d_gout.release();
         for (DBuf* b : bufs) b->release();
         for (hipEvent_t& e : ctx->pev)
             if (e) (void)hipEventDestroy(e);
@@ -280,6 +305,7 @@ extern "C" int casci_set_integrals(casci_ctx* ctx, int norb, const double* h, co
     ctx->have_full = ctx->have_s2 = false;
     ctx->have_tg_sym = ctx->have_tg_full = false;
     ctx->red_sym.have = ctx->red_full.have = false;
+    ++ctx->gen;
     return CASCI_OK;
 }
 
@@ -366,10 +392,12 @@ extern "C" int casci_build_strings(casci_ctx* ctx, int nalpha, int nbeta, int no
     ctx->ra = ra;
     ctx->rb = rb;
     ctx->has_strings = true;
+    ctx->tune_lpe[0] = ctx->tune_lpe[1] = 0;
     ctx->prepared = false;
     ctx->have_full = ctx->have_s2 = false;
     ctx->have_tg_sym = ctx->have_tg_full = false;
     ctx->red_sym.have = ctx->red_full.have = false;
+    ++ctx->gen;
     return CASCI_OK;
 }
 
@@ -554,6 +582,7 @@ static int ensure_prepared(casci_ctx* ctx, double lambda)
         ctx->have_full = false;
         ctx->have_tg_sym = ctx->have_tg_full = false;
         ctx->red_sym.have = ctx->red_full.have = false;
+        ++ctx->gen;
         ctx->prepared_lambda = std::nan("");
     }
     if (!(ctx->prepared_lambda == lambda)) {
@@ -578,6 +607,7 @@ static int ensure_prepared(casci_ctx* ctx, double lambda)
             ctx->have_full = true;
         }
         ctx->prepared_lambda = lambda;
+        ++ctx->gen;
     }
     return CASCI_OK;
 }
@@ -757,6 +787,65 @@ static int ensure_reduce(casci_ctx* ctx, bool full, AbReduce* out)
 // (with parity fused into the S + p S^T symmetrisation). Running it on a
 // second stream beside the gathers was measured not to help: each slows the
 // other by as much as the overlap gains.
+// Autotuner of the same-spin gather: the strip width (lanes per gathered
+// entry, 16/32/64) that is fastest for this string space, timed once per
+// (device, norb, nalpha, nbeta, input precision) on the context's stream and
+// cached for the process.
+static std::mutex g_tune_mu;
+static std::map<std::array<int, 5>, int> g_tune;
+
+static int autotune_gather(casci_ctx* ctx, bool lowp, const double* C, int64_t ld32)
+{
+    const std::array<int, 5> key = {ctx->device, ctx->norb, ctx->na, ctx->nb, lowp ? 1 : 0};
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_tune.find(key);
+        if (it != g_tune.end()) {
+            ctx->tune_lpe[lowp] = it->second;
+            return CASCI_OK;
+        }
+    }
+    hipStream_t st = ctx->stream;
+    HIPC(ctx->d_t1.ensure((size_t)ctx->Nd * 8));
+    hipEvent_t e0, e1;
+    HIPC(hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return ctx->fail(CASCI_E_DEVICE, "hipEventCreate failed");
+    }
+    int best = 0;
+    float best_ms = 0.f;
+    hipError_t err = hipSuccess;
+    for (int lpe : {16, 32, 64}) {
+        auto run = [&]() {
+            if (lowp)
+                return launch_ss_gather_f32in(ctx->d_fa_col.as<int32_t>(), ctx->d_fa_val.as<double>(), ctx->ra,
+                                              ctx->Na, ctx->Nb, ctx->d_c32.as<float>(), ld32, ctx->d_t1.as<double>(),
+                                              0.0, 0, st, lpe);
+            return launch_ss_gather_f64(ctx->d_fa_col.as<int32_t>(), ctx->d_fa_val.as<double>(), ctx->ra, ctx->Na,
+                                        ctx->Nb, C, ctx->d_t1.as<double>(), 0.0, 0, st, lpe);
+        };
+        if ((err = run()) != hipSuccess) break;  // warm-up
+        if ((err = hipEventRecord(e0, st)) != hipSuccess) break;
+        for (int rep = 0; rep < 2 && err == hipSuccess; ++rep) err = run();
+        if (err != hipSuccess || (err = hipEventRecord(e1, st)) != hipSuccess) break;
+        if ((err = hipEventSynchronize(e1)) != hipSuccess) break;
+        float ms = 0.f;
+        if ((err = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess) break;
+        if (best == 0 || ms < best_ms) {
+            best = lpe;
+            best_ms = ms;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    HIPC(err);
+    ctx->tune_lpe[lowp] = best;
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune[key] = best;
+    return CASCI_OK;
+}
+
 static int sigma_dev(casci_ctx* ctx, const double* C, double* S, int ab_prec, double lambda,
                      int parity = 0)
 {
@@ -808,12 +897,14 @@ static int sigma_dev(casci_ctx* ctx, const double* C, double* S, int ab_prec, do
         CHECK_RC(mark(4, st));
     }
     const double s_aa = parity != 0 ? 0.5 * shift : shift;  // halved: S + p S^T doubles it
+    if (ctx->tune_lpe[lowp ? 1 : 0] == 0) CHECK_RC(autotune_gather(ctx, lowp, C, ld32));
+    const int lpe = ctx->tune_lpe[lowp ? 1 : 0];
     if (lowp)
         HIPC(launch_ss_gather_f32in(ctx->d_fa_col.as<int32_t>(), ctx->d_fa_val.as<double>(), ctx->ra, Na, Nb,
-                                    ctx->d_c32.as<float>(), ld32, S, s_aa, 0, st));
+                                    ctx->d_c32.as<float>(), ld32, S, s_aa, 0, st, lpe));
     else
         HIPC(launch_ss_gather_f64(ctx->d_fa_col.as<int32_t>(), ctx->d_fa_val.as<double>(), ctx->ra, Na, Nb,
-                                  C, S, s_aa, 0, st));
+                                  C, S, s_aa, 0, st, lpe));
     CHECK_RC(mark(1, st));
     if (parity == 0 && ctx->nb > 0) {
         HIPC(ctx->d_t1.ensure((size_t)Nd * 8));
@@ -823,7 +914,8 @@ static int sigma_dev(casci_ctx* ctx, const double* C, double* S, int ab_prec, do
         const DBuf& fval = same ? ctx->d_fa_val : ctx->d_fb_val;
         HIPC(launch_transpose_f64(C, ctx->d_t1.as<double>(), Na, Nb, 0, 1.0, st));
         HIPC(launch_ss_gather_f64(fcol.as<int32_t>(), fval.as<double>(), ctx->rb, Nb, Na,
-                                  ctx->d_t1.as<double>(), ctx->d_t2.as<double>(), 0.0, 0, st));
+                                  ctx->d_t1.as<double>(), ctx->d_t2.as<double>(), 0.0, 0, st,
+                                  same && !lowp ? lpe : 0));
         HIPC(launch_transpose_f64(ctx->d_t2.as<double>(), S, Nb, Na, 1, 1.0, st));
     }
     CHECK_RC(mark(2, st));
@@ -853,6 +945,97 @@ static int sigma_dev(casci_ctx* ctx, const double* C, double* S, int ab_prec, do
         pr[4] += t_tot;
         pr[5] += 1;
     }
+    return CASCI_OK;
+}
+
+// Device buffers a captured sigma build reads or writes; a graph is replayed
+// only while all of them are where they were at capture.
+static std::vector<void*> sigma_buffers(const casci_ctx* ctx)
+{
+    return {ctx->d_t1.p, ctx->d_t2.p, ctx->d_t3.p, ctx->d_c32.p, ctx->d_clp.p, ctx->d_fa_col.p,
+            ctx->d_fa_val.p, ctx->d_fb_col.p, ctx->d_fb_val.p, ctx->d_vt_sym.p, ctx->d_vt_full.p,
+            ctx->d_vt_sym_lp[0].p, ctx->d_vt_sym_lp[1].p, ctx->d_vt_full_lp[0].p, ctx->d_vt_full_lp[1].p,
+            ctx->d_tg_sym.p, ctx->d_tg_full.p, ctx->red_sym.tab.p, ctx->red_sym.tinfo.p, ctx->red_full.tab.p,
+            ctx->red_full.tinfo.p, ctx->d_la_j.p, ctx->d_la_pq.p, ctx->d_lb_j.p, ctx->d_bstr.p,
+            ctx->d_pairs_sym.p, ctx->d_pairs_full.p, ctx->d_gin.p, ctx->d_gout.p};
+}
+
+// sigma_dev replayed from a captured HIP graph: one launch per build instead
+// of one per kernel (what dominates for small active spaces). C is staged
+// into d_gin and the result copied out of d_gout around the replay. The
+// first build of a (precision, parity, lambda) runs eagerly once (it
+// allocates, builds the tables and autotunes), then the same build is
+// captured. The captured graph holds no memset nodes.
+static int sigma_graph(casci_ctx* ctx, const double* C, double* S, int ab_prec, double lambda, int parity)
+{
+    hipStream_t st = ctx->stream;
+    const size_t vb = (size_t)ctx->Nd * 8;
+    HIPC(ctx->d_gin.ensure(vb));
+    HIPC(ctx->d_gout.ensure(vb));
+    // drop stale graphs
+    const std::vector<void*> now = sigma_buffers(ctx);
+    for (size_t i = 0; i < ctx->graphs.size();) {
+        auto& g = ctx->graphs[i];
+        if (g.gen != ctx->gen || g.sig != now) {
+            (void)hipGraphExecDestroy(g.exec);
+            ctx->graphs.erase(ctx->graphs.begin() + i);
+        } else {
+            ++i;
+        }
+    }
+    hipGraphExec_t exec = nullptr;
+    for (auto& g : ctx->graphs)
+        if (g.prec == ab_prec && g.parity == parity && g.lambda == lambda) exec = g.exec;
+    HIPC(hipMemcpyAsync(ctx->d_gin.p, C, vb, hipMemcpyDeviceToDevice, st));
+    if (!exec) {
+        CHECK_RC(sigma_dev(ctx, ctx->d_gin.as<double>(), ctx->d_gout.as<double>(), ab_prec, lambda, parity));
+        HIPC(hipStreamSynchronize(st));
+        const bool prof = ctx->profiling;
+        ctx->profiling = false;
+        HIPC(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+        const int rc = sigma_dev(ctx, ctx->d_gin.as<double>(), ctx->d_gout.as<double>(), ab_prec, lambda, parity);
+        hipGraph_t graph = nullptr;
+        const hipError_t ec = hipStreamEndCapture(st, &graph);
+        ctx->profiling = prof;
+        if (rc < 0) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return rc;
+        }
+        HIPC(ec);
+        const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        HIPC(ei);
+        casci_ctx::Graph g;
+        g.prec = ab_prec;
+        g.parity = parity;
+        g.lambda = lambda;
+        g.gen = ctx->gen;
+        g.sig = sigma_buffers(ctx);
+        g.exec = exec;
+        ctx->graphs.push_back(g);
+    }
+    HIPC(hipGraphLaunch(exec, st));
+    HIPC(hipMemcpyAsync(S, ctx->d_gout.p, vb, hipMemcpyDeviceToDevice, st));
+    return CASCI_OK;
+}
+
+extern "C" int casci_set_tuning(casci_ctx* ctx, int f64_lpe, int f32in_lpe)
+{
+    if (!ctx) return CASCI_E_ARG;
+    for (int v : {f64_lpe, f32in_lpe})
+        if (v != 0 && v != 16 && v != 32 && v != 64)
+            return ctx->fail(CASCI_E_ARG, "lanes per entry must be 0, 16, 32 or 64");
+    ctx->tune_lpe[0] = f64_lpe;
+    ctx->tune_lpe[1] = f32in_lpe;
+    ++ctx->gen;  // captured graphs hold the old choice
+    return CASCI_OK;
+}
+
+extern "C" int casci_get_tuning(casci_ctx* ctx, int* out)
+{
+    if (!ctx || !out) return CASCI_E_ARG;
+    out[0] = ctx->tune_lpe[0];
+    out[1] = ctx->tune_lpe[1];
     return CASCI_OK;
 }
 
@@ -1258,7 +1441,12 @@ static int davidson_impl(casci_ctx* ctx, int nroots, double tol, const casci_dav
     CHECK_RC(need_device(ctx));
     DeviceGuard guard(ctx->device);
 
-    const int k = nroots;
+    // nroots requested roots plus buffer roots: Davidson converges the roots it
+    // follows, and the highest requested one is easily replaced by a higher
+    // state when no root above it is followed
+    const int kreq = nroots;
+    const int nbuf = o.buffer_roots < 0 ? 0 : (o.buffer_roots == 0 ? 1 : o.buffer_roots);
+    const int k = (int)std::min<int64_t>({(int64_t)kreq + nbuf, (int64_t)CASCI_MAX_ROOTS, Nd});
     const int max_iter = o.max_iter > 0 ? o.max_iter : 200;
     int m_max = o.m_max > 0 ? o.m_max : std::max(8, 8 * k);
     m_max = std::min<int64_t>(std::min(m_max, 64), Nd);
@@ -1338,7 +1526,10 @@ static int davidson_impl(casci_ctx* ctx, int nroots, double tol, const casci_dav
     std::vector<int> par(m_max + k, 0), xpar(2 * k, 0);
     auto run_sigma_p = [&](const double* c, double* s, int parity, int p) -> int {
         HIPC(hipEventRecord(ev0, st));
-        CHECK_RC(sigma_dev(ctx, c, s, p, lambda, use_par ? parity : 0));
+        if (o.graph)
+            CHECK_RC(sigma_graph(ctx, c, s, p, lambda, use_par ? parity : 0));
+        else
+            CHECK_RC(sigma_dev(ctx, c, s, p, lambda, use_par ? parity : 0));
         HIPC(hipEventRecord(ev1, st));
         HIPC(hipEventSynchronize(ev1));
         float ms = 0;
@@ -1653,18 +1844,22 @@ static int davidson_impl(casci_ctx* ctx, int nroots, double tol, const casci_dav
         std::vector<int> todo;
         for (int j = 0; j < k; ++j) {
             rn[j] = std::sqrt(std::max(rs[4 * j], 0.0));
-            rmax = std::max(rmax, rn[j]);
+            if (j < kreq) rmax = std::max(rmax, rn[j]);
             const double dth_j = std::fabs(theta[j] - theta_prev[j]);
-            if (!(rn[j] < r_tol && dth_j < tol)) todo.push_back(j);
+            if (j < kreq && !(rn[j] < r_tol && dth_j < tol)) todo.push_back(j);
         }
+        // buffer roots get corrections while a requested root is unconverged
+        if (!todo.empty())
+            for (int j = kreq; j < k; ++j)
+                if (!(rn[j] < r_tol && std::fabs(theta[j] - theta_prev[j]) < tol)) todo.push_back(j);
         if (info && info->hist_energy && it < info->hist_len)
-            for (int j = 0; j < k; ++j) info->hist_energy[(size_t)it * k + j] = theta[j];
+            for (int j = 0; j < kreq; ++j) info->hist_energy[(size_t)it * kreq + j] = theta[j];
         if (info && info->hist_residual && it < info->hist_len)
-            for (int j = 0; j < k; ++j) info->hist_residual[(size_t)it * k + j] = rn[j];
+            for (int j = 0; j < kreq; ++j) info->hist_residual[(size_t)it * kreq + j] = rn[j];
         if (info && info->hist_time_ms && it < info->hist_len) info->hist_time_ms[it] = wall.ms();
         for (int j = 0; j < k; ++j) theta_prev[j] = theta[j];
-        if (o.progress) o.progress(o.progress_user, it, k, theta.data(), rn.data(), wall.ms());
-        if (col) CHECK_RC(collect_step(ctx, col, k, X, SX, theta, rn, dmin));
+        if (o.progress) o.progress(o.progress_user, it, kreq, theta.data(), rn.data(), wall.ms());
+        if (col) CHECK_RC(collect_step(ctx, col, kreq, X, SX, theta, rn, dmin));
         if (!std::isfinite(rmax)) return ctx->fail(CASCI_E_NONFINITE, "non-finite residual in Davidson");
         // collapse: keep current and previous Ritz vectors (room for ncorr new ones)
         auto collapse = [&](int ncorr) -> int {
@@ -1769,7 +1964,7 @@ static int davidson_impl(casci_ctx* ctx, int nroots, double tol, const casci_dav
                 bool ok = true;
                 for (int j = 0; j < k; ++j) {
                     const double r = std::sqrt(std::max(rx[4 * j], 0.0));
-                    ok = ok && r < r_tol && std::fabs(th[j] - theta[j]) < tol;
+                    if (j < kreq) ok = ok && r < r_tol && std::fabs(th[j] - theta[j]) < tol;
                     rn[j] = r;
                 }
                 if (ok) {
@@ -1826,10 +2021,10 @@ static int davidson_impl(casci_ctx* ctx, int nroots, double tol, const casci_dav
     }
 
     // results
-    for (int j = 0; j < k; ++j) energies[j] = theta[j];
-    std::vector<double> s2v(k, 0.0);
+    for (int j = 0; j < kreq; ++j) energies[j] = theta[j];
+    std::vector<double> s2v(kreq, 0.0);
     if (vectors || info) {
-        for (int j = 0; j < k; ++j) {
+        for (int j = 0; j < kreq; ++j) {
             // phase: largest-|c| entry positive (ties: lowest index)
             std::vector<double> hv(Nd);
             HIPC(hipMemcpyAsync(hv.data(), vX(j), vb, hipMemcpyDeviceToHost, st));
@@ -1841,7 +2036,7 @@ static int davidson_impl(casci_ctx* ctx, int nroots, double tol, const casci_dav
             if (info) CHECK_RC(spin_square_dev(ctx, vX(j), &s2v[j]));
         }
         if (vectors)
-            HIPC(hipMemcpyAsync(vectors, X, vb * k,
+            HIPC(hipMemcpyAsync(vectors, X, vb * kreq,
                                 mem == CASCI_MEM_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice, st));
         HIPC(hipStreamSynchronize(st));
     }
@@ -1854,8 +2049,8 @@ static int davidson_impl(casci_ctx* ctx, int nroots, double tol, const casci_dav
         info->mlp_fallbacks = mlp_fallbacks;
         info->refinements = refinements;
         for (int j = 0; j < CASCI_MAX_ROOTS; ++j) {
-            info->residual[j] = j < k ? rn[j] : 0.0;
-            info->s2[j] = j < k ? s2v[j] : 0.0;
+            info->residual[j] = j < kreq ? rn[j] : 0.0;
+            info->s2[j] = j < kreq ? s2v[j] : 0.0;
         }
         info->time_sigma_ms = sigma_ms;
         info->time_setup_ms = setup_ms;
@@ -2106,3 +2301,39 @@ extern "C" int casci_mlp_features(casci_ctx* ctx, const double* x, const double*
     bf.release();
     return CASCI_OK;
 }
+
+extern "C" int casci_batch_davidson(casci_ctx* const* ctxs, int count, int nroots, double tol,
+                                    const casci_davidson_opts* opts, double* energies,
+                                    casci_davidson_info* infos, int nthreads)
+{
+    if (!ctxs || count < 0 || (count > 0 && !energies)) return CASCI_E_ARG;
+    for (int i = 0; i < count; ++i) {
+        if (!ctxs[i]) return CASCI_E_ARG;
+        for (int j = 0; j < i; ++j)
+            if (ctxs[j] == ctxs[i]) return ctxs[i]->fail(CASCI_E_ARG, "a context appears twice in the batch");
+    }
+    if (count == 0) return CASCI_OK;
+    int nt = nthreads > 0 ? nthreads : 16;
+    nt = std::max(1, std::min(nt, count));
+    std::atomic<int> next(0);
+    std::vector<int> rc(count, CASCI_OK);
+    auto worker = [&]() {
+        for (;;) {
+            const int i = next.fetch_add(1);
+            if (i >= count) break;
+            rc[i] = davidson_impl(ctxs[i], nroots, tol, opts, energies + (size_t)i * nroots, nullptr,
+                                  CASCI_MEM_HOST, infos ? infos + i : nullptr, nullptr);
+        }
+    };
+    std::vector<std::thread> pool;
+    pool.reserve(nt - 1);
+    for (int t = 1; t < nt; ++t) pool.emplace_back(worker);
+    worker();
+    for (auto& th : pool) th.join();
+    int out = CASCI_OK;
+    for (int i = 0; i < count; ++i)
+        if (rc[i] < 0) return rc[i];
+        else if (rc[i] > 0) out = rc[i];
+    return out;
+}
+

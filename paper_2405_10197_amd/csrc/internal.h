@@ -56,13 +56,15 @@ hipError_t launch_scatter_values(const int64_t* idx, const double* v, int P, dou
 
 // sigma_kernels.hip
 // Y(I,:) = [acc ? Y(I,:) : 0] + sum_e val[I*r+e] X(col[I*r+e], :) + shift * X(I,:)
+// (lpe: lanes per gathered entry, 16/32/64; 0 = default 32)
 hipError_t launch_ss_gather_f64(const int32_t* col, const double* val, int r, int64_t nrows,
                                 int64_t ncols, const double* X, double* Y, double shift, int acc,
-                                hipStream_t st);
+                                hipStream_t st, int lpe = 0);
 // same gather reading an FP32 copy of X with row stride ldx, FP64 output
+// (lpe as above; 0 = default 64)
 hipError_t launch_ss_gather_f32in(const int32_t* col, const double* val, int r, int64_t nrows,
                                   int64_t ncols, const float* X, int64_t ldx, double* Y, double shift,
-                                  int acc, hipStream_t st);
+                                  int acc, hipStream_t st, int lpe = 0);
 // S <- scale (S + p S^T) [+ T], S square n x n, in place (T may be null)
 hipError_t launch_sym_add(double* S, int64_t n, int p, double scale, hipStream_t st,
                           const double* T = nullptr);

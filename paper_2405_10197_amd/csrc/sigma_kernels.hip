@@ -125,16 +125,28 @@ static hipError_t ss_gather(const int32_t* col, const double* val, int r, int64_
 
 hipError_t launch_ss_gather_f64(const int32_t* col, const double* val, int r, int64_t nrows,
                                 int64_t ncols, const double* X, double* Y, double shift, int acc,
-                                hipStream_t st)
+                                hipStream_t st, int lpe)
 {
-    return ss_gather<double, double, 32>(col, val, r, nrows, ncols, X, ncols, Y, shift, acc, st);
+    switch (lpe) {
+    case 16: return ss_gather<double, double, 16>(col, val, r, nrows, ncols, X, ncols, Y, shift, acc, st);
+    case 0:
+    case 32: return ss_gather<double, double, 32>(col, val, r, nrows, ncols, X, ncols, Y, shift, acc, st);
+    case 64: return ss_gather<double, double, 64>(col, val, r, nrows, ncols, X, ncols, Y, shift, acc, st);
+    default: return invalid("same-spin gather: lanes per entry must be 16, 32 or 64");
+    }
 }
 
 hipError_t launch_ss_gather_f32in(const int32_t* col, const double* val, int r, int64_t nrows,
                                   int64_t ncols, const float* X, int64_t ldx, double* Y, double shift,
-                                  int acc, hipStream_t st)
+                                  int acc, hipStream_t st, int lpe)
 {
-    return ss_gather<float, double, 64>(col, val, r, nrows, ncols, X, ldx, Y, shift, acc, st);
+    switch (lpe) {
+    case 16: return ss_gather<float, double, 16>(col, val, r, nrows, ncols, X, ldx, Y, shift, acc, st);
+    case 32: return ss_gather<float, double, 32>(col, val, r, nrows, ncols, X, ldx, Y, shift, acc, st);
+    case 0:
+    case 64: return ss_gather<float, double, 64>(col, val, r, nrows, ncols, X, ldx, Y, shift, acc, st);
+    default: return invalid("same-spin gather: lanes per entry must be 16, 32 or 64");
+    }
 }
 
 hipError_t launch_ss_gather_f32(const int32_t* col, const double* val, int r, int64_t nrows,

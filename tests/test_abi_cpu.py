@@ -147,3 +147,16 @@ def test_struct_layout_matches_binding(L):
     assert list(lay) == [ctypes.sizeof(casci.DavidsonOpts), ctypes.sizeof(casci.DavidsonInfo),
                          casci.DavidsonOpts.progress.offset, casci.DavidsonInfo.residual.offset,
                          casci.DavidsonInfo.hist_energy.offset, casci.DavidsonInfo.hist_len.offset]
+
+
+def test_batch_rejects_duplicate_contexts_and_bad_tuning(L):
+    c = casci.Context(-1)
+    with pytest.raises(ValueError):
+        casci.batch_davidson([c, c], 1, 1e-8)
+    import ctypes
+    arr = (ctypes.c_void_p * 2)(c._h, c._h)
+    E = np.zeros(2)
+    assert L.casci_batch_davidson(arr, 2, 1, 1e-8, None, E.ctypes.data, None, 1) == casci.E_ARG
+    assert L.casci_batch_davidson(arr, 0, 1, 1e-8, None, E.ctypes.data, None, 1) == casci.OK
+    with pytest.raises(casci.CasciError):
+        c.set_tuning(24, 0)

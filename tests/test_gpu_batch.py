@@ -1,0 +1,111 @@
+"""Many small active spaces: graph-replayed sigma builds, the gather
+autotuner, and concurrent batched solves against single solves and the
+oracle."""
+import numpy as np
+import pytest
+import scipy.sparse.linalg as sla
+
+import oracle
+from paper_2405_10197_amd import casci, synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    if not t.cuda.is_available():
+        pytest.skip("no GPU")
+    return t
+
+
+def electrons(n):
+    """CAS(n e, n o): nalpha = ceil(n/2), nbeta = floor(n/2)."""
+    return (n + 1) // 2, n // 2
+
+
+def make(n, seed, own_stream=False):
+    na, nb = electrons(n)
+    h, eri, _ = synth.integrals(n, seed)
+    c = casci.Context(0, own_stream=own_stream)
+    c.set_integrals(h, eri)
+    c.build_strings(na, nb, n)
+    return c, h, eri
+
+
+def lowest(h, eri, n, k):
+    na, nb = electrons(n)
+    H = oracle.hamiltonian_csr(h, eri, na, nb)
+    return np.sort(sla.eigsh(H, k=k, which="SA", tol=1e-12)[0])
+
+
+@pytest.mark.parametrize("prec", ["f64", "bf16"])
+def test_graph_replay_reproduces_eager_solve(torch, prec):
+    """Every sigma replayed from the captured graph equals the eager build: the
+    whole solve (with eager work and synchronisations between replays) takes
+    the same path, iteration by iteration, up to the summation order of the
+    FP64 alpha-beta kernel's atomic adds (~1e-14; in BF16 runs such a
+    difference can flip a rounding and the paths then differ by ~1e-10 in
+    mid-solve before meeting at the converged energies)."""
+    c, h, eri = make(8, 3000)
+    E0, _, i0 = c.davidson(4, 1e-11, r_tol=1e-7, vectors=False, ab_prec=prec, history=500)
+    E1, _, i1 = c.davidson(4, 1e-11, r_tol=1e-7, vectors=False, ab_prec=prec, history=500, graph=True)
+    assert i0["converged"] and i1["converged"]
+    assert abs(i0["iterations"] - i1["iterations"]) <= 1
+    nc = min(len(i0["hist_energy"]), len(i1["hist_energy"]))
+    assert np.abs(i0["hist_energy"][:nc] - i1["hist_energy"][:nc]).max() < (1e-10 if prec == "f64" else 1e-7)
+    assert np.abs(E0 - E1).max() < 1e-11
+
+
+@pytest.mark.parametrize("n", [8, 9])
+def test_every_gather_width_matches_oracle(torch, n):
+    """Each strip width the autotuner can pick gives sigma = H C (FP64 and
+    FP32-input gathers), and the autotuner's choice is one of them."""
+    c, h, eri = make(n, 3010 + n)
+    na, nb = electrons(n)
+    d = c.dims
+    x = synth.ci_vector(d["Na"], d["Nb"], 5)[0]
+    ref = oracle.sigma(h, eri, na, nb, x)
+    xt = torch.from_numpy(x).cuda()
+    for lpe in (16, 32, 64):
+        c.set_tuning(lpe, lpe)
+        s64 = c.sigma(xt).cpu().numpy()
+        assert np.abs(s64 - ref).max() < 1e-11 * max(1.0, np.abs(ref).max())
+        s32 = c.sigma(xt, ab_prec="f32").cpu().numpy()
+        assert np.abs(s32 - ref).max() < 1e-5 * np.abs(ref).max()
+    c.set_tuning(0, 0)
+    c.sigma(xt)
+    c.sigma(xt, ab_prec="f32")
+    t = c.tuning()
+    assert t["f64"] in (16, 32, 64) and t["f32in"] in (16, 32, 64)
+
+
+def test_batch_matches_single_solves_and_oracle(torch):
+    """Uneven active spaces CAS(8,8) .. CAS(10,10) (CAS(9,9) as a doublet), 4
+    roots each, own integrals each, solved concurrently with graph-replayed
+    sigma builds: every instance matches its own single solve and (n <= 9) the
+    oracle to 1e-10 Eh."""
+    ns = [8, 9, 10, 8, 9, 10]
+    k = 4
+    items = [make(n, 3100 + i, own_stream=True) for i, n in enumerate(ns)]
+    E, infos = casci.batch_davidson([c for c, _, _ in items], k, 1e-11, r_tol=1e-7, graph=True, nthreads=6)
+    for i, (n, (c, h, eri)) in enumerate(zip(ns, items)):
+        assert infos[i]["converged"], (i, n)
+        Es, _, _ = c.davidson(k, 1e-11, r_tol=1e-7, vectors=False)
+        assert np.abs(E[i] - Es).max() < 1e-10, (i, n, E[i], Es)
+        if n <= 9:
+            Eo = lowest(h, eri, n, k)
+            assert np.abs(E[i] - Eo).max() < 1e-10, (i, n, E[i], Eo)
+
+
+@pytest.mark.parametrize("prec", ["f32", "bf16"])
+def test_batch_mixed_precision_matches_fp64(torch, prec):
+    ns = [8, 10, 9, 10]
+    k = 4
+    items = [make(n, 3200 + i, own_stream=True) for i, n in enumerate(ns)]
+    ctxs = [c for c, _, _ in items]
+    E64, i64 = casci.batch_davidson(ctxs, k, 1e-11, r_tol=1e-7, graph=True)
+    El, il = casci.batch_davidson(ctxs, k, 1e-11, r_tol=1e-7, graph=True, ab_prec=prec, precond="olsen")
+    assert all(x["converged"] for x in i64 + il)
+    assert np.abs(El - E64).max() < 1e-9
+    assert sum(x["sigma_calls_fp64"] for x in il) < sum(x["sigma_calls"] for x in il) / 2
