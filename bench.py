@@ -17,6 +17,7 @@ Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload cas16|cas
        python bench.py --sigma-only f64|f32|bf16 --steps K   (kernel profiling aid)
        python bench.py --copy-probe GIB                       (counter calibration: one plain copy)
        python bench.py --batch [--batch-count 64]             (64 uneven CAS(8..10) solves, 4 roots)
+       python bench.py --cas18                                (CAS(18,18) sigma throughput, FP32 storage)
 """
 from __future__ import annotations
 
@@ -170,6 +171,85 @@ def batch_mode(args):
                       "batched": res, "sequential_fp64_seconds": seq}))
 
 
+def cas18_mode(args):
+    """Single sigma(C) calls at CAS(18e,18o) (2,363,904,400 determinants) on
+    a seeded normalised random C (N(0,1) from seed 50, drawn in FP64 and
+    normalised, then rounded to FP32 storage): FP32-storage builds with FP32
+    and BF16 alpha-beta arithmetic, against the FP64 build of the same rounded
+    values upcast."""
+    import torch
+    from paper_2405_10197_amd import casci, synth
+    n = args.cas18_norb
+    ne = n // 2
+    h, eri, _ = synth.integrals(n, 5)
+    ctx = casci.Context(0)
+    t0 = time.perf_counter()
+    ctx.set_integrals(h, eri)
+    ctx.build_strings(ne, ne, n)
+    d = ctx.dims
+    Na, Nb, Nd = d["Na"], d["Nb"], d["Ndet"]
+    g = torch.Generator(device="cuda").manual_seed(50)
+    C = torch.empty((Na, Nb), dtype=torch.float32, device="cuda")
+    rows = max(1, (1 << 27) // Nb)
+    for r0 in range(0, Na, rows):  # drawn in FP64 slab by slab, rounded to FP32
+        C[r0:r0 + rows] = torch.randn((min(rows, Na - r0), Nb), dtype=torch.float64, device="cuda",
+                                      generator=g).to(torch.float32)
+    nrm = float(torch.linalg.vector_norm(C.view(-1), dtype=torch.float64))
+    C /= nrm
+    S = torch.empty_like(C)
+    log("[cas18] %d determinants, vectors %.1f GB each in FP32; setup %.1f s" % (Nd, Nd * 4 / 1e9,
+                                                                                   time.perf_counter() - t0))
+    M = n * (n + 1) // 2
+    ab_flops = 2.0 * M * d["sa"] * Nd
+    out = {}
+    results = {}
+    for prec in ("f32", "bf16"):
+        ctx.sigma(C, out=S, ab_prec=prec)  # first build: tables, autotuner
+        torch.cuda.synchronize()
+        ctx.profile(True)
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            ctx.sigma(C, out=S, ab_prec=prec)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / args.steps
+        P = ctx.profile_read()["lowp"]
+        ctx.profile(False)
+        k = max(P["sigma_builds"], 1)
+        aa, bb, ab = P["aa_ms"] / k, P["bb_ms"] / k, P["ab_ms"] / k
+        gather_bytes = Nd * 4.0 * 2 + Na * d["ra"] * 12.0
+        out[prec] = {"ms_per_sigma": dt * 1e3, "alpha_alpha_ms": aa, "beta_beta_ms": bb, "alpha_beta_ms": ab,
+                     "gather_GBps_algorithmic": gather_bytes / (aa * 1e-3) / 1e9,
+                     "gather_GBps_gathered_operands": d["ra"] * Nd * 4.0 / (aa * 1e-3) / 1e9,
+                     "alpha_beta_TFLOPs": ab_flops / (ab * 1e-3) / 1e12,
+                     "alpha_beta_mfma_util": ab_flops / (ab * 1e-3) / 1e12 / (PEAK["f32_TF"] if prec == "f32" else PEAK["bf16_TF"])}
+        results[prec] = S.clone() if prec == "f32" else S
+        log("[cas18] %s: %.0f ms per sigma (aa %.0f, bb %.0f, ab %.0f)" % (prec, dt * 1e3, aa, bb, ab))
+    # FP64 reference of the same rounded values
+    s32 = results.pop("f32")
+    s16 = results.pop("bf16")
+    del S
+    torch.cuda.empty_cache()
+    C64 = C.to(torch.float64)
+    S64 = torch.empty_like(C64)
+    t0 = time.perf_counter()
+    ctx.sigma(C64, out=S64, ab_prec="f64")
+    torch.cuda.synchronize()
+    t64 = time.perf_counter() - t0
+    nref = float(torch.linalg.vector_norm(S64.view(-1)))
+    for prec, sv in (("f32", s32), ("bf16", s16)):
+        diff = 0.0
+        for r0 in range(0, Na, rows):
+            diff += float(((sv[r0:r0 + rows].to(torch.float64) - S64[r0:r0 + rows]) ** 2).sum())
+        out[prec]["rel_error_vs_fp64"] = math.sqrt(diff) / nref
+    log("[cas18] FP64 reference sigma %.1f s" % t64)
+    print(json.dumps({"metric": "CAS(18,18) sigma build, FP32 storage", "value": out["bf16"]["ms_per_sigma"],
+                      "unit": "ms per sigma", "n_gpus": 1, "higher_is_better": False, "dtype": "f32 storage",
+                      "data": "synthetic", "config": {"workload": "CAS(%de,%do), %d determinants, integrals seed 5, "
+                                                                   "C seed 50" % (n, n, Nd)},
+                      "sigma": out, "fp64_reference_seconds": t64,
+                      "alpha_beta_flops": ab_flops}))
+
+
 def kernel_figures(P, dims, n, tag):
     """Per-launch averages and rates of the sigma kernels from HIP events recorded
     on the library's stream (P = profile_read()[tag])."""
@@ -212,6 +292,8 @@ def main():
     ap.add_argument("--sigma-only", default=None, choices=["f64", "f32", "bf16"],
                     help="profiling aid: only run --steps sigma builds of the workload in this precision")
     ap.add_argument("--batch", action="store_true", help="run the batched small-active-space workload instead")
+    ap.add_argument("--cas18", action="store_true", help="run the CAS(18,18) FP32-storage sigma workload instead")
+    ap.add_argument("--cas18-norb", type=int, default=18, help=argparse.SUPPRESS)
     ap.add_argument("--batch-count", type=int, default=64)
     ap.add_argument("--copy-probe", type=float, default=None,
                     help="counter calibration: copy GIB gibibytes once with a plain device copy")
@@ -236,6 +318,9 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     if args.batch:
         batch_mode(args)
+        return
+    if args.cas18:
+        cas18_mode(args)
         return
     n, na, nb, k, seed, spin, desc = WORKLOADS[args.workload]
     h, eri, _ = synth.integrals(n, seed)

@@ -159,12 +159,13 @@ int casci_get_diagonal(casci_ctx* ctx, double* out, int mem);
 /*
  * sigma: sigma = H C for one CI vector (the sigma build of Sec. II.A.1).
  * C and sigma are Na x Nb row-major arrays of `dtype` (CASCI_F64, or
- * CASCI_F32 for single-precision storage with FP64 accumulation of the
- * same-spin terms). ab_prec selects the arithmetic of the alpha-beta
- * contraction: CASCI_F64 (FP64 MFMA), CASCI_F32 (FP32 MFMA) or CASCI_BF16
- * (BF16 MFMA, FP32 accumulate); the alpha-alpha / beta-beta terms are
- * computed in FP64 arithmetic. sigma is overwritten, never accumulated.
- * C and sigma must not overlap.
+ * CASCI_F32 for single-precision storage). ab_prec selects the arithmetic
+ * of the alpha-beta contraction: CASCI_F64 (FP64 MFMA), CASCI_F32 (FP32
+ * MFMA) or CASCI_BF16 (BF16 MFMA, FP32 accumulate); the alpha-alpha /
+ * beta-beta terms accumulate in FP64. FP32 storage on the device with
+ * ab_prec F32/BF16 keeps every vector-sized buffer in FP32 (no FP64 copy:
+ * the large-active-space path); other FP32 cases convert to FP64 inside.
+ * sigma is overwritten, never accumulated. C and sigma must not overlap.
  */
 int casci_sigma(casci_ctx* ctx, const void* C, void* sigma, int dtype, int ab_prec, int mem);
 

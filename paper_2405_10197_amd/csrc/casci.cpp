@@ -948,6 +948,82 @@ static int sigma_dev(casci_ctx* ctx, const double* C, double* S, int ab_prec, do
     return CASCI_OK;
 }
 
+// sigma = H C for an FP32-stored vector, without FP64 copies of the vector
+// (the footprint that lets CAS(18e,18o) vectors, 9.5 GB each in FP32, be
+// processed with room to spare). C32, S32: device, Na x Nb FP32. The
+// same-spin gathers accumulate in FP64 registers and store FP32; the
+// alpha-beta term (FP32 or BF16 MFMA, FP32 accumulation) is added into S32.
+// Timed parts go to the low-precision profile slots.
+static int sigma_dev_f32(casci_ctx* ctx, const float* C32, float* S32, int ab_prec)
+{
+    hipStream_t st = ctx->stream;
+    const int64_t Na = ctx->Na, Nb = ctx->Nb, Nd = ctx->Nd;
+    const double ms = 0.5 * (ctx->na - ctx->nb);
+    (void)ms;
+    const double shift = ctx->ecore;
+    const bool prof = ctx->profiling;
+    const bool has_ab = ctx->na > 0 && ctx->nb > 0;
+    set_launch_reason("");
+    auto mark = [&](int i) -> int {
+        if (prof) HIPC(hipEventRecord(ctx->pev[i], st));
+        return CASCI_OK;
+    };
+    CHECK_RC(mark(0));
+    CHECK_RC(mark(3));
+    const int lpe = ctx->tune_lpe[1];
+    // alpha-alpha: S32 = F_a C + shift C
+    HIPC(launch_ss_gather_f32(ctx->d_fa_col.as<int32_t>(), ctx->d_fa_val.as<double>(), ctx->ra, Na, Nb, C32, S32,
+                              shift, 0, st, lpe));
+    CHECK_RC(mark(4));
+    CHECK_RC(mark(1));
+    // beta-beta: S32 += (F_b C^T)^T through two FP32 transposes
+    if (ctx->nb > 0) {
+        HIPC(ctx->d_t1.ensure((size_t)Nd * 4));
+        HIPC(ctx->d_t2.ensure((size_t)Nd * 4));
+        const bool same = ctx->nb == ctx->na;
+        const DBuf& fcol = same ? ctx->d_fa_col : ctx->d_fb_col;
+        const DBuf& fval = same ? ctx->d_fa_val : ctx->d_fb_val;
+        HIPC(launch_transpose_f32(C32, ctx->d_t1.as<float>(), Na, Nb, 0, st));
+        HIPC(launch_ss_gather_f32(fcol.as<int32_t>(), fval.as<double>(), ctx->rb, Nb, Na, ctx->d_t1.as<float>(),
+                                  ctx->d_t2.as<float>(), 0.0, 0, st, same ? lpe : 0));
+        HIPC(launch_transpose_f32(ctx->d_t2.as<float>(), S32, Nb, Na, 1, st));
+    }
+    CHECK_RC(mark(2));
+    // alpha-beta, added into S32
+    if (has_ab) {
+        AbParams p = ab_params(ctx, false);
+        p.overwrite = 0;
+        AbReduce red;
+        CHECK_RC(ensure_reduce(ctx, false, &red));
+        const int pr = ab_prec == CASCI_F32 ? 1 : 2;
+        const int64_t ld = lowp_ld(pr, Nb);
+        const void* Cs = C32;
+        if (pr == 2 || ld != Nb) {
+            DBuf& buf = pr == 1 ? ctx->d_c32 : ctx->d_clp;
+            HIPC(buf.ensure((size_t)Na * ld * (pr == 1 ? 4 : 2)));
+            HIPC(launch_convert_lowp_f32in(pr, C32, buf.p, Na, Nb, ld, st));
+            Cs = buf.p;
+        }
+        HIPC(launch_ab_lowp(p, red, pr, ctx->d_vt_sym_lp[pr - 1].p, Cs, ld, S32, st));
+    }
+    CHECK_RC(mark(5));
+    if (prof) {
+        HIPC(hipEventSynchronize(ctx->pev[5]));
+        float t_aa = 0, t_bb = 0, t_ab = 0, t_tot = 0;
+        HIPC(hipEventElapsedTime(&t_aa, ctx->pev[0], ctx->pev[1]));
+        HIPC(hipEventElapsedTime(&t_bb, ctx->pev[1], ctx->pev[2]));
+        HIPC(hipEventElapsedTime(&t_ab, ctx->pev[2], ctx->pev[5]));
+        HIPC(hipEventElapsedTime(&t_tot, ctx->pev[0], ctx->pev[5]));
+        double* q = ctx->prof + 6;
+        q[0] += t_aa;
+        q[1] += t_bb;
+        q[2] += t_ab;
+        q[4] += t_tot;
+        q[5] += 1;
+    }
+    return CASCI_OK;
+}
+
 // Device buffers a captured sigma build reads or writes; a graph is replayed
 // only while all of them are where they were at capture.
 static std::vector<void*> sigma_buffers(const casci_ctx* ctx)
@@ -1141,6 +1217,8 @@ extern "C" int casci_sigma(casci_ctx* ctx, const void* C, void* sigma, int dtype
     const size_t Nd = (size_t)ctx->Nd;
     const size_t esz = dtype == CASCI_F64 ? 8 : 4;
     hipStream_t st = ctx->stream;
+    if (dtype == CASCI_F32 && mem == CASCI_MEM_DEVICE && ab_prec != CASCI_F64)
+        return sigma_dev_f32(ctx, (const float*)C, (float*)sigma, ab_prec);
     const double* cin;
     double* sout;
     if (dtype == CASCI_F64 && mem == CASCI_MEM_DEVICE) {

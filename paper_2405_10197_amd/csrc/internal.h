@@ -70,7 +70,7 @@ hipError_t launch_sym_add(double* S, int64_t n, int p, double scale, hipStream_t
                           const double* T = nullptr);
 hipError_t launch_ss_gather_f32(const int32_t* col, const double* val, int r, int64_t nrows,
                                 int64_t ncols, const float* X, float* Y, double shift, int acc,
-                                hipStream_t st);
+                                hipStream_t st, int lpe = 0);
 // out[j][i] (+)= in[i][j], in: rows x cols
 hipError_t launch_transpose_f64(const double* in, double* out, int64_t rows, int64_t cols, int acc,
                                 double scale, hipStream_t st);
@@ -124,10 +124,15 @@ hipError_t launch_ab_f64(const AbParams& p, const double* Vt, const double* C, d
                          hipStream_t st);
 hipError_t launch_ab_lowp(const AbParams& p, const AbReduce& r, int prec, const void* Vt, const void* Cs,
                           int64_t ldc, double* sigma, hipStream_t st);
+// same, for an FP32 sigma (FP32-storage builds)
+hipError_t launch_ab_lowp(const AbParams& p, const AbReduce& r, int prec, const void* Vt, const void* Cs,
+                          int64_t ldc, float* sigma, hipStream_t st);
 // padded row stride of the low-precision copy of C, and the conversion itself
 int64_t lowp_ld(int prec, int64_t cols);
 hipError_t launch_convert_lowp(int prec, const double* C, void* out, int64_t rows, int64_t cols,
                                int64_t ld, hipStream_t st);
+hipError_t launch_convert_lowp_f32in(int prec, const float* C, void* out, int64_t rows, int64_t cols, int64_t ld,
+                                     hipStream_t st);
 hipError_t launch_convert_f64_to_f32(const double* in, float* out, int64_t n, hipStream_t st);
 hipError_t launch_convert_f32_to_f64(const float* in, double* out, int64_t n, hipStream_t st);
 hipError_t launch_axpby_f64(double a, const double* x, double b, double* y, int64_t n, hipStream_t st);

@@ -151,9 +151,15 @@ hipError_t launch_ss_gather_f32in(const int32_t* col, const double* val, int r, 
 
 hipError_t launch_ss_gather_f32(const int32_t* col, const double* val, int r, int64_t nrows,
                                 int64_t ncols, const float* X, float* Y, double shift, int acc,
-                                hipStream_t st)
+                                hipStream_t st, int lpe)
 {
-    return ss_gather<float, float, 64>(col, val, r, nrows, ncols, X, ncols, Y, shift, acc, st);
+    switch (lpe) {
+    case 16: return ss_gather<float, float, 16>(col, val, r, nrows, ncols, X, ncols, Y, shift, acc, st);
+    case 32: return ss_gather<float, float, 32>(col, val, r, nrows, ncols, X, ncols, Y, shift, acc, st);
+    case 0:
+    case 64: return ss_gather<float, float, 64>(col, val, r, nrows, ncols, X, ncols, Y, shift, acc, st);
+    default: return invalid("same-spin gather: lanes per entry must be 16, 32 or 64");
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -574,10 +580,10 @@ __global__ __launch_bounds__(64 * AB_MAX_WAVES) void k_ab(AbParams p, const type
 // the current tile is multiplied and reduced.
 constexpr int ABL_MAX_WAVES = 12;
 
-template <typename MF, int KBMAX, int MT, int SPT>
+template <typename MF, int KBMAX, int MT, int SPT, typename TO>
 __global__ __launch_bounds__(64 * ABL_MAX_WAVES) void k_ab_lp(
     AbParams p, AbReduce r, const typename MF::elem* __restrict__ Vt,
-    const typename MF::elem* __restrict__ Cs, int64_t ldc, double* __restrict__ sigma, int kb_count,
+    const typename MF::elem* __restrict__ Cs, int64_t ldc, TO* __restrict__ sigma, int kb_count,
     int64_t chunk, int nchunks)
 {
     using elem = typename MF::elem;
@@ -781,11 +787,11 @@ __global__ __launch_bounds__(64 * ABL_MAX_WAVES) void k_ab_lp(
         ti1 = ti3;
     }
     __syncthreads();
-    double* srow = sigma + ia * p.Nb;
+    TO* srow = sigma + ia * p.Nb;
     if (p.overwrite)
-        for (int64_t i = tid; i < hi - lo; i += nth) srow[lo + i] = (double)sig[i];
+        for (int64_t i = tid; i < hi - lo; i += nth) srow[lo + i] = (TO)sig[i];
     else
-        for (int64_t i = tid; i < hi - lo; i += nth) srow[lo + i] += (double)sig[i];
+        for (int64_t i = tid; i < hi - lo; i += nth) srow[lo + i] = (TO)((double)srow[lo + i] + (double)sig[i]);
 }
 
 int abl_waves(int Mp)
@@ -808,9 +814,9 @@ static int64_t abl_lds_bytes(int kb_count, int ldT, int max_nseg, int64_t chunk)
     return b;
 }
 
-template <typename MF>
+template <typename MF, typename TO>
 static hipError_t abl_launch(const AbParams& p, const AbReduce& r, const void* Vt, const void* Cs, int64_t ldc,
-                             double* sigma, hipStream_t st)
+                             TO* sigma, hipStream_t st)
 {
     if (p.Na <= 0 || p.Nb <= 0 || p.sa <= 0 || p.M <= 0) return hipSuccess;
     if (r.ldT < p.Mp + 4 || (int64_t)AB_TN * r.ldT + 1 > 0x7fff || r.ldT % 4 != 0)
@@ -836,7 +842,7 @@ static hipError_t abl_launch(const AbParams& p, const AbReduce& r, const void* V
     dim3 blk(64 * nwaves);
 #define ABL_GO(KBV, MTV, SPTV)                                                                      \
     {                                                                                               \
-        auto kern = k_ab_lp<MF, KBV, MTV, SPTV>;                                                    \
+        auto kern = k_ab_lp<MF, KBV, MTV, SPTV, TO>;                                                \
         hipError_t e = hipFuncSetAttribute((const void*)kern,                                       \
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);   \
         if (e != hipSuccess) {                                                                      \
@@ -879,8 +885,8 @@ static hipError_t abl_launch(const AbParams& p, const AbReduce& r, const void* V
 }
 
 // C (FP64, rows x cols) -> padded copy in the MFMA input type, row stride ld
-template <typename T>
-__global__ void k_convert_pad(const double* __restrict__ C, T* __restrict__ out, int64_t rows,
+template <typename T, typename TI>
+__global__ void k_convert_pad(const TI* __restrict__ C, T* __restrict__ out, int64_t rows,
                               int64_t cols, int64_t ld)
 {
     const int64_t total = rows * ld;
@@ -990,10 +996,18 @@ hipError_t launch_ab_f64(const AbParams& p, const double* Vt, const double* C, d
 }
 
 hipError_t launch_ab_lowp(const AbParams& p, const AbReduce& r, int prec, const void* Vt, const void* Cs,
+                          int64_t ldc, float* sigma, hipStream_t st)
+{
+    if (prec == 1) return abl_launch<MfmaF32, float>(p, r, Vt, Cs, ldc, sigma, st);
+    if (prec == 2) return abl_launch<MfmaBF16, float>(p, r, Vt, Cs, ldc, sigma, st);
+    return invalid("alpha-beta: unknown precision");
+}
+
+hipError_t launch_ab_lowp(const AbParams& p, const AbReduce& r, int prec, const void* Vt, const void* Cs,
                           int64_t ldc, double* sigma, hipStream_t st)
 {
-    if (prec == 1) return abl_launch<MfmaF32>(p, r, Vt, Cs, ldc, sigma, st);
-    if (prec == 2) return abl_launch<MfmaBF16>(p, r, Vt, Cs, ldc, sigma, st);
+    if (prec == 1) return abl_launch<MfmaF32, double>(p, r, Vt, Cs, ldc, sigma, st);
+    if (prec == 2) return abl_launch<MfmaBF16, double>(p, r, Vt, Cs, ldc, sigma, st);
     return invalid("alpha-beta: unknown precision");
 }
 
@@ -1011,11 +1025,27 @@ hipError_t launch_convert_lowp(int prec, const double* C, void* out, int64_t row
     int64_t g = (total + 255) / 256;
     if (g > 16384) g = 16384;
     if (prec == 1)
-        hipLaunchKernelGGL(k_convert_pad<float>, dim3((unsigned)g), dim3(256), 0, st, C, (float*)out, rows,
-                           cols, ld);
+        hipLaunchKernelGGL((k_convert_pad<float, double>), dim3((unsigned)g), dim3(256), 0, st, C, (float*)out,
+                           rows, cols, ld);
     else
-        hipLaunchKernelGGL(k_convert_pad<__bf16>, dim3((unsigned)g), dim3(256), 0, st, C, (__bf16*)out, rows,
-                           cols, ld);
+        hipLaunchKernelGGL((k_convert_pad<__bf16, double>), dim3((unsigned)g), dim3(256), 0, st, C, (__bf16*)out,
+                           rows, cols, ld);
+    return hipGetLastError();
+}
+
+hipError_t launch_convert_lowp_f32in(int prec, const float* C, void* out, int64_t rows, int64_t cols, int64_t ld,
+                                     hipStream_t st)
+{
+    const int64_t total = rows * ld;
+    if (total <= 0) return hipSuccess;
+    int64_t g = (total + 255) / 256;
+    if (g > 16384) g = 16384;
+    if (prec == 1)
+        hipLaunchKernelGGL((k_convert_pad<float, float>), dim3((unsigned)g), dim3(256), 0, st, C, (float*)out,
+                           rows, cols, ld);
+    else
+        hipLaunchKernelGGL((k_convert_pad<__bf16, float>), dim3((unsigned)g), dim3(256), 0, st, C, (__bf16*)out,
+                           rows, cols, ld);
     return hipGetLastError();
 }
 

@@ -337,3 +337,22 @@ def test_davidson_parity_path_cas10_vs_eigsh(torch):
     pars = [float(np.sum(x * x.T)) for x in X]
     assert all(abs(abs(p) - 1) < 1e-8 for p in pars)
     assert any(p < 0 for p in pars) and any(p > 0 for p in pars)
+
+
+@pytest.mark.parametrize("n,na,nb", [(10, 5, 5), (9, 5, 4), (6, 4, 2), (5, 3, 0)])
+def test_fp32_storage_sigma(torch, n, na, nb):
+    """FP32-stored vectors (device float32 in and out, no FP64 copies): sigma
+    against the oracle's sigma of the same rounded values, with FP32 and BF16
+    alpha-beta arithmetic; ragged row lengths exercise the padded copies."""
+    c, h, eri = make(n, na, nb, 3300 + n)
+    d = c.dims
+    x = synth.ci_vector(d["Na"], d["Nb"], 9)[0].astype(np.float32)
+    ref = oracle.sigma(h, eri, na, nb, x.astype(np.float64))
+    xt = torch.from_numpy(x).cuda()
+    scale = np.abs(ref).max()
+    s32 = c.sigma(xt, ab_prec="f32").cpu().numpy().astype(np.float64)
+    assert np.abs(s32 - ref).max() < 2e-6 * scale
+    s16 = c.sigma(xt, ab_prec="bf16").cpu().numpy().astype(np.float64)
+    assert np.abs(s16 - ref).max() < 2e-2 * scale
+    if na > 0 and nb > 0:
+        assert np.abs(s16 - ref).max() > np.abs(s32 - ref).max()

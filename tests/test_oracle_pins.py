@@ -308,3 +308,23 @@ def test_singlet_selection_and_ground_state_parity():
     np.testing.assert_allclose(X[0], X[0].T, atol=1e-12)
     Ea = np.linalg.eigvalsh(oracle.hamiltonian(h, eri, 3, 3))
     assert E[0] >= Ea[0] - 1e-12
+
+
+def test_oracle_reproduces_stored_fixtures():
+    """The stored oracle fixtures (tests/golden, written by make_fixtures.py from
+    the oracle alone) are reproduced: a later change of the oracle's arithmetic
+    must be deliberate."""
+    import json
+    import os
+    from paper_2405_10197_amd import synth
+    fx = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "oracle_fixtures.json")))
+    h, eri, _ = synth.integrals(6, 1)
+    E, _, s2 = oracle.solve(h, eri, 3, 3, nroots=6)
+    assert np.abs(E - np.array(fx["cas66_seed1"]["energies"])).max() < 1e-11
+    assert np.abs(s2 - np.array(fx["cas66_seed1"]["s2"])).max() < 1e-9
+    Es, _, _ = oracle.solve(h, eri, 3, 3, nroots=1, spin="singlet")
+    assert abs(Es[0] - fx["cas66_seed1"]["singlet_ground"]) < 1e-11
+    h, eri, _ = synth.integrals(5, 7)
+    x = synth.ci_vector(10, 5, 11)[0]
+    s = oracle.sigma(h, eri, 3, 1, x).ravel()
+    assert np.abs(s - np.array(fx["cas5_31_seed7_sigma"]["sigma"])).max() < 1e-12
