@@ -1646,10 +1646,22 @@ static int davidson_impl(casci_ctx* ctx, int nroots, double tol, const casci_dav
             before[j] = std::sqrt(nn[0]);
         }
         if (m > 0) {
+            // classical Gram-Schmidt against the basis; the second pass runs only
+            // when the first removed most of a vector (norm ratio below 1/sqrt2),
+            // which is when one pass can leave a loss of orthogonality
             for (int pass = 0; pass < 2; ++pass) {
                 CHECK_RC(dots_dev(vB(0), m, vB(m), cnt, c));
                 for (double& x : c) x = -x;
                 CHECK_RC(combine(vB(0), m, c, cnt, 1.0, vB(m)));
+                if (pass == 0) {
+                    bool again = false;
+                    for (int j = 0; j < cnt && !again; ++j) {
+                        std::vector<double> nn;
+                        CHECK_RC(dots_dev(vB(m + j), 1, vB(m + j), 1, nn));
+                        again = !(std::sqrt(std::max(nn[0], 0.0)) > 0.7071 * before[j]);
+                    }
+                    if (!again) break;
+                }
             }
         }
         kept = 0;

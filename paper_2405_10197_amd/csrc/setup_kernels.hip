@@ -157,21 +157,22 @@ __global__ void k_diagonal(int n, int64_t Na, int64_t Nb, const uint64_t* __rest
     extern __shared__ double sj[];
     for (int t = threadIdx.x; t < n * n; t += blockDim.x) sj[t] = jpq[t];
     __syncthreads();
-    int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (x >= Na * Nb) return;
-    int64_t ia = x / Nb, ib = x - ia * Nb;
-    uint64_t a = astr[ia], b = bstr[ib];
-    double v = fa[ia * ra] + fb[ib * rb] + shift;
-    for (uint64_t aa = a; aa; aa &= aa - 1) {
-        int p = __builtin_ctzll(aa);
-        for (uint64_t bb = b; bb; bb &= bb - 1) v += sj[p * n + __builtin_ctzll(bb)];
+    for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < Na * Nb;
+         x += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t ia = x / Nb, ib = x - ia * Nb;
+        const uint64_t a = astr[ia], b = bstr[ib];
+        double v = fa[ia * ra] + fb[ib * rb] + shift;
+        for (uint64_t aa = a; aa; aa &= aa - 1) {
+            int p = __builtin_ctzll(aa);
+            for (uint64_t bb = b; bb; bb &= bb - 1) v += sj[p * n + __builtin_ctzll(bb)];
+        }
+        if (lambda_s2 != 0.0) {
+            int na = __popcll(a), nb = __popcll(b);
+            double ms = 0.5 * (na - nb);
+            v += lambda_s2 * (ms * ms + ms + nb - __popcll(a & b));
+        }
+        out[x] = v;
     }
-    if (lambda_s2 != 0.0) {
-        int na = __popcll(a), nb = __popcll(b);
-        double ms = 0.5 * (na - nb);
-        v += lambda_s2 * (ms * ms + ms + nb - __popcll(a & b));
-    }
-    out[x] = v;
 }
 
 static inline unsigned nblk(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
@@ -210,7 +211,9 @@ hipError_t launch_diagonal(int n, int64_t Na, int64_t Nb, const uint64_t* astr,
 {
     int64_t nd = Na * Nb;
     if (nd <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_diagonal, dim3(nblk(nd, 256)), dim3(256), sizeof(double) * n * n, st, n, Na,
+    // capped grid (the launch size in work-items is 32-bit); the kernel strides
+    const unsigned g = (unsigned)std::min<int64_t>((nd + 255) / 256, 1 << 20);
+    hipLaunchKernelGGL(k_diagonal, dim3(g), dim3(256), sizeof(double) * n * n, st, n, Na,
                        Nb, astr, bstr, fa, ra, fb, rb, jpq, shift, lambda_s2, out);
     return hipGetLastError();
 }

@@ -53,57 +53,63 @@ __global__ __launch_bounds__(256) void k_ss_gather(const int32_t* __restrict__ c
                                                    int64_t nrows, int64_t ncols,
                                                    const TX* __restrict__ X, int64_t ldx,
                                                    TY* __restrict__ Y, double shift, int acc,
-                                                   int64_t nrowblk, int64_t nitems)
+                                                   int64_t nrowblk, int64_t nitems, int64_t ipw)
 {
     constexpr int G = 64 / LPE;
     const int64_t per_xcd = gridDim.x / 8;
-    const int64_t t = (int64_t)(blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
-    if (t >= nitems) return;
-    const int64_t strip = t / nrowblk;
-    const int64_t rb = t - strip * nrowblk;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int64_t I = rb * 4 + wave;
-    if (I >= nrows) return;
     const int g = lane / LPE, li = lane % LPE;
-    const int64_t c = strip * LPE + li;
-    const bool cok = c < ncols;
-    const int32_t* colI = col + I * (int64_t)r;
-    const double* valI = val + I * (int64_t)r;
-    double a0 = 0.0, a1 = 0.0;
-    for (int base = 0; base < r; base += 64) {
-        const int e = base + lane;
-        const int cj = e < r ? colI[e] : 0;
-        const double vj = e < r ? valI[e] : 0.0;
+    // The grid is capped (the launch size in work-items is a 32-bit quantity);
+    // workgroup w takes the ipw consecutive items [w*ipw, (w+1)*ipw), w in XCD
+    // order, so the workgroups running on one XCD still cover one stretch of
+    // consecutive row blocks of the same strip.
+    const int64_t w = (int64_t)(blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
+    const int64_t t_end = min(nitems, (w + 1) * ipw);
+    for (int64_t t = w * ipw; t < t_end; ++t) {
+        const int64_t strip = t / nrowblk;
+        const int64_t rb = t - strip * nrowblk;
+        const int64_t I = rb * 4 + wave;
+        if (I >= nrows) continue;
+        const int64_t c = strip * LPE + li;
+        const bool cok = c < ncols;
+        const int32_t* colI = col + I * (int64_t)r;
+        const double* valI = val + I * (int64_t)r;
+        double a0 = 0.0, a1 = 0.0;
+        for (int base = 0; base < r; base += 64) {
+            const int e = base + lane;
+            const int cj = e < r ? colI[e] : 0;
+            const double vj = e < r ? valI[e] : 0.0;
 #pragma unroll
-        for (int j = 0; j < 64; j += 2 * G) {
-            // two independent accumulators for memory-level parallelism; lane
-            // group g takes entries j+g and j+G+g (all readlanes are uniform)
-            int J0 = bcast_i32(cj, j), J1 = bcast_i32(cj, j + G);
-            double v0 = bcast_f64(vj, j), v1 = bcast_f64(vj, j + G);
+            for (int j = 0; j < 64; j += 2 * G) {
+                // two independent accumulators for memory-level parallelism; lane
+                // group g takes entries j+g and j+G+g (all readlanes are uniform)
+                int J0 = bcast_i32(cj, j), J1 = bcast_i32(cj, j + G);
+                double v0 = bcast_f64(vj, j), v1 = bcast_f64(vj, j + G);
 #pragma unroll
-            for (int q = 1; q < G; ++q) {
-                const int Jq0 = bcast_i32(cj, j + q), Jq1 = bcast_i32(cj, j + G + q);
-                const double vq0 = bcast_f64(vj, j + q), vq1 = bcast_f64(vj, j + G + q);
-                J0 = g == q ? Jq0 : J0;
-                J1 = g == q ? Jq1 : J1;
-                v0 = g == q ? vq0 : v0;
-                v1 = g == q ? vq1 : v1;
-            }
-            // entries past r carry v = 0 and J = 0 (a valid row): no branch needed
-            if (cok) {
-                a0 += v0 * (double)X[(int64_t)J0 * ldx + c];
-                a1 += v1 * (double)X[(int64_t)J1 * ldx + c];
+                for (int q = 1; q < G; ++q) {
+                    const int Jq0 = bcast_i32(cj, j + q), Jq1 = bcast_i32(cj, j + G + q);
+                    const double vq0 = bcast_f64(vj, j + q), vq1 = bcast_f64(vj, j + G + q);
+                    J0 = g == q ? Jq0 : J0;
+                    J1 = g == q ? Jq1 : J1;
+                    v0 = g == q ? vq0 : v0;
+                    v1 = g == q ? vq1 : v1;
+                }
+                // entries past r carry v = 0 and J = 0 (a valid row): no branch needed
+                if (cok) {
+                    a0 += v0 * (double)X[(int64_t)J0 * ldx + c];
+                    a1 += v1 * (double)X[(int64_t)J1 * ldx + c];
+                }
             }
         }
-    }
-    double a = a0 + a1;
+        double a = a0 + a1;
 #pragma unroll
-    for (int off = LPE; off < 64; off <<= 1) a += __shfl_xor(a, off);
-    if (g == 0 && cok) {
-        const int64_t o = I * ncols + c;
-        double y = a + shift * (double)X[I * ldx + c];
-        if (acc) y += (double)Y[o];
-        Y[o] = (TY)y;
+        for (int off = LPE; off < 64; off <<= 1) a += __shfl_xor(a, off);
+        if (g == 0 && cok) {
+            const int64_t o = I * ncols + c;
+            double y = a + shift * (double)X[I * ldx + c];
+            if (acc) y += (double)Y[o];
+            Y[o] = (TY)y;
+        }
     }
 }
 
@@ -116,10 +122,13 @@ static hipError_t ss_gather(const int32_t* col, const double* val, int r, int64_
     const int64_t nrowblk = (nrows + 3) / 4;
     const int64_t nstrip = (ncols + LPE - 1) / LPE;
     const int64_t nitems = nrowblk * nstrip;
-    const int64_t grid = (nitems + 7) / 8 * 8;
-    if (grid > 0x7fffffffLL) return invalid("same-spin gather: grid too large");
+    // at most 2^22 workgroups of 256 (each takes ipw consecutive items)
+    const int64_t cap = (int64_t)1 << 22;
+    const int64_t ipw = (nitems + cap - 1) / cap;
+    const int64_t nwg = (nitems + ipw - 1) / ipw;
+    const int64_t grid = (nwg + 7) / 8 * 8;
     hipLaunchKernelGGL((k_ss_gather<TX, TY, LPE>), dim3((unsigned)grid), dim3(256), 0, st, col, val, r,
-                       nrows, ncols, X, ldx, Y, shift, acc, nrowblk, nitems);
+                       nrows, ncols, X, ldx, Y, shift, acc, nrowblk, nitems, ipw);
     return hipGetLastError();
 }
 
@@ -129,8 +138,8 @@ hipError_t launch_ss_gather_f64(const int32_t* col, const double* val, int r, in
 {
     switch (lpe) {
     case 16: return ss_gather<double, double, 16>(col, val, r, nrows, ncols, X, ncols, Y, shift, acc, st);
-    case 0:
     case 32: return ss_gather<double, double, 32>(col, val, r, nrows, ncols, X, ncols, Y, shift, acc, st);
+    case 0:
     case 64: return ss_gather<double, double, 64>(col, val, r, nrows, ncols, X, ncols, Y, shift, acc, st);
     default: return invalid("same-spin gather: lanes per entry must be 16, 32 or 64");
     }

@@ -356,3 +356,39 @@ def test_fp32_storage_sigma(torch, n, na, nb):
     assert np.abs(s16 - ref).max() < 2e-2 * scale
     if na > 0 and nb > 0:
         assert np.abs(s16 - ref).max() > np.abs(s32 - ref).max()
+
+
+def test_cas18_sampled_rows(torch):
+    """CAS(18e,18o), 2,363,904,400 determinants (more than 2^31): FP32-storage
+    sigma (BF16 and FP32 alpha-beta) and the FP64 build, each with a gather
+    strip width that needs more than one pass of the capped grid, against
+    sampled rows (first, last, around 2^31, random) recomputed by the oracle."""
+    n, ne = 18, 9
+    h, eri, _ = synth.integrals(n, 5)
+    c = casci.Context(0)
+    c.set_integrals(h, eri)
+    c.build_strings(ne, ne, n)
+    d = c.dims
+    Nd = d["Ndet"]
+    g = torch.Generator(device="cuda").manual_seed(50)
+    C = torch.randn((d["Na"], d["Nb"]), dtype=torch.float32, device="cuda", generator=g)
+    C /= float(torch.linalg.vector_norm(C.view(-1), dtype=torch.float64))
+    rng = np.random.default_rng(5)
+    pick = np.unique(np.concatenate([[0, 1, Nd - 1, (1 << 31) - 1, 1 << 31, (1 << 31) + 1],
+                                     rng.integers(0, Nd, 40)]))
+    ref = oracle.sigma_rows(h, eri, ne, ne, C.cpu().numpy(), pick)
+    scale = np.abs(ref).max()
+    idx = torch.from_numpy(pick).cuda()
+    for prec, lpe, tol in (("bf16", 16, 2e-2), ("f32", 64, 1e-6)):
+        c.set_tuning(0, lpe)
+        S = c.sigma(C, ab_prec=prec)
+        got = S.view(-1)[idx].double().cpu().numpy()
+        del S
+        assert np.abs(got - ref).max() < tol * scale, prec
+    C64 = C.double()
+    del C
+    torch.cuda.empty_cache()
+    c.set_tuning(16, 0)
+    S64 = c.sigma(C64)
+    got = S64.view(-1)[idx].cpu().numpy()
+    assert np.abs(got - ref).max() < 1e-12 * scale
