@@ -256,12 +256,14 @@ int casci_batch_davidson(casci_ctx* const* ctxs, int count, int nroots, double t
 
 /*
  * Autotuner choice of the same-spin gather for this context's string space:
- * out[0] / out[1] = lanes per gathered entry (16, 32 or 64) of the FP64 and
- * of the FP32-input gather; 0 until the first sigma build in that precision.
+ * out[0] / out[1] = strip width code of the FP64 and of the FP32-input
+ * gather: 16, 32 or 64 lanes per gathered entry with one column each, or 128
+ * (64 lanes with two adjacent columns each); 0 until the first sigma build
+ * in that precision.
  */
 int casci_get_tuning(casci_ctx* ctx, int* out);
 
-/* Override the autotuner: lanes per gathered entry (16, 32 or 64; 0 = autotune)
+/* Override the autotuner: strip width code (16, 32, 64 or 128; 0 = autotune)
  * of the FP64 and of the FP32-input gather for this context. */
 int casci_set_tuning(casci_ctx* ctx, int f64_lpe, int f32in_lpe);
 

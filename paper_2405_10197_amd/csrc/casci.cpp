@@ -816,7 +816,7 @@ static int autotune_gather(casci_ctx* ctx, bool lowp, const double* C, int64_t l
     int best = 0;
     float best_ms = 0.f;
     hipError_t err = hipSuccess;
-    for (int lpe : {16, 32, 64}) {
+    for (int lpe : {16, 32, 64, 128}) {
         auto run = [&]() {
             if (lowp)
                 return launch_ss_gather_f32in(ctx->d_fa_col.as<int32_t>(), ctx->d_fa_val.as<double>(), ctx->ra,
@@ -1099,8 +1099,8 @@ extern "C" int casci_set_tuning(casci_ctx* ctx, int f64_lpe, int f32in_lpe)
 {
     if (!ctx) return CASCI_E_ARG;
     for (int v : {f64_lpe, f32in_lpe})
-        if (v != 0 && v != 16 && v != 32 && v != 64)
-            return ctx->fail(CASCI_E_ARG, "lanes per entry must be 0, 16, 32 or 64");
+        if (v != 0 && v != 16 && v != 32 && v != 64 && v != 128)
+            return ctx->fail(CASCI_E_ARG, "strip width code must be 0, 16, 32, 64 or 128");
     ctx->tune_lpe[0] = f64_lpe;
     ctx->tune_lpe[1] = f32in_lpe;
     ++ctx->gen;  // captured graphs hold the old choice

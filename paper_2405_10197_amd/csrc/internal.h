@@ -56,7 +56,7 @@ hipError_t launch_scatter_values(const int64_t* idx, const double* v, int P, dou
 
 // sigma_kernels.hip
 // Y(I,:) = [acc ? Y(I,:) : 0] + sum_e val[I*r+e] X(col[I*r+e], :) + shift * X(I,:)
-// (lpe: lanes per gathered entry, 16/32/64; 0 = default 64)
+// (lpe: strip width code 16/32/64 lanes per entry, 128 = 64 lanes x 2 columns; 0 = 64)
 hipError_t launch_ss_gather_f64(const int32_t* col, const double* val, int r, int64_t nrows,
                                 int64_t ncols, const double* X, double* Y, double shift, int acc,
                                 hipStream_t st, int lpe = 0);

@@ -31,7 +31,8 @@ static hipError_t invalid(const char* why)
 // ---------------------------------------------------------------------------
 // same-spin gather: Y(I,:) = [acc ? Y : 0] + sum_e val(I,e) X(col(I,e),:) + shift X(I,:)
 // ---------------------------------------------------------------------------
-// One wave computes one row I over a strip of LPE columns. The row's list
+// One wave computes one row I over a strip of LPE x VW columns (VW adjacent
+// columns per lane, loaded as one vector). The row's list
 // (col, val) is read 64 entries at a time, one per lane (coalesced), and
 // broadcast with readlane; G = 64/LPE entries are gathered per wave-wide
 // load, one per lane group, and the group partials are combined with xor
@@ -47,7 +48,22 @@ __device__ inline double bcast_f64(double v, int lane)
     return *reinterpret_cast<double*>(&u);
 }
 
-template <typename TX, typename TY, int LPE>
+template <typename T, int VW>
+struct Vec;
+template <typename T>
+struct Vec<T, 1> {
+    using type = T;
+};
+template <>
+struct Vec<float, 2> {
+    using type = float2;
+};
+template <>
+struct Vec<double, 2> {
+    using type = double2;
+};
+
+template <typename TX, typename TY, int LPE, int VW>
 __global__ __launch_bounds__(256) void k_ss_gather(const int32_t* __restrict__ col,
                                                    const double* __restrict__ val, int r,
                                                    int64_t nrows, int64_t ncols,
@@ -56,6 +72,7 @@ __global__ __launch_bounds__(256) void k_ss_gather(const int32_t* __restrict__ c
                                                    int64_t nrowblk, int64_t nitems, int64_t ipw)
 {
     constexpr int G = 64 / LPE;
+    using VX = typename Vec<TX, VW>::type;
     const int64_t per_xcd = gridDim.x / 8;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int g = lane / LPE, li = lane % LPE;
@@ -70,105 +87,135 @@ __global__ __launch_bounds__(256) void k_ss_gather(const int32_t* __restrict__ c
         const int64_t rb = t - strip * nrowblk;
         const int64_t I = rb * 4 + wave;
         if (I >= nrows) continue;
-        const int64_t c = strip * LPE + li;
+        // this lane's VW consecutive columns (VW = 2 needs an even ldx: aligned pairs)
+        const int64_t c = (strip * LPE + li) * VW;
+        const bool full = c + VW <= ncols;
         const bool cok = c < ncols;
         const int32_t* colI = col + I * (int64_t)r;
         const double* valI = val + I * (int64_t)r;
-        double a0 = 0.0, a1 = 0.0;
+        auto load = [&](int J, double* out) {
+            const TX* src = X + (int64_t)J * ldx + c;
+            if constexpr (VW == 1) {
+                out[0] = (double)*src;
+            } else {
+                if (full) {
+                    const VX v = *reinterpret_cast<const VX*>(src);
+                    out[0] = (double)v.x;
+                    out[1] = (double)v.y;
+                } else {
+                    out[0] = (double)src[0];
+                    out[1] = 0.0;
+                }
+            }
+        };
+        constexpr int NACC = 4;  // independent accumulators: loads in flight per wave
+        double acc_[NACC][VW] = {};
         for (int base = 0; base < r; base += 64) {
             const int e = base + lane;
             const int cj = e < r ? colI[e] : 0;
             const double vj = e < r ? valI[e] : 0.0;
 #pragma unroll
-            for (int j = 0; j < 64; j += 2 * G) {
-                // two independent accumulators for memory-level parallelism; lane
-                // group g takes entries j+g and j+G+g (all readlanes are uniform)
-                int J0 = bcast_i32(cj, j), J1 = bcast_i32(cj, j + G);
-                double v0 = bcast_f64(vj, j), v1 = bcast_f64(vj, j + G);
+            for (int j = 0; j < 64; j += NACC * G) {
+                // lane group g takes entries j + h*G + g, h < NACC (readlanes are uniform)
+                int J[NACC];
+                double v[NACC];
 #pragma unroll
-                for (int q = 1; q < G; ++q) {
-                    const int Jq0 = bcast_i32(cj, j + q), Jq1 = bcast_i32(cj, j + G + q);
-                    const double vq0 = bcast_f64(vj, j + q), vq1 = bcast_f64(vj, j + G + q);
-                    J0 = g == q ? Jq0 : J0;
-                    J1 = g == q ? Jq1 : J1;
-                    v0 = g == q ? vq0 : v0;
-                    v1 = g == q ? vq1 : v1;
+                for (int h = 0; h < NACC; ++h) {
+                    J[h] = bcast_i32(cj, j + h * G);
+                    v[h] = bcast_f64(vj, j + h * G);
+#pragma unroll
+                    for (int q = 1; q < G; ++q) {
+                        const int Jq = bcast_i32(cj, j + h * G + q);
+                        const double vq = bcast_f64(vj, j + h * G + q);
+                        J[h] = g == q ? Jq : J[h];
+                        v[h] = g == q ? vq : v[h];
+                    }
                 }
                 // entries past r carry v = 0 and J = 0 (a valid row): no branch needed
                 if (cok) {
-                    a0 += v0 * (double)X[(int64_t)J0 * ldx + c];
-                    a1 += v1 * (double)X[(int64_t)J1 * ldx + c];
+                    double x[NACC][VW];
+#pragma unroll
+                    for (int h = 0; h < NACC; ++h) load(J[h], x[h]);
+#pragma unroll
+                    for (int h = 0; h < NACC; ++h)
+#pragma unroll
+                        for (int u = 0; u < VW; ++u) acc_[h][u] += v[h] * x[h][u];
                 }
             }
         }
-        double a = a0 + a1;
 #pragma unroll
-        for (int off = LPE; off < 64; off <<= 1) a += __shfl_xor(a, off);
-        if (g == 0 && cok) {
-            const int64_t o = I * ncols + c;
-            double y = a + shift * (double)X[I * ldx + c];
-            if (acc) y += (double)Y[o];
-            Y[o] = (TY)y;
+        for (int u = 0; u < VW; ++u) {
+            double a = (acc_[0][u] + acc_[1][u]) + (acc_[2][u] + acc_[3][u]);
+#pragma unroll
+            for (int off = LPE; off < 64; off <<= 1) a += __shfl_xor(a, off);
+            if (g == 0 && c + u < ncols) {
+                const int64_t o = I * ncols + c + u;
+                double y = a + shift * (double)X[I * ldx + c + u];
+                if (acc) y += (double)Y[o];
+                Y[o] = (TY)y;
+            }
         }
     }
 }
 
-template <typename TX, typename TY, int LPE>
+template <typename TX, typename TY, int LPE, int VW>
 static hipError_t ss_gather(const int32_t* col, const double* val, int r, int64_t nrows,
                             int64_t ncols, const TX* X, int64_t ldx, TY* Y, double shift, int acc,
                             hipStream_t st)
 {
     if (nrows <= 0 || ncols <= 0) return hipSuccess;
+    if (VW > 1 && ldx % VW != 0) return invalid("same-spin gather: paired columns need an even row stride");
     const int64_t nrowblk = (nrows + 3) / 4;
-    const int64_t nstrip = (ncols + LPE - 1) / LPE;
+    const int64_t nstrip = (ncols + LPE * VW - 1) / (LPE * VW);
     const int64_t nitems = nrowblk * nstrip;
     // at most 2^22 workgroups of 256 (each takes ipw consecutive items)
     const int64_t cap = (int64_t)1 << 22;
     const int64_t ipw = (nitems + cap - 1) / cap;
     const int64_t nwg = (nitems + ipw - 1) / ipw;
     const int64_t grid = (nwg + 7) / 8 * 8;
-    hipLaunchKernelGGL((k_ss_gather<TX, TY, LPE>), dim3((unsigned)grid), dim3(256), 0, st, col, val, r,
+    hipLaunchKernelGGL((k_ss_gather<TX, TY, LPE, VW>), dim3((unsigned)grid), dim3(256), 0, st, col, val, r,
                        nrows, ncols, X, ldx, Y, shift, acc, nrowblk, nitems, ipw);
     return hipGetLastError();
+}
+
+// strip width code: 16 / 32 / 64 lanes per entry with one column each, or 128
+// = 64 lanes with two adjacent columns each (needs an even row stride; an odd
+// one falls back to 64)
+template <typename TX, typename TY>
+static hipError_t ss_gather_w(const int32_t* col, const double* val, int r, int64_t nrows, int64_t ncols,
+                              const TX* X, int64_t ldx, TY* Y, double shift, int acc, hipStream_t st, int lpe)
+{
+    switch (lpe) {
+    case 16: return ss_gather<TX, TY, 16, 1>(col, val, r, nrows, ncols, X, ldx, Y, shift, acc, st);
+    case 32: return ss_gather<TX, TY, 32, 1>(col, val, r, nrows, ncols, X, ldx, Y, shift, acc, st);
+    case 0:
+    case 64: return ss_gather<TX, TY, 64, 1>(col, val, r, nrows, ncols, X, ldx, Y, shift, acc, st);
+    case 128:
+        if (ldx % 2 != 0) return ss_gather<TX, TY, 64, 1>(col, val, r, nrows, ncols, X, ldx, Y, shift, acc, st);
+        return ss_gather<TX, TY, 64, 2>(col, val, r, nrows, ncols, X, ldx, Y, shift, acc, st);
+    default: return invalid("same-spin gather: strip width code must be 16, 32, 64 or 128");
+    }
 }
 
 hipError_t launch_ss_gather_f64(const int32_t* col, const double* val, int r, int64_t nrows,
                                 int64_t ncols, const double* X, double* Y, double shift, int acc,
                                 hipStream_t st, int lpe)
 {
-    switch (lpe) {
-    case 16: return ss_gather<double, double, 16>(col, val, r, nrows, ncols, X, ncols, Y, shift, acc, st);
-    case 32: return ss_gather<double, double, 32>(col, val, r, nrows, ncols, X, ncols, Y, shift, acc, st);
-    case 0:
-    case 64: return ss_gather<double, double, 64>(col, val, r, nrows, ncols, X, ncols, Y, shift, acc, st);
-    default: return invalid("same-spin gather: lanes per entry must be 16, 32 or 64");
-    }
+    return ss_gather_w<double, double>(col, val, r, nrows, ncols, X, ncols, Y, shift, acc, st, lpe);
 }
 
 hipError_t launch_ss_gather_f32in(const int32_t* col, const double* val, int r, int64_t nrows,
                                   int64_t ncols, const float* X, int64_t ldx, double* Y, double shift,
                                   int acc, hipStream_t st, int lpe)
 {
-    switch (lpe) {
-    case 16: return ss_gather<float, double, 16>(col, val, r, nrows, ncols, X, ldx, Y, shift, acc, st);
-    case 32: return ss_gather<float, double, 32>(col, val, r, nrows, ncols, X, ldx, Y, shift, acc, st);
-    case 0:
-    case 64: return ss_gather<float, double, 64>(col, val, r, nrows, ncols, X, ldx, Y, shift, acc, st);
-    default: return invalid("same-spin gather: lanes per entry must be 16, 32 or 64");
-    }
+    return ss_gather_w<float, double>(col, val, r, nrows, ncols, X, ldx, Y, shift, acc, st, lpe);
 }
 
 hipError_t launch_ss_gather_f32(const int32_t* col, const double* val, int r, int64_t nrows,
                                 int64_t ncols, const float* X, float* Y, double shift, int acc,
                                 hipStream_t st, int lpe)
 {
-    switch (lpe) {
-    case 16: return ss_gather<float, float, 16>(col, val, r, nrows, ncols, X, ncols, Y, shift, acc, st);
-    case 32: return ss_gather<float, float, 32>(col, val, r, nrows, ncols, X, ncols, Y, shift, acc, st);
-    case 0:
-    case 64: return ss_gather<float, float, 64>(col, val, r, nrows, ncols, X, ncols, Y, shift, acc, st);
-    default: return invalid("same-spin gather: lanes per entry must be 16, 32 or 64");
-    }
+    return ss_gather_w<float, float>(col, val, r, nrows, ncols, X, ncols, Y, shift, acc, st, lpe);
 }
 
 // ---------------------------------------------------------------------------
