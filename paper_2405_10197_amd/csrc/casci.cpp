@@ -816,13 +816,16 @@ static int autotune_gather(casci_ctx* ctx, bool lowp, const double* C, int64_t l
     int best = 0;
     float best_ms = 0.f;
     hipError_t err = hipSuccess;
+    // timed on the first eighth of the rows (at least 2048): the same strips and
+    // operator rows, a fraction of the cost on large spaces
+    const int64_t nt = std::min<int64_t>(ctx->Na, std::max<int64_t>(2048, ctx->Na / 8));
     for (int lpe : {16, 32, 64, 128}) {
         auto run = [&]() {
             if (lowp)
                 return launch_ss_gather_f32in(ctx->d_fa_col.as<int32_t>(), ctx->d_fa_val.as<double>(), ctx->ra,
-                                              ctx->Na, ctx->Nb, ctx->d_c32.as<float>(), ld32, ctx->d_t1.as<double>(),
+                                              nt, ctx->Nb, ctx->d_c32.as<float>(), ld32, ctx->d_t1.as<double>(),
                                               0.0, 0, st, lpe);
-            return launch_ss_gather_f64(ctx->d_fa_col.as<int32_t>(), ctx->d_fa_val.as<double>(), ctx->ra, ctx->Na,
+            return launch_ss_gather_f64(ctx->d_fa_col.as<int32_t>(), ctx->d_fa_val.as<double>(), ctx->ra, nt,
                                         ctx->Nb, C, ctx->d_t1.as<double>(), 0.0, 0, st, lpe);
         };
         if ((err = run()) != hipSuccess) break;  // warm-up
