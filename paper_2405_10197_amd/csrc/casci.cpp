@@ -108,6 +108,7 @@ struct casci_ctx {
     bool prepared = false;
     double prepared_lambda = 0.0;
     DBuf d_h, d_eri, d_fa_col, d_fa_val, d_fb_col, d_fb_val, d_jpq, d_diag;
+    DBuf d_fa_c16, d_fa_v32, d_fb_c16, d_fb_v32;  // compact operator copies (< 65536 strings)
     DBuf d_vt_sym, d_pairs_sym, d_vt_full, d_pairs_full, d_vt_s2;
     DBuf d_tg_sym, d_tg_full;  // alpha-beta scatter targets per (beta string, pair row)
     struct Reduce {            // target-grouped scatter table (AbReduce) of one pair set
@@ -223,7 +224,7 @@ extern "C" void casci_destroy(casci_ctx* ctx)
         DBuf* bufs[] = {&ctx->d_binom, &ctx->d_astr, &ctx->d_bstr, &ctx->d_la_j, &ctx->d_la_pq,
                         &ctx->d_lb_j, &ctx->d_lb_pq, &ctx->d_h, &ctx->d_eri, &ctx->d_fa_col,
                         &ctx->d_fa_val, &ctx->d_fb_col, &ctx->d_fb_val, &ctx->d_jpq, &ctx->d_diag,
-                        &ctx->d_vt_sym, &ctx->d_pairs_sym, &ctx->d_vt_full, &ctx->d_pairs_full, &ctx->d_tg_sym, &ctx->d_tg_full,
+                        &ctx->d_vt_sym, &ctx->d_pairs_sym, &ctx->d_vt_full, &ctx->d_pairs_full, &ctx->d_tg_sym, &ctx->d_tg_full, &ctx->d_fa_c16, &ctx->d_fa_v32, &ctx->d_fb_c16, &ctx->d_fb_v32,
                         &ctx->red_sym.tab, &ctx->red_sym.tinfo, &ctx->red_full.tab, &ctx->red_full.tinfo,
                         &ctx->d_vt_s2, &ctx->d_t1, &ctx->d_t2, &ctx->d_vin, &ctx->d_vout,
                         &ctx->d_work, &ctx->d_small, &ctx->d_vt_sym_lp[0], &ctx->d_vt_sym_lp[1],
@@ -562,6 +563,25 @@ static int ensure_prepared(casci_ctx* ctx, double lambda)
             ctx->d_fb_col.release();
             ctx->d_fb_val.release();
         }
+        // compact copies for the gathers: 16-bit columns, FP32 values
+        if (ctx->Na < 65536) {
+            HIPC(ctx->d_fa_c16.ensure((size_t)ctx->Na * ctx->ra * 2));
+            HIPC(ctx->d_fa_v32.ensure((size_t)ctx->Na * ctx->ra * 4));
+            HIPC(launch_compact_op(ctx->d_fa_col.as<int32_t>(), ctx->d_fa_val.as<double>(), ctx->Na * ctx->ra,
+                                   ctx->d_fa_c16.as<uint16_t>(), ctx->d_fa_v32.as<float>(), st));
+        } else {
+            ctx->d_fa_c16.release();
+            ctx->d_fa_v32.release();
+        }
+        if (ctx->nb != ctx->na && ctx->Nb < 65536) {
+            HIPC(ctx->d_fb_c16.ensure((size_t)ctx->Nb * ctx->rb * 2));
+            HIPC(ctx->d_fb_v32.ensure((size_t)ctx->Nb * ctx->rb * 4));
+            HIPC(launch_compact_op(ctx->d_fb_col.as<int32_t>(), ctx->d_fb_val.as<double>(), ctx->Nb * ctx->rb,
+                                   ctx->d_fb_c16.as<uint16_t>(), ctx->d_fb_v32.as<float>(), st));
+        } else {
+            ctx->d_fb_c16.release();
+            ctx->d_fb_v32.release();
+        }
         std::vector<double> jpq((size_t)n * n);
         for (int p = 0; p < n; ++p)
             for (int q = 0; q < n; ++q) jpq[p * n + q] = ctx->eri[(((size_t)p * n + p) * n + q) * n + q];
@@ -787,6 +807,20 @@ static int ensure_reduce(casci_ctx* ctx, bool full, AbReduce* out)
 // (with parity fused into the S + p S^T symmetrisation). Running it on a
 // second stream beside the gathers was measured not to help: each slows the
 // other by as much as the overlap gains.
+// The same-spin operator of one spin (1: beta; the alpha one when nalpha = nbeta)
+// with its compact copies when they exist.
+static SsOp ss_op(const casci_ctx* ctx, int spin)
+{
+    const bool b = spin == 1 && ctx->nb != ctx->na;
+    SsOp op;
+    op.col = (b ? ctx->d_fb_col : ctx->d_fa_col).as<int32_t>();
+    op.val = (b ? ctx->d_fb_val : ctx->d_fa_val).as<double>();
+    op.col16 = (b ? ctx->d_fb_c16 : ctx->d_fa_c16).as<uint16_t>();
+    op.val32 = (b ? ctx->d_fb_v32 : ctx->d_fa_v32).as<float>();
+    op.r = spin == 1 ? ctx->rb : ctx->ra;
+    return op;
+}
+
 // Autotuner of the same-spin gather: the strip width (lanes per gathered
 // entry, 16/32/64) that is fastest for this string space, timed once per
 // (device, norb, nalpha, nbeta, input precision) on the context's stream and
@@ -822,11 +856,9 @@ static int autotune_gather(casci_ctx* ctx, bool lowp, const double* C, int64_t l
     for (int lpe : {16, 32, 64, 128}) {
         auto run = [&]() {
             if (lowp)
-                return launch_ss_gather_f32in(ctx->d_fa_col.as<int32_t>(), ctx->d_fa_val.as<double>(), ctx->ra,
-                                              nt, ctx->Nb, ctx->d_c32.as<float>(), ld32, ctx->d_t1.as<double>(),
-                                              0.0, 0, st, lpe);
-            return launch_ss_gather_f64(ctx->d_fa_col.as<int32_t>(), ctx->d_fa_val.as<double>(), ctx->ra, nt,
-                                        ctx->Nb, C, ctx->d_t1.as<double>(), 0.0, 0, st, lpe);
+                return launch_ss_gather_f32in(ss_op(ctx, 0), nt, ctx->Nb, ctx->d_c32.as<float>(), ld32,
+                                              ctx->d_t1.as<double>(), 0.0, 0, st, lpe);
+            return launch_ss_gather_f64(ss_op(ctx, 0), nt, ctx->Nb, C, ctx->d_t1.as<double>(), 0.0, 0, st, lpe);
         };
         if ((err = run()) != hipSuccess) break;  // warm-up
         if ((err = hipEventRecord(e0, st)) != hipSuccess) break;
@@ -903,22 +935,17 @@ static int sigma_dev(casci_ctx* ctx, const double* C, double* S, int ab_prec, do
     if (ctx->tune_lpe[lowp ? 1 : 0] == 0) CHECK_RC(autotune_gather(ctx, lowp, C, ld32));
     const int lpe = ctx->tune_lpe[lowp ? 1 : 0];
     if (lowp)
-        HIPC(launch_ss_gather_f32in(ctx->d_fa_col.as<int32_t>(), ctx->d_fa_val.as<double>(), ctx->ra, Na, Nb,
-                                    ctx->d_c32.as<float>(), ld32, S, s_aa, 0, st, lpe));
+        HIPC(launch_ss_gather_f32in(ss_op(ctx, 0), Na, Nb, ctx->d_c32.as<float>(), ld32, S, s_aa, 0, st, lpe));
     else
-        HIPC(launch_ss_gather_f64(ctx->d_fa_col.as<int32_t>(), ctx->d_fa_val.as<double>(), ctx->ra, Na, Nb,
-                                  C, S, s_aa, 0, st, lpe));
+        HIPC(launch_ss_gather_f64(ss_op(ctx, 0), Na, Nb, C, S, s_aa, 0, st, lpe));
     CHECK_RC(mark(1, st));
     if (parity == 0 && ctx->nb > 0) {
         HIPC(ctx->d_t1.ensure((size_t)Nd * 8));
         HIPC(ctx->d_t2.ensure((size_t)Nd * 8));
         const bool same = ctx->nb == ctx->na;
-        const DBuf& fcol = same ? ctx->d_fa_col : ctx->d_fb_col;
-        const DBuf& fval = same ? ctx->d_fa_val : ctx->d_fb_val;
         HIPC(launch_transpose_f64(C, ctx->d_t1.as<double>(), Na, Nb, 0, 1.0, st));
-        HIPC(launch_ss_gather_f64(fcol.as<int32_t>(), fval.as<double>(), ctx->rb, Nb, Na,
-                                  ctx->d_t1.as<double>(), ctx->d_t2.as<double>(), 0.0, 0, st,
-                                  same && !lowp ? lpe : 0));
+        HIPC(launch_ss_gather_f64(ss_op(ctx, 1), Nb, Na, ctx->d_t1.as<double>(), ctx->d_t2.as<double>(), 0.0, 0,
+                                  st, same && !lowp ? lpe : 0));
         HIPC(launch_transpose_f64(ctx->d_t2.as<double>(), S, Nb, Na, 1, 1.0, st));
     }
     CHECK_RC(mark(2, st));
@@ -975,8 +1002,7 @@ static int sigma_dev_f32(casci_ctx* ctx, const float* C32, float* S32, int ab_pr
     CHECK_RC(mark(3));
     const int lpe = ctx->tune_lpe[1];
     // alpha-alpha: S32 = F_a C + shift C
-    HIPC(launch_ss_gather_f32(ctx->d_fa_col.as<int32_t>(), ctx->d_fa_val.as<double>(), ctx->ra, Na, Nb, C32, S32,
-                              shift, 0, st, lpe));
+    HIPC(launch_ss_gather_f32(ss_op(ctx, 0), Na, Nb, C32, S32, shift, 0, st, lpe));
     CHECK_RC(mark(4));
     CHECK_RC(mark(1));
     // beta-beta: S32 += (F_b C^T)^T through two FP32 transposes
@@ -984,11 +1010,9 @@ static int sigma_dev_f32(casci_ctx* ctx, const float* C32, float* S32, int ab_pr
         HIPC(ctx->d_t1.ensure((size_t)Nd * 4));
         HIPC(ctx->d_t2.ensure((size_t)Nd * 4));
         const bool same = ctx->nb == ctx->na;
-        const DBuf& fcol = same ? ctx->d_fa_col : ctx->d_fb_col;
-        const DBuf& fval = same ? ctx->d_fa_val : ctx->d_fb_val;
         HIPC(launch_transpose_f32(C32, ctx->d_t1.as<float>(), Na, Nb, 0, st));
-        HIPC(launch_ss_gather_f32(fcol.as<int32_t>(), fval.as<double>(), ctx->rb, Nb, Na, ctx->d_t1.as<float>(),
-                                  ctx->d_t2.as<float>(), 0.0, 0, st, same ? lpe : 0));
+        HIPC(launch_ss_gather_f32(ss_op(ctx, 1), Nb, Na, ctx->d_t1.as<float>(), ctx->d_t2.as<float>(), 0.0, 0, st,
+                                  same ? lpe : 0));
         HIPC(launch_transpose_f32(ctx->d_t2.as<float>(), S32, Nb, Na, 1, st));
     }
     CHECK_RC(mark(2));
@@ -1036,7 +1060,8 @@ static std::vector<void*> sigma_buffers(const casci_ctx* ctx)
             ctx->d_vt_sym_lp[0].p, ctx->d_vt_sym_lp[1].p, ctx->d_vt_full_lp[0].p, ctx->d_vt_full_lp[1].p,
             ctx->d_tg_sym.p, ctx->d_tg_full.p, ctx->red_sym.tab.p, ctx->red_sym.tinfo.p, ctx->red_full.tab.p,
             ctx->red_full.tinfo.p, ctx->d_la_j.p, ctx->d_la_pq.p, ctx->d_lb_j.p, ctx->d_bstr.p,
-            ctx->d_pairs_sym.p, ctx->d_pairs_full.p, ctx->d_gin.p, ctx->d_gout.p};
+            ctx->d_pairs_sym.p, ctx->d_pairs_full.p, ctx->d_gin.p, ctx->d_gout.p, ctx->d_fa_c16.p,
+            ctx->d_fa_v32.p, ctx->d_fb_c16.p, ctx->d_fb_v32.p};
 }
 
 // sigma_dev replayed from a captured HIP graph: one launch per build instead

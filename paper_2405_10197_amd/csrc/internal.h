@@ -55,22 +55,32 @@ hipError_t launch_pspace_h(int n, int P, const int64_t* dets, int64_t Nb, const 
 hipError_t launch_scatter_values(const int64_t* idx, const double* v, int P, double* out, hipStream_t st);
 
 // sigma_kernels.hip
+// A same-spin operator in row form: r entries per row, int32 columns and
+// FP64 values; optional compact copies (16-bit columns when there are fewer
+// than 65536 strings, FP32 values) that the gathers use when present.
+struct SsOp {
+    const int32_t* col;
+    const double* val;
+    const uint16_t* col16;  // may be null
+    const float* val32;     // may be null
+    int r;
+};
 // Y(I,:) = [acc ? Y(I,:) : 0] + sum_e val[I*r+e] X(col[I*r+e], :) + shift * X(I,:)
-// (lpe: strip width code 16/32/64 lanes per entry, 128 = 64 lanes x 2 columns; 0 = 64)
-hipError_t launch_ss_gather_f64(const int32_t* col, const double* val, int r, int64_t nrows,
-                                int64_t ncols, const double* X, double* Y, double shift, int acc,
-                                hipStream_t st, int lpe = 0);
-// same gather reading an FP32 copy of X with row stride ldx, FP64 output
-// (lpe as above; 0 = default 64)
-hipError_t launch_ss_gather_f32in(const int32_t* col, const double* val, int r, int64_t nrows,
-                                  int64_t ncols, const float* X, int64_t ldx, double* Y, double shift,
-                                  int acc, hipStream_t st, int lpe = 0);
+// (lpe: strip width code 16/32/64 lanes per entry, 128 = 64 lanes x 2 columns; 0 = 64).
+// FP64 X and Y: FP64 values (16-bit columns when present).
+hipError_t launch_ss_gather_f64(const SsOp& op, int64_t nrows, int64_t ncols, const double* X, double* Y,
+                                double shift, int acc, hipStream_t st, int lpe = 0);
+// FP32 copy of X with row stride ldx, FP64 Y (compact operator when present)
+hipError_t launch_ss_gather_f32in(const SsOp& op, int64_t nrows, int64_t ncols, const float* X, int64_t ldx,
+                                  double* Y, double shift, int acc, hipStream_t st, int lpe = 0);
+// FP32 X and Y (FP64 accumulation; compact operator when present)
+hipError_t launch_ss_gather_f32(const SsOp& op, int64_t nrows, int64_t ncols, const float* X, float* Y,
+                                double shift, int acc, hipStream_t st, int lpe = 0);
+hipError_t launch_compact_op(const int32_t* col, const double* val, int64_t n, uint16_t* col16, float* val32,
+                             hipStream_t st);
 // S <- scale (S + p S^T) [+ T], S square n x n, in place (T may be null)
 hipError_t launch_sym_add(double* S, int64_t n, int p, double scale, hipStream_t st,
                           const double* T = nullptr);
-hipError_t launch_ss_gather_f32(const int32_t* col, const double* val, int r, int64_t nrows,
-                                int64_t ncols, const float* X, float* Y, double shift, int acc,
-                                hipStream_t st, int lpe = 0);
 // out[j][i] (+)= in[i][j], in: rows x cols
 hipError_t launch_transpose_f64(const double* in, double* out, int64_t rows, int64_t cols, int acc,
                                 double scale, hipStream_t st);

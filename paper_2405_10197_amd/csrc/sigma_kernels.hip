@@ -63,9 +63,15 @@ struct Vec<double, 2> {
     using type = double2;
 };
 
-template <typename TX, typename TY, int LPE, int VW>
-__global__ __launch_bounds__(256) void k_ss_gather(const int32_t* __restrict__ col,
-                                                   const double* __restrict__ val, int r,
+__device__ inline float bcast_val(float v, int lane)
+{
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
+}
+__device__ inline double bcast_val(double v, int lane) { return bcast_f64(v, lane); }
+
+template <typename TX, typename TY, int LPE, int VW, typename TC, typename TV>
+__global__ __launch_bounds__(256) void k_ss_gather(const TC* __restrict__ col,
+                                                   const TV* __restrict__ val, int r,
                                                    int64_t nrows, int64_t ncols,
                                                    const TX* __restrict__ X, int64_t ldx,
                                                    TY* __restrict__ Y, double shift, int acc,
@@ -91,8 +97,8 @@ __global__ __launch_bounds__(256) void k_ss_gather(const int32_t* __restrict__ c
         const int64_t c = (strip * LPE + li) * VW;
         const bool full = c + VW <= ncols;
         const bool cok = c < ncols;
-        const int32_t* colI = col + I * (int64_t)r;
-        const double* valI = val + I * (int64_t)r;
+        const TC* colI = col + I * (int64_t)r;
+        const TV* valI = val + I * (int64_t)r;
         auto load = [&](int J, double* out) {
             const TX* src = X + (int64_t)J * ldx + c;
             if constexpr (VW == 1) {
@@ -112,8 +118,8 @@ __global__ __launch_bounds__(256) void k_ss_gather(const int32_t* __restrict__ c
         double acc_[NACC][VW] = {};
         for (int base = 0; base < r; base += 64) {
             const int e = base + lane;
-            const int cj = e < r ? colI[e] : 0;
-            const double vj = e < r ? valI[e] : 0.0;
+            const int cj = e < r ? (int)colI[e] : 0;
+            const TV vj = e < r ? valI[e] : (TV)0;
 #pragma unroll
             for (int j = 0; j < 64; j += NACC * G) {
                 // lane group g takes entries j + h*G + g, h < NACC (readlanes are uniform)
@@ -122,11 +128,11 @@ __global__ __launch_bounds__(256) void k_ss_gather(const int32_t* __restrict__ c
 #pragma unroll
                 for (int h = 0; h < NACC; ++h) {
                     J[h] = bcast_i32(cj, j + h * G);
-                    v[h] = bcast_f64(vj, j + h * G);
+                    v[h] = (double)bcast_val(vj, j + h * G);
 #pragma unroll
                     for (int q = 1; q < G; ++q) {
                         const int Jq = bcast_i32(cj, j + h * G + q);
-                        const double vq = bcast_f64(vj, j + h * G + q);
+                        const double vq = (double)bcast_val(vj, j + h * G + q);
                         J[h] = g == q ? Jq : J[h];
                         v[h] = g == q ? vq : v[h];
                     }
@@ -158,8 +164,8 @@ __global__ __launch_bounds__(256) void k_ss_gather(const int32_t* __restrict__ c
     }
 }
 
-template <typename TX, typename TY, int LPE, int VW>
-static hipError_t ss_gather(const int32_t* col, const double* val, int r, int64_t nrows,
+template <typename TX, typename TY, int LPE, int VW, typename TC, typename TV>
+static hipError_t ss_gather(const TC* col, const TV* val, int r, int64_t nrows,
                             int64_t ncols, const TX* X, int64_t ldx, TY* Y, double shift, int acc,
                             hipStream_t st)
 {
@@ -173,7 +179,7 @@ static hipError_t ss_gather(const int32_t* col, const double* val, int r, int64_
     const int64_t ipw = (nitems + cap - 1) / cap;
     const int64_t nwg = (nitems + ipw - 1) / ipw;
     const int64_t grid = (nwg + 7) / 8 * 8;
-    hipLaunchKernelGGL((k_ss_gather<TX, TY, LPE, VW>), dim3((unsigned)grid), dim3(256), 0, st, col, val, r,
+    hipLaunchKernelGGL((k_ss_gather<TX, TY, LPE, VW, TC, TV>), dim3((unsigned)grid), dim3(256), 0, st, col, val, r,
                        nrows, ncols, X, ldx, Y, shift, acc, nrowblk, nitems, ipw);
     return hipGetLastError();
 }
@@ -181,8 +187,8 @@ static hipError_t ss_gather(const int32_t* col, const double* val, int r, int64_
 // strip width code: 16 / 32 / 64 lanes per entry with one column each, or 128
 // = 64 lanes with two adjacent columns each (needs an even row stride; an odd
 // one falls back to 64)
-template <typename TX, typename TY>
-static hipError_t ss_gather_w(const int32_t* col, const double* val, int r, int64_t nrows, int64_t ncols,
+template <typename TX, typename TY, typename TC, typename TV>
+static hipError_t ss_gather_w(const TC* col, const TV* val, int r, int64_t nrows, int64_t ncols,
                               const TX* X, int64_t ldx, TY* Y, double shift, int acc, hipStream_t st, int lpe)
 {
     switch (lpe) {
@@ -197,25 +203,47 @@ static hipError_t ss_gather_w(const int32_t* col, const double* val, int r, int6
     }
 }
 
-hipError_t launch_ss_gather_f64(const int32_t* col, const double* val, int r, int64_t nrows,
-                                int64_t ncols, const double* X, double* Y, double shift, int acc,
-                                hipStream_t st, int lpe)
+hipError_t launch_ss_gather_f64(const SsOp& op, int64_t nrows, int64_t ncols, const double* X, double* Y,
+                                double shift, int acc, hipStream_t st, int lpe)
 {
-    return ss_gather_w<double, double>(col, val, r, nrows, ncols, X, ncols, Y, shift, acc, st, lpe);
+    if (op.col16)
+        return ss_gather_w<double, double>(op.col16, op.val, op.r, nrows, ncols, X, ncols, Y, shift, acc, st, lpe);
+    return ss_gather_w<double, double>(op.col, op.val, op.r, nrows, ncols, X, ncols, Y, shift, acc, st, lpe);
 }
 
-hipError_t launch_ss_gather_f32in(const int32_t* col, const double* val, int r, int64_t nrows,
-                                  int64_t ncols, const float* X, int64_t ldx, double* Y, double shift,
-                                  int acc, hipStream_t st, int lpe)
+hipError_t launch_ss_gather_f32in(const SsOp& op, int64_t nrows, int64_t ncols, const float* X, int64_t ldx,
+                                  double* Y, double shift, int acc, hipStream_t st, int lpe)
 {
-    return ss_gather_w<float, double>(col, val, r, nrows, ncols, X, ldx, Y, shift, acc, st, lpe);
+    if (op.col16 && op.val32)
+        return ss_gather_w<float, double>(op.col16, op.val32, op.r, nrows, ncols, X, ldx, Y, shift, acc, st, lpe);
+    return ss_gather_w<float, double>(op.col, op.val, op.r, nrows, ncols, X, ldx, Y, shift, acc, st, lpe);
 }
 
-hipError_t launch_ss_gather_f32(const int32_t* col, const double* val, int r, int64_t nrows,
-                                int64_t ncols, const float* X, float* Y, double shift, int acc,
-                                hipStream_t st, int lpe)
+hipError_t launch_ss_gather_f32(const SsOp& op, int64_t nrows, int64_t ncols, const float* X, float* Y,
+                                double shift, int acc, hipStream_t st, int lpe)
 {
-    return ss_gather_w<float, float>(col, val, r, nrows, ncols, X, ncols, Y, shift, acc, st, lpe);
+    if (op.col16 && op.val32)
+        return ss_gather_w<float, float>(op.col16, op.val32, op.r, nrows, ncols, X, ncols, Y, shift, acc, st, lpe);
+    return ss_gather_w<float, float>(op.col, op.val, op.r, nrows, ncols, X, ncols, Y, shift, acc, st, lpe);
+}
+
+// compact copies of an operator: 16-bit columns (N < 65536) and FP32 values
+__global__ void k_compact_op(const int32_t* __restrict__ col, const double* __restrict__ val, int64_t n,
+                             uint16_t* __restrict__ col16, float* __restrict__ val32)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        col16[i] = (uint16_t)col[i];
+        val32[i] = (float)val[i];
+    }
+}
+
+hipError_t launch_compact_op(const int32_t* col, const double* val, int64_t n, uint16_t* col16, float* val32,
+                             hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    const int64_t g = std::min<int64_t>((n + 255) / 256, 1 << 16);
+    hipLaunchKernelGGL(k_compact_op, dim3((unsigned)g), dim3(256), 0, st, col, val, n, col16, val32);
+    return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
