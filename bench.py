@@ -384,10 +384,12 @@ def main():
         peak = PEAK["bf16_TF"] if tag == "lowp" else PEAK["f64_TF"]
         kname = "k_ab_lp<MfmaBF16>" if tag == "lowp" else "k_ab<MfmaF64>"
         ach = fig["alpha_beta_TFLOPs"]
+        traffic = read_traffic(os.path.join(ROOT, "profiles", "%s_%s_pmc.txt" % (
+            "ab_lp_bf16" if tag == "lowp" else "ab_f64", args.workload)))
         roof = {"kernel": kname, "bound": "mfma", "achieved": ach, "peak": peak, "unit": "TFLOP/s",
-                "frac": ach / peak, "traffic": None}
+                "frac": ach / peak, "traffic": traffic}
     else:
-        kname = "k_ss_gather<float,double,64>" if tag == "lowp" else "k_ss_gather<double,double,32>"
+        kname = "k_ss_gather<float,double>" if tag == "lowp" else "k_ss_gather<double,double>"
         ach = fig["gather_GBps_algorithmic"]
         traffic = read_traffic(os.path.join(ROOT, "profiles", "%s_%s_pmc.txt" % (
             "ss_gather_f32" if tag == "lowp" else "ss_gather_f64", args.workload)))
