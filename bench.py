@@ -288,6 +288,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=0)
     ap.add_argument("--workload", default="cas16", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--m-max", type=int, default=None, help="subspace size of the timed solver (default 48)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--sigma-only", default=None, choices=["f64", "f32", "bf16"],
                     help="profiling aid: only run --steps sigma builds of the workload in this precision")
@@ -344,6 +345,8 @@ def main():
     torch.cuda.empty_cache()
 
     # headline solver, timed steps
+    if args.m_max:
+        HEADLINE["m_max"] = args.m_max
     times, ttt, infos, profs = [], [], [], []
     E = None
     for step in range(args.warmup + args.steps):

@@ -1986,7 +1986,8 @@ static int davidson_impl(casci_ctx* ctx, int nroots, double tol, const casci_dav
             HIPC(hipMemcpyAsync(vB(0), vX(0), vb * nkeep, hipMemcpyDeviceToDevice, st));
             HIPC(hipMemcpyAsync(vS(0), vSX(0), vb * nkeep, hipMemcpyDeviceToDevice, st));
             for (int j = 0; j < nkeep; ++j) par[j] = xpar[j];
-            if (refine) {  // FP64 sigma of the current Ritz vectors
+            if (refine) {  // FP64 sigma of the current Ritz vectors, buffer roots included
+                // (refining those in low precision was measured to cost iterations)
                 for (int j = 0; j < k; ++j) CHECK_RC(run_sigma_p(vB(j), vS(j), par[j], CASCI_F64));
                 ++refinements;
             }
