@@ -664,7 +664,7 @@ __global__ __launch_bounds__(64 * AB_MAX_WAVES) void k_ab(AbParams p, const type
 // the current tile is multiplied and reduced.
 constexpr int ABL_MAX_WAVES = 12;
 
-template <typename MF, int KBMAX, int MT, int SPT, typename TO>
+template <typename MF, int KBMAX, int MT, int SPT, typename TO, int NS>
 __global__ __launch_bounds__(64 * ABL_MAX_WAVES) void k_ab_lp(
     AbParams p, AbReduce r, const typename MF::elem* __restrict__ Vt,
     const typename MF::elem* __restrict__ Cs, int64_t ldc, TO* __restrict__ sigma, int kb_count,
@@ -702,10 +702,15 @@ __global__ __launch_bounds__(64 * ABL_MAX_WAVES) void k_ab_lp(
     for (int i = tid; i < Kp; i += nth) sJ[i] = i < p.sa ? l1_index(p.la_j[ia * p.sa + i]) : -1;
     if (tid == 0) Ts[zslot] = 0.f;
 
+    // Waves form 4/NS column groups (NS 16-column sub-tiles of the 64-column
+    // tile each) x nwaves*NS/4 pair-row groups (MT consecutive 16-row M tiles
+    // each): a wave reads only its columns of the D tile from LDS.
+    constexpr int NG = 4 / NS;
+    const int ngrp = wave % NG, mgrp = wave / NG;
     typename MF::frag afr[MT][KBMAX];
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt) {
-        const int m0 = (wave + mt * nwaves) * 16;
+        const int m0 = (mgrp * MT + mt) * 16;
         const int m = m0 + MF::arow(lane & 15);
 #pragma unroll
         for (int kb = 0; kb < KBMAX; ++kb) {
@@ -776,36 +781,44 @@ __global__ __launch_bounds__(64 * ABL_MAX_WAVES) void k_ab_lp(
     };
     // multiply and reduce the tile held in LDS; then commit the next one (in pfn)
     auto step = [&](int64_t tile, int nch, const vec_t (&pfn)[SPT], bool has_next, int nseg_next) {
+        {
+            acc_t acc[MT][NS];
 #pragma unroll
-        for (int mt = 0; mt < MT; ++mt) {
-            const int mtile = wave + mt * nwaves;
-            if (mtile * 16 >= p.Mp) continue;
-            acc_t acc[4];
+            for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
-            for (int ns = 0; ns < 4; ++ns)
+                for (int ns = 0; ns < NS; ++ns)
 #pragma unroll
-                for (int v = 0; v < 4; ++v) acc[ns][v] = 0.f;
+                    for (int v = 0; v < 4; ++v) acc[mt][ns][v] = 0.f;
 #pragma unroll
             for (int kb = 0; kb < KBMAX; ++kb) {
                 if (kb < kb_count) {
 #pragma unroll
-                    for (int ns = 0; ns < 4; ++ns) {
+                    for (int ns = 0; ns < NS; ++ns) {
+                        const int c = (ngrp * NS + ns) * 16 + (lane & 15);
                         typename MF::frag b;
-                        const int c = ns * 16 + (lane & 15);
                         if constexpr (MF::kmajor_tile) {
                             b = *reinterpret_cast<const typename MF::frag*>(
                                 &Dt[TileLayout<MF>::at(kb * MF::K + (lane >> 4) * (MF::K / 4), c, Kp)]);
                         } else {
                             b = Dt[TileLayout<MF>::at(kb * MF::K + (lane >> 4), c, Kp)];
                         }
-                        acc[ns] = MF::mma(afr[mt][kb], b, acc[ns]);
+#pragma unroll
+                        for (int mt = 0; mt < MT; ++mt)
+                            if ((mgrp * MT + mt) * 16 < p.Mp) acc[mt][ns] = MF::mma(afr[mt][kb], b, acc[mt][ns]);
                     }
                 }
             }
-            // element v of this lane: pair row mtile*16 + 4*(lane/16) + v, column ns*16 + lane%16
+            // element v of this lane: pair row mtile*16 + 4*(lane/16) + v, column c
 #pragma unroll
-            for (int ns = 0; ns < 4; ++ns)
-                *reinterpret_cast<f4*>(&Ts[(ns * 16 + (lane & 15)) * ldT + mtile * 16 + 4 * (lane >> 4)]) = acc[ns];
+            for (int mt = 0; mt < MT; ++mt) {
+                const int mtile = mgrp * MT + mt;
+                if (mtile * 16 < p.Mp)
+#pragma unroll
+                    for (int ns = 0; ns < NS; ++ns) {
+                        const int c = (ngrp * NS + ns) * 16 + (lane & 15);
+                        *reinterpret_cast<f4*>(&Ts[c * ldT + mtile * 16 + 4 * (lane >> 4)]) = acc[mt][ns];
+                    }
+            }
         }
         __syncthreads();
         if (has_next) commit_d(pfn);
@@ -880,10 +893,23 @@ __global__ __launch_bounds__(64 * ABL_MAX_WAVES) void k_ab_lp(
 
 int abl_waves(int Mp)
 {
+    (void)Mp;
+    return ABL_MAX_WAVES;  // 4 column groups x 3 pair-row groups
+}
+
+// layout of the low-precision kernel's waves: NS 16-column sub-tiles per wave
+// (1: 4 column groups x 3 row groups; 4: one column group x 12 row groups)
+// and MT 16-row M tiles per wave
+static void abl_layout(int Mp, int& NS, int& MT)
+{
     const int mtiles = Mp / 16;
-    const int MT = mtiles <= ABL_MAX_WAVES ? 1 : 2;
-    const int w = (mtiles + MT - 1) / MT;
-    return w < 4 ? 4 : w;  // more loaders and reducers for small pair counts
+    if (mtiles <= 4 * (ABL_MAX_WAVES / 4)) {
+        NS = 1;
+        MT = (mtiles + ABL_MAX_WAVES / 4 - 1) / (ABL_MAX_WAVES / 4);
+    } else {
+        NS = 4;
+        MT = (mtiles + ABL_MAX_WAVES - 1) / ABL_MAX_WAVES;
+    }
 }
 
 template <typename MF>
@@ -907,10 +933,10 @@ static hipError_t abl_launch(const AbParams& p, const AbReduce& r, const void* V
         return invalid("alpha-beta: T tile stride does not fit the table's 15-bit offsets");
     if (p.Nb >= 0xffff) return invalid("alpha-beta: more than 65534 beta strings for the low-precision table");
     const int kb_count = (p.sa + MF::K - 1) / MF::K;
-    const int mtiles = p.Mp / 16;
-    const int MT = mtiles <= ABL_MAX_WAVES ? 1 : 2;
     const int nwaves = abl_waves(p.Mp);
-    if (nwaves > ABL_MAX_WAVES) return invalid("alpha-beta: too many pair rows (norb too large)");
+    int NS = 1, MT = 1;
+    abl_layout(p.Mp, NS, MT);
+    if (NS == 4 && MT > 2) return invalid("alpha-beta: too many pair rows (norb too large)");
     const int64_t fixed = abl_lds_bytes<MF>(kb_count, r.ldT, r.max_nseg, 0);
     const int64_t cap = 160 * 1024 - 512;
     int64_t chunk = (cap - fixed) / 4;
@@ -924,9 +950,9 @@ static hipError_t abl_launch(const AbParams& p, const AbReduce& r, const void* V
     const int64_t items = p.Na * nchunks;
     const int64_t grid = (items + 7) / 8 * 8;
     dim3 blk(64 * nwaves);
-#define ABL_GO(KBV, MTV, SPTV)                                                                      \
+#define ABL_GO(KBV, MTV, SPTV, NSV)                                                                 \
     {                                                                                               \
-        auto kern = k_ab_lp<MF, KBV, MTV, SPTV, TO>;                                                \
+        auto kern = k_ab_lp<MF, KBV, MTV, SPTV, TO, NSV>;                                           \
         hipError_t e = hipFuncSetAttribute((const void*)kern,                                       \
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);   \
         if (e != hipSuccess) {                                                                      \
@@ -938,32 +964,37 @@ static hipError_t abl_launch(const AbParams& p, const AbReduce& r, const void* V
                            kb_count, chunk, nchunks);                                               \
         return hipGetLastError();                                                                   \
     }
-#define ABL_KB(KBV, MTV)                                                                            \
-    if (kb_count <= KBV && MT == MTV) {                                                             \
-        if (spt <= 2) ABL_GO(KBV, MTV, 2)                                                           \
-        if (spt <= 4) ABL_GO(KBV, MTV, 4)                                                           \
-        ABL_GO(KBV, MTV, 8)                                                                         \
+#define ABL_SPT(KBV, MTV, NSV)                                                                      \
+    {                                                                                               \
+        if (spt <= 2) ABL_GO(KBV, MTV, 2, NSV)                                                      \
+        if (spt <= 4) ABL_GO(KBV, MTV, 4, NSV)                                                      \
+        ABL_GO(KBV, MTV, 8, NSV)                                                                    \
+    }
+#define ABL_KB(KBV)                                                                                 \
+    if (kb_count <= KBV) {                                                                          \
+        if (NS == 1 && MT == 1) ABL_SPT(KBV, 1, 1)                                                  \
+        if (NS == 1 && MT == 2) ABL_SPT(KBV, 2, 1)                                                  \
+        if (NS == 1 && MT == 3) ABL_SPT(KBV, 3, 1)                                                  \
+        if (NS == 1 && MT == 4) ABL_SPT(KBV, 4, 1)                                                  \
+        if (NS == 4 && MT == 1) ABL_SPT(KBV, 1, 4)                                                  \
+        ABL_SPT(KBV, 2, 4)                                                                          \
     }
     if constexpr (MF::K == 4) {
-        ABL_KB(3, 1)
-        ABL_KB(5, 1)
-        ABL_KB(8, 1)
-        ABL_KB(11, 1)
-        ABL_KB(14, 1)
-        ABL_KB(18, 1)
-        ABL_KB(23, 1)
-        ABL_KB(14, 2)
-        ABL_KB(18, 2)
-        ABL_KB(23, 2)
+        ABL_KB(3)
+        ABL_KB(5)
+        ABL_KB(8)
+        ABL_KB(11)
+        ABL_KB(14)
+        ABL_KB(18)
+        ABL_KB(23)
     } else {
-        ABL_KB(1, 1)
-        ABL_KB(2, 1)
-        ABL_KB(3, 1)
-        ABL_KB(4, 1)
-        ABL_KB(3, 2)
-        ABL_KB(4, 2)
+        ABL_KB(1)
+        ABL_KB(2)
+        ABL_KB(3)
+        ABL_KB(4)
     }
 #undef ABL_KB
+#undef ABL_SPT
 #undef ABL_GO
     return invalid("alpha-beta: no kernel variant for this K-block count");
 }
