@@ -1915,8 +1915,7 @@ static int davidson_impl(casci_ctx* ctx, int nroots, double tol, const casci_dav
     std::vector<double> theta(64), Y(64 * 64), rn(k, 0.0);
     bool converged = false, have_prev = false;
     int it = 0, switch_iter = -1;
-    double last_rmax = std::numeric_limits<double>::infinity();
-    int stall = 0, empty_steps = 0, mlp_fallbacks = 0, refinements = 0;
+    int empty_steps = 0, mlp_fallbacks = 0, refinements = 0;
     std::vector<double> best_hist;
     for (it = 0; it < max_iter; ++it) {
         // Rayleigh-Ritz on the device
@@ -2047,7 +2046,6 @@ static int davidson_impl(casci_ctx* ctx, int nroots, double tol, const casci_dav
                 double before = *std::min_element(best_hist.begin(), best_hist.end() - 40);
                 stalled = recent > 0.5 * before;
             }
-            (void)stall;
             const bool to_f64 = stalled || (refine_at > 0 && rmax < refine_at);
             if (to_f64) {
                 // FP64 from here on: restart from the Ritz vectors
@@ -2064,7 +2062,6 @@ static int davidson_impl(casci_ctx* ctx, int nroots, double tol, const casci_dav
                 std::fill(G.begin(), G.end(), 0.0);
                 CHECK_RC(extend_G(0, m));
                 have_prev = false;
-                last_rmax = std::numeric_limits<double>::infinity();
                 for (int j = 0; j < k; ++j) theta_prev[j] = std::numeric_limits<double>::infinity();
                 continue;
             }
@@ -2095,7 +2092,6 @@ static int davidson_impl(casci_ctx* ctx, int nroots, double tol, const casci_dav
                 continue;
             }
         }
-        last_rmax = rmax;
         if (m + (int)todo.size() > m_max) CHECK_RC(collapse((int)todo.size()));
         // corrections for unconverged roots
         const int cnt = (int)todo.size();

@@ -340,8 +340,10 @@ hipError_t launch_transpose_f32(const float* in, float* out, int64_t rows, int64
 // ---------------------------------------------------------------------------
 // alpha-beta contraction on MFMA
 // ---------------------------------------------------------------------------
-// One workgroup owns one alpha string Ia (and one chunk [lo, lo+chunk) of
-// the sigma row, accumulated in LDS). For every tile of TN beta strings Jb:
+// FP64 kernel (k_ab; the FP32/BF16 kernel below shares the contraction and
+// replaces the atomic scatter). One workgroup owns one alpha string Ia (and
+// one chunk [lo, lo+chunk) of the sigma row, accumulated in LDS). For every
+// tile of TN beta strings Jb:
 //   D(e, Jb)  = C(J_e, Jb),  e in L1(Ia)           (row gathers -> LDS)
 //   T(m, Jb)  = sum_e A(m, e) D(e, Jb),             A(m,e) = s_e (p_e q_e|r_m s_m)
 //             (one 16-row M tile per wave, 16x16xK MFMA, four N sub-tiles
