@@ -392,3 +392,23 @@ def test_cas18_sampled_rows(torch):
     S64 = c.sigma(C64)
     got = S64.view(-1)[idx].cpu().numpy()
     assert np.abs(got - ref).max() < 1e-12 * scale
+
+
+@pytest.mark.parametrize("n,na,nb,k", [(3, 3, 3, 1), (2, 1, 1, 4), (5, 3, 0, 3), (4, 0, 2, 2), (3, 1, 2, 9),
+                                       (6, 3, 3, 12)])
+def test_davidson_degenerate_spaces(torch, n, na, nb, k):
+    """Edge cases of the solver: a single determinant (full occupation), every
+    root of the space (k = Ndet, no room for a buffer root), one spin empty,
+    and a large root count against LAPACK."""
+    c, h, eri = make(n, na, nb, 77 + n)
+    d = c.dims
+    E, X, info = c.davidson(k, 1e-11, r_tol=1e-7)
+    Eo, Xo, _ = oracle_roots(h, eri, na, nb, k)
+    assert info["converged"]
+    assert np.abs(E - Eo).max() < 1e-10
+    ov = np.abs(np.einsum("kij,kij->k", X.reshape(k, d["Na"], d["Nb"]), Xo))
+    # non-degenerate roots: the vectors themselves agree
+    gaps = np.diff(Eo)
+    for j in range(k):
+        if (j == 0 or gaps[j - 1] > 1e-6) and (j == k - 1 or gaps[j] > 1e-6):
+            assert abs(ov[j] - 1) < 1e-7, (j, ov[j])
