@@ -440,6 +440,9 @@ def main():
         "energies": E.tolist(), "energy_error_vs_fp64_reference": float(np.abs(E - Eref).max()),
         "sigma_fp64": f64_base, "sigma_lowp_bf16": lowp, "sigma_fp64_in_headline": f64,
         "headline_device_time_s": device_time_s, "refinements": infos[-1]["refinements"],
+        "first_iteration_s": float(infos[-1]["hist_time_ms"][0]) / 1000.0,
+        "fp64_diag_first_iteration_s": float(ib["hist_time_ms"][0]) / 1000.0,
+        "setup_s": infos[-1]["time_setup_ms"] / 1000.0,
         "m_max": HEADLINE["m_max"],
     }
     print(json.dumps(out))

@@ -1514,6 +1514,28 @@ static void host_eigh(std::vector<double>& A, int P, std::vector<double>& w, std
     V.swap(V2);
 }
 
+// Addresses of the `want` lowest entries of d (ties: lower address), ascending:
+// one pass with a bounded max-heap, no index array of the full space.
+static std::vector<int64_t> lowest_entries(const std::vector<double>& d, int64_t want)
+{
+    auto less = [&](int64_t a, int64_t b) { return d[a] < d[b] || (d[a] == d[b] && a < b); };
+    std::vector<int64_t> heap;
+    heap.reserve((size_t)want);
+    const int64_t N = (int64_t)d.size();
+    for (int64_t i = 0; i < N && want > 0; ++i) {
+        if ((int64_t)heap.size() < want) {
+            heap.push_back(i);
+            std::push_heap(heap.begin(), heap.end(), less);
+        } else if (less(i, heap.front())) {
+            std::pop_heap(heap.begin(), heap.end(), less);
+            heap.back() = i;
+            std::push_heap(heap.begin(), heap.end(), less);
+        }
+    }
+    std::sort(heap.begin(), heap.end(), less);
+    return heap;
+}
+
 static int davidson_impl(casci_ctx* ctx, int nroots, double tol, const casci_davidson_opts* opts,
                          double* energies, void* vectors, int mem, casci_davidson_info* info,
                          Collector* col)
@@ -1766,12 +1788,8 @@ static int davidson_impl(casci_ctx* ctx, int nroots, double tol, const casci_dav
         // instead lets Davidson settle on the lowest states of one symmetry
         // and never see a lower state of another.
         const int Pt = (int)std::min<int64_t>(Nd, 240);
-        std::vector<int64_t> idx(Nd);
-        for (int64_t i = 0; i < Nd; ++i) idx[i] = i;
         const int64_t want = std::min<int64_t>(Nd, 2 * (int64_t)Pt);
-        std::partial_sort(idx.begin(), idx.begin() + want, idx.end(), [&](int64_t a, int64_t b) {
-            return diag[a] < diag[b] || (diag[a] == diag[b] && a < b);
-        });
+        const std::vector<int64_t> idx = lowest_entries(diag, want);
         const bool paired = ctx->na == ctx->nb;
         std::vector<int64_t> dets;
         auto has = [&](int64_t x) { return std::find(dets.begin(), dets.end(), x) != dets.end(); };
@@ -1835,12 +1853,8 @@ static int davidson_impl(casci_ctx* ctx, int nroots, double tol, const casci_dav
         // (e_ab +- e_ba)/sqrt2: transposition commutes with H and with the
         // diagonal preconditioner, so a space without antisymmetric vectors
         // would never reach odd-S states. SINGLET keeps the + combinations.
-        std::vector<int64_t> idx(Nd);
-        for (int64_t i = 0; i < Nd; ++i) idx[i] = i;
         const int64_t want = std::min<int64_t>(Nd, 8 * k + 16);
-        std::partial_sort(idx.begin(), idx.begin() + want, idx.end(), [&](int64_t a, int64_t b) {
-            return diag[a] < diag[b] || (diag[a] == diag[b] && a < b);
-        });
+        const std::vector<int64_t> idx = lowest_entries(diag, want);
 
         struct Pick {
             int64_t lo, hi;
