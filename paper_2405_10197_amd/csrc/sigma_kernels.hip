@@ -421,10 +421,15 @@ struct MfmaBF16 {
 
 template <typename MF>
 struct TileLayout {
-    // D tile of Kp rows (k) x TN columns
-    __host__ __device__ static int ld(int Kp) { return MF::kmajor_tile ? Kp + 8 : AB_TN + 2; }
-    __host__ __device__ static int size(int Kp) { return MF::kmajor_tile ? AB_TN * (Kp + 8) : Kp * (AB_TN + 2); }
-    __device__ static int at(int k, int c, int Kp) { return MF::kmajor_tile ? c * (Kp + 8) + k : k * (AB_TN + 2) + c; }
+    // D tile of Kp rows (k) x TN columns. The [column][k] form shifts each
+    // group of 8 columns by another 16 bytes: a wave's commit writes 8 columns
+    // of 8 rows, and with the plain row stride (a multiple of 16 bytes) every
+    // column group would land in the same LDS banks.
+    __host__ __device__ static int size(int Kp) { return MF::kmajor_tile ? AB_TN * (Kp + 9) : Kp * (AB_TN + 2); }
+    __device__ static int at(int k, int c, int Kp)
+    {
+        return MF::kmajor_tile ? c * (Kp + 8) + 8 * (c >> 3) + k : k * (AB_TN + 2) + c;
+    }
 };
 
 // target and sign of the pair (r, s) acting on the beta string jb (column jcol)
