@@ -907,10 +907,15 @@ int abl_waves(int Mp)
 // layout of the low-precision kernel's waves: NS 16-column sub-tiles per wave
 // (1: 4 column groups x 3 row groups; 4: one column group x 12 row groups)
 // and MT 16-row M tiles per wave
-static void abl_layout(int Mp, int& NS, int& MT)
+// afr_regs: registers of one M tile's A fragments (kb_count operands). The
+// column-group layout gives a wave up to four M tiles; when their fragments
+// would take more than 64 registers (FP32 at n = 18: 4 x 23) the kernel
+// spills, and the one-tile-per-wave layout is used instead.
+static void abl_layout(int Mp, int afr_regs, int& NS, int& MT)
 {
     const int mtiles = Mp / 16;
-    if (mtiles <= 4 * (ABL_MAX_WAVES / 4)) {
+    const int mt3 = (mtiles + ABL_MAX_WAVES / 4 - 1) / (ABL_MAX_WAVES / 4);
+    if (mtiles <= 4 * (ABL_MAX_WAVES / 4) && mt3 * afr_regs <= 64) {
         NS = 1;
         MT = (mtiles + ABL_MAX_WAVES / 4 - 1) / (ABL_MAX_WAVES / 4);
     } else {
@@ -942,7 +947,7 @@ static hipError_t abl_launch(const AbParams& p, const AbReduce& r, const void* V
     const int kb_count = (p.sa + MF::K - 1) / MF::K;
     const int nwaves = abl_waves(p.Mp);
     int NS = 1, MT = 1;
-    abl_layout(p.Mp, NS, MT);
+    abl_layout(p.Mp, kb_count * (int)(sizeof(typename MF::frag) / 4), NS, MT);
     if (NS == 4 && MT > 2) return invalid("alpha-beta: too many pair rows (norb too large)");
     const int64_t fixed = abl_lds_bytes<MF>(kb_count, r.ldT, r.max_nseg, 0);
     const int64_t cap = 160 * 1024 - 512;
