@@ -260,16 +260,18 @@ def kernel_figures(P, dims, n, tag):
     M = n * (n + 1) // 2
     ab_flops = 2.0 * M * dims["sa"] * Nd
     ab_ms = P["ab_ms"] / nb_sig
-    aa_ms = P["aa_ms"] / nb_sig
+    cv_ms = P.get("convert_ms", 0.0) / nb_sig
+    aa_ms = P["aa_ms"] / nb_sig - cv_ms  # the gather launch alone
     esz = 8 if tag == "f64" else 4
-    # one same-spin gather launch: read C, write sigma, read the operator rows (int32 + FP64)
-    gather_bytes = Nd * esz + Nd * 8.0 + dims["Na"] * dims["ra"] * 12.0
+    # one same-spin gather launch: read C, write sigma in FP64, read the
+    # operator rows (16-bit columns and values in the input's type)
+    gather_bytes = Nd * esz + Nd * 8.0 + dims["Na"] * dims["ra"] * (2.0 + esz)
     gathered = dims["ra"] * Nd * float(esz)
     peak = PEAK["f64_TF"] if tag == "f64" else PEAK["bf16_TF"]
     return {
         "sigma_builds": int(nb_sig),
         "ms_per_sigma": P["total_ms"] / nb_sig,
-        "alpha_alpha_gather_ms": aa_ms, "beta_beta_ms": P["bb_ms"] / nb_sig,
+        "alpha_alpha_gather_ms": aa_ms, "convert_ms": cv_ms, "beta_beta_ms": P["bb_ms"] / nb_sig,
         "combine_ms": P["combine_ms"] / nb_sig,
         "alpha_beta_ms": ab_ms,
         "alpha_beta_TFLOPs": ab_flops / (ab_ms * 1e-3) / 1e12,

@@ -349,9 +349,11 @@ int casci_profile_enable(casci_ctx* ctx, int on);
  * out[0..15]: out[0..5] for sigma builds with FP64 alpha-beta arithmetic and
  * out[6..11] for low-precision builds, each = {alpha-alpha gather ms (with the
  * conversions of C if any), beta-beta ms (transposes + gather, or nothing
- * with parity), alpha-beta contraction ms (on a second stream, overlapping
- * the gathers), join + final combination ms, whole build ms, number of
- * builds}; out[12..15] = 0. Accumulated since casci_profile_enable(ctx, 1).
+ * with parity), alpha-beta contraction ms, final combination ms, whole build
+ * ms, number of builds}; out[12] = the conversions of C alone in the
+ * low-precision builds of FP64 vectors (included in out[6]); out[13..15] = 0.
+ * All parts run in order on the context's stream. Accumulated since
+ * casci_profile_enable(ctx, 1).
  */
 int casci_profile_read(const casci_ctx* ctx, double* out);
 

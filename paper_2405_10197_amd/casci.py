@@ -382,14 +382,17 @@ class Context:
         """Per-part device time (ms) of the sigma builds since profile(True), split by
         the arithmetic of the alpha-beta term ('f64' and 'lowp'): alpha-alpha gather
         (with the conversions of C), beta-beta work, alpha-beta contraction, final
-        combination and whole build, all from events on the library's stream."""
+        combination and whole build, all from events on the library's stream;
+        'convert_ms' is the conversions alone (part of 'aa_ms')."""
         out = np.zeros(16)
         self._check(self._L.casci_profile_read(self._h, out.ctypes.data))
         keys = ["aa_ms", "bb_ms", "ab_ms", "combine_ms", "total_ms", "sigma_builds"]
         res = {}
         for tag, off in (("f64", 0), ("lowp", 6)):
             res[tag] = {k: float(out[off + i]) for i, k in enumerate(keys)}
-        res.update({k: res["f64"][k] + res["lowp"][k] for k in keys})
+        res["f64"]["convert_ms"] = 0.0
+        res["lowp"]["convert_ms"] = float(out[12])
+        res.update({k: res["f64"][k] + res["lowp"][k] for k in keys + ["convert_ms"]})
         return res
 
     def spin_square(self, C):

@@ -973,6 +973,7 @@ static int sigma_dev(casci_ctx* ctx, const double* C, double* S, int ab_prec, do
         pr[2] += t_ab;
         pr[3] += t_end;
         pr[4] += t_tot;
+        if (lowp) ctx->prof[12] += t_cv;  // the conversions alone (already in pr[0])
         pr[5] += 1;
     }
     return CASCI_OK;
