@@ -400,6 +400,10 @@ def main():
             "ss_gather_f32" if tag == "lowp" else "ss_gather_f64", args.workload)))
         roof = {"kernel": kname, "bound": "hbm", "achieved": ach, "peak": PEAK["hbm_GBps"], "unit": "GB/s",
                 "frac": ach / PEAK["hbm_GBps"], "traffic": traffic}
+    # the counters' HBM-side bytes over the same launch time (what the memory
+    # side actually moved, against the algorithmic bytes of 'achieved')
+    t_ms = fig["alpha_beta_ms"] if part == "ab" else fig["alpha_alpha_gather_ms"]
+    roof["traffic_GBps"] = traffic / (t_ms * 1e-3) / 1e9 if traffic else None
 
     # CPU oracle on a bounded sample: rows of sigma at the same size, scaled to
     # the sigma builds of the GPU solve
