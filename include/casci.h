@@ -275,6 +275,18 @@ int casci_set_tuning(casci_ctx* ctx, int f64_lpe, int f32in_lpe);
  */
 int casci_abi_layout(int64_t* out, int n);
 
+/*
+ * Dense symmetric eigensolver of the Davidson solver's small projected
+ * matrices (Rayleigh-Ritz step, start-space block), host memory only, no
+ * device needed: Householder tridiagonalisation, then implicit QR with
+ * Wilkinson shifts. A: n x n row-major, symmetric (the lower triangle is
+ * read). w[n]: eigenvalues ascending. Z[n x n] row-major: column j is the
+ * unit eigenvector of w[j]. Returns CASCI_E_ARG (n < 0 or a null pointer),
+ * CASCI_E_NONFINITE, or CASCI_E_UNSUPPORTED if the iteration did not
+ * converge. Costs O(n^3); meant for n up to a few hundred.
+ */
+int casci_sym_eig(const double* A, int n, double* w, double* Z);
+
 /* ------------------------------------------------------------------------
  * Learned Davidson preconditioner (CASCI_PRECOND_MLP). A per-determinant
  * network 8 -> 64 -> 64 -> 1 (tanh, FP32) predicts the correction vector

@@ -136,6 +136,7 @@ def lib():
         "casci_mlp_features": (I, [P, P, P, D, P, I, P]),
         "casci_profile_read": (I, [P, P]),
         "casci_abi_layout": (I, [P, I]),
+        "casci_sym_eig": (I, [P, I, P, P]),
         "casci_batch_davidson": (I, [P, I, I, D, P, P, P, I]),
         "casci_get_tuning": (I, [P, P]),
         "casci_set_tuning": (I, [P, I, I]),
@@ -470,3 +471,18 @@ def batch_davidson(contexts, nroots: int = 1, tol: float = 1e-10, *, nthreads: i
         d["status"] = OK if infos[i].converged else NOCONV
         out.append(d)
     return E, out
+
+
+def sym_eig(A):
+    """Eigenpairs of a dense symmetric matrix with the solver's host eigensolver
+    (casci_sym_eig): (w ascending, Z with unit eigenvectors as columns)."""
+    A = np.ascontiguousarray(A, dtype=np.float64)
+    if A.ndim != 2 or A.shape[0] != A.shape[1]:
+        raise ValueError("A must be square")
+    n = A.shape[0]
+    w = np.zeros(n)
+    Z = np.zeros((n, n))
+    rc = lib().casci_sym_eig(A.ctypes.data, n, w.ctypes.data, Z.ctypes.data)
+    if rc < 0:
+        raise CasciError(rc, "casci_sym_eig failed")
+    return w, Z

@@ -1463,56 +1463,184 @@ static int collect_step(casci_ctx* ctx, Collector* col, int k, const double* X, 
     return CASCI_OK;
 }
 
-// Eigenpairs of a small symmetric host matrix A (P x P, row-major; destroyed)
-// by cyclic Jacobi rotations: w ascending, V column j = eigenvector j.
-static void host_eigh(std::vector<double>& A, int P, std::vector<double>& w, std::vector<double>& V)
+// Eigenpairs of a dense symmetric n x n matrix on the host: Householder
+// reduction to tridiagonal form with the orthogonal factor formed
+// explicitly, then implicit symmetric QR steps with Wilkinson shifts (bulge
+// chased by Givens rotations) on the tridiagonal matrix, the rotations
+// accumulated into the factor (Golub and Van Loan, Matrix Computations,
+// Sec. 5.1 and 8.3). A: row-major, symmetric. w: eigenvalues ascending.
+// Z: row-major, column j the unit eigenvector of w[j]. Returns false if the
+// QR iteration did not converge.
+static bool sym_eig(const double* A, int n, double* w, double* Z)
 {
-    V.assign((size_t)P * P, 0.0);
-    for (int i = 0; i < P; ++i) V[(size_t)i * P + i] = 1.0;
-    for (int sweep = 0; sweep < 60; ++sweep) {
-        double off = 0.0, tot = 0.0;
-        for (int i = 0; i < P; ++i)
-            for (int j = 0; j < P; ++j) {
-                const double x = A[(size_t)i * P + j] * A[(size_t)i * P + j];
-                tot += x;
-                if (i != j) off += x;
-            }
-        if (off <= 1e-30 * tot) break;
-        for (int p = 0; p < P - 1; ++p)
-            for (int q = p + 1; q < P; ++q) {
-                const double apq = A[(size_t)p * P + q];
-                if (std::fabs(apq) < 1e-300) continue;
-                const double th = (A[(size_t)q * P + q] - A[(size_t)p * P + p]) / (2.0 * apq);
-                const double t = (th >= 0 ? 1.0 : -1.0) / (std::fabs(th) + std::sqrt(th * th + 1.0));
-                const double c = 1.0 / std::sqrt(t * t + 1.0), sn = t * c;
-                for (int r = 0; r < P; ++r) {  // A <- A J
-                    const double a = A[(size_t)r * P + p], b = A[(size_t)r * P + q];
-                    A[(size_t)r * P + p] = c * a - sn * b;
-                    A[(size_t)r * P + q] = sn * a + c * b;
-                }
-                for (int r = 0; r < P; ++r) {  // A <- J^T A
-                    const double a = A[(size_t)p * P + r], b = A[(size_t)q * P + r];
-                    A[(size_t)p * P + r] = c * a - sn * b;
-                    A[(size_t)q * P + r] = sn * a + c * b;
-                }
-                for (int r = 0; r < P; ++r) {  // V <- V J
-                    const double a = V[(size_t)r * P + p], b = V[(size_t)r * P + q];
-                    V[(size_t)r * P + p] = c * a - sn * b;
-                    V[(size_t)r * P + q] = sn * a + c * b;
-                }
-            }
+    if (n <= 0) return true;
+    std::vector<double> a((size_t)n * n);
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j <= i; ++j) a[(size_t)i * n + j] = a[(size_t)j * n + i] = A[(size_t)i * n + j];
+    // reflectors P_k = I - beta_k v_k v_k^T acting on indices k+1..n-1 (v_k[k+1] = 1)
+    std::vector<double> vs((size_t)n * n, 0.0), beta(n, 0.0), p(n), wv(n);
+    for (int k = 0; k + 2 < n; ++k) {
+        const int L = n - k - 1;
+        double* v = &vs[(size_t)k * n + k + 1];
+        const double x0 = a[(size_t)(k + 1) * n + k];
+        double sigma = 0.0;
+        for (int i = 1; i < L; ++i) {
+            const double xi = a[(size_t)(k + 1 + i) * n + k];
+            sigma += xi * xi;
+            v[i] = xi;
+        }
+        v[0] = 1.0;
+        double b, mu;
+        if (sigma == 0.0) {
+            // already reduced in this column (a sign flip is not needed: T may
+            // carry a negative off-diagonal)
+            beta[k] = 0.0;
+            continue;
+        }
+        mu = std::sqrt(x0 * x0 + sigma);
+        const double v0 = x0 <= 0.0 ? x0 - mu : -sigma / (x0 + mu);
+        b = 2.0 * v0 * v0 / (sigma + v0 * v0);
+        for (int i = 1; i < L; ++i) v[i] /= v0;
+        beta[k] = b;
+        // trailing block S = a[k+1.., k+1..] <- P S P
+        for (int i = 0; i < L; ++i) {
+            const double* row = &a[(size_t)(k + 1 + i) * n + k + 1];
+            double s = 0.0;
+            for (int j = 0; j < L; ++j) s += row[j] * v[j];
+            p[i] = b * s;
+        }
+        double pv = 0.0;
+        for (int i = 0; i < L; ++i) pv += p[i] * v[i];
+        const double K = 0.5 * b * pv;
+        for (int i = 0; i < L; ++i) wv[i] = p[i] - K * v[i];
+        for (int i = 0; i < L; ++i) {
+            double* row = &a[(size_t)(k + 1 + i) * n + k + 1];
+            const double vi = v[i], wi = wv[i];
+            for (int j = 0; j < L; ++j) row[j] -= vi * wv[j] + wi * v[j];
+        }
+        a[(size_t)(k + 1) * n + k] = a[(size_t)k * n + k + 1] = mu;
+        for (int i = k + 2; i < n; ++i) a[(size_t)i * n + k] = a[(size_t)k * n + i] = 0.0;
     }
-    std::vector<int> ord(P);
-    for (int i = 0; i < P; ++i) ord[i] = i;
-    std::stable_sort(ord.begin(), ord.end(),
-                     [&](int a, int b) { return A[(size_t)a * P + a] < A[(size_t)b * P + b]; });
-    std::vector<double> V2((size_t)P * P);
-    w.resize(P);
-    for (int j = 0; j < P; ++j) {
-        w[j] = A[(size_t)ord[j] * P + ord[j]];
-        for (int i = 0; i < P; ++i) V2[(size_t)i * P + j] = V[(size_t)i * P + ord[j]];
+    std::vector<double> d(n), e(n, 0.0);
+    for (int i = 0; i < n; ++i) d[i] = a[(size_t)i * n + i];
+    for (int i = 0; i + 1 < n; ++i) e[i] = a[(size_t)(i + 1) * n + i];
+    // Q = P_0 P_1 ... P_{n-3}, stored by columns (zc[j*n + i] = Q[i][j]),
+    // accumulated backwards
+    std::vector<double> zc((size_t)n * n, 0.0);
+    for (int i = 0; i < n; ++i) zc[(size_t)i * n + i] = 1.0;
+    for (int k = n - 3; k >= 0; --k) {
+        if (beta[k] == 0.0) continue;
+        const double* v = &vs[(size_t)k * n + k + 1];
+        const int L = n - k - 1;
+        for (int j = k + 1; j < n; ++j) {
+            double* q = &zc[(size_t)j * n + k + 1];
+            double s = 0.0;
+            for (int i = 0; i < L; ++i) s += v[i] * q[i];
+            s *= beta[k];
+            for (int i = 0; i < L; ++i) q[i] -= s * v[i];
+        }
     }
-    V.swap(V2);
+    // implicit symmetric QR on the tridiagonal (d, e)
+    const double eps = std::numeric_limits<double>::epsilon();
+    int iters = 0;
+    const int max_iters = 40 * n + 40;
+    int h = n - 1;
+    while (h > 0) {
+        if (std::fabs(e[h - 1]) <= eps * (std::fabs(d[h - 1]) + std::fabs(d[h])) || e[h - 1] == 0.0) {
+            e[h - 1] = 0.0;
+            --h;
+            continue;
+        }
+        int l = h - 1;
+        while (l > 0 && !(std::fabs(e[l - 1]) <= eps * (std::fabs(d[l - 1]) + std::fabs(d[l])) || e[l - 1] == 0.0))
+            --l;
+        if (l > 0) e[l - 1] = 0.0;
+        if (++iters > max_iters) return false;
+        // Wilkinson shift from the trailing 2 x 2 block
+        const double dl = 0.5 * (d[h - 1] - d[h]);
+        const double eh = e[h - 1];
+        const double sg = dl >= 0.0 ? 1.0 : -1.0;
+        const double mu = d[h] - eh * eh / (dl + sg * std::hypot(dl, eh));
+        double x = d[l] - mu, z = e[l];
+        for (int k = l; k < h; ++k) {
+            const double r = std::hypot(x, z);
+            double c = 1.0, s = 0.0;
+            if (r > 0.0) {
+                c = x / r;
+                s = z / r;
+            }
+            if (k > l) e[k - 1] = r;
+            const double a0 = d[k], b0 = e[k], f0 = d[k + 1];
+            d[k] = c * c * a0 + 2.0 * c * s * b0 + s * s * f0;
+            d[k + 1] = s * s * a0 - 2.0 * c * s * b0 + c * c * f0;
+            e[k] = c * s * (f0 - a0) + (c * c - s * s) * b0;
+            if (k + 1 < h) {
+                z = s * e[k + 1];
+                e[k + 1] *= c;
+                x = e[k];
+            }
+            double* zk = &zc[(size_t)k * n];
+            double* zk1 = &zc[(size_t)(k + 1) * n];
+            for (int i = 0; i < n; ++i) {
+                const double u = zk[i], t = zk1[i];
+                zk[i] = c * u + s * t;
+                zk1[i] = -s * u + c * t;
+            }
+        }
+    }
+    std::vector<int> ord(n);
+    for (int i = 0; i < n; ++i) ord[i] = i;
+    std::stable_sort(ord.begin(), ord.end(), [&](int x1, int x2) { return d[x1] < d[x2]; });
+    for (int j = 0; j < n; ++j) {
+        w[j] = d[ord[j]];
+        const double* col = &zc[(size_t)ord[j] * n];
+        for (int i = 0; i < n; ++i) Z[(size_t)i * n + j] = col[i];
+    }
+    return true;
+}
+
+// Eigenpairs of the projected matrix G (m x m, row stride ldg). With parity
+// (par[i] = +-1 for every basis vector) G is block diagonal and each block is
+// solved on its own, so every Ritz vector lies exactly in one parity block;
+// the pairs of both blocks are merged in ascending order. theta[0..m), Y
+// row-major m x m (column j = eigenvector j).
+static bool ritz_eig(const double* G, int ldg, int m, const int* par, bool use_par, double* theta, double* Y)
+{
+    std::fill(Y, Y + (size_t)m * m, 0.0);
+    std::vector<int> blk[2];
+    for (int i = 0; i < m; ++i) blk[use_par && par[i] < 0 ? 1 : 0].push_back(i);
+    std::vector<std::pair<double, std::pair<int, int>>> all;  // (value, (block, column))
+    std::vector<double> wv[2], zv[2];
+    for (int b = 0; b < 2; ++b) {
+        const int nb = (int)blk[b].size();
+        if (nb == 0) continue;
+        std::vector<double> Ab((size_t)nb * nb);
+        for (int i = 0; i < nb; ++i)
+            for (int j = 0; j < nb; ++j) Ab[(size_t)i * nb + j] = G[(size_t)blk[b][i] * ldg + blk[b][j]];
+        wv[b].resize(nb);
+        zv[b].resize((size_t)nb * nb);
+        if (!sym_eig(Ab.data(), nb, wv[b].data(), zv[b].data())) return false;
+        for (int j = 0; j < nb; ++j) all.push_back({wv[b][j], {b, j}});
+    }
+    std::stable_sort(all.begin(), all.end(),
+                     [](const std::pair<double, std::pair<int, int>>& x, const std::pair<double, std::pair<int, int>>& y) {
+                         return x.first < y.first;
+                     });
+    for (int j = 0; j < m; ++j) {
+        const int b = all[j].second.first, c = all[j].second.second;
+        const int nb = (int)blk[b].size();
+        theta[j] = all[j].first;
+        for (int i = 0; i < nb; ++i) Y[(size_t)blk[b][i] * m + j] = zv[b][(size_t)i * nb + c];
+    }
+    return true;
+}
+
+extern "C" int casci_sym_eig(const double* A, int n, double* w, double* Z)
+{
+    if (n < 0 || (n > 0 && (!A || !w || !Z))) return CASCI_E_ARG;
+    for (int64_t i = 0; i < (int64_t)n * n; ++i)
+        if (!std::isfinite(A[i])) return CASCI_E_NONFINITE;
+    return sym_eig(A, n, w, Z) ? CASCI_OK : CASCI_E_UNSUPPORTED;
 }
 
 // Addresses of the `want` lowest entries of d (ties: lower address), ascending:
@@ -1626,10 +1754,8 @@ static int davidson_impl(casci_ctx* ctx, int nroots, double tol, const casci_dav
     auto vSX = [&](int i) { return SX + (size_t)i * Nd; };
     HIPC(ctx->d_small.ensure(64 * 1024 * 8));
     double* dsm = ctx->d_small.as<double>();
-    // d_small layout (doubles): [0, 4096) G, [4096, 8192) Y, [8192, 8256) theta,
-    // [8320, 8320+4096) coefficients, [16384, ...) reduction results (dots)
-    double* dG = dsm;
-    double* dY = dsm + 4096;
+    // d_small layout (doubles): [8192, 8256) theta, [8320, 8320+4096)
+    // coefficients, [32768, ...) reduction results (dots)
     double* dth = dsm + 8192;
     double* dcoef = dsm + 8320;
     double* dres = dsm + 32768;
@@ -1819,7 +1945,10 @@ static int davidson_impl(casci_ctx* ctx, int nroots, double tol, const casci_dav
         HIPC(hipStreamSynchronize(st));
         for (int i = 0; i < P; ++i)  // symmetric by construction up to rounding of the sums
             for (int j = 0; j < i; ++j) Hp[(size_t)i * P + j] = Hp[(size_t)j * P + i];
-        host_eigh(Hp, P, wp, Vp);
+        wp.resize(P);
+        Vp.resize((size_t)P * P);
+        if (!sym_eig(Hp.data(), P, wp.data(), Vp.data()))
+            return ctx->fail(CASCI_E_UNSUPPORTED, "start space: eigensolver did not converge");
         std::vector<int> partner(P, -1);
         if (paired)
             for (int i = 0; i < P; ++i) {
@@ -1933,7 +2062,7 @@ static int davidson_impl(casci_ctx* ctx, int nroots, double tol, const casci_dav
     int empty_steps = 0, mlp_fallbacks = 0, refinements = 0;
     std::vector<double> best_hist;
     for (it = 0; it < max_iter; ++it) {
-        // Rayleigh-Ritz on the device
+        // Rayleigh-Ritz (G = B^T H B is kept on the host)
         // With parity, B^T H B is block diagonal (the two parities are orthogonal
         // and H preserves them); its off-block entries are rounding noise and are
         // set to zero, so every Ritz vector lies exactly in one parity block.
@@ -1941,11 +2070,9 @@ static int davidson_impl(casci_ctx* ctx, int nroots, double tol, const casci_dav
         for (int i = 0; i < m; ++i)
             for (int j = 0; j < m; ++j)
                 Gc[(size_t)i * m + j] = (use_par && par[i] != par[j]) ? 0.0 : G[(size_t)i * m_max + j];
-        HIPC(hipMemcpyAsync(dG, Gc.data(), Gc.size() * 8, hipMemcpyHostToDevice, st));
-        HIPC(launch_jacobi_eigh(dG, m, m, dth, dY, st));
-        HIPC(hipMemcpyAsync(theta.data(), dth, m * 8, hipMemcpyDeviceToHost, st));
-        HIPC(hipMemcpyAsync(Y.data(), dY, (size_t)m * m * 8, hipMemcpyDeviceToHost, st));
-        HIPC(hipStreamSynchronize(st));
+        // G is held on the host: its small eigenproblem is solved there
+        if (!ritz_eig(Gc.data(), m, m, par.data(), use_par, theta.data(), Y.data()))
+            return ctx->fail(CASCI_E_UNSUPPORTED, "Rayleigh-Ritz: eigensolver did not converge");
         // previous Ritz vectors move to slots [k, 2k)
         if (have_prev) {
             HIPC(hipMemcpyAsync(vX(k), vX(0), vb * k, hipMemcpyDeviceToDevice, st));

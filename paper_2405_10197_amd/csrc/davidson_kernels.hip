@@ -58,15 +58,19 @@ __global__ __launch_bounds__(RED_THREADS) void k_block_dot(const double* __restr
         }
 }
 
-// stage 2: one thread per output, partials summed in index order
-__global__ void k_reduce_partials(const double* __restrict__ work, int nout, int nparts,
-                                  double* __restrict__ out)
+// stage 2: one wave per output (four per workgroup); lane l sums partials
+// l, l + 64, ... in order, then a fixed xor tree over the lanes (the result
+// does not depend on timing)
+__global__ __launch_bounds__(256) void k_reduce_partials(const double* __restrict__ work, int nout, int nparts,
+                                                         double* __restrict__ out)
 {
-    int o = blockIdx.x * blockDim.x + threadIdx.x;
-    if (o >= nout) return;
+    const int o = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (o >= nout) return;  // uniform per wave
     double s = 0.0;
-    for (int k = 0; k < nparts; ++k) s += work[(int64_t)o * nparts + k];
-    out[o] = s;
+    for (int k = lane; k < nparts; k += 64) s += work[(int64_t)o * nparts + k];
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+    if (lane == 0) out[o] = s;
 }
 
 hipError_t launch_block_dot(const double* A, int64_t lda, int na, const double* B, int64_t ldb,
@@ -78,8 +82,7 @@ hipError_t launch_block_dot(const double* A, int64_t lda, int na, const double* 
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     int nout = na * nb;
-    hipLaunchKernelGGL(k_reduce_partials, dim3((nout + 127) / 128), dim3(128), 0, st, work, nout,
-                       RED_BLOCKS, out);
+    hipLaunchKernelGGL(k_reduce_partials, dim3((nout + 3) / 4), dim3(256), 0, st, work, nout, RED_BLOCKS, out);
     return hipGetLastError();
 }
 
@@ -183,8 +186,7 @@ hipError_t launch_residual(const double* X, const double* SX, int64_t ld, int k,
                        diag, len, work);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_reduce_partials, dim3((4 * k + 127) / 128), dim3(128), 0, st, work, 4 * k,
-                       RED_BLOCKS, out);
+    hipLaunchKernelGGL(k_reduce_partials, dim3((4 * k + 3) / 4), dim3(256), 0, st, work, 4 * k, RED_BLOCKS, out);
     return hipGetLastError();
 }
 
@@ -218,135 +220,6 @@ hipError_t launch_scale(double* x, double a, int64_t n, hipStream_t st)
 {
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_scale, dim3(ew_grid(n)), dim3(256), 0, st, x, a, n);
-    return hipGetLastError();
-}
-
-// ---------------------------------------------------------------------------
-// Rayleigh-Ritz: cyclic Jacobi on the projected matrix, one workgroup, FP64.
-// Round-robin ordering: each round rotates mm/2 disjoint (p, q) planes at
-// once (mm = m rounded up to even; the padding index has zero coupling).
-// Rotation zeroing A_pq (A' = J^T A J, J_pp = J_qq = c, J_pq = s, J_qp = -s):
-//   th = (A_qq - A_pp) / (2 A_pq), t = sgn(th) / (|th| + sqrt(th^2 + 1)),
-//   c = 1/sqrt(t^2 + 1), s = t c.
-// ---------------------------------------------------------------------------
-constexpr int JAC_MAX = 64;
-
-__global__ __launch_bounds__(256) void k_jacobi(const double* __restrict__ G, int m, int ldg,
-                                                double* __restrict__ theta, double* __restrict__ Y)
-{
-    __shared__ double A[JAC_MAX][JAC_MAX + 1];
-    __shared__ double V[JAC_MAX][JAC_MAX + 1];
-    __shared__ double cs[JAC_MAX / 2][2];
-    __shared__ int pq[JAC_MAX / 2][2];
-    __shared__ double red[256];
-    __shared__ int order[JAC_MAX];
-    const int tid = threadIdx.x;
-    const int mm = m + (m & 1);
-    for (int t = tid; t < mm * mm; t += 256) {
-        int i = t / mm, j = t - i * mm;
-        double v = 0.0;
-        if (i < m && j < m) v = 0.5 * (G[i * ldg + j] + G[j * ldg + i]);
-        A[i][j] = v;
-        V[i][j] = (i == j) ? 1.0 : 0.0;
-    }
-    __syncthreads();
-    for (int sweep = 0; sweep < 60; ++sweep) {
-        double off = 0.0, dg = 0.0;
-        for (int t = tid; t < mm * mm; t += 256) {
-            int i = t / mm, j = t - i * mm;
-            if (i != j) off += A[i][j] * A[i][j];
-            else dg += A[i][j] * A[i][j];
-        }
-        red[tid] = off;
-        __syncthreads();
-        for (int s = 128; s > 0; s >>= 1) {
-            if (tid < s) red[tid] += red[tid + s];
-            __syncthreads();
-        }
-        const double offn = red[0];
-        __syncthreads();
-        red[tid] = dg;
-        __syncthreads();
-        for (int s = 128; s > 0; s >>= 1) {
-            if (tid < s) red[tid] += red[tid + s];
-            __syncthreads();
-        }
-        const double dgn = red[0];
-        __syncthreads();
-        if (offn <= 1e-32 * dgn || offn == 0.0) break;
-        for (int round = 0; round < mm - 1; ++round) {
-            if (tid < mm / 2) {
-                // player at position k: position 0 fixed, others rotate
-                auto player = [&](int pos) {
-                    return pos == 0 ? 0 : ((pos - 1 + round) % (mm - 1)) + 1;
-                };
-                int p = player(tid), q = player(mm - 1 - tid);
-                if (p > q) { int tt = p; p = q; q = tt; }
-                double c = 1.0, s = 0.0;
-                const double apq = A[p][q];
-                if (apq != 0.0) {
-                    const double th = (A[q][q] - A[p][p]) / (2.0 * apq);
-                    const double t = (th >= 0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
-                    c = 1.0 / sqrt(t * t + 1.0);
-                    s = t * c;
-                }
-                pq[tid][0] = p;
-                pq[tid][1] = q;
-                cs[tid][0] = c;
-                cs[tid][1] = s;
-            }
-            __syncthreads();
-            // rows: A <- J^T A
-            for (int t = tid; t < (mm / 2) * mm; t += 256) {
-                int k = t / mm, j = t - k * mm;
-                int p = pq[k][0], q = pq[k][1];
-                double c = cs[k][0], s = cs[k][1];
-                double ap = A[p][j], aq = A[q][j];
-                A[p][j] = c * ap - s * aq;
-                A[q][j] = s * ap + c * aq;
-            }
-            __syncthreads();
-            // columns: A <- A J, V <- V J
-            for (int t = tid; t < (mm / 2) * mm; t += 256) {
-                int k = t / mm, i = t - k * mm;
-                int p = pq[k][0], q = pq[k][1];
-                double c = cs[k][0], s = cs[k][1];
-                double ap = A[i][p], aq = A[i][q];
-                A[i][p] = c * ap - s * aq;
-                A[i][q] = s * ap + c * aq;
-                double vp = V[i][p], vq = V[i][q];
-                V[i][p] = c * vp - s * vq;
-                V[i][q] = s * vp + c * vq;
-            }
-            __syncthreads();
-        }
-    }
-    if (tid == 0) {
-        // ascending order of the m real eigenvalues (stable selection, ties by index)
-        for (int i = 0; i < m; ++i) order[i] = i;
-        for (int i = 0; i < m; ++i) {
-            int best = i;
-            for (int j = i + 1; j < m; ++j)
-                if (A[order[j]][order[j]] < A[order[best]][order[best]]) best = j;
-            int tt = order[i];
-            order[i] = order[best];
-            order[best] = tt;
-        }
-    }
-    __syncthreads();
-    for (int t = tid; t < m; t += 256) theta[t] = A[order[t]][order[t]];
-    for (int t = tid; t < m * m; t += 256) {
-        int i = t / m, j = t - i * m;  // Y[i][j] = component i of vector j
-        Y[t] = V[i][order[j]];
-    }
-}
-
-hipError_t launch_jacobi_eigh(const double* G, int m, int ldg, double* theta, double* Y,
-                              hipStream_t st)
-{
-    if (m <= 0) return hipSuccess;
-    if (m > JAC_MAX) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_jacobi, dim3(1), dim3(256), 0, st, G, m, ldg, theta, Y);
     return hipGetLastError();
 }
 

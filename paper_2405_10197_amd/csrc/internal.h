@@ -162,9 +162,6 @@ hipError_t launch_residual(const double* X, const double* SX, int64_t ld, int k,
 // t = -(D-th)^-1 r + eps (D-th)^-1 x  (eps = 0 for the diagonal preconditioner)
 hipError_t launch_precondition(const double* X, const double* SX, double theta, double eps,
                                const double* diag, int64_t len, double* T, hipStream_t st);
-// symmetric eigensolve of G[m x m] (ld = ldg), ascending: theta[m], Y[m x m] column j = vector j
-hipError_t launch_jacobi_eigh(const double* G, int m, int ldg, double* theta, double* Y,
-                              hipStream_t st);
 hipError_t launch_scale(double* x, double a, int64_t n, hipStream_t st);
 
 // mlp_kernels.hip (learned preconditioner)
