@@ -6,7 +6,15 @@
 
 namespace casci {
 
-constexpr int RED_BLOCKS = 512;  // stage-1 partials per output
+constexpr int RED_BLOCKS = 512;  // most stage-1 partials per output
+
+// stage-1 blocks for vectors of length len: about 4096 elements per block
+// (short vectors: launch-bound, fewer partials), at most RED_BLOCKS. The
+// count depends on len only, so every sum is taken in the same order.
+static int red_blocks(int64_t len)
+{
+    return (int)std::min<int64_t>(RED_BLOCKS, std::max<int64_t>(8, (len + 4095) / 4096));
+}
 constexpr int RED_THREADS = 256;
 
 __device__ inline double block_sum(double v, double* sh)
@@ -23,7 +31,7 @@ __device__ inline double block_sum(double v, double* sh)
     return r;
 }
 
-// stage 1: partial[(i*nb + j) * RED_BLOCKS + blockIdx.x] over a 4x4 group of (i, j)
+// stage 1: partial[(i*nb + j) * gridDim.x + blockIdx.x] over a 4x4 group of (i, j)
 __global__ __launch_bounds__(RED_THREADS) void k_block_dot(const double* __restrict__ A, int64_t lda,
                                                            int na, const double* __restrict__ B,
                                                            int64_t ldb, int nb, int64_t len,
@@ -54,7 +62,7 @@ __global__ __launch_bounds__(RED_THREADS) void k_block_dot(const double* __restr
         for (int j = 0; j < 4; ++j) {
             double s = block_sum(acc[i][j], sh);
             if (threadIdx.x == 0 && i0 + i < na && j0 + j < nb)
-                work[((int64_t)(i0 + i) * nb + (j0 + j)) * RED_BLOCKS + blockIdx.x] = s;
+                work[((int64_t)(i0 + i) * nb + (j0 + j)) * gridDim.x + blockIdx.x] = s;
         }
 }
 
@@ -77,12 +85,13 @@ hipError_t launch_block_dot(const double* A, int64_t lda, int na, const double* 
                             int nb, int64_t len, double* work, double* out, hipStream_t st)
 {
     if (na <= 0 || nb <= 0) return hipSuccess;
-    dim3 grid(RED_BLOCKS, (na + 3) / 4, (nb + 3) / 4);
+    const int nblk = red_blocks(len);
+    dim3 grid(nblk, (na + 3) / 4, (nb + 3) / 4);
     hipLaunchKernelGGL(k_block_dot, grid, dim3(RED_THREADS), 0, st, A, lda, na, B, ldb, nb, len, work);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     int nout = na * nb;
-    hipLaunchKernelGGL(k_reduce_partials, dim3((nout + 3) / 4), dim3(256), 0, st, work, nout, RED_BLOCKS, out);
+    hipLaunchKernelGGL(k_reduce_partials, dim3((nout + 3) / 4), dim3(256), 0, st, work, nout, nblk, out);
     return hipGetLastError();
 }
 
@@ -170,10 +179,10 @@ __global__ __launch_bounds__(RED_THREADS) void k_residual(const double* __restri
     }
     double s0 = block_sum(rr, sh), s1 = block_sum(xr, sh), s2 = block_sum(xx, sh);
     if (threadIdx.x == 0) {
-        work[((int64_t)k * 4 + 0) * RED_BLOCKS + blockIdx.x] = s0;
-        work[((int64_t)k * 4 + 1) * RED_BLOCKS + blockIdx.x] = s1;
-        work[((int64_t)k * 4 + 2) * RED_BLOCKS + blockIdx.x] = s2;
-        work[((int64_t)k * 4 + 3) * RED_BLOCKS + blockIdx.x] = 0.0;
+        work[((int64_t)k * 4 + 0) * gridDim.x + blockIdx.x] = s0;
+        work[((int64_t)k * 4 + 1) * gridDim.x + blockIdx.x] = s1;
+        work[((int64_t)k * 4 + 2) * gridDim.x + blockIdx.x] = s2;
+        work[((int64_t)k * 4 + 3) * gridDim.x + blockIdx.x] = 0.0;
     }
 }
 
@@ -182,11 +191,11 @@ hipError_t launch_residual(const double* X, const double* SX, int64_t ld, int k,
                            hipStream_t st)
 {
     if (k <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_residual, dim3(RED_BLOCKS, k), dim3(RED_THREADS), 0, st, X, SX, ld, theta,
-                       diag, len, work);
+    const int nblk = red_blocks(len);
+    hipLaunchKernelGGL(k_residual, dim3(nblk, k), dim3(RED_THREADS), 0, st, X, SX, ld, theta, diag, len, work);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_reduce_partials, dim3((4 * k + 3) / 4), dim3(256), 0, st, work, 4 * k, RED_BLOCKS, out);
+    hipLaunchKernelGGL(k_reduce_partials, dim3((4 * k + 3) / 4), dim3(256), 0, st, work, 4 * k, nblk, out);
     return hipGetLastError();
 }
 
