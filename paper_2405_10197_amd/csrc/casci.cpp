@@ -1817,11 +1817,16 @@ static int davidson_impl(casci_ctx* ctx, int nroots, double tol, const casci_dav
     auto orthonormalize = [&](int m, int cnt, int& kept) -> int {
         std::vector<double> c;
         std::vector<double> before(cnt);
-        for (int j = 0; j < cnt; ++j) {
-            std::vector<double> nn;
-            CHECK_RC(dots_dev(vB(m + j), 1, vB(m + j), 1, nn));
-            before[j] = std::sqrt(nn[0]);
-        }
+        // norms of all new vectors from one Gram-matrix call (its diagonal is
+        // summed exactly as a single dot product would be)
+        auto norms = [&](std::vector<double>& out) -> int {
+            std::vector<double> gram;
+            CHECK_RC(dots_dev(vB(m), cnt, vB(m), cnt, gram));
+            out.resize(cnt);
+            for (int j = 0; j < cnt; ++j) out[j] = std::sqrt(std::max(gram[(size_t)j * cnt + j], 0.0));
+            return CASCI_OK;
+        };
+        CHECK_RC(norms(before));
         if (m > 0) {
             // classical Gram-Schmidt against the basis; the second pass runs only
             // when the first removed most of a vector (norm ratio below 1/sqrt2),
@@ -1831,12 +1836,10 @@ static int davidson_impl(casci_ctx* ctx, int nroots, double tol, const casci_dav
                 for (double& x : c) x = -x;
                 CHECK_RC(combine(vB(0), m, c, cnt, 1.0, vB(m)));
                 if (pass == 0) {
+                    std::vector<double> after;
+                    CHECK_RC(norms(after));
                     bool again = false;
-                    for (int j = 0; j < cnt && !again; ++j) {
-                        std::vector<double> nn;
-                        CHECK_RC(dots_dev(vB(m + j), 1, vB(m + j), 1, nn));
-                        again = !(std::sqrt(std::max(nn[0], 0.0)) > 0.7071 * before[j]);
-                    }
+                    for (int j = 0; j < cnt; ++j) again = again || !(after[j] > 0.7071 * before[j]);
                     if (!again) break;
                 }
             }
