@@ -31,21 +31,30 @@ __device__ inline double block_sum(double v, double* sh)
     return r;
 }
 
-// stage 1: partial[(i*nb + j) * gridDim.x + blockIdx.x] over a 4x4 group of (i, j)
+// stage 1: partial[(i*nb + j) * nblk + xb] over a 4x4 group of (i, j), for
+// x-block xb of nblk. The 1-D grid is laid out so that the workgroups of one
+// x-block (all its (i, j) groups) run on the same XCD one after another: the
+// vectors they share are then read from that XCD's L2 instead of from HBM
+// once per group. Workgroup w runs on XCD w % 8.
 __global__ __launch_bounds__(RED_THREADS) void k_block_dot(const double* __restrict__ A, int64_t lda,
                                                            int na, const double* __restrict__ B,
-                                                           int64_t ldb, int nb, int64_t len,
-                                                           double* __restrict__ work)
+                                                           int64_t ldb, int nb, int64_t len, int nblk,
+                                                           int gj, int ngrp, double* __restrict__ work)
 {
     __shared__ double sh[RED_THREADS];
-    const int i0 = blockIdx.y * 4, j0 = blockIdx.z * 4;
+    const int w = blockIdx.x;
+    const int loc = w / 8;
+    const int xb = (loc / ngrp) * 8 + w % 8;
+    if (xb >= nblk) return;
+    const int g = loc % ngrp;
+    const int i0 = (g / gj) * 4, j0 = (g % gj) * 4;
     double acc[4][4];
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
         for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < len; x += stride) {
+    const int64_t stride = (int64_t)nblk * blockDim.x;
+    for (int64_t x = (int64_t)xb * blockDim.x + threadIdx.x; x < len; x += stride) {
         double a[4], b[4];
 #pragma unroll
         for (int i = 0; i < 4; ++i) a[i] = (i0 + i < na) ? A[(int64_t)(i0 + i) * lda + x] : 0.0;
@@ -62,7 +71,7 @@ __global__ __launch_bounds__(RED_THREADS) void k_block_dot(const double* __restr
         for (int j = 0; j < 4; ++j) {
             double s = block_sum(acc[i][j], sh);
             if (threadIdx.x == 0 && i0 + i < na && j0 + j < nb)
-                work[((int64_t)(i0 + i) * nb + (j0 + j)) * gridDim.x + blockIdx.x] = s;
+                work[((int64_t)(i0 + i) * nb + (j0 + j)) * nblk + xb] = s;
         }
 }
 
@@ -86,8 +95,10 @@ hipError_t launch_block_dot(const double* A, int64_t lda, int na, const double* 
 {
     if (na <= 0 || nb <= 0) return hipSuccess;
     const int nblk = red_blocks(len);
-    dim3 grid(nblk, (na + 3) / 4, (nb + 3) / 4);
-    hipLaunchKernelGGL(k_block_dot, grid, dim3(RED_THREADS), 0, st, A, lda, na, B, ldb, nb, len, work);
+    const int gj = (nb + 3) / 4, ngrp = ((na + 3) / 4) * gj;
+    const int64_t nwg = (int64_t)((nblk + 7) / 8) * 8 * ngrp;
+    hipLaunchKernelGGL(k_block_dot, dim3((unsigned)nwg), dim3(RED_THREADS), 0, st, A, lda, na, B, ldb, nb, len,
+                       nblk, gj, ngrp, work);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     int nout = na * nb;
