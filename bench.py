@@ -267,7 +267,7 @@ def kernel_figures(P, dims, n, tag):
     # operator rows (16-bit columns and values in the input's type)
     gather_bytes = Nd * esz + Nd * 8.0 + dims["Na"] * dims["ra"] * (2.0 + esz)
     gathered = dims["ra"] * Nd * float(esz)
-    peak = PEAK["f64_TF"] if tag == "f64" else PEAK["bf16_TF"]
+    peak = PEAK["%s_TF" % ("f64" if tag == "f64" else HEADLINE["ab_prec"])]
     return {
         "sigma_builds": int(nb_sig),
         "ms_per_sigma": P["total_ms"] / nb_sig,
@@ -291,6 +291,8 @@ def main():
     ap.add_argument("--workload", default="cas16", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--m-max", type=int, default=None, help="subspace size of the timed solver (default 48)")
+    ap.add_argument("--ab-prec", default=None, choices=["f64", "f32", "bf16"],
+                    help="alpha-beta arithmetic of the timed solver's corrections (default bf16)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--sigma-only", default=None, choices=["f64", "f32", "bf16"],
                     help="profiling aid: only run --steps sigma builds of the workload in this precision")
@@ -349,6 +351,8 @@ def main():
     # headline solver, timed steps
     if args.m_max:
         HEADLINE["m_max"] = args.m_max
+    if args.ab_prec:
+        HEADLINE["ab_prec"] = args.ab_prec
     times, ttt, infos, profs = [], [], [], []
     E = None
     for step in range(args.warmup + args.steps):
@@ -386,11 +390,12 @@ def main():
     _, tag, part, fig = cand[0]
     device_time_s = {"%s_%s" % (t, p): round(ms / 1000.0, 3) for ms, t, p, _ in cand}
     if part == "ab":
-        peak = PEAK["bf16_TF"] if tag == "lowp" else PEAK["f64_TF"]
-        kname = "k_ab_lp<MfmaBF16>" if tag == "lowp" else "k_ab<MfmaF64>"
+        lp = HEADLINE["ab_prec"]
+        peak = PEAK["%s_TF" % lp] if tag == "lowp" else PEAK["f64_TF"]
+        kname = ("k_ab_lp<Mfma%s>" % lp.upper()) if tag == "lowp" else "k_ab<MfmaF64>"
         ach = fig["alpha_beta_TFLOPs"]
         traffic = read_traffic(os.path.join(ROOT, "profiles", "%s_%s_pmc.txt" % (
-            "ab_lp_bf16" if tag == "lowp" else "ab_f64", args.workload)))
+            "ab_lp_" + lp if tag == "lowp" else "ab_f64", args.workload)))
         roof = {"kernel": kname, "bound": "mfma", "achieved": ach, "peak": peak, "unit": "TFLOP/s",
                 "frac": ach / peak, "traffic": traffic}
     else:
@@ -432,10 +437,12 @@ def main():
     out = {
         "metric": METRIC, "value": med, "unit": "s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": 1000.0 * float(np.mean(times)), "higher_is_better": False,
-        "scaling": "strong", "vs_baseline": None, "dtype": "bf16+f64", "data": "synthetic",
+        "scaling": "strong", "vs_baseline": None, "dtype": "%s+f64" % HEADLINE["ab_prec"], "data": "synthetic",
         "config": {"workload": desc, "norb": n, "nalpha": na, "nbeta": nb, "nroots": k, "seed": seed,
-                   "spin": spin, "solver": "BF16 alpha-beta (FP32 accumulate) for corrections + FP64 sigma "
-                                           "of the Ritz vectors at each collapse, Olsen, m_max 48"},
+                   "spin": spin, "solver": "%s alpha-beta (%s) for corrections + FP64 sigma of the Ritz "
+                                           "vectors at each collapse, Olsen, m_max %d"
+                   % (HEADLINE["ab_prec"].upper(), "FP32 accumulate" if HEADLINE["ab_prec"] != "f64" else "FP64",
+                      HEADLINE["m_max"])},
         "roofline": roof,
         "cpu_baseline": cpu,
         "fp64_diag_time_to_1e8_s": t_base,
@@ -444,7 +451,7 @@ def main():
         "iterations": infos[-1]["iterations"], "sigma_calls": infos[-1]["sigma_calls"],
         "sigma_calls_fp64": infos[-1]["sigma_calls_fp64"], "switch_iteration": infos[-1]["switch_iter"],
         "energies": E.tolist(), "energy_error_vs_fp64_reference": float(np.abs(E - Eref).max()),
-        "sigma_fp64": f64_base, "sigma_lowp_bf16": lowp, "sigma_fp64_in_headline": f64,
+        "sigma_fp64": f64_base, "sigma_lowp_" + HEADLINE["ab_prec"]: lowp, "sigma_fp64_in_headline": f64,
         "headline_device_time_s": device_time_s, "refinements": infos[-1]["refinements"],
         "first_iteration_s": float(infos[-1]["hist_time_ms"][0]) / 1000.0,
         "fp64_diag_first_iteration_s": float(ib["hist_time_ms"][0]) / 1000.0,
