@@ -2251,7 +2251,7 @@ static int davidson_impl(casci_ctx* ctx, int nroots, double tol, const casci_dav
                 HIPC(launch_mlp_correction(fa, ctx->d_mlp.as<float>(), vB(m + t), st));
                 std::vector<double> nn;
                 CHECK_RC(dots_dev(vB(m + t), 1, vB(m + t), 1, nn));
-                // the judge: a non-finite or vanishing learned correction falls back to Olsen
+                // fallback: a non-finite or vanishing learned correction is replaced by Olsen
                 done = std::isfinite(nn[0]) && nn[0] > 0.0;
                 if (!done) ++mlp_fallbacks;
             }
