@@ -2262,7 +2262,10 @@ static int davidson_impl(casci_ctx* ctx, int nroots, double tol, const casci_dav
                                          st));
             }
             par[m + t] = xpar[j];
-            if (use_par) CHECK_RC(symmetrize(vB(m + t), xpar[j]));
+            // Olsen and diagonal corrections of a parity-pure Ritz pair have its
+            // parity up to the rounding of H_II, which the re-projection in
+            // orthonormalize removes; a learned correction is projected here
+            if (use_par && o.precond == CASCI_PRECOND_MLP) CHECK_RC(symmetrize(vB(m + t), xpar[j]));
         }
         int kept = 0;
         CHECK_RC(orthonormalize(m, cnt, kept));
