@@ -313,8 +313,8 @@ def main():
         print(json.dumps({"copy_probe_bytes_read": nb, "copy_probe_bytes_written": nb}))
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py: this build runs on exactly one GPU (the string-CASCI path is measured "
-              "on one MI355X); --gpus %d is not supported" % args.gpus, file=sys.stderr)
+        print("bench.py: the string-CASCI path runs and is measured on exactly one GPU (one MI355X); "
+              "--gpus %d is not supported" % args.gpus, file=sys.stderr)
         sys.exit(2)
 
     import torch
