@@ -170,6 +170,22 @@ int casci_get_diagonal(casci_ctx* ctx, double* out, int mem);
 int casci_sigma(casci_ctx* ctx, const void* C, void* sigma, int dtype, int ab_prec, int mem);
 
 /*
+ * sigma = H C for a CI vector of definite transposition parity, C = parity C^T
+ * (parity = +1 or -1; needs nalpha = nbeta and FP64 storage). For equal
+ * electron counts, transposing C (swapping the alpha and beta strings of every
+ * determinant) commutes with H, and with the determinant phase of this header
+ * it maps a spin-S state to (-1)^S times itself: singlets have parity +1,
+ * triplets -1. The beta-beta term is then parity times the transpose of the
+ * alpha-alpha term, so one same-spin gather serves both spins; the Davidson
+ * solver builds every sigma this way when nalpha = nbeta. ab_prec as in
+ * casci_sigma (F32/BF16: the same-spin gather reads an FP32 copy of C and
+ * accumulates in FP64). The parity of C is the caller's promise and is not
+ * checked: for a C without it the result is F_a C + parity (F_a C)^T + the
+ * alpha-beta term, not H C.
+ */
+int casci_sigma_parity(casci_ctx* ctx, const double* C, double* sigma, int ab_prec, int parity, int mem);
+
+/*
  * <S^2> of a normalised FP64 CI vector C (Na x Nb): S^2 = Sz^2 + Sz + S- S+.
  * Result to host *s2.
  */
@@ -345,6 +361,7 @@ int casci_mlp_collect(casci_ctx* ctx, int nroots, double tol, const casci_davids
 /*
  * Features F[m][8] (host) of the determinants idx[0..m) (host) for the Ritz
  * pair (theta, x) whose sigma vector is sx (x, sx: device FP64 [Ndet]).
+ * CASCI_E_ARG if an index lies outside [0, Ndet) (checked before any device work).
  */
 int casci_mlp_features(casci_ctx* ctx, const double* x, const double* sx, double theta,
                        const int64_t* idx, int m, float* F);

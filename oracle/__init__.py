@@ -64,7 +64,9 @@ def _load():
         lib.oracle_sigma_rows.argtypes = [i, P, P, d, P, l, P, l, P, P, l, P]
         lib.oracle_dense_s2.argtypes = [i, P, l, P, l, P]
         lib.oracle_h_rows.argtypes = [i, P, P, d, P, l, P, l, P, l, l, P, P, P]
-        for f in (lib.oracle_dense_h, lib.oracle_sigma_rows, lib.oracle_dense_s2, lib.oracle_h_rows):
+        lib.oracle_single_list.argtypes = [i, P, l, i, P, P, P, P]
+        for f in (lib.oracle_dense_h, lib.oracle_sigma_rows, lib.oracle_dense_s2, lib.oracle_h_rows,
+                  lib.oracle_single_list):
             f.restype = ctypes.c_int
         _lib = lib
     return _lib
@@ -133,6 +135,48 @@ def single_list(norb: int, nel: int):
     shape = (len(strs), len(P[0]) if P else 0)
     return (np.array(P, dtype=np.int64).reshape(shape), np.array(Q, dtype=np.int64).reshape(shape),
             np.array(J, dtype=np.int64).reshape(shape), np.array(S, dtype=np.int64).reshape(shape))
+
+
+def single_list_c(norb: int, nel: int):
+    """The same single-substitution list as ``single_list`` (same order, same
+    operator-by-operator signs), computed in C (``oracle_single_list``) for the
+    large string sets (n = 16, 18) that the Python loop would take minutes on."""
+    strs = strings(norb, nel)
+    N = strs.size
+    s = nel * (norb - nel + 1)
+    out = [np.empty(N * s, dtype=np.int64) for _ in range(4)]  # J, sign, P, Q
+    if N * s:
+        rc = _load().oracle_single_list(norb, _ptr(strs), N, s, *(_ptr(a) for a in out))
+        if rc != 0:
+            raise RuntimeError("oracle_single_list failed: %d" % rc)
+    J, S, P, Q = (a.reshape(N, s) for a in out)
+    return P, Q, J, S
+
+
+def h_rows(h, eri, nalpha: int, nbeta: int, rows, ecore: float = 0.0):
+    """Rows of the explicit H for the determinant addresses ``rows``: a list of
+    (columns ascending, values) per row, from the same Slater-Condon elements
+    as ``hamiltonian`` (matrix-free, for spaces too large for a dense H)."""
+    n, h, eri = _prep(h, eri)
+    a = strings(n, nalpha)
+    b = strings(n, nbeta)
+    ne = nalpha + nbeta
+    maxc = 1 + ne * (2 * n - ne) + math.comb(ne, 2) * math.comb(2 * n - ne, 2)
+    rows = np.ascontiguousarray(np.asarray(rows, dtype=np.int64).reshape(-1))
+    cols = np.empty(rows.size * maxc, dtype=np.int64)
+    vals = np.empty(rows.size * maxc)
+    cnt = np.empty(rows.size, dtype=np.int64)
+    rc = _load().oracle_h_rows(n, _ptr(h), _ptr(eri), float(ecore), _ptr(a), a.size, _ptr(b), b.size,
+                               _ptr(rows), rows.size, maxc, _ptr(cols), _ptr(vals), _ptr(cnt))
+    if rc != 0:
+        raise RuntimeError("oracle_h_rows failed: %d" % rc)
+    out = []
+    for t in range(rows.size):
+        c = cols[t * maxc:t * maxc + cnt[t]]
+        v = vals[t * maxc:t * maxc + cnt[t]]
+        o = np.argsort(c, kind="stable")
+        out.append((c[o], v[o]))
+    return out
 
 
 # --------------------------------------------------------------------------

@@ -328,3 +328,38 @@ int oracle_dense_s2(int n, const uint64_t* astr, long Na, const uint64_t* bstr, 
     }
     return 0;
 }
+
+/*
+ * Single-substitution list of every string of one spin (Sec. II.A.1): for
+ * string I = strs[t] and each entry, in the order p over the occupied orbitals
+ * of I ascending and, for each p, q over (unoccupied orbitals of I) + {p}
+ * ascending, the string J = I - p + q and sign = <I| a+_p a_q |J>, obtained by
+ * applying a_q and then a+_p to J one operator at a time. Outputs are [N][s]
+ * with s = ne (n - ne + 1); J is the position of the string in strs.
+ */
+int oracle_single_list(int n, const uint64_t* strs, long N, int s, long* J, long* sign, long* P, long* Q)
+{
+    if (n < 1 || n > 64) return -1;
+    for (long t = 0; t < N; ++t) {
+        const det_t I = strs[t];
+        long e = 0;
+        for (int p = 0; p < n; ++p) {
+            if (!occ(I, p)) continue;
+            for (int q = 0; q < n; ++q) {
+                if (occ(I, q) && q != p) continue;
+                det_t d = (I & ~((det_t)1 << p)) | ((det_t)1 << q);
+                const long jj = find_string(strs, N, d);
+                int sg = 1;
+                if (jj < 0 || !apply_annihilate(&d, q, &sg) || !apply_create(&d, p, &sg) || d != I) return -2;
+                if (e >= s) return -3;
+                J[t * s + e] = jj;
+                sign[t * s + e] = sg;
+                P[t * s + e] = p;
+                Q[t * s + e] = q;
+                ++e;
+            }
+        }
+        if (e != s) return -3;
+    }
+    return 0;
+}

@@ -15,7 +15,8 @@ CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libcasci.so")
-SOURCES = ["setup_kernels.hip", "sigma_kernels.hip", "davidson_kernels.hip", "mlp_kernels.hip", "casci.cpp"]
+SOURCES = ["ab_lowp_f32_d.hip", "ab_lowp_f32_f.hip", "ab_lowp_bf16_d.hip", "ab_lowp_bf16_f.hip", "ab_f64.hip", "sigma_kernels.hip", "setup_kernels.hip",
+           "davidson_kernels.hip", "mlp_kernels.hip", "casci.cpp"]
 ARCH = "gfx950"
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
@@ -38,7 +39,7 @@ def _compile(src: str, build_dir: str) -> str:
 def build(verbose: bool = False) -> str:
     build_dir = os.path.join(HERE, "_build")
     os.makedirs(build_dir, exist_ok=True)
-    with ThreadPoolExecutor(max_workers=min(4, len(SOURCES))) as ex:
+    with ThreadPoolExecutor(max_workers=min(8, len(SOURCES))) as ex:
         objs = list(ex.map(lambda s: _compile(s, build_dir), SOURCES))
     tmp = LIB + ".tmp%d" % os.getpid()
     cmd = [HIPCC, "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp] + objs

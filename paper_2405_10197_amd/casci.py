@@ -124,6 +124,7 @@ def lib():
         "casci_get_same_spin_operator": (I, [P, I, P, P]),
         "casci_get_diagonal": (I, [P, P, I]),
         "casci_sigma": (I, [P, P, P, I, I, I]),
+        "casci_sigma_parity": (I, [P, P, P, I, I, I]),
         "casci_spin_square": (I, [P, P, P, I]),
         "casci_davidson": (I, [P, I, D, P, P, P, I, P]),
         "casci_profile_enable": (I, [P, I]),
@@ -169,8 +170,33 @@ def _ptr(a):
     raise TypeError("expected a numpy array or a torch tensor")
 
 
+def _dtype_name(a):
+    return str(a.dtype).split(".")[-1]
+
+
 class Context:
     """One CASCI problem on one GPU (device=-1: validate-only, no GPU needed)."""
+
+    def _vec(self, a, count, name, dtypes=("float64",), device_only=False):
+        """Pointer and memory flag of an array argument after checking its element
+        count, dtype and placement: a wrong one would make the kernels read or write
+        out of bounds, so it is rejected here, before any library call."""
+        if not hasattr(a, "shape") or not hasattr(a, "dtype"):
+            raise TypeError("%s must be a numpy array or a torch tensor" % name)
+        if _dtype_name(a) not in dtypes:
+            raise TypeError("%s must be %s, got %s" % (name, " or ".join(dtypes), _dtype_name(a)))
+        n = int(np.prod(tuple(a.shape)))
+        if n != int(count):
+            raise ValueError("%s has %d elements, expected %d" % (name, n, int(count)))
+        if isinstance(a, np.ndarray):
+            if device_only:
+                raise ValueError("%s must be a device tensor" % name)
+        elif getattr(a, "is_cuda", False):
+            if self.device < 0 or a.device.index != self.device:
+                raise ValueError("%s lives on %s, the context on device %d" % (name, a.device, self.device))
+        elif device_only:
+            raise ValueError("%s must be a device tensor" % name)
+        return _ptr(a)
 
     def __init__(self, device: int = 0, stream=None, own_stream: bool = False):
         """device -1: validate-only context (no GPU work). stream: HIP stream
@@ -284,7 +310,7 @@ class Context:
         d = self.dims
         if out is None:
             out = np.zeros((d["Na"], d["Nb"]))
-        p, mem = _ptr(out)
+        p, mem = self._vec(out, d["Ndet"], "out")
         self._check(self._L.casci_get_diagonal(self._h, p, mem))
         return out
 
@@ -297,15 +323,30 @@ class Context:
             else:
                 import torch
                 out = torch.empty_like(C)
-        dt = str(C.dtype)
-        dtype = F64 if dt.endswith("float64") else (F32 if dt.endswith("float32") else None)
-        if dtype is None:
-            raise TypeError("C must be float64 or float32")
-        pc, mem = _ptr(C)
-        ps, mem2 = _ptr(out)
-        if mem != mem2 or str(out.dtype) != dt:
+        nd = self.dims["Ndet"]
+        pc, mem = self._vec(C, nd, "C", ("float64", "float32"))
+        ps, mem2 = self._vec(out, nd, "out", ("float64", "float32"))
+        if mem != mem2 or _dtype_name(out) != _dtype_name(C):
             raise ValueError("C and out must share memory kind and dtype")
+        dtype = F64 if _dtype_name(C) == "float64" else F32
         self._check(self._L.casci_sigma(self._h, pc, ps, dtype, PREC[ab_prec], mem))
+        return out
+
+    def sigma_parity(self, C, parity: int, out=None, ab_prec: str = "f64"):
+        """sigma = H C for a float64 C with C = parity * C^T (nalpha = nbeta): the
+        path the Davidson solver takes (one same-spin gather serves both spins)."""
+        if out is None:
+            if isinstance(C, np.ndarray):
+                out = np.empty_like(C)
+            else:
+                import torch
+                out = torch.empty_like(C)
+        nd = self.dims["Ndet"]
+        pc, mem = self._vec(C, nd, "C")
+        ps, mem2 = self._vec(out, nd, "out")
+        if mem != mem2:
+            raise ValueError("C and out must share memory kind")
+        self._check(self._L.casci_sigma_parity(self._h, pc, ps, PREC[ab_prec], int(parity), mem))
         return out
 
     # -- learned preconditioner ------------------------------------------
@@ -337,8 +378,9 @@ class Context:
 
     def mlp_train(self, X, T, epochs=10, batch=4096, lr=1e-3, seed=0):
         """X, T: numpy (host) or torch CUDA tensors. Returns per-epoch training loss."""
-        px, mem = _ptr(X)
-        pt, mem2 = _ptr(T)
+        N = int(X.shape[0])
+        px, mem = self._vec(X, N * 8, "X", ("float32",))
+        pt, mem2 = self._vec(T, N, "T", ("float32",))
         if mem != mem2:
             raise ValueError("X and T must share memory kind")
         hist = np.zeros(epochs)
@@ -349,11 +391,12 @@ class Context:
     def mlp_collect(self, nroots, tol, xstar, samples=2048, seed=0, max_rows=1 << 20, **opts):
         """Training rows (features, targets) from a Davidson run; xstar: torch CUDA [nroots, Na, Nb]."""
         import torch
-        F = torch.empty((max_rows, 8), dtype=torch.float32, device="cuda")
-        T = torch.empty(max_rows, dtype=torch.float32, device="cuda")
+        px, _ = self._vec(xstar, int(nroots) * self.dims["Ndet"], "xstar", device_only=True)
+        F = torch.empty((max_rows, 8), dtype=torch.float32, device="cuda:%d" % self.device)
+        T = torch.empty(max_rows, dtype=torch.float32, device="cuda:%d" % self.device)
         o = self._opts(**opts)
         n = ctypes.c_int64()
-        rc = self._L.casci_mlp_collect(self._h, int(nroots), float(tol), ctypes.byref(o), xstar.data_ptr(),
+        rc = self._L.casci_mlp_collect(self._h, int(nroots), float(tol), ctypes.byref(o), px,
                                        int(samples), int(seed), F.data_ptr(), T.data_ptr(), int(max_rows),
                                        ctypes.byref(n))
         self._check(rc, allow=(OK, NOCONV))
@@ -361,9 +404,14 @@ class Context:
 
     def mlp_features(self, x, sx, theta, idx):
         """Features of determinants idx for the Ritz pair (theta, x) with sigma sx (torch CUDA FP64)."""
-        idx = np.ascontiguousarray(idx, dtype=np.int64)
+        nd = self.dims["Ndet"]
+        px, _ = self._vec(x, nd, "x", device_only=True)
+        ps, _ = self._vec(sx, nd, "sx", device_only=True)
+        idx = np.ascontiguousarray(idx, dtype=np.int64).reshape(-1)
+        if idx.size and (idx.min() < 0 or idx.max() >= nd):
+            raise ValueError("determinant index out of range [0, %d)" % nd)
         F = np.zeros((idx.size, 8), dtype=np.float32)
-        self._check(self._L.casci_mlp_features(self._h, x.data_ptr(), sx.data_ptr(), float(theta),
+        self._check(self._L.casci_mlp_features(self._h, px, ps, float(theta),
                                                idx.ctypes.data, idx.size, F.ctypes.data))
         return F
 
@@ -397,7 +445,7 @@ class Context:
         return res
 
     def spin_square(self, C):
-        pc, mem = _ptr(C)
+        pc, mem = self._vec(C, self.dims["Ndet"], "C")
         s2 = ctypes.c_double()
         self._check(self._L.casci_spin_square(self._h, pc, ctypes.byref(s2), mem))
         return s2.value
@@ -417,8 +465,9 @@ class Context:
                            r_tol=r_tol, refine_rnorm=refine_rnorm, s2_penalty=s2_penalty, progress=progress,
                            graph=graph, buffer_roots=buffer_roots)
         if guess is not None:
-            gp, gm = _ptr(guess)
-            o.guess, o.nguess, o.guess_mem = gp, int(guess.shape[0]), gm
+            ng = int(guess.shape[0])
+            gp, gm = self._vec(guess, ng * self.dims["Ndet"], "guess")
+            o.guess, o.nguess, o.guess_mem = gp, ng, gm
         info = DavidsonInfo()
         hist = None
         if history:
@@ -430,7 +479,7 @@ class Context:
         vec = None
         if vectors_out is not None:
             vec = vectors_out
-            vp, vm = _ptr(vec)
+            vp, vm = self._vec(vec, int(nroots) * self.dims["Ndet"], "vectors_out")
         elif vectors:
             d = self.dims
             vec = np.zeros((nroots, d["Na"], d["Nb"]))

@@ -123,6 +123,7 @@ struct casci_ctx {
 
     // workspaces
     DBuf d_t1, d_t2, d_t3, d_vin, d_vout, d_work, d_small, d_clp, d_c32;
+    DBuf d_rowmax;  // max_c |C(J, c)| per alpha string: bound of the FP64 alpha-beta fixed-point sums
 
     // learned preconditioner parameters (FP32, MLP_NPARAM values)
     DBuf d_mlp, d_mlp_m, d_mlp_v, d_mlp_g, d_mlp_part, d_mlp_perm, d_mlp_sse, d_mlp_idx;
@@ -230,7 +231,7 @@ extern "C" void casci_destroy(casci_ctx* ctx)
                         &ctx->d_work, &ctx->d_small, &ctx->d_vt_sym_lp[0], &ctx->d_vt_sym_lp[1],
                         &ctx->d_vt_full_lp[0], &ctx->d_vt_full_lp[1], &ctx->d_clp, &ctx->d_c32, &ctx->d_t3,
                         &ctx->d_mlp, &ctx->d_mlp_m, &ctx->d_mlp_v, &ctx->d_mlp_g, &ctx->d_mlp_part,
-                        &ctx->d_mlp_perm, &ctx->d_mlp_sse, &ctx->d_mlp_idx};
+                        &ctx->d_mlp_perm, &ctx->d_mlp_sse, &ctx->d_mlp_idx, &ctx->d_rowmax};
         for (auto& gr : ctx->graphs) (void)hipGraphExecDestroy(gr.exec);
         ctx->graphs.clear();
         ctx->d_gin.release();
@@ -919,7 +920,9 @@ static int sigma_dev(casci_ctx* ctx, const double* C, double* S, int ab_prec, do
         double* T = ctx->d_t3.as<double>();
         if (!lowp) {
             const DBuf& vt = full ? ctx->d_vt_full : ctx->d_vt_sym;
-            HIPC(launch_ab_f64(p, vt.as<double>(), C, T, st));
+            HIPC(ctx->d_rowmax.ensure((size_t)Na * 8));
+            HIPC(launch_row_absmax(C, Na, Nb, ctx->d_rowmax.as<double>(), st));
+            HIPC(launch_ab_f64(p, vt.as<double>(), C, ctx->d_rowmax.as<double>(), T, st));
         } else {
             const DBuf* lp = full ? ctx->d_vt_full_lp : ctx->d_vt_sym_lp;
             AbReduce red;
@@ -1062,7 +1065,7 @@ static std::vector<void*> sigma_buffers(const casci_ctx* ctx)
             ctx->d_tg_sym.p, ctx->d_tg_full.p, ctx->red_sym.tab.p, ctx->red_sym.tinfo.p, ctx->red_full.tab.p,
             ctx->red_full.tinfo.p, ctx->d_la_j.p, ctx->d_la_pq.p, ctx->d_lb_j.p, ctx->d_bstr.p,
             ctx->d_pairs_sym.p, ctx->d_pairs_full.p, ctx->d_gin.p, ctx->d_gout.p, ctx->d_fa_c16.p,
-            ctx->d_fa_v32.p, ctx->d_fb_c16.p, ctx->d_fb_v32.p};
+            ctx->d_fa_v32.p, ctx->d_fb_c16.p, ctx->d_fb_v32.p, ctx->d_rowmax.p};
 }
 
 // sigma_dev replayed from a captured HIP graph: one launch per build instead
@@ -1234,12 +1237,17 @@ static int check_vec_args(casci_ctx* ctx, const void* C, const void* S, int dtyp
     return CASCI_OK;
 }
 
-extern "C" int casci_sigma(casci_ctx* ctx, const void* C, void* sigma, int dtype, int ab_prec, int mem)
+// sigma of a host or device vector (FP64 or FP32 storage); parity != 0
+// declares C = parity C^T (nalpha = nbeta) and takes the one-gather path
+static int sigma_impl(casci_ctx* ctx, const void* C, void* sigma, int dtype, int ab_prec, int parity, int mem)
 {
     if (!ctx) return CASCI_E_ARG;
     CHECK_RC(check_vec_args(ctx, C, sigma, dtype, ab_prec, mem));
     if (!ctx->has_ints) return ctx->fail(CASCI_E_STATE, "set_integrals first");
     if (!ctx->has_strings) return ctx->fail(CASCI_E_STATE, "build_strings first");
+    if (parity != 0 && parity != 1 && parity != -1) return ctx->fail(CASCI_E_ARG, "parity must be +1 or -1");
+    if (parity != 0 && ctx->na != ctx->nb) return ctx->fail(CASCI_E_ARG, "parity needs nalpha == nbeta");
+    if (parity != 0 && dtype != CASCI_F64) return ctx->fail(CASCI_E_ARG, "parity needs FP64 storage");
     CHECK_RC(need_device(ctx));
     DeviceGuard g(ctx->device);
     CHECK_RC(ensure_prepared(ctx, 0.0));
@@ -1270,7 +1278,7 @@ extern "C" int casci_sigma(casci_ctx* ctx, const void* C, void* sigma, int dtype
             HIPC(launch_convert_f32_to_f64(src, ctx->d_vin.as<double>(), (int64_t)Nd, st));
         }
     }
-    CHECK_RC(sigma_dev(ctx, cin, sout, ab_prec, 0.0));
+    CHECK_RC(sigma_dev(ctx, cin, sout, ab_prec, 0.0, parity));
     if (!(dtype == CASCI_F64 && mem == CASCI_MEM_DEVICE)) {
         if (dtype == CASCI_F64) {
             HIPC(hipMemcpyAsync(sigma, sout, Nd * 8, hipMemcpyDeviceToHost, st));
@@ -1283,6 +1291,18 @@ extern "C" int casci_sigma(casci_ctx* ctx, const void* C, void* sigma, int dtype
         if (mem == CASCI_MEM_HOST) HIPC(hipStreamSynchronize(st));
     }
     return CASCI_OK;
+}
+
+extern "C" int casci_sigma(casci_ctx* ctx, const void* C, void* sigma, int dtype, int ab_prec, int mem)
+{
+    return sigma_impl(ctx, C, sigma, dtype, ab_prec, 0, mem);
+}
+
+extern "C" int casci_sigma_parity(casci_ctx* ctx, const double* C, double* sigma, int ab_prec, int parity, int mem)
+{
+    if (!ctx) return CASCI_E_ARG;
+    if (parity == 0) return ctx->fail(CASCI_E_ARG, "parity must be +1 or -1");
+    return sigma_impl(ctx, C, sigma, CASCI_F64, ab_prec, parity, mem);
 }
 
 // small device scratch: reduction partials + results
@@ -1341,7 +1361,9 @@ static int spin_square_dev(casci_ctx* ctx, const double* C, double* s2)
         HIPC(hipMemsetAsync(ctx->d_t2.p, 0, (size_t)ctx->Nd * 8, st));
         CHECK_RC(ensure_targets(ctx, true));
         AbParams p = ab_params(ctx, true);
-        HIPC(launch_ab_f64(p, ctx->d_vt_s2.as<double>(), C, ctx->d_t2.as<double>(), st));
+        HIPC(ctx->d_rowmax.ensure((size_t)ctx->Na * 8));
+        HIPC(launch_row_absmax(C, ctx->Na, ctx->Nb, ctx->d_rowmax.as<double>(), st));
+        HIPC(launch_ab_f64(p, ctx->d_vt_s2.as<double>(), C, ctx->d_rowmax.as<double>(), ctx->d_t2.as<double>(), st));
         std::vector<double> cs;
         CHECK_RC(dots(ctx, C, 1, ctx->d_t2.as<double>(), 1, cs));
         x = cs[0];
@@ -2288,14 +2310,12 @@ static int davidson_impl(casci_ctx* ctx, int nroots, double tol, const casci_dav
     std::vector<double> s2v(kreq, 0.0);
     if (vectors || info) {
         for (int j = 0; j < kreq; ++j) {
-            // phase: largest-|c| entry positive (ties: lowest index)
-            std::vector<double> hv(Nd);
-            HIPC(hipMemcpyAsync(hv.data(), vX(j), vb, hipMemcpyDeviceToHost, st));
+            // phase: largest-|c| entry positive (ties: lowest index), found on the device
+            double am[2];
+            HIPC(launch_absmax(vX(j), Nd, ctx->d_work.as<double>(), dres, st));
+            HIPC(hipMemcpyAsync(am, dres, sizeof(am), hipMemcpyDeviceToHost, st));
             HIPC(hipStreamSynchronize(st));
-            int64_t best = 0;
-            for (int64_t i = 1; i < Nd; ++i)
-                if (std::fabs(hv[i]) > std::fabs(hv[best])) best = i;
-            if (hv[best] < 0) HIPC(launch_scale(vX(j), -1.0, Nd, st));
+            if (am[0] < 0) HIPC(launch_scale(vX(j), -1.0, Nd, st));
             if (info) CHECK_RC(spin_square_dev(ctx, vX(j), &s2v[j]));
         }
         if (vectors)
@@ -2538,6 +2558,8 @@ extern "C" int casci_mlp_features(casci_ctx* ctx, const double* x, const double*
     if (!x || !sx || !idx || !F || m < 0) return ctx->fail(CASCI_E_ARG, "bad arguments");
     if (!ctx->has_ints) return ctx->fail(CASCI_E_STATE, "set_integrals first");
     if (!ctx->has_strings) return ctx->fail(CASCI_E_STATE, "build_strings first");
+    for (int i = 0; i < m; ++i)
+        if (idx[i] < 0 || idx[i] >= ctx->Nd) return ctx->fail(CASCI_E_ARG, "determinant index out of range");
     CHECK_RC(need_device(ctx));
     DeviceGuard g(ctx->device);
     CHECK_RC(ensure_prepared(ctx, ctx->prepared ? ctx->prepared_lambda : 0.0));

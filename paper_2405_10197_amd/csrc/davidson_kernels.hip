@@ -243,4 +243,78 @@ hipError_t launch_scale(double* x, double a, int64_t n, hipStream_t st)
     return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// position of the largest |x_i| (ties: the lowest index), for the phase of a
+// converged vector: stage 1 takes one contiguous range per block, stage 2 one
+// wave over the partials (both orders fixed)
+// ---------------------------------------------------------------------------
+__device__ inline void absmax_pick(double& a, int64_t& i, double b, int64_t j)
+{
+    // larger |x| wins; an equal one with a lower index wins
+    if (b > a || (b == a && j < i)) {
+        a = b;
+        i = j;
+    }
+}
+
+__global__ __launch_bounds__(RED_THREADS) void k_absmax_partial(const double* __restrict__ x, int64_t n,
+                                                                int nblk, double* __restrict__ pv,
+                                                                int64_t* __restrict__ pi)
+{
+    __shared__ double sv[RED_THREADS];
+    __shared__ int64_t si[RED_THREADS];
+    const int64_t per = (n + nblk - 1) / nblk;
+    const int64_t lo = (int64_t)blockIdx.x * per, hi = min(n, lo + per);
+    double a = -1.0;
+    int64_t ai = INT64_MAX;
+    for (int64_t k = lo + threadIdx.x; k < hi; k += RED_THREADS) absmax_pick(a, ai, fabs(x[k]), k);
+    sv[threadIdx.x] = a;
+    si[threadIdx.x] = ai;
+    __syncthreads();
+    for (int st = RED_THREADS / 2; st > 0; st >>= 1) {
+        if ((int)threadIdx.x < st) {
+            double b = sv[threadIdx.x];
+            int64_t bi = si[threadIdx.x];
+            absmax_pick(b, bi, sv[threadIdx.x + st], si[threadIdx.x + st]);
+            sv[threadIdx.x] = b;
+            si[threadIdx.x] = bi;
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        pv[blockIdx.x] = sv[0];
+        pi[blockIdx.x] = si[0];
+    }
+}
+
+// out[0] = x at the position, out[1] = the position (as a double: exact below 2^53)
+__global__ __launch_bounds__(64) void k_absmax_final(const double* __restrict__ x, const double* __restrict__ pv,
+                                                     const int64_t* __restrict__ pi, int nblk,
+                                                     double* __restrict__ out)
+{
+    double a = -1.0;
+    int64_t ai = INT64_MAX;
+    for (int b = threadIdx.x; b < nblk; b += 64) absmax_pick(a, ai, pv[b], pi[b]);
+    for (int off = 32; off > 0; off >>= 1) {
+        const double b = __shfl_xor(a, off);
+        const int64_t bi = __shfl_xor(ai, off);
+        absmax_pick(a, ai, b, bi);
+    }
+    if (threadIdx.x == 0) {
+        out[0] = ai == INT64_MAX ? 0.0 : x[ai];
+        out[1] = ai == INT64_MAX ? -1.0 : (double)ai;
+    }
+}
+
+hipError_t launch_absmax(const double* x, int64_t n, double* work, double* out, hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    const int nblk = red_blocks(n);
+    double* pv = work;
+    int64_t* pi = reinterpret_cast<int64_t*>(work + RED_BLOCKS);
+    hipLaunchKernelGGL(k_absmax_partial, dim3(nblk), dim3(RED_THREADS), 0, st, x, n, nblk, pv, pi);
+    hipLaunchKernelGGL(k_absmax_final, dim3(1), dim3(64), 0, st, x, pv, pi, nblk, out);
+    return hipGetLastError();
+}
+
 }  // namespace casci

@@ -54,7 +54,7 @@ hipError_t launch_pspace_h(int n, int P, const int64_t* dets, int64_t Nb, const 
 // out[idx[i]] = v[i]
 hipError_t launch_scatter_values(const int64_t* idx, const double* v, int P, double* out, hipStream_t st);
 
-// sigma_kernels.hip
+// sigma_kernels.hip, ab_*.hip
 // A same-spin operator in row form: r entries per row, int32 columns and
 // FP64 values; optional compact copies (16-bit columns when there are fewer
 // than 65536 strings, FP32 values) that the gathers use when present.
@@ -130,13 +130,25 @@ struct AbReduce {
 int abl_waves(int Mp);
 // sigma(Ia, :) += alpha-beta term; Vt[pq][Mp] in the arithmetic's type
 // (prec 1: float, FP32 MFMA; prec 2: bf16, BF16 MFMA; both accumulate in FP32)
-hipError_t launch_ab_f64(const AbParams& p, const double* Vt, const double* C, double* sigma,
-                         hipStream_t st);
+// FP64: fixed-point (order-independent) accumulation; rowmax[Na] = max_c |C(J, c)|
+// from launch_row_absmax bounds the partial sums
+hipError_t launch_ab_f64(const AbParams& p, const double* Vt, const double* C, const double* rowmax,
+                         double* sigma, hipStream_t st);
+hipError_t launch_row_absmax(const double* C, int64_t rows, int64_t cols, double* out, hipStream_t st);
 hipError_t launch_ab_lowp(const AbParams& p, const AbReduce& r, int prec, const void* Vt, const void* Cs,
                           int64_t ldc, double* sigma, hipStream_t st);
 // same, for an FP32 sigma (FP32-storage builds)
 hipError_t launch_ab_lowp(const AbParams& p, const AbReduce& r, int prec, const void* Vt, const void* Cs,
                           int64_t ldc, float* sigma, hipStream_t st);
+// per-precision instances (ab_lowp_{f32,bf16}_{d,f}.hip)
+hipError_t launch_ab_lowp_f32(const AbParams& p, const AbReduce& r, const void* Vt, const void* Cs, int64_t ldc,
+                              double* sigma, hipStream_t st);
+hipError_t launch_ab_lowp_f32(const AbParams& p, const AbReduce& r, const void* Vt, const void* Cs, int64_t ldc,
+                              float* sigma, hipStream_t st);
+hipError_t launch_ab_lowp_bf16(const AbParams& p, const AbReduce& r, const void* Vt, const void* Cs, int64_t ldc,
+                               double* sigma, hipStream_t st);
+hipError_t launch_ab_lowp_bf16(const AbParams& p, const AbReduce& r, const void* Vt, const void* Cs, int64_t ldc,
+                               float* sigma, hipStream_t st);
 // padded row stride of the low-precision copy of C, and the conversion itself
 int64_t lowp_ld(int prec, int64_t cols);
 hipError_t launch_convert_lowp(int prec, const double* C, void* out, int64_t rows, int64_t cols,
@@ -163,6 +175,9 @@ hipError_t launch_residual(const double* X, const double* SX, int64_t ld, int k,
 hipError_t launch_precondition(const double* X, const double* SX, double theta, double eps,
                                const double* diag, int64_t len, double* T, hipStream_t st);
 hipError_t launch_scale(double* x, double a, int64_t n, hipStream_t st);
+// out[0] = x_i and out[1] = i for the largest |x_i| (ties: lowest i); work holds
+// 2 * 512 doubles of partials
+hipError_t launch_absmax(const double* x, int64_t n, double* work, double* out, hipStream_t st);
 
 // mlp_kernels.hip (learned preconditioner)
 constexpr int MLP_IN = 8, MLP_HIDDEN = 64;

@@ -211,3 +211,88 @@ def test_sym_eig_arguments():
     A = np.array([[2.0, 99.0], [1.0, 2.0]])
     w, _ = casci.sym_eig(A)
     assert np.allclose(w, [1.0, 3.0], rtol=0, atol=1e-15)
+
+
+# --------------------------------------------------------------------------
+# the binding rejects wrong-sized, wrongly typed or misplaced buffers before
+# any library call (a wrong size would make the kernels run out of bounds)
+# --------------------------------------------------------------------------
+def _ctx633():
+    h, eri, _ = synth.integrals(6, 1)
+    c = vctx()
+    c.set_integrals(h, eri)
+    c.build_strings(3, 3, 6)
+    return c
+
+
+def test_binding_rejects_bad_vector_arguments():
+    c = _ctx633()
+    nd = c.dims["Ndet"]
+    with pytest.raises(ValueError):
+        c.sigma(np.zeros(nd - 1))
+    with pytest.raises(TypeError):
+        c.sigma(np.zeros(nd, dtype=np.int64))
+    with pytest.raises(ValueError):
+        c.sigma(np.zeros(nd), out=np.zeros(nd + 1))
+    with pytest.raises(ValueError):
+        c.sigma(np.zeros(nd), out=np.zeros(nd, dtype=np.float32))
+    with pytest.raises(ValueError):
+        c.sigma_parity(np.zeros(nd - 3), 1)
+    with pytest.raises(TypeError):
+        c.sigma_parity(np.zeros(nd, dtype=np.float32), 1)
+    with pytest.raises(ValueError):
+        c.diagonal(out=np.zeros(nd + 5))
+    with pytest.raises(TypeError):
+        c.diagonal(out=np.zeros(nd, dtype=np.float32))
+    with pytest.raises(ValueError):
+        c.spin_square(np.zeros(2 * nd))
+    with pytest.raises(ValueError):
+        c.davidson(2, 1e-8, guess=np.zeros((2, nd - 1)))
+    with pytest.raises(ValueError):
+        c.davidson(2, 1e-8, vectors_out=np.zeros((1, nd)))
+    with pytest.raises(ValueError):
+        c.mlp_train(np.zeros((10, 8), dtype=np.float32), np.zeros(9, dtype=np.float32))
+    with pytest.raises(TypeError):
+        c.mlp_train(np.zeros((10, 8)), np.zeros(10, dtype=np.float32))
+
+
+def test_binding_rejects_host_arrays_where_device_tensors_are_needed():
+    c = _ctx633()
+    nd = c.dims["Ndet"]
+    x = np.zeros(nd)
+    with pytest.raises(ValueError):
+        c.mlp_features(x, x, 0.0, [0, 1])
+
+
+def test_mlp_features_index_range_checked_in_the_abi(L):
+    c = _ctx633()
+    nd = c.dims["Ndet"]
+    F = np.zeros((2, 8), dtype=np.float32)
+    for bad in ([0, nd], [-1, 3]):
+        idx = np.array(bad, dtype=np.int64)
+        # non-null stand-in pointers: the range check comes before any device work
+        rc = L.casci_mlp_features(c._h, ctypes.c_void_p(16), ctypes.c_void_p(16), 0.0, idx.ctypes.data, 2,
+                                  F.ctypes.data)
+        assert rc == casci.E_ARG
+        assert "out of range" in c.last_error()
+
+
+def test_sigma_parity_argument_checks(L):
+    c = _ctx633()
+    nd = c.dims["Ndet"]
+    C = np.zeros(nd)
+    S = np.zeros(nd)
+    assert L.casci_sigma_parity(c._h, C.ctypes.data, S.ctypes.data, casci.F64, 0, casci.MEM_HOST) == casci.E_ARG
+    assert L.casci_sigma_parity(c._h, C.ctypes.data, S.ctypes.data, casci.F64, 2, casci.MEM_HOST) == casci.E_ARG
+    # validate-only: a valid call stops at the device check
+    assert L.casci_sigma_parity(c._h, C.ctypes.data, S.ctypes.data, casci.BF16, -1,
+                                casci.MEM_HOST) == casci.E_UNSUPPORTED
+    h, eri, _ = synth.integrals(5, 2)
+    d = vctx()
+    d.set_integrals(h, eri)
+    d.build_strings(3, 2, 5)
+    nd = d.dims["Ndet"]
+    C = np.zeros(nd)
+    S = np.zeros(nd)
+    assert L.casci_sigma_parity(d._h, C.ctypes.data, S.ctypes.data, casci.F64, 1, casci.MEM_HOST) == casci.E_ARG
+    assert "nalpha == nbeta" in d.last_error()

@@ -164,11 +164,19 @@ def test_sigma_is_reproducible(torch):
     c, h, eri = make(10, 5, 5, 9)
     d = c.dims
     Ct = torch.from_numpy(synth.ci_vector(d["Na"], d["Nb"], 1)[0]).cuda()
-    a = c.sigma(Ct)
-    b = c.sigma(Ct)
-    torch.cuda.synchronize()
-    # the alpha-beta scatter uses LDS atomics: equal up to rounding order
-    assert (a - b).abs().max().item() < 1e-13
+    for prec in ("f64", "f32", "bf16"):
+        a = c.sigma(Ct, ab_prec=prec)
+        b = c.sigma(Ct, ab_prec=prec)
+        torch.cuda.synchronize()
+        # fixed summation orders everywhere (the FP64 alpha-beta scatter adds in
+        # fixed point): bitwise equal
+        assert torch.equal(a, b), prec
+    # and independent of the autotuned strip width of the same-spin gathers
+    ref = c.sigma(Ct)
+    for lpe in (16, 32, 64, 128):
+        c.set_tuning(lpe, lpe)
+        assert torch.equal(c.sigma(Ct), ref), lpe
+    c.set_tuning(0, 0)
 
 
 # --------------------------------------------------------------------------

@@ -328,3 +328,24 @@ def test_oracle_reproduces_stored_fixtures():
     x = synth.ci_vector(10, 5, 11)[0]
     s = oracle.sigma(h, eri, 3, 1, x).ravel()
     assert np.abs(s - np.array(fx["cas5_31_seed7_sigma"]["sigma"])).max() < 1e-12
+
+
+def test_single_list_in_c_matches_the_python_construction():
+    """The C list builder used for the large string sets (n = 16, 18) gives the
+    same entries, order and signs as the Python operator-by-operator one."""
+    for n, ne in [(1, 1), (2, 1), (5, 3), (6, 3), (8, 4), (9, 5), (10, 5), (7, 0), (4, 4), (11, 3)]:
+        a = oracle.single_list(n, ne)
+        b = oracle.single_list_c(n, ne)
+        for x, y in zip(a, b):
+            assert np.array_equal(x, y), (n, ne)
+
+
+def test_h_rows_match_the_dense_matrix():
+    h, eri, _ = synth.integrals(6, 3)
+    H = oracle.hamiltonian(h, eri, 3, 2, 0.25)
+    rows = [0, 7, 55, H.shape[0] - 1]
+    for r, (c, v) in zip(rows, oracle.h_rows(h, eri, 3, 2, rows, 0.25)):
+        nz = np.nonzero(H[r])[0]
+        assert set(nz.tolist()) <= set(c.tolist())
+        assert np.all(np.diff(c) > 0)
+        assert np.abs(H[r, c] - v).max() < 1e-14
