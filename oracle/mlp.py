@@ -22,8 +22,12 @@ r = H x - theta x (d = H_II, N = number of determinants):
 Training target for iteration k of a solve converging to x*:
     t_I = (x* - x_k)_I sqrt(N) / |x* - x_k|, with x* signed so that x* . x_k > 0.
 
-Pins (tests): finite differences of the loss for the gradient, and special
-weights for which the network reduces to closed forms.
+Pins (tests): finite differences of the loss for the gradient, special
+weights for which the network reduces to closed forms, and for the features:
+rows of a CAS(2,2) case worked out by hand (including both signs of the
+clamp), the inverse maps that recover d, r, x and -r/(d - theta) from
+f0..f3 and f7, excitation counts and open-shell fractions of hand-listed
+strings with unequal divisors, and the clamp boundary.
 """
 from __future__ import annotations
 

@@ -656,10 +656,12 @@ static AbParams ab_params(const casci_ctx* ctx, bool full)
 }
 
 // scatter-target table of the pair set (needs the strings, lists and pairs on device)
-static int ensure_targets(casci_ctx* ctx, bool full)
+static int ensure_targets(casci_ctx* ctx, bool full, bool may_alloc = true)
 {
     bool& have = full ? ctx->have_tg_full : ctx->have_tg_sym;
     if (have) return CASCI_OK;
+    if (!may_alloc)
+        return ctx->fail(CASCI_E_STATE, "alpha-beta scatter targets not built: run casci_sigma once first");
     DBuf& tg = full ? ctx->d_tg_full : ctx->d_tg_sym;
     AbParams p = ab_params(ctx, full);
     HIPC(tg.ensure((size_t)ctx->Nb * p.Mp * 4));
@@ -671,9 +673,11 @@ static int ensure_targets(casci_ctx* ctx, bool full)
 
 // Target-grouped table of the low-precision alpha-beta kernel (layout in
 // internal.h, AbReduce), built on the host from the target table.
-static int ensure_reduce(casci_ctx* ctx, bool full, AbReduce* out)
+static int ensure_reduce(casci_ctx* ctx, bool full, AbReduce* out, bool may_alloc = true)
 {
     casci_ctx::Reduce& R = full ? ctx->red_full : ctx->red_sym;
+    if (!R.have && !may_alloc)
+        return ctx->fail(CASCI_E_STATE, "alpha-beta reduction table not built: run casci_sigma once first");
     if (!R.have) {
         CHECK_RC(ensure_targets(ctx, full));
         const int Mp = full ? ctx->Mp_full : ctx->Mp_sym;
@@ -825,11 +829,12 @@ static SsOp ss_op(const casci_ctx* ctx, int spin)
 // Autotuner of the same-spin gather: the strip width (lanes per gathered
 // entry, 16/32/64) that is fastest for this string space, timed once per
 // (device, norb, nalpha, nbeta, input precision) on the context's stream and
-// cached for the process.
+// cached for the process. The gather's summation order does not depend on
+// the width, so the choice changes the speed only, never the result.
 static std::mutex g_tune_mu;
 static std::map<std::array<int, 5>, int> g_tune;
 
-static int autotune_gather(casci_ctx* ctx, bool lowp, const double* C, int64_t ld32)
+static int autotune_gather(casci_ctx* ctx, bool lowp, const double* C, const float* C32, int64_t ld32)
 {
     const std::array<int, 5> key = {ctx->device, ctx->norb, ctx->na, ctx->nb, lowp ? 1 : 0};
     {
@@ -857,8 +862,8 @@ static int autotune_gather(casci_ctx* ctx, bool lowp, const double* C, int64_t l
     for (int lpe : {16, 32, 64, 128}) {
         auto run = [&]() {
             if (lowp)
-                return launch_ss_gather_f32in(ss_op(ctx, 0), nt, ctx->Nb, ctx->d_c32.as<float>(), ld32,
-                                              ctx->d_t1.as<double>(), 0.0, 0, st, lpe);
+                return launch_ss_gather_f32in(ss_op(ctx, 0), nt, ctx->Nb, C32, ld32, ctx->d_t1.as<double>(), 0.0,
+                                              0, st, lpe);
             return launch_ss_gather_f64(ss_op(ctx, 0), nt, ctx->Nb, C, ctx->d_t1.as<double>(), 0.0, 0, st, lpe);
         };
         if ((err = run()) != hipSuccess) break;  // warm-up
@@ -882,8 +887,58 @@ static int autotune_gather(casci_ctx* ctx, bool lowp, const double* C, int64_t l
     return CASCI_OK;
 }
 
+// Vector-sized work buffers of one sigma build. sigma_dev fills them from the
+// context's own (growing) buffers, or takes them from the caller: the
+// allocation-free entry point passes slices of the library's static scratch.
+struct SigmaWork {
+    double* t1 = nullptr;      // C^T (general vectors, nbeta > 0): Nd
+    double* t2 = nullptr;      // beta-beta gather on C^T: Nd
+    double* t3 = nullptr;      // alpha-beta term: Nd
+    double* rowmax = nullptr;  // FP64 alpha-beta: max |C(J, :)| per alpha string: Na
+    float* c32 = nullptr;      // FP32 copy of C (low-precision builds): Na x lowp_ld(1, Nb)
+    void* clp = nullptr;       // BF16 copy of C (BF16 builds): Na x lowp_ld(2, Nb)
+};
+
+// bytes of the work buffers one build needs (each piece 256-byte aligned), and
+// their placement in one block of memory
+static size_t sigma_work_layout(const casci_ctx* ctx, int ab_prec, int parity, unsigned char* base, SigmaWork* w)
+{
+    const int64_t Na = ctx->Na, Nb = ctx->Nb, Nd = ctx->Nd;
+    const bool lowp = ab_prec != CASCI_F64;
+    const bool has_ab = ctx->na > 0 && ctx->nb > 0;
+    size_t off = 0;
+    auto take = [&](size_t bytes) -> unsigned char* {
+        unsigned char* p = base ? base + off : nullptr;
+        off += (bytes + 255) / 256 * 256;
+        return p;
+    };
+    SigmaWork x;
+    if (parity == 0 && ctx->nb > 0) {
+        x.t1 = (double*)take((size_t)Nd * 8);
+        x.t2 = (double*)take((size_t)Nd * 8);
+    }
+    if (has_ab) x.t3 = (double*)take((size_t)Nd * 8);
+    if (has_ab && !lowp) x.rowmax = (double*)take((size_t)Na * 8);
+    if (lowp) x.c32 = (float*)take((size_t)Na * lowp_ld(1, Nb) * 4);
+    if (lowp && has_ab && ab_prec == CASCI_BF16) x.clp = take((size_t)Na * lowp_ld(2, Nb) * 2);
+    if (w) *w = x;
+    return off;
+}
+
+// sigma = (H + lambda S^2) C on device vectors (FP64 storage).
+// parity = +1 / -1 declares C = +-C^T (nalpha = nbeta only): transposition
+// commutes with H, so sigma_bb = parity * sigma_aa^T and one same-spin gather
+// serves both spins. parity = 0: general C. ab_prec != F64 also reads the
+// same-spin gather operand from an FP32 copy of C (accumulation stays FP64).
+// The alpha-beta contraction writes its own buffer, added in by the final pass
+// (with parity fused into the S + p S^T symmetrisation). Running it on a
+// second stream beside the gathers was measured not to help: each slows the
+// other by as much as the overlap gains.
+// work = nullptr: the context's buffers (allocated or grown as needed, the
+// tables built, the gather autotuned). work given: nothing is allocated; the
+// tables must exist and the gather uses its tuned (or default) strip width.
 static int sigma_dev(casci_ctx* ctx, const double* C, double* S, int ab_prec, double lambda,
-                     int parity = 0)
+                     int parity = 0, const SigmaWork* work = nullptr)
 {
     hipStream_t st = ctx->stream;
     const int64_t Na = ctx->Na, Nb = ctx->Nb, Nd = ctx->Nd;
@@ -892,8 +947,36 @@ static int sigma_dev(casci_ctx* ctx, const double* C, double* S, int ab_prec, do
     const bool prof = ctx->profiling;
     const bool lowp = ab_prec != CASCI_F64;
     const bool has_ab = ctx->na > 0 && ctx->nb > 0;
+    const bool alloc = work == nullptr;
     if (parity != 0 && ctx->na != ctx->nb) return ctx->fail(CASCI_E_ARG, "parity needs nalpha == nbeta");
     set_launch_reason("");
+    SigmaWork w;
+    if (alloc) {
+        if (parity == 0 && ctx->nb > 0) {
+            HIPC(ctx->d_t1.ensure((size_t)Nd * 8));
+            HIPC(ctx->d_t2.ensure((size_t)Nd * 8));
+            w.t1 = ctx->d_t1.as<double>();
+            w.t2 = ctx->d_t2.as<double>();
+        }
+        if (has_ab) {
+            HIPC(ctx->d_t3.ensure((size_t)Nd * 8));
+            w.t3 = ctx->d_t3.as<double>();
+        }
+        if (has_ab && !lowp) {
+            HIPC(ctx->d_rowmax.ensure((size_t)Na * 8));
+            w.rowmax = ctx->d_rowmax.as<double>();
+        }
+        if (lowp) {
+            HIPC(ctx->d_c32.ensure((size_t)Na * lowp_ld(1, Nb) * 4));
+            w.c32 = ctx->d_c32.as<float>();
+        }
+        if (lowp && has_ab && ab_prec == CASCI_BF16) {
+            HIPC(ctx->d_clp.ensure((size_t)Na * lowp_ld(2, Nb) * 2));
+            w.clp = ctx->d_clp.p;
+        }
+    } else {
+        w = *work;
+    }
     auto mark = [&](int i, hipStream_t s) -> int {
         if (prof) HIPC(hipEventRecord(ctx->pev[i], s));
         return CASCI_OK;
@@ -902,60 +985,51 @@ static int sigma_dev(casci_ctx* ctx, const double* C, double* S, int ab_prec, do
     // inputs in the arithmetic's types (stream order: before the fork)
     const int64_t ld32 = lowp_ld(1, Nb), ld16 = lowp_ld(2, Nb);
     if (lowp) {
-        HIPC(ctx->d_c32.ensure((size_t)Na * ld32 * 4));
-        HIPC(launch_convert_lowp(1, C, ctx->d_c32.p, Na, Nb, ld32, st));
-        if (has_ab && ab_prec == CASCI_BF16) {
-            HIPC(ctx->d_clp.ensure((size_t)Na * ld16 * 2));
-            HIPC(launch_convert_lowp(2, C, ctx->d_clp.p, Na, Nb, ld16, st));
-        }
+        HIPC(launch_convert_lowp(1, C, w.c32, Na, Nb, ld32, st));
+        if (has_ab && ab_prec == CASCI_BF16) HIPC(launch_convert_lowp(2, C, w.clp, Na, Nb, ld16, st));
     }
-    // alpha-beta, overwriting d_t3
+    // alpha-beta, overwriting t3
     if (has_ab) {
-        HIPC(ctx->d_t3.ensure((size_t)Nd * 8));
         CHECK_RC(mark(3, st));
         const bool full = lambda != 0.0;
-        CHECK_RC(ensure_targets(ctx, full));
+        CHECK_RC(ensure_targets(ctx, full, alloc));
         AbParams p = ab_params(ctx, full);
         p.overwrite = 1;
-        double* T = ctx->d_t3.as<double>();
         if (!lowp) {
             const DBuf& vt = full ? ctx->d_vt_full : ctx->d_vt_sym;
-            HIPC(ctx->d_rowmax.ensure((size_t)Na * 8));
-            HIPC(launch_row_absmax(C, Na, Nb, ctx->d_rowmax.as<double>(), st));
-            HIPC(launch_ab_f64(p, vt.as<double>(), C, ctx->d_rowmax.as<double>(), T, st));
+            HIPC(launch_row_absmax(C, Na, Nb, w.rowmax, st));
+            HIPC(launch_ab_f64(p, vt.as<double>(), C, w.rowmax, w.t3, st));
         } else {
             const DBuf* lp = full ? ctx->d_vt_full_lp : ctx->d_vt_sym_lp;
             AbReduce red;
-            CHECK_RC(ensure_reduce(ctx, full, &red));
+            CHECK_RC(ensure_reduce(ctx, full, &red, alloc));
             if (ab_prec == CASCI_F32)
-                HIPC(launch_ab_lowp(p, red, 1, lp[0].p, ctx->d_c32.p, ld32, T, st));
+                HIPC(launch_ab_lowp(p, red, 1, lp[0].p, w.c32, ld32, w.t3, st));
             else
-                HIPC(launch_ab_lowp(p, red, 2, lp[1].p, ctx->d_clp.p, ld16, T, st));
+                HIPC(launch_ab_lowp(p, red, 2, lp[1].p, w.clp, ld16, w.t3, st));
         }
         CHECK_RC(mark(4, st));
     }
     const double s_aa = parity != 0 ? 0.5 * shift : shift;  // halved: S + p S^T doubles it
-    if (ctx->tune_lpe[lowp ? 1 : 0] == 0) CHECK_RC(autotune_gather(ctx, lowp, C, ld32));
+    // the strip width changes only the speed, not the sums (fixed summation order)
+    if (alloc && ctx->tune_lpe[lowp ? 1 : 0] == 0) CHECK_RC(autotune_gather(ctx, lowp, C, w.c32, ld32));
     const int lpe = ctx->tune_lpe[lowp ? 1 : 0];
     if (lowp)
-        HIPC(launch_ss_gather_f32in(ss_op(ctx, 0), Na, Nb, ctx->d_c32.as<float>(), ld32, S, s_aa, 0, st, lpe));
+        HIPC(launch_ss_gather_f32in(ss_op(ctx, 0), Na, Nb, w.c32, ld32, S, s_aa, 0, st, lpe));
     else
         HIPC(launch_ss_gather_f64(ss_op(ctx, 0), Na, Nb, C, S, s_aa, 0, st, lpe));
     CHECK_RC(mark(1, st));
     if (parity == 0 && ctx->nb > 0) {
-        HIPC(ctx->d_t1.ensure((size_t)Nd * 8));
-        HIPC(ctx->d_t2.ensure((size_t)Nd * 8));
         const bool same = ctx->nb == ctx->na;
-        HIPC(launch_transpose_f64(C, ctx->d_t1.as<double>(), Na, Nb, 0, 1.0, st));
-        HIPC(launch_ss_gather_f64(ss_op(ctx, 1), Nb, Na, ctx->d_t1.as<double>(), ctx->d_t2.as<double>(), 0.0, 0,
-                                  st, same && !lowp ? lpe : 0));
-        HIPC(launch_transpose_f64(ctx->d_t2.as<double>(), S, Nb, Na, 1, 1.0, st));
+        HIPC(launch_transpose_f64(C, w.t1, Na, Nb, 0, 1.0, st));
+        HIPC(launch_ss_gather_f64(ss_op(ctx, 1), Nb, Na, w.t1, w.t2, 0.0, 0, st, same && !lowp ? lpe : 0));
+        HIPC(launch_transpose_f64(w.t2, S, Nb, Na, 1, 1.0, st));
     }
     CHECK_RC(mark(2, st));
     if (parity != 0)
-        HIPC(launch_sym_add(S, Na, parity, 1.0, st, has_ab ? ctx->d_t3.as<double>() : nullptr));
+        HIPC(launch_sym_add(S, Na, parity, 1.0, st, has_ab ? w.t3 : nullptr));
     else if (has_ab)
-        HIPC(launch_axpby_f64(1.0, ctx->d_t3.as<double>(), 1.0, S, Nd, st));
+        HIPC(launch_axpby_f64(1.0, w.t3, 1.0, S, Nd, st));
     CHECK_RC(mark(5, st));
     if (prof) {
         HIPC(hipEventSynchronize(ctx->pev[5]));
