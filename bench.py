@@ -458,13 +458,18 @@ def headline(args):
     est = 0.8 * t_ref  # a step is the faster solve; refined by the measured steps
     times, ttt, infos, profs, Es = [], [], [], [], []
     ran_w = ran_t = 0
+    # Timed steps come first: one warm-up if the budget leaves room for it and a
+    # timed step, more only where every requested timed step still fits.
+    n_fit = int((budget_end - time.time()) // est)
+    w_plan = min(args.warmup, max(0, n_fit - args.steps), n_fit - 1)
+    if args.warmup > 0 and n_fit >= 2:
+        w_plan = max(w_plan, 1)
+    w_plan = max(w_plan, 0)
+    if w_plan < args.warmup:
+        log("[bench] budget: %d of %d warm-up steps (about %d steps fit)" % (w_plan, args.warmup, n_fit))
     while True:
         remaining = budget_end - time.time()
-        if ran_w < args.warmup:
-            if remaining < 2.0 * est:  # a warm-up must leave room for a timed step
-                log("[bench] budget: %d of %d warm-up steps" % (ran_w, args.warmup))
-                args.warmup = ran_w
-                continue
+        if ran_w < w_plan:
             warm = True
         elif ran_t < args.steps:
             if ran_t >= 1 and remaining < est:

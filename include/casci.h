@@ -273,14 +273,19 @@ int casci_batch_davidson(casci_ctx* const* ctxs, int count, int nroots, double t
 /*
  * Autotuner choice of the same-spin gather for this context's string space:
  * out[0] / out[1] = strip width code of the FP64 and of the FP32-input
- * gather: 16, 32 or 64 lanes per gathered entry with one column each, or 128
- * (64 lanes with two adjacent columns each); 0 until the first sigma build
- * in that precision.
+ * gather: 16, 32 or 64 lanes per gathered entry with one column each, 128
+ * (64 lanes with two adjacent columns each), or L * 100 + V for L lanes per
+ * entry with V adjacent columns each (1602, 3202; FP32 input also 1604, 3204,
+ * 6404); 0 until the first sigma build in that precision. The code changes
+ * only the speed: every width sums in the same order, so sigma is bitwise
+ * the same whichever is chosen.
  */
 int casci_get_tuning(casci_ctx* ctx, int* out);
 
-/* Override the autotuner: strip width code (16, 32, 64 or 128; 0 = autotune)
- * of the FP64 and of the FP32-input gather for this context. */
+/* Override the autotuner: strip width code (16, 32, 64, 128, 1602, 3202, 1604,
+ * 3204 or 6404 as above; 0 = autotune) of the FP64 and of the FP32-input gather
+ * for this context (a vector width the row stride does not allow falls back
+ * to one column per lane). */
 int casci_set_tuning(casci_ctx* ctx, int f64_lpe, int f32in_lpe);
 
 /*

@@ -74,25 +74,30 @@ __device__ inline void ab_load_targets(const AbParams& p, int64_t j0, int wave, 
     }
 }
 
-// fixed-point scatter-add of one 16x64 accumulator block into the LDS row chunk [lo, hi)
+// fixed-point scatter-add of one 16x64 accumulator block into the LDS row chunk
+// [lo, hi): all sixteen conversions first (independent, so they pipeline), then
+// the integer adds of the elements whose target lies in the chunk
 __device__ inline void ab_scatter_fixed(unsigned long long* sig, const d4 (&acc)[4], const i4 (&tgt)[4],
                                         int64_t lo, int64_t hi, double scale)
 {
+    long long q[4][4];
+    int off[4][4];
 #pragma unroll
     for (int ns = 0; ns < 4; ++ns) {
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
             const int32_t e = tgt[ns][v];
-            if (e != AB_NONE) {
-                const int64_t tgi = l1_index(e);
-                if (tgi >= lo && tgi < hi) {
-                    const double x = e >= 0 ? acc[ns][v] : -acc[ns][v];
-                    const long long q = __double2ll_rn(x * scale);
-                    atomicAdd(&sig[tgi - lo], (unsigned long long)q);
-                }
-            }
+            const int64_t tgi = l1_index(e);
+            const bool in = e != AB_NONE && tgi >= lo && tgi < hi;
+            off[ns][v] = in ? (int)(tgi - lo) : -1;
+            q[ns][v] = __double2ll_rn((e >= 0 ? acc[ns][v] : -acc[ns][v]) * scale);
         }
     }
+#pragma unroll
+    for (int ns = 0; ns < 4; ++ns)
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+            if (off[ns][v] >= 0) atomicAdd(&sig[off[ns][v]], (unsigned long long)q[ns][v]);
 }
 
 template <int KBMAX, int MT, int PF>

@@ -177,6 +177,7 @@ struct casci_ctx {
 
 static const char* kValidateOnly = "validate-only context: no device work is launched";
 
+
 // ---------------------------------------------------------------------------
 // context
 // ---------------------------------------------------------------------------
@@ -859,7 +860,12 @@ static int autotune_gather(casci_ctx* ctx, bool lowp, const double* C, const flo
     // timed on the first eighth of the rows (at least 2048): the same strips and
     // operator rows, a fraction of the cost on large spaces
     const int64_t nt = std::min<int64_t>(ctx->Na, std::max<int64_t>(2048, ctx->Na / 8));
-    for (int lpe : {16, 32, 64, 128}) {
+    static const int cand64[] = {16, 32, 64, 128, 1602, 3202};
+    static const int cand32[] = {16, 32, 64, 128, 1602, 3202, 1604, 3204, 6404};
+    const int* cand = lowp ? cand32 : cand64;
+    const int ncand = lowp ? 9 : 6;
+    for (int ci = 0; ci < ncand; ++ci) {
+        const int lpe = cand[ci];
         auto run = [&]() {
             if (lowp)
                 return launch_ss_gather_f32in(ss_op(ctx, 0), nt, ctx->Nb, C32, ld32, ctx->d_t1.as<double>(), 0.0,
@@ -1205,8 +1211,10 @@ extern "C" int casci_set_tuning(casci_ctx* ctx, int f64_lpe, int f32in_lpe)
 {
     if (!ctx) return CASCI_E_ARG;
     for (int v : {f64_lpe, f32in_lpe})
-        if (v != 0 && v != 16 && v != 32 && v != 64 && v != 128)
-            return ctx->fail(CASCI_E_ARG, "strip width code must be 0, 16, 32, 64 or 128");
+        if (v != 0 && v != 16 && v != 32 && v != 64 && v != 128 && v != 1602 && v != 3202 && v != 1604 &&
+            v != 3204 && v != 6404)
+            return ctx->fail(CASCI_E_ARG,
+                             "strip width code must be 0, 16, 32, 64, 128, 1602, 3202, 1604, 3204 or 6404");
     ctx->tune_lpe[0] = f64_lpe;
     ctx->tune_lpe[1] = f32in_lpe;
     ++ctx->gen;  // captured graphs hold the old choice

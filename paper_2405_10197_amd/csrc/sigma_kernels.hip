@@ -60,6 +60,10 @@ template <>
 struct Vec<double, 2> {
     using type = double2;
 };
+template <>
+struct Vec<float, 4> {
+    using type = float4;
+};
 
 __device__ inline float bcast_val(float v, int lane)
 {
@@ -92,7 +96,8 @@ __global__ __launch_bounds__(256) void k_ss_gather(const TC* __restrict__ col,
         const int64_t rb = t - strip * nrowblk;
         const int64_t I = rb * 4 + wave;
         if (I >= nrows) continue;
-        // this lane's VW consecutive columns (VW = 2 needs an even ldx: aligned pairs)
+        // this lane's VW consecutive columns (VW > 1 needs ldx % VW == 0: aligned
+        // 8- or 16-byte loads)
         const int64_t c = (strip * LPE + li) * VW;
         const bool full = c + VW <= ncols;
         const bool cok = c < ncols;
@@ -105,11 +110,12 @@ __global__ __launch_bounds__(256) void k_ss_gather(const TC* __restrict__ col,
             } else {
                 if (full) {
                     const VX v = *reinterpret_cast<const VX*>(src);
-                    out[0] = (double)v.x;
-                    out[1] = (double)v.y;
+                    const TX* e = reinterpret_cast<const TX*>(&v);
+#pragma unroll
+                    for (int u = 0; u < VW; ++u) out[u] = (double)e[u];
                 } else {
-                    out[0] = (double)src[0];
-                    out[1] = 0.0;
+#pragma unroll
+                    for (int u = 0; u < VW; ++u) out[u] = c + u < ncols ? (double)src[u] : 0.0;
                 }
             }
         };
@@ -198,13 +204,17 @@ static hipError_t ss_gather(const TC* col, const TV* val, int r, int64_t nrows,
     return hipGetLastError();
 }
 
-// strip width code: 16 / 32 / 64 lanes per entry with one column each, or 128
-// = 64 lanes with two adjacent columns each (needs an even row stride; an odd
-// one falls back to 64)
+// strip width code: 16 / 32 / 64 lanes per entry with one column each, 128 =
+// 64 lanes with two adjacent columns each, or LPE * 100 + VW for LPE lanes per
+// entry with VW adjacent columns each (1602, 3202: 16-byte loads of FP64 pairs
+// with 4 or 2 entries per wave-wide load; 1604, 3204, 6404: FP32 quadruples).
+// A vector width the row stride does not allow falls back to one column per
+// lane. The summation order is the same for every code.
 template <typename TX, typename TY, typename TC, typename TV>
 static hipError_t ss_gather_w(const TC* col, const TV* val, int r, int64_t nrows, int64_t ncols,
                               const TX* X, int64_t ldx, TY* Y, double shift, int acc, hipStream_t st, int lpe)
 {
+    constexpr bool f32 = sizeof(TX) == 4;
     switch (lpe) {
     case 16: return ss_gather<TX, TY, 16, 1>(col, val, r, nrows, ncols, X, ldx, Y, shift, acc, st);
     case 32: return ss_gather<TX, TY, 32, 1>(col, val, r, nrows, ncols, X, ldx, Y, shift, acc, st);
@@ -213,7 +223,24 @@ static hipError_t ss_gather_w(const TC* col, const TV* val, int r, int64_t nrows
     case 128:
         if (ldx % 2 != 0) return ss_gather<TX, TY, 64, 1>(col, val, r, nrows, ncols, X, ldx, Y, shift, acc, st);
         return ss_gather<TX, TY, 64, 2>(col, val, r, nrows, ncols, X, ldx, Y, shift, acc, st);
-    default: return invalid("same-spin gather: strip width code must be 16, 32, 64 or 128");
+    case 1602:
+        if (ldx % 2 != 0) return ss_gather<TX, TY, 16, 1>(col, val, r, nrows, ncols, X, ldx, Y, shift, acc, st);
+        return ss_gather<TX, TY, 16, 2>(col, val, r, nrows, ncols, X, ldx, Y, shift, acc, st);
+    case 3202:
+        if (ldx % 2 != 0) return ss_gather<TX, TY, 32, 1>(col, val, r, nrows, ncols, X, ldx, Y, shift, acc, st);
+        return ss_gather<TX, TY, 32, 2>(col, val, r, nrows, ncols, X, ldx, Y, shift, acc, st);
+    case 1604:
+    case 3204:
+    case 6404:
+        if constexpr (f32) {
+            if (ldx % 4 == 0) {
+                if (lpe == 1604) return ss_gather<TX, TY, 16, 4>(col, val, r, nrows, ncols, X, ldx, Y, shift, acc, st);
+                if (lpe == 3204) return ss_gather<TX, TY, 32, 4>(col, val, r, nrows, ncols, X, ldx, Y, shift, acc, st);
+                return ss_gather<TX, TY, 64, 4>(col, val, r, nrows, ncols, X, ldx, Y, shift, acc, st);
+            }
+        }
+        return ss_gather<TX, TY, 64, 1>(col, val, r, nrows, ncols, X, ldx, Y, shift, acc, st);
+    default: return invalid("same-spin gather: unknown strip width code");
     }
 }
 

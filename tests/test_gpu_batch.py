@@ -54,6 +54,9 @@ def test_graph_replay_reproduces_eager_solve(torch, prec):
     assert np.array_equal(E0, E1)
 
 
+WIDTHS = (16, 32, 64, 128, 1602, 3202, 1604, 3204, 6404)
+
+
 @pytest.mark.parametrize("n", [8, 9])
 def test_every_gather_width_matches_oracle(torch, n):
     """Each strip width the autotuner can pick (16/32/64 lanes per entry, or
@@ -66,17 +69,22 @@ def test_every_gather_width_matches_oracle(torch, n):
     x = synth.ci_vector(d["Na"], d["Nb"], 5)[0]
     ref = oracle.sigma(h, eri, na, nb, x)
     xt = torch.from_numpy(x).cuda()
-    for lpe in (16, 32, 64, 128):
+    first64 = first32 = None
+    for lpe in WIDTHS:
         c.set_tuning(lpe, lpe)
         s64 = c.sigma(xt).cpu().numpy()
         assert np.abs(s64 - ref).max() < 1e-11 * max(1.0, np.abs(ref).max())
         s32 = c.sigma(xt, ab_prec="f32").cpu().numpy()
         assert np.abs(s32 - ref).max() < 1e-5 * np.abs(ref).max()
+        # the same summation order for every width: bitwise the same results
+        first64 = s64 if first64 is None else first64
+        first32 = s32 if first32 is None else first32
+        assert np.array_equal(s64, first64) and np.array_equal(s32, first32), lpe
     c.set_tuning(0, 0)
     c.sigma(xt)
     c.sigma(xt, ab_prec="f32")
     t = c.tuning()
-    assert t["f64"] in (16, 32, 64, 128) and t["f32in"] in (16, 32, 64, 128)
+    assert t["f64"] in WIDTHS and t["f32in"] in WIDTHS
 
 
 def test_batch_matches_single_solves_and_oracle(torch):
