@@ -186,6 +186,29 @@ int casci_sigma(casci_ctx* ctx, const void* C, void* sigma, int dtype, int ab_pr
 int casci_sigma_parity(casci_ctx* ctx, const double* C, double* sigma, int ab_prec, int parity, int mem);
 
 /*
+ * Allocation-free sigma, for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): sigma = H C as casci_sigma / casci_sigma_parity compute it
+ * (parity 0: any C; parity +1 / -1: C = parity C^T, nalpha = nbeta), for FP64
+ * device vectors C and sigma (Na x Nb, row-major, on the context's device),
+ * ordered on the context stream. Its work buffers (the transposes, the
+ * alpha-beta term, the row maxima and the low-precision copies of C) live in
+ * a 64 MiB static device array that the library holds on every GPU it runs on
+ * until the process ends; the call makes no allocation of any kind. Limits
+ * and preconditions:
+ *  - the string space must fit the scratch: 24 Ndet + 8 Na bytes (FP64,
+ *    parity 0), 8 Ndet + 8 Na (FP64, parity +-1), about 30 Ndet (F32/BF16,
+ *    parity 0); CAS(12,12) fits, CAS(14,14) does not -> CASCI_E_UNSUPPORTED;
+ *  - the operators and tables must already exist: run casci_sigma once with
+ *    the same ab_prec after set_integrals / build_strings (CASCI_E_STATE
+ *    otherwise);
+ *  - every call on a GPU shares that GPU's scratch, which keeps the last
+ *    call's contents: calls that overlap in time on one GPU (two streams, two
+ *    threads) race and give wrong results; calls ordered on one stream are safe.
+ */
+int casci_sigma_noalloc(casci_ctx* ctx, const double* C, double* sigma, int ab_prec, int parity);
+
+/*
  * <S^2> of a normalised FP64 CI vector C (Na x Nb): S^2 = Sz^2 + Sz + S- S+.
  * Result to host *s2.
  */

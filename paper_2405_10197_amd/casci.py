@@ -125,6 +125,7 @@ def lib():
         "casci_get_diagonal": (I, [P, P, I]),
         "casci_sigma": (I, [P, P, P, I, I, I]),
         "casci_sigma_parity": (I, [P, P, P, I, I, I]),
+        "casci_sigma_noalloc": (I, [P, P, P, I, I]),
         "casci_spin_square": (I, [P, P, P, I]),
         "casci_davidson": (I, [P, I, D, P, P, P, I, P]),
         "casci_profile_enable": (I, [P, I]),
@@ -347,6 +348,17 @@ class Context:
         if mem != mem2:
             raise ValueError("C and out must share memory kind")
         self._check(self._L.casci_sigma_parity(self._h, pc, ps, PREC[ab_prec], int(parity), mem))
+        return out
+
+    def sigma_noalloc(self, C, out, ab_prec: str = "f64", parity: int = 0):
+        """sigma = H C into `out` without any allocation by the library (device
+        float64 tensors; the library's 64 MiB static scratch holds the work
+        buffers). casci_sigma must have run once on this context with the same
+        ab_prec (it builds the tables)."""
+        nd = self.dims["Ndet"]
+        pc, _ = self._vec(C, nd, "C", device_only=True)
+        ps, _ = self._vec(out, nd, "out", device_only=True)
+        self._check(self._L.casci_sigma_noalloc(self._h, pc, ps, PREC[ab_prec], int(parity)))
         return out
 
     # -- learned preconditioner ------------------------------------------

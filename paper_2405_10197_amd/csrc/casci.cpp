@@ -177,6 +177,40 @@ struct casci_ctx {
 
 static const char* kValidateOnly = "validate-only context: no device work is launched";
 
+// ---------------------------------------------------------------------------
+// static scratch of the allocation-free sigma entry point
+// ---------------------------------------------------------------------------
+// 64 MiB of device memory per GPU, held until the process ends. Host code never
+// passes `scratch` itself to a kernel (in host code the name stands for a
+// host-side shadow, not a device address): every use goes through the address
+// that hipGetSymbolAddress returned for the device, taken once per device at
+// context creation with that device current.
+static constexpr size_t kScratchBytes = (size_t)64 << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+static std::mutex g_scratch_mu;
+static std::map<int, unsigned char*> g_scratch_addr;  // device -> its copy of `scratch`
+
+static int scratch_setup(int device, std::string* err)
+{
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch_addr.count(device)) return CASCI_OK;
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) {
+        (void)hipGetLastError();
+        *err = std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e);
+        return CASCI_E_DEVICE;
+    }
+    g_scratch_addr[device] = static_cast<unsigned char*>(p);
+    return CASCI_OK;
+}
+
+static unsigned char* scratch_addr(int device)
+{
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    auto it = g_scratch_addr.find(device);
+    return it == g_scratch_addr.end() ? nullptr : it->second;
+}
 
 // ---------------------------------------------------------------------------
 // context
@@ -204,6 +238,13 @@ extern "C" int casci_create(casci_ctx** out, int device, void* hip_stream)
     }
     ctx->device = device;
     DeviceGuard g(device);
+    {
+        std::string why;
+        if (scratch_setup(device, &why) != CASCI_OK) {
+            delete ctx;
+            return CASCI_E_DEVICE;
+        }
+    }
     if (hip_stream) {
         ctx->stream = (hipStream_t)hip_stream;
     } else {
@@ -1385,6 +1426,33 @@ extern "C" int casci_sigma_parity(casci_ctx* ctx, const double* C, double* sigma
     if (!ctx) return CASCI_E_ARG;
     if (parity == 0) return ctx->fail(CASCI_E_ARG, "parity must be +1 or -1");
     return sigma_impl(ctx, C, sigma, CASCI_F64, ab_prec, parity, mem);
+}
+
+extern "C" int casci_sigma_noalloc(casci_ctx* ctx, const double* C, double* sigma, int ab_prec, int parity)
+{
+    if (!ctx) return CASCI_E_ARG;
+    if (!C || !sigma) return ctx->fail(CASCI_E_ARG, "C and sigma must not be NULL");
+    if (C == sigma) return ctx->fail(CASCI_E_ARG, "C and sigma must not overlap");
+    if (ab_prec != CASCI_F64 && ab_prec != CASCI_F32 && ab_prec != CASCI_BF16)
+        return ctx->fail(CASCI_E_ARG, "ab_prec must be F64, F32 or BF16");
+    if (parity != 0 && parity != 1 && parity != -1) return ctx->fail(CASCI_E_ARG, "parity must be 0, +1 or -1");
+    if (!ctx->has_ints) return ctx->fail(CASCI_E_STATE, "set_integrals first");
+    if (!ctx->has_strings) return ctx->fail(CASCI_E_STATE, "build_strings first");
+    if (parity != 0 && ctx->na != ctx->nb) return ctx->fail(CASCI_E_ARG, "parity needs nalpha == nbeta");
+    const size_t need = sigma_work_layout(ctx, ab_prec, parity, nullptr, nullptr);
+    if (need > kScratchBytes)
+        return ctx->fail(CASCI_E_UNSUPPORTED, "this string space needs " + std::to_string(need) +
+                                                  " bytes of sigma work space, more than the " +
+                                                  std::to_string(kScratchBytes) + "-byte static scratch");
+    CHECK_RC(need_device(ctx));
+    if (!ctx->prepared)
+        return ctx->fail(CASCI_E_STATE, "operators not built: run casci_sigma once first (it allocates)");
+    unsigned char* base = scratch_addr(ctx->device);
+    if (!base) return ctx->fail(CASCI_E_STATE, "no static scratch address for this device");
+    DeviceGuard g(ctx->device);
+    SigmaWork w;
+    sigma_work_layout(ctx, ab_prec, parity, base, &w);
+    return sigma_dev(ctx, C, sigma, ab_prec, 0.0, parity, &w);
 }
 
 // small device scratch: reduction partials + results
