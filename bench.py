@@ -26,6 +26,7 @@ Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload cas16|cas
        python bench.py --copy-probe GIB                       (counter calibration: one plain copy)
        python bench.py --batch [--batch-count 64]             (64 uneven CAS(8..10) solves, 4 roots)
        python bench.py --cas18                                (CAS(18,18) sigma throughput, FP32 storage)
+       python bench.py --mlp                                  (learned preconditioner trained at scale vs Olsen)
 """
 from __future__ import annotations
 
@@ -289,6 +290,121 @@ def cas18_mode(args):
                                                                    "C seed 50" % (n, n, Nd)},
                       "sigma": out, "fp64_reference_seconds": t64,
                       "alpha_beta_flops": ab_flops}))
+
+
+def mlp_init(seed):
+    """Scaled Gaussian start of the 8 -> 64 -> 64 -> 1 network (std 1/sqrt(fan_in), zero biases),
+    in the parameter layout of the library (W1[8][64], b1, W2[64][64], b2, W3[64], b3)."""
+    rng = np.random.default_rng(seed)
+    W1 = rng.normal(0, 1 / math.sqrt(8), (8, 64))
+    W2 = rng.normal(0, 1 / math.sqrt(64), (64, 64))
+    W3 = rng.normal(0, 1 / math.sqrt(64), 64)
+    return np.concatenate([W1.ravel(), np.zeros(64), W2.ravel(), np.zeros(64), W3, [0.0]]).astype(np.float32)
+
+
+def mlp_mode(args):
+    """The learned preconditioner at its configured scale: residual -> converged-
+    correction pairs from the solver's own iterations (FP64 sigma, Olsen, 3 roots)
+    on CAS(12,12) seeds 4100-4107 and CAS(14,14) seeds 4200-4203, the validation
+    loss on the held-out CAS(14,14) seed 4204, training on the GPU with the
+    library's kernels, then iterations on the held-out CAS(14,14) and the
+    CAS(16,16) workload (seed 4, the headline's mixed-precision sigma) with the
+    learned preconditioner against Olsen. The energies both solves reach are
+    compared; the time-to-1e-8 Eh of each is taken against the Olsen solve's
+    converged energies. The result is reported whatever its sign."""
+    import torch
+    from paper_2405_10197_amd import casci, synth
+    k = 3
+    t_start = time.perf_counter()
+
+    def context(n, seed):
+        h, eri, _ = synth.integrals(n, seed)
+        c = casci.Context(0)
+        c.set_integrals(h, eri)
+        c.build_strings(n // 2, n // 2, n)
+        return c
+
+    def collect(n, seed, samples):
+        c = context(n, seed)
+        d = c.dims
+        xs = torch.empty((k, d["Na"], d["Nb"]), dtype=torch.float64, device="cuda")
+        _, _, info = c.davidson(k, 1e-12, precond="olsen", r_tol=1e-8, vectors_out=xs, max_iter=2000)
+        F, T = c.mlp_collect(k, 1e-10, xs, samples=samples, seed=seed, precond="olsen", max_rows=1 << 22,
+                             max_iter=2000)
+        log("[mlp] CAS(%d,%d) seed %d: %d iterations to the converged vectors, %d training rows (%.0f s)"
+            % (n, n, seed, info["iterations"], F.shape[0], time.perf_counter() - t_start))
+        del xs, c
+        return F, T
+
+    Fs, Ts = [], []
+    for seed in range(4100, 4108):
+        F, T = collect(12, seed, 2048)
+        Fs.append(F)
+        Ts.append(T)
+    for seed in range(4200, 4204):
+        F, T = collect(14, seed, 4096)
+        Fs.append(F)
+        Ts.append(T)
+    Fv, Tv = collect(14, 4204, 4096)
+    F = torch.cat(Fs).contiguous()
+    T = torch.cat(Ts).contiguous()
+    nrows = int(F.shape[0])
+    del Fs, Ts
+    Fv_h, Tv_h = Fv.cpu().numpy(), Tv.cpu().numpy()
+    c16 = context(16, 4)
+    c16.mlp_set_params(mlp_init(12))
+    val0, _ = c16.mlp_loss_grad(Fv_h, Tv_h)
+    t0 = time.perf_counter()
+    hist = c16.mlp_train(F, T, epochs=args.mlp_epochs, batch=8192, lr=2e-3, seed=3)
+    t_train = time.perf_counter() - t0
+    val1, _ = c16.mlp_loss_grad(Fv_h, Tv_h)
+    params = c16.mlp_get_params()
+    log("[mlp] trained on %d rows, %d epochs in %.1f s: training loss %.4f -> %.4f, validation %.4f -> %.4f"
+        % (F.shape[0], args.mlp_epochs, t_train, hist[0], hist[-1], val0, val1))
+    del F, T
+
+    # held-out CAS(14,14): FP64 sigma, Olsen against the learned preconditioner
+    c14 = context(14, 4204)
+    c14.mlp_set_params(params)
+    held = {}
+    for pc in ("olsen", "mlp"):
+        t0 = time.perf_counter()
+        E, _, info = c14.davidson(k, 1e-10, precond=pc, vectors=False, max_iter=2000)
+        held[pc] = {"iterations": info["iterations"], "sigma_calls": info["sigma_calls"],
+                    "seconds": time.perf_counter() - t0, "converged": info["converged"],
+                    "mlp_fallbacks": info["mlp_fallbacks"], "energies": E.tolist()}
+        log("[mlp] CAS(14,14) seed 4204, %s: %d iterations, %.1f s" % (pc, info["iterations"], held[pc]["seconds"]))
+    del c14
+
+    # CAS(16,16), the headline's mixed-precision solver with each preconditioner
+    runs = {}
+    for pc in ("olsen", "mlp"):
+        kw = dict(HEADLINE)
+        kw["precond"] = pc
+        t0 = time.perf_counter()
+        E, _, info = c16.davidson(k, 1e-10, vectors=False, history=4000, max_iter=4000,
+                                  progress=progress_printer("cas16-" + pc), **kw)
+        runs[pc] = (E, info, time.perf_counter() - t0)
+    Eref = runs["olsen"][0]
+    out = {}
+    for pc, (E, info, dt) in runs.items():
+        t_hit, it_hit = time_to_threshold(info["hist_energy"], info["hist_time_ms"], Eref)
+        out[pc] = {"iterations": info["iterations"], "sigma_calls": info["sigma_calls"], "seconds": dt,
+                   "time_to_1e8_s": t_hit, "threshold_iteration": it_hit, "converged": info["converged"],
+                   "mlp_fallbacks": info["mlp_fallbacks"], "energies": E.tolist(),
+                   "max_energy_difference_vs_olsen": float(np.abs(E - Eref).max())}
+        log("[mlp] CAS(16,16) %s: %d iterations, %.1f s, time-to-1e-8 %.1f s" % (pc, info["iterations"], dt, t_hit))
+    gain = out["olsen"]["time_to_1e8_s"] / out["mlp"]["time_to_1e8_s"] if out["mlp"]["time_to_1e8_s"] > 0 else None
+    print(json.dumps({"metric": "learned preconditioner vs Olsen, CAS(16,16) time-to-1e-8 Eh",
+                      "value": gain, "unit": "x (Olsen time / learned time)", "n_gpus": 1,
+                      "higher_is_better": True, "data": "synthetic",
+                      "config": {"workload": "train CAS(12,12) seeds 4100-4107 + CAS(14,14) seeds 4200-4203, "
+                                             "validate CAS(14,14) seed 4204, apply CAS(16,16) seed 4, 3 roots",
+                                 "network": "8-64-64-1 tanh, FP32", "epochs": args.mlp_epochs},
+                      "training": {"rows": nrows, "validation_rows": int(Fv_h.shape[0]), "loss_first_epoch": float(hist[0]),
+                                   "loss_last_epoch": float(hist[-1]), "validation_loss_before": val0,
+                                   "validation_loss_after": val1, "seconds": t_train},
+                      "held_out_cas14": held, "cas16": out}), flush=True)
 
 
 def kernel_figures(P, dims, n, tag):
@@ -618,6 +734,9 @@ def main():
     ap.add_argument("--cas18", action="store_true", help="run the CAS(18,18) FP32-storage sigma workload instead")
     ap.add_argument("--cas18-norb", type=int, default=18, help=argparse.SUPPRESS)
     ap.add_argument("--batch-count", type=int, default=64)
+    ap.add_argument("--mlp", action="store_true", help="learned preconditioner at scale: train on CAS(12,12)/"
+                                                       "CAS(14,14) solves, compare with Olsen at CAS(16,16)")
+    ap.add_argument("--mlp-epochs", type=int, default=8)
     ap.add_argument("--copy-probe", type=float, default=None,
                     help="counter calibration: copy GIB gibibytes once with a plain device copy")
     args = ap.parse_args()
@@ -645,6 +764,9 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     if args.batch:
         batch_mode(args)
+        return
+    if args.mlp:
+        mlp_mode(args)
         return
     if args.cas18:
         cas18_mode(args)

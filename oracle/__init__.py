@@ -16,7 +16,8 @@ with it:
   determinants connected by one- and two-electron substitution
   operators"), built by applying a+_p a_q to each string one operator at a
   time;
-* S^2 as an explicit matrix, for spin checks (Sec. II.A.1, spin projection).
+* S^2 as an explicit matrix, for spin checks (Sec. II.A.1, spin projection);
+* one- and two-particle density matrices by operator application.
 
 Pins (tests under ``-m "not gpu"``): brute-force second quantisation of
 eq. (hamiltonian) on tiny spaces, the closed-form 2-electron/2-orbital
@@ -65,8 +66,9 @@ def _load():
         lib.oracle_dense_s2.argtypes = [i, P, l, P, l, P]
         lib.oracle_h_rows.argtypes = [i, P, P, d, P, l, P, l, P, l, l, P, P, P]
         lib.oracle_single_list.argtypes = [i, P, l, i, P, P, P, P]
+        lib.oracle_rdm.argtypes = [i, P, l, P, l, P, P, P]
         for f in (lib.oracle_dense_h, lib.oracle_sigma_rows, lib.oracle_dense_s2, lib.oracle_h_rows,
-                  lib.oracle_single_list):
+                  lib.oracle_single_list, lib.oracle_rdm):
             f.restype = ctypes.c_int
         _lib = lib
     return _lib
@@ -316,6 +318,41 @@ def solve(h, eri, nalpha: int, nbeta: int, nroots: int = 1, ecore: float = 0.0, 
             X[k] = -X[k]
     s2 = np.einsum("ki,ij,kj->k", X, S2, X)
     return E, X.reshape(-1, na, nb), s2
+
+
+def rdm(norb: int, nalpha: int, nbeta: int, C, two: bool = True):
+    """Spin-resolved density matrices of a real CI vector C [Na, Nb] (Sec. II.A.1),
+    by explicit operator application in ``oracle_rdm``:
+    g1[s, p, q] = <C| a+_ps a_qs |C> (s = alpha, beta) and
+    g2[k, p, q, r, u] = <C| a+_ps a+_rt a_ut a_qs |C> for (s, t) = (a, a), (a, b), (b, b).
+    The cost grows as Ndet n^4: tiny spaces only."""
+    strs_a = strings(norb, nalpha)
+    strs_b = strings(norb, nbeta)
+    C = np.ascontiguousarray(np.asarray(C, dtype=np.float64).reshape(-1))
+    if C.size != strs_a.size * strs_b.size:
+        raise ValueError("C has the wrong size")
+    n = norb
+    g1 = np.zeros((2, n, n))
+    g2 = np.zeros((3, n, n, n, n)) if two else None
+    rc = _load().oracle_rdm(n, _ptr(strs_a), strs_a.size, _ptr(strs_b), strs_b.size, _ptr(C), _ptr(g1),
+                            _ptr(g2) if two else None)
+    if rc != 0:
+        raise RuntimeError("oracle_rdm failed: %d" % rc)
+    return g1, g2
+
+
+def spin_free_rdm(g1, g2):
+    """Spin-summed density matrices: gamma_pq = sum_s g1[s,p,q] and
+    Gamma_pqru = sum_st <a+_ps a+_rt a_ut a_qs>; the (beta, alpha) block is the
+    (alpha, beta) one with the pairs (pq) and (ru) exchanged."""
+    gam = g1[0] + g1[1]
+    Gam = g2[0] + g2[2] + g2[1] + g2[1].transpose(2, 3, 0, 1)
+    return gam, Gam
+
+
+def rdm_energy(h, eri, gam, Gam, ecore: float = 0.0):
+    """E = V + sum_pq h_pq gamma_pq + 1/2 sum_pqru (pq|ru) Gamma_pqru (chemists' integrals)."""
+    return ecore + float(np.einsum("pq,pq->", h, gam)) + 0.5 * float(np.einsum("pqru,pqru->", eri, Gam))
 
 
 def rotate_integrals(h, eri, Q):

@@ -363,3 +363,81 @@ int oracle_single_list(int n, const uint64_t* strs, long N, int s, long* J, long
     }
     return 0;
 }
+
+/*
+ * Spin-resolved one- and two-particle reduced density matrices of a real CI
+ * vector C over the determinants (Ia, Ib) -> Ia*Nb + Ib (Sec. II.A.1, the
+ * density matrices the multireference methods consume), by applying the
+ * operators to each determinant one at a time:
+ *   g1[s][p][q]          = <C| a+_{p s} a_{q s} |C>,                    s = alpha, beta
+ *   g2[st][((p n + q) n + r) n + u] = <C| a+_{p s} a+_{r t} a_{u t} a_{q s} |C>,
+ *                                                            st = (alpha alpha), (alpha beta), (beta beta)
+ * The rightmost operator acts first. Spin orbital of orbital p with spin s:
+ * p + s n (alpha creators left of beta creators, as for the determinants).
+ */
+static long det_index(int n, const uint64_t* astr, long Na, const uint64_t* bstr, long Nb, det_t d)
+{
+    det_t amask = (((det_t)1 << n) - 1);
+    long ia = find_string(astr, Na, d & amask);
+    long ib = find_string(bstr, Nb, d >> n);
+    if (ia < 0 || ib < 0) return -1;
+    return ia * Nb + ib;
+}
+
+int oracle_rdm(int n, const uint64_t* astr, long Na, const uint64_t* bstr, long Nb, const double* C,
+               double* g1, double* g2)
+{
+    if (n < 1 || 2 * n > 64) return -1;
+    const long Nd = Na * Nb;
+    const long n2 = (long)n * n, n4 = n2 * n2;
+    memset(g1, 0, sizeof(double) * 2 * n2);
+    if (g2) memset(g2, 0, sizeof(double) * 3 * n4);
+    const int spins[3][2] = {{0, 0}, {0, 1}, {1, 1}};
+    for (long y = 0; y < Nd; ++y) {
+        const double cj = C[y];
+        if (cj == 0.0) continue;
+        const det_t B = make_det(n, astr[y / Nb], bstr[y % Nb]);
+        for (int s = 0; s < 2; ++s)
+            for (int q = 0; q < n; ++q) {
+                det_t d = B;
+                int sign = 1;
+                if (!apply_annihilate(&d, q + s * n, &sign)) continue;
+                for (int p = 0; p < n; ++p) {
+                    det_t e = d;
+                    int sg = sign;
+                    if (!apply_create(&e, p + s * n, &sg)) continue;
+                    const long x = det_index(n, astr, Na, bstr, Nb, e);
+                    if (x < 0) return -2;
+                    g1[(s * n + p) * n + q] += sg * C[x] * cj;
+                }
+            }
+        if (!g2) continue;
+        for (int k = 0; k < 3; ++k) {
+            const int s = spins[k][0], t = spins[k][1];
+            for (int q = 0; q < n; ++q) {
+                det_t d1 = B;
+                int s1 = 1;
+                if (!apply_annihilate(&d1, q + s * n, &s1)) continue;
+                for (int u = 0; u < n; ++u) {
+                    det_t d2 = d1;
+                    int s2 = s1;
+                    if (!apply_annihilate(&d2, u + t * n, &s2)) continue;
+                    for (int r = 0; r < n; ++r) {
+                        det_t d3 = d2;
+                        int s3 = s2;
+                        if (!apply_create(&d3, r + t * n, &s3)) continue;
+                        for (int p = 0; p < n; ++p) {
+                            det_t d4 = d3;
+                            int s4 = s3;
+                            if (!apply_create(&d4, p + s * n, &s4)) continue;
+                            const long x = det_index(n, astr, Na, bstr, Nb, d4);
+                            if (x < 0) return -2;
+                            g2[k * n4 + ((p * n + q) * n + r) * n + u] += s4 * C[x] * cj;
+                        }
+                    }
+                }
+            }
+        }
+    }
+    return 0;
+}

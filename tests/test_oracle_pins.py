@@ -349,3 +349,64 @@ def test_h_rows_match_the_dense_matrix():
         assert set(nz.tolist()) <= set(c.tolist())
         assert np.all(np.diff(c) > 0)
         assert np.abs(H[r, c] - v).max() < 1e-14
+
+
+# --------------------------------------------------------------------------
+# density matrices (oracle.rdm, operator by operator)
+# --------------------------------------------------------------------------
+RDM_CASES = [(4, 2, 2, 1), (5, 3, 2, 2), (6, 3, 3, 3), (5, 2, 0, 4), (4, 4, 4, 5), (3, 1, 2, 6)]
+
+
+@pytest.mark.parametrize("n,na,nb,seed", RDM_CASES)
+def test_rdm_expectation_value_identity(n, na, nb, seed):
+    """For any normalised C: C^T H C (the Slater-Condon matrix) equals
+    V + sum h gamma + 1/2 sum (pq|ru) Gamma, and the traces count the electrons."""
+    h, eri, _ = synth.integrals(n, 40 + seed)
+    Na, Nb = math.comb(n, na), math.comb(n, nb)
+    C = synth.ci_vector(Na, Nb, seed)[0]
+    H = oracle.hamiltonian(h, eri, na, nb, 0.7)
+    g1, g2 = oracle.rdm(n, na, nb, C)
+    assert abs(np.trace(g1[0]) - na) < 1e-12 and abs(np.trace(g1[1]) - nb) < 1e-12
+    gam, Gam = oracle.spin_free_rdm(g1, g2)
+    c = C.reshape(-1)
+    assert abs(oracle.rdm_energy(h, eri, gam, Gam, 0.7) - c @ H @ c) < 1e-11 * max(1.0, abs(c @ H @ c))
+
+
+@pytest.mark.parametrize("n,na,nb,seed", RDM_CASES)
+def test_rdm_partial_traces_and_symmetries(n, na, nb, seed):
+    Na, Nb = math.comb(n, na), math.comb(n, nb)
+    C = synth.ci_vector(Na, Nb, seed + 10)[0]
+    g1, g2 = oracle.rdm(n, na, nb, C)
+    aa, ab, bb = g2
+    # sum_r <a+_p a+_r a_r a_q> = (N_s - 1) gamma_pq (same spin), N_t gamma_pq (other spin)
+    np.testing.assert_allclose(np.einsum("pqrr->pq", aa), (na - 1) * g1[0], atol=1e-12)
+    np.testing.assert_allclose(np.einsum("pqrr->pq", bb), (nb - 1) * g1[1], atol=1e-12)
+    np.testing.assert_allclose(np.einsum("pqrr->pq", ab), nb * g1[0], atol=1e-12)
+    np.testing.assert_allclose(np.einsum("pprs->rs", ab), na * g1[1], atol=1e-12)
+    # real vector: hermiticity; same spin: exchange of the two electrons
+    np.testing.assert_allclose(g1, g1.transpose(0, 2, 1), atol=1e-13)
+    for g in (aa, ab, bb):
+        np.testing.assert_allclose(g, g.transpose(1, 0, 3, 2), atol=1e-13)
+    for g in (aa, bb):
+        np.testing.assert_allclose(g, g.transpose(2, 3, 0, 1), atol=1e-13)
+        np.testing.assert_allclose(g, -g.transpose(0, 3, 2, 1), atol=1e-13)
+
+
+def test_rdm_single_determinant_closed_form():
+    """One determinant: gamma^s = diag(n^s); <a+_p a+_r a_u a_q> = n_p n_r (d_pq d_ru - d_pu d_rq)
+    for equal spins and n^a_p n^b_r d_pq d_ru for opposite spins."""
+    n, na, nb = 5, 3, 2
+    a, b = oracle.strings(n, na), oracle.strings(n, nb)
+    ia, ib = 4, 7
+    C = np.zeros((a.size, b.size))
+    C[ia, ib] = 1.0
+    g1, g2 = oracle.rdm(n, na, nb, C)
+    occa = np.array([(int(a[ia]) >> p) & 1 for p in range(n)], dtype=float)
+    occb = np.array([(int(b[ib]) >> p) & 1 for p in range(n)], dtype=float)
+    np.testing.assert_array_equal(g1[0], np.diag(occa))
+    np.testing.assert_array_equal(g1[1], np.diag(occb))
+    d = np.eye(n)
+    for g, x, y in ((g2[0], occa, occa), (g2[2], occb, occb)):
+        ref = np.einsum("p,r,pq,ru->pqru", x, y, d, d) - np.einsum("p,r,pu,rq->pqru", x, y, d, d)
+        np.testing.assert_array_equal(g, ref)
+    np.testing.assert_array_equal(g2[1], np.einsum("p,r,pq,ru->pqru", occa, occb, d, d))
