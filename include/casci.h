@@ -209,6 +209,29 @@ int casci_sigma_parity(casci_ctx* ctx, const double* C, double* sigma, int ab_pr
 int casci_sigma_noalloc(casci_ctx* ctx, const double* C, double* sigma, int ab_prec, int parity);
 
 /*
+ * Reduced density matrices of a real CI vector C (Na x Nb FP64, host or
+ * device per mem; it need not be normalised: the matrices scale with |C|^2),
+ * the quantities the orbital optimisation and perturbation theories built on
+ * the CASCI solve consume (Sec. II.A.1; Sec. II.B uses the one- and
+ * two-particle density matrices of the CI vectors). Spin-resolved, host outputs:
+ *   g1[s][p][q]        = <C| a+_{p s} a_{q s} |C>,  s = 0 alpha, 1 beta      (2 n^2)
+ *   g2[k][p][q][r][u]  = <C| a+_{p s} a+_{r t} a_{u t} a_{q s} |C>          (3 n^4)
+ *                        k = 0: (s,t) = (alpha,alpha), 1: (alpha,beta), 2: (beta,beta)
+ * g2 = NULL skips the two-particle matrix. With real orbitals the energy is
+ * E = V + sum_pq h_pq gamma_pq + 1/2 sum_pqru (pq|ru) Gamma_pqru with the
+ * spin sums of casci_rdm_spin_free. Needs strings (not integrals). Works on
+ * blocks of alpha strings holding at most 512 MiB of pair-excitation rows.
+ */
+int casci_rdm(casci_ctx* ctx, const double* C, int mem, double* g1, double* g2);
+
+/*
+ * Spin-summed density matrices of C (host outputs): gamma[p][q] = g1[0] + g1[1]
+ * (n^2) and Gamma[p][q][r][u] = sum over both spins of
+ * <C| a+_p a+_r a_u a_q |C> (n^4; NULL skips it). Same conditions as casci_rdm.
+ */
+int casci_rdm_spin_free(casci_ctx* ctx, const double* C, int mem, double* gamma, double* Gamma);
+
+/*
  * <S^2> of a normalised FP64 CI vector C (Na x Nb): S^2 = Sz^2 + Sz + S- S+.
  * Result to host *s2.
  */
@@ -299,14 +322,15 @@ int casci_batch_davidson(casci_ctx* const* ctxs, int count, int nroots, double t
  * gather: 16, 32 or 64 lanes per gathered entry with one column each, 128
  * (64 lanes with two adjacent columns each), or L * 100 + V for L lanes per
  * entry with V adjacent columns each (1602, 3202; FP32 input also 1604, 3204,
- * 6404); 0 until the first sigma build in that precision. The code changes
- * only the speed: every width sums in the same order, so sigma is bitwise
- * the same whichever is chosen.
+ * 6404), or 99: row blocks of 16 strings whose union of neighbour rows is
+ * staged in LDS (fewer than 65536 strings); 0 until the first sigma build in
+ * that precision. The code changes only the speed: every width sums in the
+ * same order, so sigma is bitwise the same whichever is chosen.
  */
 int casci_get_tuning(casci_ctx* ctx, int* out);
 
 /* Override the autotuner: strip width code (16, 32, 64, 128, 1602, 3202, 1604,
- * 3204 or 6404 as above; 0 = autotune) of the FP64 and of the FP32-input gather
+ * 3204, 6404 or 99 as above; 0 = autotune) of the FP64 and of the FP32-input gather
  * for this context (a vector width the row stride does not allow falls back
  * to one column per lane). */
 int casci_set_tuning(casci_ctx* ctx, int f64_lpe, int f32in_lpe);

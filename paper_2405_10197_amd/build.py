@@ -15,8 +15,8 @@ CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libcasci.so")
-SOURCES = ["ab_lowp_f32_d.hip", "ab_lowp_f32_f.hip", "ab_lowp_bf16_d.hip", "ab_lowp_bf16_f.hip", "ab_f64.hip", "sigma_kernels.hip", "setup_kernels.hip",
-           "davidson_kernels.hip", "mlp_kernels.hip", "casci.cpp"]
+SOURCES = ["ab_lowp_f32_d.hip", "ab_lowp_f32_f.hip", "ab_lowp_bf16_d.hip", "ab_lowp_bf16_f.hip", "ab_f64.hip", "ab_bf16_fixed.hip", "sigma_kernels.hip", "setup_kernels.hip",
+           "davidson_kernels.hip", "mlp_kernels.hip", "rdm_kernels.hip", "casci.cpp"]
 ARCH = "gfx950"
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
@@ -42,7 +42,7 @@ def build(verbose: bool = False) -> str:
     with ThreadPoolExecutor(max_workers=min(8, len(SOURCES))) as ex:
         objs = list(ex.map(lambda s: _compile(s, build_dir), SOURCES))
     tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = [HIPCC, "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp] + objs
+    cmd = [HIPCC, "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp] + objs + ["-lrocblas"]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError("link failed:\n%s\n%s" % (r.stdout, r.stderr))

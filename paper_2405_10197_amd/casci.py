@@ -127,6 +127,8 @@ def lib():
         "casci_sigma_parity": (I, [P, P, P, I, I, I]),
         "casci_sigma_noalloc": (I, [P, P, P, I, I]),
         "casci_spin_square": (I, [P, P, P, I]),
+        "casci_rdm": (I, [P, P, I, P, P]),
+        "casci_rdm_spin_free": (I, [P, P, I, P, P]),
         "casci_davidson": (I, [P, I, D, P, P, P, I, P]),
         "casci_profile_enable": (I, [P, I]),
         "casci_mlp_set_params": (I, [P, P, I64, I]),
@@ -455,6 +457,23 @@ class Context:
         res["lowp"]["convert_ms"] = float(out[12])
         res.update({k: res["f64"][k] + res["lowp"][k] for k in keys + ["convert_ms"]})
         return res
+
+    def rdm(self, C, two: bool = True, spin_free: bool = False):
+        """Density matrices of a float64 CI vector C (host or device). Spin-resolved:
+        (g1[2, n, n], g2[3, n, n, n, n] or None), the blocks (alpha, beta) and
+        (alpha-alpha, alpha-beta, beta-beta); spin_free: (gamma[n, n], Gamma[n, n, n, n] or None)."""
+        pc, mem = self._vec(C, self.dims["Ndet"], "C")
+        n = self.dims["norb"]
+        if spin_free:
+            o1 = np.zeros((n, n))
+            o2 = np.zeros((n, n, n, n)) if two else None
+            fn = self._L.casci_rdm_spin_free
+        else:
+            o1 = np.zeros((2, n, n))
+            o2 = np.zeros((3, n, n, n, n)) if two else None
+            fn = self._L.casci_rdm
+        self._check(fn(self._h, pc, mem, o1.ctypes.data, o2.ctypes.data if two else None))
+        return o1, o2
 
     def spin_square(self, C):
         pc, mem = self._vec(C, self.dims["Ndet"], "C")

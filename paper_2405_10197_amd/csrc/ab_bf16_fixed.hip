@@ -1,0 +1,349 @@
+// BF16 alpha-beta contraction (BF16 MFMA, FP32 accumulation) with the scatter
+// done straight from the accumulator registers into a 32-bit fixed-point sigma
+// row in LDS.
+//
+// Same contraction as the other alpha-beta kernels (ab_common.h): one
+// workgroup owns one alpha string Ia and its whole sigma row; per tile of
+// AB_TN beta strings Jb the rows C(J_e, tile) of Ia's list are gathered into
+// one of two LDS buffers (the next tile's loads are in flight while the
+// current one is multiplied), each wave multiplies its pair-row tiles with
+// 16x16x32 BF16 MFMA, and every accumulator element T(m, Jb) is added to
+// sigma(Ia, E_m Jb) with an integer LDS atomic. There is no T tile in LDS, no
+// reduction table and one barrier per tile.
+//
+// Fixed point. Integer adds are associative, so the row does not depend on
+// the order in which waves add (bitwise reproducible), which floating-point
+// LDS atomics would not give. Every partial sum of a sigma element is bounded
+// by B = s_b amax cmax (s_b contributions per element, one per entry of its
+// beta list; |T(m, Jb)| <= max_m sum_e |A(m, e)| max_e max_Jb |C(J_e, Jb)|,
+// with a 1% margin for the BF16 rounding of C); with B < 2^ex the unit is
+// 2^(ex-30), so every partial sum stays below 2^30 < 2^31. The rounding of a
+// contribution to the unit adds at most 2^-31 B, far below the BF16 rounding
+// of the inputs (2^-9 relative).
+//
+// Targets: a 16-bit table in the order of the MFMA accumulator elements, one
+// 8-byte load per lane and 16x16 block: entry [lane][v] of block (tile, M
+// tile, sub-tile) is pair row 16 mt + 4 (lane / 16) + v and column
+// 64 t + 16 ns + lane % 16; bit 15 = negative sign, 0xffff = E_m Jb vanishes.
+// It needs fewer than 32767 beta strings; the sigma row needs Nb * 4 bytes of
+// LDS (Nb <= 15360).
+#include "ab_common.h"
+
+namespace casci {
+
+constexpr int ABF_WAVES = 12;  // 4 column groups x 3 pair-row groups
+constexpr uint16_t TG16_NONE = 0xffff;
+
+__global__ __launch_bounds__(256) void k_tg16(const int32_t* __restrict__ tg, int64_t Nb, int Mp, int64_t ntile,
+                                              uint16_t* __restrict__ out)
+{
+    const int mtiles = Mp / 16;
+    const int64_t total = ntile * mtiles * 4 * 256;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t blk = i / 256;
+        const int w = (int)(i % 256);
+        const int lane = w / 4, v = w % 4;
+        const int ns = (int)(blk % 4);
+        const int64_t rest = blk / 4;
+        const int mt = (int)(rest % mtiles);
+        const int64_t t = rest / mtiles;
+        const int m = mt * 16 + 4 * (lane >> 4) + v;
+        const int64_t jc = t * AB_TN + ns * 16 + (lane & 15);
+        uint16_t val = TG16_NONE;
+        if (jc < Nb) {
+            const int32_t e = tg[jc * Mp + m];
+            if (e != AB_NONE) val = (uint16_t)((l1_index(e) & 0x7fff) | (e < 0 ? 0x8000 : 0));
+        }
+        out[i] = val;
+    }
+}
+
+hipError_t launch_tg16(const int32_t* tg, int64_t Nb, int Mp, uint16_t* out, hipStream_t st)
+{
+    if (Nb <= 0) return hipSuccess;
+    if (Nb >= 0x7fff) return ab_invalid("alpha-beta: 16-bit targets need fewer than 32767 beta strings");
+    if (Mp % 16 != 0) return ab_invalid("alpha-beta: pair rows not padded to 16");
+    const int64_t ntile = (Nb + AB_TN - 1) / AB_TN;
+    const int64_t total = ntile * (Mp / 16) * 4 * 256;
+    int64_t g = (total + 255) / 256;
+    if (g > 65536) g = 65536;
+    hipLaunchKernelGGL(k_tg16, dim3((unsigned)g), dim3(256), 0, st, tg, Nb, Mp, ntile, out);
+    return hipGetLastError();
+}
+
+int64_t tg16_entries(int64_t Nb, int Mp)
+{
+    return (Nb + AB_TN - 1) / AB_TN * (Mp / 16) * 4 * 256;
+}
+
+template <typename TO, int KBMAX, int MT>
+__global__ __launch_bounds__(64 * ABF_WAVES) void k_ab_bf16(AbParams p, const __bf16* __restrict__ Vt,
+                                                            const __bf16* __restrict__ Cs, int64_t ldc,
+                                                            const double* __restrict__ rowmax,
+                                                            const uint16_t* __restrict__ tg16,
+                                                            TO* __restrict__ sigma, int kb_count)
+{
+    using MF = MfmaBF16;
+    using vec_t = uint4;
+    constexpr int VEC = 8;            // bf16 per 16-byte segment
+    constexpr int SEGS = AB_TN / VEC; // segments per tile row
+    __shared__ double s_amax[ABF_WAVES], s_cmax[ABF_WAVES];
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int Kp = kb_count * MF::K;
+    const int tsz = ((TileLayout<MF>::size(Kp) * 2 + 15) / 16) * 16;  // bytes of one D buffer
+    unsigned* sig = reinterpret_cast<unsigned*>(smem);
+    unsigned char* dbase = smem + ((p.Nb * 4 + 15) / 16) * 16;
+    int* sJ = reinterpret_cast<int*>(dbase + 2 * tsz);
+
+    const int64_t per_xcd = gridDim.x / 8;
+    const int64_t ia = (int64_t)(blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
+    if (ia >= p.Na) return;
+    const int tid = threadIdx.x, nth = blockDim.x;
+    const int wave = tid >> 6, lane = tid & 63;
+    const int ngrp = wave & 3, mgrp = wave >> 2;
+    const int mtiles = p.Mp / 16;
+
+    for (int64_t i = tid; i < p.Nb; i += nth) sig[i] = 0u;
+    for (int i = tid; i < Kp; i += nth) sJ[i] = i < p.sa ? l1_index(p.la_j[ia * p.sa + i]) : -1;
+
+    // A fragments: row lane % 16 of M tile (mgrp * MT + mt), k = 32 kb + 8 (lane / 16) + q
+    typename MF::frag afr[MT][KBMAX];
+    double amax = 0.0;
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) {
+        const int m = (mgrp * MT + mt) * 16 + (lane & 15);
+        double rs = 0.0;
+#pragma unroll
+        for (int kb = 0; kb < KBMAX; ++kb) {
+            typename MF::frag f;
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const int e = kb * MF::K + (lane >> 4) * 8 + q;
+                __bf16 v = (__bf16)0.0f;
+                if (kb < kb_count && e < p.sa && m < p.M) {
+                    const int32_t enc = p.la_j[ia * p.sa + e];
+                    const int pq = p.la_pq[ia * p.sa + e];
+                    v = Vt[(int64_t)((pq & 0xff) * p.n + (pq >> 8)) * p.Mp + m];
+                    if (l1_sign(enc) < 0) v = -v;
+                }
+                f[q] = v;
+                rs += fabs((double)(float)v);
+            }
+            afr[mt][kb] = f;
+        }
+        rs += __shfl_xor(rs, 16);
+        rs += __shfl_xor(rs, 32);
+        amax = fmax(amax, rs);
+    }
+    double cmax = 0.0;
+    for (int i = tid; i < p.sa; i += nth) cmax = fmax(cmax, rowmax[l1_index(p.la_j[ia * p.sa + i])]);
+    for (int off = 1; off < 64; off <<= 1) {
+        amax = fmax(amax, __shfl_xor(amax, off));
+        cmax = fmax(cmax, __shfl_xor(cmax, off));
+    }
+    if (lane == 0) {
+        s_amax[wave] = amax;
+        s_cmax[wave] = cmax;
+    }
+    __syncthreads();
+    amax = 0.0;
+    cmax = 0.0;
+    for (int w = 0; w < nth / 64; ++w) {
+        amax = fmax(amax, s_amax[w]);
+        cmax = fmax(cmax, s_cmax[w]);
+    }
+    TO* srow = sigma + ia * p.Nb;
+    const double B = (double)p.sb * amax * cmax * 1.01;
+    int ex = 0;
+    if (B > 0.0) (void)frexp(B, &ex);
+    // unit 2^-se with se = 30 - ex; below 2^-96 the bound leaves room for the largest
+    // FP32 scale (se = 126), above 2^156 the FP32 scale would underflow
+    int se = 30 - ex;
+    if (se > 126) se = 126;
+    if (!(B <= 1.7976931348623157e308) || se < -126) {  // a non-finite (or far too large) row: NaN
+        for (int64_t i = tid; i < p.Nb; i += nth) srow[i] = (TO)__builtin_nan("");
+        return;
+    }
+    const float scale = ldexpf(1.0f, se);
+    const double unit = ldexp(1.0, -se);
+
+    const int nseg = Kp * SEGS;
+    const int64_t ntiles = (p.Nb + AB_TN - 1) / AB_TN;
+    constexpr int SPT = 2;  // segments per thread: Kp * 8 <= 2 * 768 for Kp <= 192
+    vec_t pf[SPT];
+    auto issue = [&](int64_t tile) {
+        const int64_t j0 = tile * AB_TN;
+#pragma unroll
+        for (int q = 0; q < SPT; ++q) {
+            const int sidx = tid + q * nth;
+            vec_t v = {0u, 0u, 0u, 0u};
+            if (sidx < nseg) {
+                const int k = sidx / SEGS, sg = sidx - k * SEGS;
+                const int64_t col = j0 + sg * VEC;
+                const int J = sJ[k];
+                if (J >= 0 && col < ldc) v = *reinterpret_cast<const vec_t*>(Cs + (int64_t)J * ldc + col);
+            }
+            pf[q] = v;
+        }
+    };
+    auto commit = [&](int buf) {
+        __bf16* Dt = reinterpret_cast<__bf16*>(dbase + buf * tsz);
+#pragma unroll
+        for (int q = 0; q < SPT; ++q) {
+            const int sidx = tid + q * nth;
+            if (sidx < nseg) {
+                const int k = sidx / SEGS, sg = sidx - k * SEGS;
+                const __bf16* ve = reinterpret_cast<const __bf16*>(&pf[q]);
+#pragma unroll
+                for (int e = 0; e < VEC; ++e) Dt[TileLayout<MF>::at(k, sg * VEC + e, Kp)] = ve[e];
+            }
+        }
+    };
+    // this lane's targets of one tile: 4 entries per M tile (its four accumulator rows)
+    auto load_tg = [&](int64_t tile, uint2 (&dst)[MT]) {
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) {
+            const int mtile = mgrp * MT + mt;
+            uint2 v = {0xffffffffu, 0xffffffffu};
+            if (mtile < mtiles)
+                v = *reinterpret_cast<const uint2*>(tg16 + (((tile * mtiles + mtile) * 4 + ngrp) * 256 + lane * 4));
+            dst[mt] = v;
+        }
+    };
+
+    issue(0);
+    commit(0);
+    uint2 tgc[MT], tgn[MT];
+    load_tg(0, tgc);
+    __syncthreads();
+    for (int64_t t = 0; t < ntiles; ++t) {
+        const bool more = t + 1 < ntiles;
+        if (more) {
+            issue(t + 1);
+            load_tg(t + 1, tgn);
+        }
+        const __bf16* Dt = reinterpret_cast<const __bf16*>(dbase + (t & 1) * tsz);
+        f4 acc[MT];
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) acc[mt][v] = 0.f;
+        const int c = ngrp * 16 + (lane & 15);
+#pragma unroll
+        for (int kb = 0; kb < KBMAX; ++kb) {
+            if (kb < kb_count) {
+                const bf8 b = *reinterpret_cast<const bf8*>(&Dt[TileLayout<MF>::at(kb * MF::K + (lane >> 4) * 8, c, Kp)]);
+#pragma unroll
+                for (int mt = 0; mt < MT; ++mt)
+                    if ((mgrp * MT + mt) < mtiles) acc[mt] = MF::mma(afr[mt][kb], b, acc[mt]);
+            }
+        }
+        // fixed-point scatter: all conversions first, then the integer adds
+        int q[MT][4];
+        unsigned tgt[MT][4];
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const unsigned w = v < 2 ? tgc[mt].x : tgc[mt].y;
+                const unsigned e = (w >> (16 * (v & 1))) & 0xffffu;
+                tgt[mt][v] = e;
+                const int qi = __float2int_rn(acc[mt][v] * scale);
+                q[mt][v] = (e & 0x8000u) ? -qi : qi;
+            }
+        }
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+            for (int v = 0; v < 4; ++v)
+                if (tgt[mt][v] != TG16_NONE) atomicAdd(&sig[tgt[mt][v] & 0x7fffu], (unsigned)q[mt][v]);
+        if (more) {
+            commit((int)((t + 1) & 1));
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt) tgc[mt] = tgn[mt];
+        }
+        __syncthreads();
+    }
+    if (p.overwrite) {
+        for (int64_t i = tid; i < p.Nb; i += nth) srow[i] = (TO)((double)(int)sig[i] * unit);
+    } else {
+        for (int64_t i = tid; i < p.Nb; i += nth) srow[i] = (TO)((double)srow[i] + (double)(int)sig[i] * unit);
+    }
+}
+
+static int64_t abf_lds_bytes(int kb_count, int64_t Nb)
+{
+    const int Kp = kb_count * MfmaBF16::K;
+    int64_t b = (Nb * 4 + 15) / 16 * 16;
+    b += 2 * (((int64_t)TileLayout<MfmaBF16>::size(Kp) * 2 + 15) / 16 * 16);
+    b += (int64_t)Kp * 4 + 64;
+    return b;
+}
+
+bool ab_bf16_fixed_fits(int64_t Nb, int sa, int Mp)
+{
+    const int kb_count = (sa + MfmaBF16::K - 1) / MfmaBF16::K;
+    const int mtiles = Mp / 16;
+    return Nb < 0x7fff && kb_count <= 4 && (mtiles + 2) / 3 <= 4 && kb_count * MfmaBF16::K * 8 <= 2 * 64 * ABF_WAVES &&
+           abf_lds_bytes(kb_count, Nb) <= 160 * 1024 - 512 - 2 * ABF_WAVES * 8;
+}
+
+template <typename TO>
+static hipError_t abf_launch(const AbParams& p, const void* Vt, const void* Cs, int64_t ldc, const double* rowmax,
+                             const uint16_t* tg16, TO* sigma, hipStream_t st)
+{
+    if (p.Na <= 0 || p.Nb <= 0 || p.sa <= 0 || p.M <= 0) return hipSuccess;
+    if (!rowmax || !tg16) return ab_invalid("alpha-beta: row maxima or 16-bit targets missing");
+    if (!ab_bf16_fixed_fits(p.Nb, p.sa, p.Mp)) return ab_invalid("alpha-beta: shape outside the fixed-point BF16 kernel");
+    const int kb_count = (p.sa + MfmaBF16::K - 1) / MfmaBF16::K;
+    const int mtiles = p.Mp / 16;
+    const int MT = (mtiles + 2) / 3;
+    const size_t lds = (size_t)abf_lds_bytes(kb_count, p.Nb);
+    const int64_t grid = (p.Na + 7) / 8 * 8;
+#define ABF_GO(KBV, MTV)                                                                            \
+    if (kb_count <= KBV && MT == MTV) {                                                             \
+        auto kern = k_ab_bf16<TO, KBV, MTV>;                                                        \
+        hipError_t e = hipFuncSetAttribute((const void*)kern,                                       \
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);   \
+        if (e != hipSuccess) {                                                                      \
+            set_launch_reason("hipFuncSetAttribute(max dynamic LDS) failed");                       \
+            return e;                                                                               \
+        }                                                                                           \
+        hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(64 * ABF_WAVES), lds, st, p,            \
+                           (const __bf16*)Vt, (const __bf16*)Cs, ldc, rowmax, tg16, sigma, kb_count); \
+        return hipGetLastError();                                                                   \
+    }
+    ABF_GO(1, 1)
+    ABF_GO(2, 1)
+    ABF_GO(3, 1)
+    ABF_GO(4, 1)
+    ABF_GO(1, 2)
+    ABF_GO(2, 2)
+    ABF_GO(3, 2)
+    ABF_GO(4, 2)
+    ABF_GO(1, 3)
+    ABF_GO(2, 3)
+    ABF_GO(3, 3)
+    ABF_GO(4, 3)
+    ABF_GO(1, 4)
+    ABF_GO(2, 4)
+    ABF_GO(3, 4)
+    ABF_GO(4, 4)
+#undef ABF_GO
+    return ab_invalid("alpha-beta: no fixed-point BF16 kernel variant for this shape");
+}
+
+hipError_t launch_ab_bf16_fixed(const AbParams& p, const void* Vt, const void* Cs, int64_t ldc, const double* rowmax,
+                                const uint16_t* tg16, double* sigma, hipStream_t st)
+{
+    return abf_launch<double>(p, Vt, Cs, ldc, rowmax, tg16, sigma, st);
+}
+
+hipError_t launch_ab_bf16_fixed(const AbParams& p, const void* Vt, const void* Cs, int64_t ldc, const double* rowmax,
+                                const uint16_t* tg16, float* sigma, hipStream_t st)
+{
+    return abf_launch<float>(p, Vt, Cs, ldc, rowmax, tg16, sigma, st);
+}
+
+}  // namespace casci

@@ -182,8 +182,11 @@ __global__ __launch_bounds__(64 * AB_MAX_WAVES) void k_ab(AbParams p, const doub
     }
     int ex = 0;
     if (B > 0.0) (void)frexp(B, &ex);
-    const double scale = B > 0.0 ? ldexp(1.0, 62 - ex) : 0.0;
-    const double unit = B > 0.0 ? ldexp(1.0, ex - 62) : 0.0;
+    // unit 2^-se, se = 62 - ex (capped where the bound is so small that the scale
+    // alone could leave the double range)
+    const int se = 62 - ex > 1000 ? 1000 : 62 - ex;
+    const double scale = ldexp(1.0, se);
+    const double unit = ldexp(1.0, -se);
 
     const int tile_elems = Kp * AB_TN;
     double pf[PF];

@@ -21,6 +21,8 @@
 
 #include "internal.h"
 
+#include <rocblas/rocblas.h>
+
 using namespace casci;
 
 namespace {
@@ -100,6 +102,7 @@ struct casci_ctx {
     int norb = 0, na = 0, nb = 0;
     int64_t Na = 0, Nb = 0, Nd = 0;
     int sa = 0, sb = 0, ra = 0, rb = 0;
+    bool ops_sorted = false;  // same-spin operator rows ascending past the diagonal
     std::vector<int64_t> binom;  // (norb+1)^2
 
     DBuf d_binom, d_astr, d_bstr, d_la_j, d_la_pq, d_lb_j, d_lb_pq;
@@ -109,8 +112,14 @@ struct casci_ctx {
     double prepared_lambda = 0.0;
     DBuf d_h, d_eri, d_fa_col, d_fa_val, d_fb_col, d_fb_val, d_jpq, d_diag;
     DBuf d_fa_c16, d_fa_v32, d_fb_c16, d_fb_v32;  // compact operator copies (< 65536 strings)
+    struct Blocks {  // row-blocked form of one same-spin operator (SsBlk)
+        DBuf uni, binfo, pos, offs;
+        int64_t nblk = 0;
+        bool have = false;
+    } blk[2];        // [0]: alpha (and beta when nalpha = nbeta), [1]: beta
     DBuf d_vt_sym, d_pairs_sym, d_vt_full, d_pairs_full, d_vt_s2;
     DBuf d_tg_sym, d_tg_full;  // alpha-beta scatter targets per (beta string, pair row)
+    DBuf d_tg16;               // the same (symmetric pairs), 16-bit, in MFMA element order
     struct Reduce {            // target-grouped scatter table (AbReduce) of one pair set
         DBuf tab, tinfo;
         int max_nseg = 0, ldT = 0;
@@ -119,11 +128,14 @@ struct casci_ctx {
     DBuf d_vt_sym_lp[2], d_vt_full_lp[2];  // FP32 and BF16 copies (round to nearest even)
     int M_sym = 0, Mp_sym = 0, M_full = 0, Mp_full = 0;
     bool have_full = false, have_s2 = false;
-    bool have_tg_sym = false, have_tg_full = false;
+    bool have_tg_sym = false, have_tg_full = false, have_tg16 = false;
 
     // workspaces
     DBuf d_t1, d_t2, d_t3, d_vin, d_vout, d_work, d_small, d_clp, d_c32;
     DBuf d_rowmax;  // max_c |C(J, c)| per alpha string: bound of the FP64 alpha-beta fixed-point sums
+    // density matrices: pair-excitation rows of a block of alpha strings, their Gram matrix
+    DBuf d_rdm_M, d_rdm_G, d_rdm_out;
+    rocblas_handle blas = nullptr;
 
     // learned preconditioner parameters (FP32, MLP_NPARAM values)
     DBuf d_mlp, d_mlp_m, d_mlp_v, d_mlp_g, d_mlp_part, d_mlp_perm, d_mlp_sse, d_mlp_idx;
@@ -267,13 +279,21 @@ extern "C" void casci_destroy(casci_ctx* ctx)
         DBuf* bufs[] = {&ctx->d_binom, &ctx->d_astr, &ctx->d_bstr, &ctx->d_la_j, &ctx->d_la_pq,
                         &ctx->d_lb_j, &ctx->d_lb_pq, &ctx->d_h, &ctx->d_eri, &ctx->d_fa_col,
                         &ctx->d_fa_val, &ctx->d_fb_col, &ctx->d_fb_val, &ctx->d_jpq, &ctx->d_diag,
-                        &ctx->d_vt_sym, &ctx->d_pairs_sym, &ctx->d_vt_full, &ctx->d_pairs_full, &ctx->d_tg_sym, &ctx->d_tg_full, &ctx->d_fa_c16, &ctx->d_fa_v32, &ctx->d_fb_c16, &ctx->d_fb_v32,
+                        &ctx->d_vt_sym, &ctx->d_pairs_sym, &ctx->d_vt_full, &ctx->d_pairs_full, &ctx->d_tg_sym, &ctx->d_tg_full, &ctx->d_tg16, &ctx->d_fa_c16, &ctx->d_fa_v32, &ctx->d_fb_c16, &ctx->d_fb_v32,
                         &ctx->red_sym.tab, &ctx->red_sym.tinfo, &ctx->red_full.tab, &ctx->red_full.tinfo,
                         &ctx->d_vt_s2, &ctx->d_t1, &ctx->d_t2, &ctx->d_vin, &ctx->d_vout,
                         &ctx->d_work, &ctx->d_small, &ctx->d_vt_sym_lp[0], &ctx->d_vt_sym_lp[1],
                         &ctx->d_vt_full_lp[0], &ctx->d_vt_full_lp[1], &ctx->d_clp, &ctx->d_c32, &ctx->d_t3,
                         &ctx->d_mlp, &ctx->d_mlp_m, &ctx->d_mlp_v, &ctx->d_mlp_g, &ctx->d_mlp_part,
-                        &ctx->d_mlp_perm, &ctx->d_mlp_sse, &ctx->d_mlp_idx, &ctx->d_rowmax};
+                        &ctx->d_mlp_perm, &ctx->d_mlp_sse, &ctx->d_mlp_idx, &ctx->d_rowmax,
+                        &ctx->d_rdm_M, &ctx->d_rdm_G, &ctx->d_rdm_out};
+        if (ctx->blas) (void)rocblas_destroy_handle(ctx->blas);
+        for (auto& bl : ctx->blk) {
+            bl.uni.release();
+            bl.binfo.release();
+            bl.pos.release();
+            bl.offs.release();
+        }
         for (auto& gr : ctx->graphs) (void)hipGraphExecDestroy(gr.exec);
         ctx->graphs.clear();
         ctx->d_gin.release();
@@ -347,7 +367,8 @@ extern "C" int casci_set_integrals(casci_ctx* ctx, int norb, const double* h, co
     ctx->has_ints = true;
     ctx->prepared = false;
     ctx->have_full = ctx->have_s2 = false;
-    ctx->have_tg_sym = ctx->have_tg_full = false;
+    ctx->have_tg_sym = ctx->have_tg_full = ctx->have_tg16 = false;
+    ctx->blk[0].have = ctx->blk[1].have = false;
     ctx->red_sym.have = ctx->red_full.have = false;
     ++ctx->gen;
     return CASCI_OK;
@@ -439,7 +460,8 @@ extern "C" int casci_build_strings(casci_ctx* ctx, int nalpha, int nbeta, int no
     ctx->tune_lpe[0] = ctx->tune_lpe[1] = 0;
     ctx->prepared = false;
     ctx->have_full = ctx->have_s2 = false;
-    ctx->have_tg_sym = ctx->have_tg_full = false;
+    ctx->have_tg_sym = ctx->have_tg_full = ctx->have_tg16 = false;
+    ctx->blk[0].have = ctx->blk[1].have = false;
     ctx->red_sym.have = ctx->red_full.have = false;
     ++ctx->gen;
     return CASCI_OK;
@@ -595,6 +617,12 @@ static int ensure_prepared(casci_ctx* ctx, double lambda)
                                        ctx->d_binom.as<int64_t>(), ctx->d_h.as<double>(),
                                        ctx->d_eri.as<double>(), ctx->ra, ctx->d_fa_col.as<int32_t>(),
                                        ctx->d_fa_val.as<double>(), st));
+        // rows in ascending column order past the diagonal: the canonical
+        // summation order of every gather, and what the row-blocked form needs
+        const auto sortable = [](int r) { return r - 1 <= sort_ss_rows_max(); };
+        ctx->ops_sorted = sortable(ctx->ra) && (ctx->nb == ctx->na || sortable(ctx->rb));
+        if (ctx->ops_sorted)
+            HIPC(launch_sort_ss_rows(ctx->Na, ctx->ra, ctx->d_fa_col.as<int32_t>(), ctx->d_fa_val.as<double>(), st));
         if (ctx->nb != ctx->na) {
             HIPC(ctx->d_fb_col.ensure((size_t)ctx->Nb * ctx->rb * 4));
             HIPC(ctx->d_fb_val.ensure((size_t)ctx->Nb * ctx->rb * 8));
@@ -602,6 +630,9 @@ static int ensure_prepared(casci_ctx* ctx, double lambda)
                                            ctx->d_binom.as<int64_t>(), ctx->d_h.as<double>(),
                                            ctx->d_eri.as<double>(), ctx->rb,
                                            ctx->d_fb_col.as<int32_t>(), ctx->d_fb_val.as<double>(), st));
+            if (ctx->ops_sorted)
+                HIPC(launch_sort_ss_rows(ctx->Nb, ctx->rb, ctx->d_fb_col.as<int32_t>(), ctx->d_fb_val.as<double>(),
+                                         st));
         } else {
             ctx->d_fb_col.release();
             ctx->d_fb_val.release();
@@ -643,7 +674,7 @@ static int ensure_prepared(casci_ctx* ctx, double lambda)
         CHECK_RC(upload_lowp(ctx, vt, ctx->d_vt_sym_lp));
         ctx->prepared = true;
         ctx->have_full = false;
-        ctx->have_tg_sym = ctx->have_tg_full = false;
+        ctx->have_tg_sym = ctx->have_tg_full = ctx->have_tg16 = false;
         ctx->red_sym.have = ctx->red_full.have = false;
         ++ctx->gen;
         ctx->prepared_lambda = std::nan("");
@@ -710,6 +741,19 @@ static int ensure_targets(casci_ctx* ctx, bool full, bool may_alloc = true)
     p.tg = tg.as<int32_t>();
     HIPC(launch_ab_targets(p, tg.as<int32_t>(), ctx->stream));
     have = true;
+    return CASCI_OK;
+}
+
+// 16-bit targets of the symmetric pair set in MFMA element order (the BF16
+// fixed-point kernel), converted from the 32-bit table
+static int ensure_tg16(casci_ctx* ctx, bool may_alloc = true)
+{
+    if (ctx->have_tg16) return CASCI_OK;
+    if (!may_alloc) return ctx->fail(CASCI_E_STATE, "16-bit scatter targets not built: run casci_sigma once first");
+    CHECK_RC(ensure_targets(ctx, false));
+    HIPC(ctx->d_tg16.ensure((size_t)tg16_entries(ctx->Nb, ctx->Mp_sym) * 2));
+    HIPC(launch_tg16(ctx->d_tg_sym.as<int32_t>(), ctx->Nb, ctx->Mp_sym, ctx->d_tg16.as<uint16_t>(), ctx->stream));
+    ctx->have_tg16 = true;
     return CASCI_OK;
 }
 
@@ -865,7 +909,97 @@ static SsOp ss_op(const casci_ctx* ctx, int spin)
     op.col16 = (b ? ctx->d_fb_c16 : ctx->d_fa_c16).as<uint16_t>();
     op.val32 = (b ? ctx->d_fb_v32 : ctx->d_fa_v32).as<float>();
     op.r = spin == 1 ? ctx->rb : ctx->ra;
+    const casci_ctx::Blocks& bl = ctx->blk[b ? 1 : 0];
+    if (bl.have) {
+        op.blk.uni = bl.uni.as<uint16_t>();
+        op.blk.binfo = bl.binfo.as<int4>();
+        op.blk.pos = bl.pos.as<uint16_t>();
+        op.blk.offs = bl.offs.as<uint16_t>();
+        op.blk.ch = 64;
+        op.blk.nblk = bl.nblk;
+    }
     return op;
+}
+
+// Row-blocked form of a same-spin operator for the SS_BLOCKED gather: rows in
+// blocks of SS_BLK_R, the sorted union of the columns of each block, every
+// entry's column as its position in that union, and for each row the first
+// entry of every 64-row chunk of the union. The diagonal (entry 0) stays
+// outside: the kernel takes it from the row itself. Built on the host from
+// the operator's columns (ascending within each row past the diagonal);
+// needs fewer than 65536 strings.
+static int ensure_ss_blocks(casci_ctx* ctx, int spin)
+{
+    const bool b = spin == 1 && ctx->nb != ctx->na;
+    casci_ctx::Blocks& bl = ctx->blk[b ? 1 : 0];
+    if (bl.have) return CASCI_OK;
+    const int64_t N = b ? ctx->Nb : ctx->Na;
+    const int r = b ? ctx->rb : ctx->ra;
+    // not available: the other widths serve
+    if (!ctx->ops_sorted || N <= 0 || r <= 1 || N >= 65536 || r >= 65536) return CASCI_OK;
+    const DBuf& dcol = b ? ctx->d_fb_col : ctx->d_fa_col;
+    std::vector<int32_t> col((size_t)N * r);
+    HIPC(hipMemcpyAsync(col.data(), dcol.p, col.size() * 4, hipMemcpyDeviceToHost, ctx->stream));
+    HIPC(hipStreamSynchronize(ctx->stream));
+    const int R = SS_BLK_R, CH = 64;
+    const int64_t nblk = (N + R - 1) / R;
+    std::vector<uint16_t> uni, pos((size_t)N * r), offs;
+    std::vector<int32_t> binfo((size_t)nblk * 4);
+    std::vector<int32_t> stamp((size_t)N, -1), where((size_t)N, 0);
+    std::vector<int32_t> u;
+    for (int64_t blk = 0; blk < nblk; ++blk) {
+        const int64_t I0 = blk * R, I1 = std::min<int64_t>(N, I0 + R);
+        u.clear();
+        for (int64_t I = I0; I < I1; ++I)
+            for (int e = 1; e < r; ++e) {
+                const int32_t J = col[(size_t)I * r + e];
+                if (J < 0 || J >= N) return ctx->fail(CASCI_E_DEVICE, "same-spin operator: column out of range");
+                if (e > 1 && J <= col[(size_t)I * r + e - 1])
+                    return ctx->fail(CASCI_E_DEVICE, "same-spin operator: row not in ascending column order");
+                if (stamp[J] != (int32_t)blk) {
+                    stamp[J] = (int32_t)blk;
+                    u.push_back(J);
+                }
+            }
+        std::sort(u.begin(), u.end());
+        for (size_t k = 0; k < u.size(); ++k) where[u[k]] = (int32_t)k;
+        const int nU = (int)u.size();
+        const int nch = (nU + CH - 1) / CH;
+        binfo[(size_t)blk * 4 + 0] = (int32_t)uni.size();
+        binfo[(size_t)blk * 4 + 1] = nU;
+        binfo[(size_t)blk * 4 + 2] = (int32_t)offs.size();
+        binfo[(size_t)blk * 4 + 3] = nch;
+        if (uni.size() + u.size() > 0x7fffffffu || offs.size() + (size_t)R * (nch + 1) > 0x7fffffffu)
+            return ctx->fail(CASCI_E_UNSUPPORTED, "same-spin operator too large for the row-blocked form");
+        for (int32_t J : u) uni.push_back((uint16_t)J);
+        for (int w = 0; w < R; ++w) {
+            const int64_t I = I0 + w;
+            int e = 1;
+            for (int ch = 0; ch <= nch; ++ch) {
+                if (I < I1)
+                    while (e < r && where[col[(size_t)I * r + e]] < ch * CH) ++e;
+                offs.push_back((uint16_t)(I < I1 ? e : 1));
+            }
+            if (I < I1) {
+                pos[(size_t)I * r] = 0;  // the diagonal: not staged
+                for (int q = 1; q < r; ++q) pos[(size_t)I * r + q] = (uint16_t)where[col[(size_t)I * r + q]];
+            }
+        }
+    }
+    if (uni.empty()) uni.push_back(0);
+    HIPC(bl.uni.ensure(uni.size() * 2));
+    HIPC(bl.binfo.ensure(binfo.size() * 4));
+    HIPC(bl.pos.ensure(pos.size() * 2));
+    HIPC(bl.offs.ensure(offs.size() * 2));
+    HIPC(hipMemcpyAsync(bl.uni.p, uni.data(), uni.size() * 2, hipMemcpyHostToDevice, ctx->stream));
+    HIPC(hipMemcpyAsync(bl.binfo.p, binfo.data(), binfo.size() * 4, hipMemcpyHostToDevice, ctx->stream));
+    HIPC(hipMemcpyAsync(bl.pos.p, pos.data(), pos.size() * 2, hipMemcpyHostToDevice, ctx->stream));
+    HIPC(hipMemcpyAsync(bl.offs.p, offs.data(), offs.size() * 2, hipMemcpyHostToDevice, ctx->stream));
+    HIPC(hipStreamSynchronize(ctx->stream));  // pageable sources
+    bl.nblk = nblk;
+    bl.have = true;
+    ++ctx->gen;  // captured graphs hold the operator without the blocks
+    return CASCI_OK;
 }
 
 // Autotuner of the same-spin gather: the strip width (lanes per gathered
@@ -901,10 +1035,11 @@ static int autotune_gather(casci_ctx* ctx, bool lowp, const double* C, const flo
     // timed on the first eighth of the rows (at least 2048): the same strips and
     // operator rows, a fraction of the cost on large spaces
     const int64_t nt = std::min<int64_t>(ctx->Na, std::max<int64_t>(2048, ctx->Na / 8));
-    static const int cand64[] = {16, 32, 64, 128, 1602, 3202};
-    static const int cand32[] = {16, 32, 64, 128, 1602, 3202, 1604, 3204, 6404};
-    const int* cand = lowp ? cand32 : cand64;
-    const int ncand = lowp ? 9 : 6;
+    static const int cand64[] = {SS_BLOCKED, 16, 32, 64, 128, 1602, 3202};
+    static const int cand32[] = {SS_BLOCKED, 16, 32, 64, 128, 1602, 3202, 1604, 3204, 6404};
+    const bool blk = ctx->blk[0].have;  // the blocked width joins when its tables exist
+    const int* cand = (lowp ? cand32 : cand64) + (blk ? 0 : 1);
+    const int ncand = (lowp ? 10 : 7) - (blk ? 0 : 1);
     for (int ci = 0; ci < ncand; ++ci) {
         const int lpe = cand[ci];
         auto run = [&]() {
@@ -965,7 +1100,7 @@ static size_t sigma_work_layout(const casci_ctx* ctx, int ab_prec, int parity, u
         x.t2 = (double*)take((size_t)Nd * 8);
     }
     if (has_ab) x.t3 = (double*)take((size_t)Nd * 8);
-    if (has_ab && !lowp) x.rowmax = (double*)take((size_t)Na * 8);
+    if (has_ab) x.rowmax = (double*)take((size_t)Na * 8);
     if (lowp) x.c32 = (float*)take((size_t)Na * lowp_ld(1, Nb) * 4);
     if (lowp && has_ab && ab_prec == CASCI_BF16) x.clp = take((size_t)Na * lowp_ld(2, Nb) * 2);
     if (w) *w = x;
@@ -1009,7 +1144,7 @@ static int sigma_dev(casci_ctx* ctx, const double* C, double* S, int ab_prec, do
             HIPC(ctx->d_t3.ensure((size_t)Nd * 8));
             w.t3 = ctx->d_t3.as<double>();
         }
-        if (has_ab && !lowp) {
+        if (has_ab) {
             HIPC(ctx->d_rowmax.ensure((size_t)Na * 8));
             w.rowmax = ctx->d_rowmax.as<double>();
         }
@@ -1048,17 +1183,25 @@ static int sigma_dev(casci_ctx* ctx, const double* C, double* S, int ab_prec, do
             HIPC(launch_ab_f64(p, vt.as<double>(), C, w.rowmax, w.t3, st));
         } else {
             const DBuf* lp = full ? ctx->d_vt_full_lp : ctx->d_vt_sym_lp;
-            AbReduce red;
-            CHECK_RC(ensure_reduce(ctx, full, &red, alloc));
-            if (ab_prec == CASCI_F32)
-                HIPC(launch_ab_lowp(p, red, 1, lp[0].p, w.c32, ld32, w.t3, st));
-            else
-                HIPC(launch_ab_lowp(p, red, 2, lp[1].p, w.clp, ld16, w.t3, st));
+            if (ab_prec == CASCI_BF16 && !full && ab_bf16_fixed_fits(Nb, ctx->sa, p.Mp)) {
+                // scatter from the accumulators into a fixed-point row (no reduction table)
+                CHECK_RC(ensure_tg16(ctx, alloc));
+                HIPC(launch_row_absmax(C, Na, Nb, w.rowmax, st));
+                HIPC(launch_ab_bf16_fixed(p, lp[1].p, w.clp, ld16, w.rowmax, ctx->d_tg16.as<uint16_t>(), w.t3, st));
+            } else {
+                AbReduce red;
+                CHECK_RC(ensure_reduce(ctx, full, &red, alloc));
+                if (ab_prec == CASCI_F32)
+                    HIPC(launch_ab_lowp(p, red, 1, lp[0].p, w.c32, ld32, w.t3, st));
+                else
+                    HIPC(launch_ab_lowp(p, red, 2, lp[1].p, w.clp, ld16, w.t3, st));
+            }
         }
         CHECK_RC(mark(4, st));
     }
     const double s_aa = parity != 0 ? 0.5 * shift : shift;  // halved: S + p S^T doubles it
     // the strip width changes only the speed, not the sums (fixed summation order)
+    if (alloc) CHECK_RC(ensure_ss_blocks(ctx, 0));
     if (alloc && ctx->tune_lpe[lowp ? 1 : 0] == 0) CHECK_RC(autotune_gather(ctx, lowp, C, w.c32, ld32));
     const int lpe = ctx->tune_lpe[lowp ? 1 : 0];
     if (lowp)
@@ -1186,7 +1329,9 @@ static std::vector<void*> sigma_buffers(const casci_ctx* ctx)
             ctx->d_tg_sym.p, ctx->d_tg_full.p, ctx->red_sym.tab.p, ctx->red_sym.tinfo.p, ctx->red_full.tab.p,
             ctx->red_full.tinfo.p, ctx->d_la_j.p, ctx->d_la_pq.p, ctx->d_lb_j.p, ctx->d_bstr.p,
             ctx->d_pairs_sym.p, ctx->d_pairs_full.p, ctx->d_gin.p, ctx->d_gout.p, ctx->d_fa_c16.p,
-            ctx->d_fa_v32.p, ctx->d_fb_c16.p, ctx->d_fb_v32.p, ctx->d_rowmax.p};
+            ctx->d_fa_v32.p, ctx->d_fb_c16.p, ctx->d_fb_v32.p, ctx->d_rowmax.p, ctx->d_tg16.p, ctx->blk[0].uni.p,
+            ctx->blk[0].pos.p, ctx->blk[0].offs.p, ctx->blk[0].binfo.p, ctx->blk[1].uni.p, ctx->blk[1].pos.p,
+            ctx->blk[1].offs.p, ctx->blk[1].binfo.p};
 }
 
 // sigma_dev replayed from a captured HIP graph: one launch per build instead
@@ -1253,9 +1398,9 @@ extern "C" int casci_set_tuning(casci_ctx* ctx, int f64_lpe, int f32in_lpe)
     if (!ctx) return CASCI_E_ARG;
     for (int v : {f64_lpe, f32in_lpe})
         if (v != 0 && v != 16 && v != 32 && v != 64 && v != 128 && v != 1602 && v != 3202 && v != 1604 &&
-            v != 3204 && v != 6404)
+            v != 3204 && v != 6404 && v != SS_BLOCKED)
             return ctx->fail(CASCI_E_ARG,
-                             "strip width code must be 0, 16, 32, 64, 128, 1602, 3202, 1604, 3204 or 6404");
+                             "strip width code must be 0, 16, 32, 64, 128, 1602, 3202, 1604, 3204, 6404 or 99");
     ctx->tune_lpe[0] = f64_lpe;
     ctx->tune_lpe[1] = f32in_lpe;
     ++ctx->gen;  // captured graphs hold the old choice
@@ -1539,6 +1684,102 @@ extern "C" int casci_spin_square(casci_ctx* ctx, const double* C, double* s2, in
         c = ctx->d_vin.as<double>();
     }
     return spin_square_dev(ctx, c, s2);
+}
+
+// ---------------------------------------------------------------------------
+// reduced density matrices
+// ---------------------------------------------------------------------------
+// g1 (device, 2 n^2) and g2 (device, 3 n^4 or null) of a device vector C: the
+// rows M = [D^alpha ; D^beta ; C] of a block of alpha strings (at most 512 MiB)
+// are filled on the device and their Gram matrix G = M M^T accumulated block
+// by block with a library DGEMM (fixed blocking, so the sums are reproducible),
+// then the matrices are read off G (rdm_kernels.hip).
+static int rdm_dev(casci_ctx* ctx, const double* C, double* g1, double* g2)
+{
+    hipStream_t st = ctx->stream;
+    const int n = ctx->norb;
+    const int64_t R = 2 * (int64_t)n * n + 1;
+    const int64_t Na = ctx->Na, Nb = ctx->Nb;
+    const int64_t per_alpha = R * Nb * 8;
+    int64_t nblk = std::max<int64_t>(1, ((int64_t)512 << 20) / per_alpha);
+    nblk = std::min(nblk, Na);
+    if (nblk * Nb > 0x7fffffffLL) nblk = std::max<int64_t>(1, 0x7fffffffLL / Nb);
+    HIPC(ctx->d_rdm_M.ensure((size_t)(R * nblk * Nb * 8)));
+    HIPC(ctx->d_rdm_G.ensure((size_t)(R * R * 8)));
+    if (!ctx->blas) {
+        if (rocblas_create_handle(&ctx->blas) != rocblas_status_success) {
+            ctx->blas = nullptr;
+            return ctx->fail(CASCI_E_DEVICE, "rocblas_create_handle failed");
+        }
+    }
+    if (rocblas_set_stream(ctx->blas, st) != rocblas_status_success)
+        return ctx->fail(CASCI_E_DEVICE, "rocblas_set_stream failed");
+    double* M = ctx->d_rdm_M.as<double>();
+    double* G = ctx->d_rdm_G.as<double>();
+    const double one = 1.0, zero = 0.0;
+    for (int64_t a0 = 0; a0 < Na; a0 += nblk) {
+        const int64_t b = std::min(nblk, Na - a0);
+        const int64_t ldm = b * Nb;
+        HIPC(launch_rdm_fill(C, a0, b, Nb, n, ctx->na, ctx->nb, ctx->d_astr.as<uint64_t>(),
+                             ctx->d_bstr.as<uint64_t>(), ctx->d_la_j.as<int32_t>(), ctx->sa,
+                             ctx->d_lb_j.as<int32_t>(), ctx->sb, M, ldm, st));
+        // G (+)= M M^T: M is the column-major ldm x R matrix A = M^T, G = A^T A
+        const rocblas_status s = rocblas_dgemm(ctx->blas, rocblas_operation_transpose, rocblas_operation_none,
+                                               (rocblas_int)R, (rocblas_int)R, (rocblas_int)ldm, &one, M,
+                                               (rocblas_int)ldm, M, (rocblas_int)ldm, a0 == 0 ? &zero : &one, G,
+                                               (rocblas_int)R);
+        if (s != rocblas_status_success)
+            return ctx->fail(CASCI_E_DEVICE, std::string("rocblas_dgemm: ") + rocblas_status_to_string(s));
+    }
+    HIPC(launch_rdm_assemble(G, n, g1, g2, st));
+    return CASCI_OK;
+}
+
+static int rdm_common(casci_ctx* ctx, const double* C, int mem, bool two, bool spin_free, double* o1, double* o2)
+{
+    if (!ctx) return CASCI_E_ARG;
+    if (!C || !o1) return ctx->fail(CASCI_E_ARG, "C and the one-particle output must not be NULL");
+    if (mem != CASCI_MEM_HOST && mem != CASCI_MEM_DEVICE) return ctx->fail(CASCI_E_ARG, "bad mem flag");
+    if (!ctx->has_strings) return ctx->fail(CASCI_E_STATE, "build_strings first");
+    const int n = ctx->norb;
+    const size_t n2 = (size_t)n * n, n4 = n2 * n2;
+    CHECK_RC(need_device(ctx));
+    DeviceGuard g(ctx->device);
+    hipStream_t st = ctx->stream;
+    const double* c = C;
+    if (mem == CASCI_MEM_HOST) {
+        HIPC(ctx->d_vin.ensure((size_t)ctx->Nd * 8));
+        HIPC(hipMemcpyAsync(ctx->d_vin.p, C, (size_t)ctx->Nd * 8, hipMemcpyHostToDevice, st));
+        c = ctx->d_vin.as<double>();
+    }
+    // outputs on the device: spin-resolved g1, g2, then the spin sums
+    const size_t nres = 2 * n2 + (two ? 3 * n4 : 0), nsf = spin_free ? n2 + (two ? n4 : 0) : 0;
+    HIPC(ctx->d_rdm_out.ensure((nres + nsf) * 8));
+    double* g1 = ctx->d_rdm_out.as<double>();
+    double* g2 = two ? g1 + 2 * n2 : nullptr;
+    CHECK_RC(rdm_dev(ctx, c, g1, g2));
+    if (spin_free) {
+        double* gam = g1 + nres;
+        double* Gam = two ? gam + n2 : nullptr;
+        HIPC(launch_rdm_spin_free(g1, g2, n, gam, Gam, st));
+        HIPC(hipMemcpyAsync(o1, gam, n2 * 8, hipMemcpyDeviceToHost, st));
+        if (two) HIPC(hipMemcpyAsync(o2, Gam, n4 * 8, hipMemcpyDeviceToHost, st));
+    } else {
+        HIPC(hipMemcpyAsync(o1, g1, 2 * n2 * 8, hipMemcpyDeviceToHost, st));
+        if (two) HIPC(hipMemcpyAsync(o2, g2, 3 * n4 * 8, hipMemcpyDeviceToHost, st));
+    }
+    HIPC(hipStreamSynchronize(st));
+    return CASCI_OK;
+}
+
+extern "C" int casci_rdm(casci_ctx* ctx, const double* C, int mem, double* g1, double* g2)
+{
+    return rdm_common(ctx, C, mem, g2 != nullptr, false, g1, g2);
+}
+
+extern "C" int casci_rdm_spin_free(casci_ctx* ctx, const double* C, int mem, double* gamma, double* Gamma)
+{
+    return rdm_common(ctx, C, mem, Gamma != nullptr, true, gamma, Gamma);
 }
 
 // ---------------------------------------------------------------------------

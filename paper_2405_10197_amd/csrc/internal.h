@@ -39,6 +39,10 @@ hipError_t launch_build_strings(int n, int ne, int64_t N, const int64_t* binom, 
                                 hipStream_t st);
 hipError_t launch_single_lists(int n, int ne, int64_t N, const uint64_t* strs, const int64_t* binom,
                                int s, int32_t* lj, uint16_t* lpq, hipStream_t st);
+// entries 1..r-1 of every row in ascending column order (diagonal first);
+// rows longer than sort_ss_rows_max() + 1 entries are refused
+int sort_ss_rows_max();
+hipError_t launch_sort_ss_rows(int64_t N, int r, int32_t* col, double* val, hipStream_t st);
 hipError_t launch_same_spin_operator(int n, int ne, int64_t N, const uint64_t* strs,
                                      const int64_t* binom, const double* h, const double* eri,
                                      int r, int32_t* col, double* val, hipStream_t st);
@@ -58,12 +62,28 @@ hipError_t launch_scatter_values(const int64_t* idx, const double* v, int P, dou
 // A same-spin operator in row form: r entries per row, int32 columns and
 // FP64 values; optional compact copies (16-bit columns when there are fewer
 // than 65536 strings, FP32 values) that the gathers use when present.
+// Row-blocked form of a same-spin operator (strip width code SS_BLOCKED): rows
+// in blocks of SS_BLK_R; per block the sorted union of the columns its rows
+// touch; every entry's column as a position in its block's union. The
+// gather stages the union rows of X in LDS, SS_BLK_CH at a time, and each row
+// reads its operands there (built by build_ss_blocks in casci.cpp).
+constexpr int SS_BLOCKED = 99;
+constexpr int SS_BLK_R = 16;
+struct SsBlk {
+    const uint16_t* uni;   // unions of all blocks, concatenated (string indices < 65536)
+    const int4* binfo;     // per block {union offset, union size, offsets offset, chunks}
+    const uint16_t* pos;   // [N][r]: position of the entry's column in its block's union
+    const uint16_t* offs;  // per block [SS_BLK_R][chunks + 1]: first entry of each chunk
+    int ch;                // union rows per chunk
+    int64_t nblk;
+};
 struct SsOp {
     const int32_t* col;
     const double* val;
     const uint16_t* col16;  // may be null
     const float* val32;     // may be null
     int r;
+    SsBlk blk = {nullptr, nullptr, nullptr, nullptr, 0, 0};  // row-blocked form (blk.uni null: none)
 };
 // Y(I,:) = [acc ? Y(I,:) : 0] + sum_e val[I*r+e] X(col[I*r+e], :) + shift * X(I,:)
 // (lpe: strip width code 16/32/64 lanes per entry, 128 = 64 lanes x 2 columns; 0 = 64).
@@ -149,6 +169,16 @@ hipError_t launch_ab_lowp_bf16(const AbParams& p, const AbReduce& r, const void*
                                double* sigma, hipStream_t st);
 hipError_t launch_ab_lowp_bf16(const AbParams& p, const AbReduce& r, const void* Vt, const void* Cs, int64_t ldc,
                                float* sigma, hipStream_t st);
+// BF16 contraction with the scatter from the accumulators into a 32-bit
+// fixed-point sigma row (ab_bf16_fixed.hip): symmetric pairs, Nb < 32767 and
+// the row in LDS; tg16 from launch_tg16 (tg16_entries(Nb, Mp) entries)
+bool ab_bf16_fixed_fits(int64_t Nb, int sa, int Mp);
+int64_t tg16_entries(int64_t Nb, int Mp);
+hipError_t launch_tg16(const int32_t* tg, int64_t Nb, int Mp, uint16_t* out, hipStream_t st);
+hipError_t launch_ab_bf16_fixed(const AbParams& p, const void* Vt, const void* Cs, int64_t ldc, const double* rowmax,
+                                const uint16_t* tg16, double* sigma, hipStream_t st);
+hipError_t launch_ab_bf16_fixed(const AbParams& p, const void* Vt, const void* Cs, int64_t ldc, const double* rowmax,
+                                const uint16_t* tg16, float* sigma, hipStream_t st);
 // padded row stride of the low-precision copy of C, and the conversion itself
 int64_t lowp_ld(int prec, int64_t cols);
 hipError_t launch_convert_lowp(int prec, const double* C, void* out, int64_t rows, int64_t cols,
@@ -178,6 +208,16 @@ hipError_t launch_scale(double* x, double a, int64_t n, hipStream_t st);
 // out[0] = x_i and out[1] = i for the largest |x_i| (ties: lowest i); work holds
 // 2 * 512 doubles of partials
 hipError_t launch_absmax(const double* x, int64_t n, double* work, double* out, hipStream_t st);
+
+// rdm_kernels.hip (density matrices)
+// rows [D^alpha_pq ; D^beta_pq ; C] (row stride ldm) of the determinants of alpha strings [a0, a0 + nblk)
+hipError_t launch_rdm_fill(const double* C, int64_t a0, int64_t nblk, int64_t Nb, int n, int na, int nb,
+                           const uint64_t* astr, const uint64_t* bstr, const int32_t* la_j, int sa,
+                           const int32_t* lb_j, int sb, double* M, int64_t ldm, hipStream_t st);
+// spin-resolved g1[2][n][n] and g2[3][n^4] (may be null) from the Gram matrix G (R = 2n^2+1, column-major)
+hipError_t launch_rdm_assemble(const double* G, int n, double* g1, double* g2, hipStream_t st);
+// spin sums gamma[n][n], Gamma[n^4] (may be null) of g1, g2
+hipError_t launch_rdm_spin_free(const double* g1, const double* g2, int n, double* gam, double* Gam, hipStream_t st);
 
 // mlp_kernels.hip (learned preconditioner)
 constexpr int MLP_IN = 8, MLP_HIDDEN = 64;

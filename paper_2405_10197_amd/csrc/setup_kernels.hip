@@ -8,6 +8,9 @@
 // in ascending integer order. It is gap-free and needs no hash table.
 #include "internal.h"
 
+#include <algorithm>
+#include <climits>
+
 namespace casci {
 
 __device__ inline int64_t rank_of(uint64_t mask, const int64_t* binom, int ld)
@@ -201,6 +204,74 @@ hipError_t launch_same_spin_operator(int n, int ne, int64_t N, const uint64_t* s
     if (N <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_same_spin_operator, dim3(nblk(N, 64)), dim3(64), 0, st, n, ne, N, strs,
                        binom, h, eri, r, col, val);
+    return hipGetLastError();
+}
+
+// Entries 1..r-1 of every operator row put in ascending column order (the
+// diagonal stays at entry 0): one workgroup per row, bitonic sort of the
+// (column, value) pairs in LDS, padded to P = 2^k >= r - 1 with columns
+// INT32_MAX. Columns within a row are distinct, so the order is unique.
+__global__ __launch_bounds__(256) void k_sort_ss_rows(int64_t N, int r, int P, int32_t* __restrict__ col,
+                                                      double* __restrict__ val)
+{
+    extern __shared__ __align__(16) unsigned char sm[];
+    double* sv = reinterpret_cast<double*>(sm);
+    int32_t* sc = reinterpret_cast<int32_t*>(sv + P);
+    const int m = r - 1;
+    for (int64_t I = blockIdx.x; I < N; I += gridDim.x) {
+        int32_t* c = col + I * r + 1;
+        double* v = val + I * r + 1;
+        for (int k = threadIdx.x; k < P; k += blockDim.x) {
+            sc[k] = k < m ? c[k] : INT32_MAX;
+            sv[k] = k < m ? v[k] : 0.0;
+        }
+        __syncthreads();
+        for (int size = 2; size <= P; size <<= 1)
+            for (int stride = size >> 1; stride > 0; stride >>= 1) {
+                for (int k = threadIdx.x; k < P; k += blockDim.x) {
+                    const int l = k ^ stride;
+                    if (l <= k) continue;
+                    const bool up = (k & size) == 0;
+                    const int32_t a = sc[k], b = sc[l];
+                    if ((a > b) == up) {
+                        sc[k] = b;
+                        sc[l] = a;
+                        const double t = sv[k];
+                        sv[k] = sv[l];
+                        sv[l] = t;
+                    }
+                }
+                __syncthreads();
+            }
+        for (int k = threadIdx.x; k < m; k += blockDim.x) {
+            c[k] = sc[k];
+            v[k] = sv[k];
+        }
+        __syncthreads();
+    }
+}
+
+int sort_ss_rows_max() { return 8192; }
+
+hipError_t launch_sort_ss_rows(int64_t N, int r, int32_t* col, double* val, hipStream_t st)
+{
+    const int m = r - 1;
+    if (N <= 0 || m <= 1) return hipSuccess;
+    int P = 2;
+    while (P < m) P <<= 1;
+    if (P > sort_ss_rows_max()) {
+        set_launch_reason("same-spin operator: rows too long to sort in LDS");
+        return hipErrorInvalidValue;
+    }
+    const size_t lds = (size_t)P * 12;
+    hipError_t e = hipFuncSetAttribute((const void*)k_sort_ss_rows, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)lds);
+    if (e != hipSuccess) {
+        set_launch_reason("hipFuncSetAttribute(max dynamic LDS) failed");
+        return e;
+    }
+    const unsigned g = (unsigned)std::min<int64_t>(N, 1 << 16);
+    hipLaunchKernelGGL(k_sort_ss_rows, dim3(g), dim3(256), lds, st, N, r, P, col, val);
     return hipGetLastError();
 }
 

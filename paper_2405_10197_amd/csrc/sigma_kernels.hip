@@ -204,6 +204,132 @@ static hipError_t ss_gather(const TC* col, const TV* val, int r, int64_t nrows,
     return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// row-blocked same-spin gather (strip width code SS_BLOCKED)
+// ---------------------------------------------------------------------------
+// One workgroup of SS_BLK_R waves takes one block of SS_BLK_R consecutive rows
+// and one strip of 64 columns; wave w computes row b*R + w. The rows of X the
+// block needs (the sorted union of its rows' columns) are staged into LDS,
+// CH at a time in two buffers (the loads of the next chunk are in flight while
+// the current one is used), and each wave adds the entries of its row whose
+// column falls in the chunk, reading X from LDS. Neighbouring strings share
+// most of their neighbours (16 rows touch about 4000 distinct rows at n = 16
+// against 16 x 849 entries), so each row of X crosses the L2 once per block
+// instead of once per entry. The diagonal (entry 0, column I) comes from row
+// I of X directly; the entries 1..r-1 are stored in ascending column order,
+// so the ones of a chunk are contiguous. Summation order: that of the other
+// widths (accumulator k sums the entries e = k mod 4 in ascending order,
+// total (a0 + a1) + (a2 + a3)); entries are read in aligned groups of four,
+// and the ones outside the chunk enter as v = 0.
+template <typename TX, typename TY, typename TV, int CH>
+__global__ __launch_bounds__(64 * SS_BLK_R) void k_ss_gather_blk(SsBlk bk, const TV* __restrict__ val, int r,
+                                                                 int64_t nrows, int64_t ncols,
+                                                                 const TX* __restrict__ X, int64_t ldx,
+                                                                 TY* __restrict__ Y, double shift, int acc,
+                                                                 int64_t nitems)
+{
+    constexpr int RPW = CH / SS_BLK_R;      // union rows a wave stages per chunk
+    constexpr int SUB = CH / 64;            // 64-row chunks of the offsets table per stage
+    extern __shared__ __align__(16) unsigned char smem[];
+    TX* stage = reinterpret_cast<TX*>(smem);  // [2][CH][64]
+    const int64_t per_xcd = gridDim.x / 8;
+    const int64_t t = (int64_t)(blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
+    if (t >= nitems) return;
+    const int64_t strip = t / bk.nblk, b = t - strip * bk.nblk;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int64_t c = strip * 64 + lane;
+    const bool cok = c < ncols;
+    const int4 bi = bk.binfo[b];
+    const uint16_t* U = bk.uni + bi.x;
+    const int nU = bi.y, nch64 = bi.w;
+    const int nch = (nch64 + SUB - 1) / SUB;
+    const uint16_t* offs = bk.offs + bi.z + wave * (nch64 + 1);
+    const int64_t I = b * SS_BLK_R + wave;
+    const bool rowok = I < nrows;
+    TX pf[RPW];
+    auto issue = [&](int ch) {
+#pragma unroll
+        for (int i = 0; i < RPW; ++i) {
+            const int k = ch * CH + wave * RPW + i;
+            TX v = (TX)0;
+            if (k < nU && cok) v = X[(int64_t)U[k] * ldx + c];
+            pf[i] = v;
+        }
+    };
+    auto commit = [&](int buf) {
+#pragma unroll
+        for (int i = 0; i < RPW; ++i) stage[((int64_t)buf * CH + wave * RPW + i) * 64 + lane] = pf[i];
+    };
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    // entry 0 (the diagonal, column I) is read from the row itself, the
+    // staged union holds the columns of entries 1..r-1
+    const double xI = rowok && cok ? (double)X[I * ldx + c] : 0.0;
+    if (rowok) a0 += (double)val[I * r] * xI;
+    issue(0);
+    commit(0);
+    __syncthreads();
+    for (int ch = 0; ch < nch; ++ch) {
+        if (ch + 1 < nch) issue(ch + 1);
+        if (rowok) {
+            const int e0 = offs[ch * SUB], e1 = offs[min((ch + 1) * SUB, nch64)];
+            const TX* sb = stage + (int64_t)(ch & 1) * CH * 64;
+            const int p0 = ch * CH;
+            for (int base = e0 & ~3; base < e1; base += 64) {
+                const int e = base + lane;
+                const bool in = e >= e0 && e < e1;
+                const int pj = in ? (int)bk.pos[I * r + e] - p0 : 0;
+                const TV vj = in ? val[I * r + e] : (TV)0;
+                const int cnt = min(64, e1 - base);
+                for (int j = 0; j < cnt; j += 4) {
+                    // entries base + j + 0..3 go to accumulators 0..3 (base, j multiples of 4)
+                    const int q0 = bcast_i32(pj, j), q1 = bcast_i32(pj, j + 1);
+                    const int q2 = bcast_i32(pj, j + 2), q3 = bcast_i32(pj, j + 3);
+                    const double v0 = (double)bcast_val(vj, j), v1 = (double)bcast_val(vj, j + 1);
+                    const double v2 = (double)bcast_val(vj, j + 2), v3 = (double)bcast_val(vj, j + 3);
+                    const double x0 = (double)sb[q0 * 64 + lane], x1 = (double)sb[q1 * 64 + lane];
+                    const double x2 = (double)sb[q2 * 64 + lane], x3 = (double)sb[q3 * 64 + lane];
+                    a0 += v0 * x0;
+                    a1 += v1 * x1;
+                    a2 += v2 * x2;
+                    a3 += v3 * x3;
+                }
+            }
+        }
+        if (ch + 1 < nch) commit((ch + 1) & 1);
+        __syncthreads();
+    }
+    if (rowok && cok) {
+        const int64_t o = I * ncols + c;
+        double y = ((a0 + a1) + (a2 + a3)) + shift * xI;
+        if (acc) y += (double)Y[o];
+        Y[o] = (TY)y;
+    }
+}
+
+template <typename TX, typename TY, typename TV>
+static hipError_t ss_gather_blk(const SsBlk& bk, const TV* val, int r, int64_t nrows, int64_t ncols, const TX* X,
+                                int64_t ldx, TY* Y, double shift, int acc, hipStream_t st)
+{
+    if (nrows <= 0 || ncols <= 0) return hipSuccess;
+    if (!bk.uni || bk.ch != 64) return invalid("same-spin gather: no row-blocked operator");
+    // a prefix of the rows (the autotuner times one) takes the blocks that cover it
+    SsBlk b = bk;
+    b.nblk = (nrows + SS_BLK_R - 1) / SS_BLK_R;
+    if (b.nblk > bk.nblk) return invalid("same-spin gather: more rows than the row-blocked operator has");
+    constexpr int CH = sizeof(TX) == 4 ? 128 : 64;  // 32 KB per stage buffer either way
+    const int64_t nstrip = (ncols + 63) / 64;
+    const int64_t nitems = nstrip * b.nblk;
+    if (nitems > ((int64_t)1 << 31) - 8) return invalid("same-spin gather: too many row blocks x strips");
+    const int64_t grid = (nitems + 7) / 8 * 8;
+    const size_t lds = (size_t)2 * CH * 64 * sizeof(TX);
+    auto kern = k_ss_gather_blk<TX, TY, TV, CH>;
+    hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return invalid("hipFuncSetAttribute(max dynamic LDS) failed");
+    hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(64 * SS_BLK_R), lds, st, b, val, r, nrows, ncols, X, ldx,
+                       Y, shift, acc, nitems);
+    return hipGetLastError();
+}
+
 // strip width code: 16 / 32 / 64 lanes per entry with one column each, 128 =
 // 64 lanes with two adjacent columns each, or LPE * 100 + VW for LPE lanes per
 // entry with VW adjacent columns each (1602, 3202: 16-byte loads of FP64 pairs
@@ -247,6 +373,9 @@ static hipError_t ss_gather_w(const TC* col, const TV* val, int r, int64_t nrows
 hipError_t launch_ss_gather_f64(const SsOp& op, int64_t nrows, int64_t ncols, const double* X, double* Y,
                                 double shift, int acc, hipStream_t st, int lpe)
 {
+    if (lpe == SS_BLOCKED && op.blk.uni)
+        return ss_gather_blk<double, double>(op.blk, op.val, op.r, nrows, ncols, X, ncols, Y, shift, acc, st);
+    if (lpe == SS_BLOCKED) lpe = 64;
     if (op.col16)
         return ss_gather_w<double, double>(op.col16, op.val, op.r, nrows, ncols, X, ncols, Y, shift, acc, st, lpe);
     return ss_gather_w<double, double>(op.col, op.val, op.r, nrows, ncols, X, ncols, Y, shift, acc, st, lpe);
@@ -255,6 +384,9 @@ hipError_t launch_ss_gather_f64(const SsOp& op, int64_t nrows, int64_t ncols, co
 hipError_t launch_ss_gather_f32in(const SsOp& op, int64_t nrows, int64_t ncols, const float* X, int64_t ldx,
                                   double* Y, double shift, int acc, hipStream_t st, int lpe)
 {
+    if (lpe == SS_BLOCKED && op.blk.uni && op.val32)
+        return ss_gather_blk<float, double>(op.blk, op.val32, op.r, nrows, ncols, X, ldx, Y, shift, acc, st);
+    if (lpe == SS_BLOCKED) lpe = 64;
     if (op.col16 && op.val32)
         return ss_gather_w<float, double>(op.col16, op.val32, op.r, nrows, ncols, X, ldx, Y, shift, acc, st, lpe);
     return ss_gather_w<float, double>(op.col, op.val, op.r, nrows, ncols, X, ldx, Y, shift, acc, st, lpe);
@@ -263,6 +395,9 @@ hipError_t launch_ss_gather_f32in(const SsOp& op, int64_t nrows, int64_t ncols, 
 hipError_t launch_ss_gather_f32(const SsOp& op, int64_t nrows, int64_t ncols, const float* X, float* Y,
                                 double shift, int acc, hipStream_t st, int lpe)
 {
+    if (lpe == SS_BLOCKED && op.blk.uni && op.val32)
+        return ss_gather_blk<float, float>(op.blk, op.val32, op.r, nrows, ncols, X, ncols, Y, shift, acc, st);
+    if (lpe == SS_BLOCKED) lpe = 64;
     if (op.col16 && op.val32)
         return ss_gather_w<float, float>(op.col16, op.val32, op.r, nrows, ncols, X, ncols, Y, shift, acc, st, lpe);
     return ss_gather_w<float, float>(op.col, op.val, op.r, nrows, ncols, X, ncols, Y, shift, acc, st, lpe);

@@ -296,3 +296,21 @@ def test_sigma_parity_argument_checks(L):
     S = np.zeros(nd)
     assert L.casci_sigma_parity(d._h, C.ctypes.data, S.ctypes.data, casci.F64, 1, casci.MEM_HOST) == casci.E_ARG
     assert "nalpha == nbeta" in d.last_error()
+
+
+def test_rdm_argument_checks(L):
+    c = vctx()
+    C = np.zeros(16)
+    g1 = np.zeros((2, 4, 4))
+    # strings first
+    assert L.casci_rdm(c._h, C.ctypes.data, casci.MEM_HOST, g1.ctypes.data, None) == casci.E_STATE
+    c.build_strings(2, 2, 4)
+    C = np.zeros(c.dims["Ndet"])
+    assert L.casci_rdm(c._h, None, casci.MEM_HOST, g1.ctypes.data, None) == casci.E_ARG
+    assert L.casci_rdm(c._h, C.ctypes.data, 7, g1.ctypes.data, None) == casci.E_ARG
+    assert L.casci_rdm(c._h, C.ctypes.data, casci.MEM_HOST, None, None) == casci.E_ARG
+    # integrals are not needed; a validate-only context stops at the device check
+    assert L.casci_rdm(c._h, C.ctypes.data, casci.MEM_HOST, g1.ctypes.data, None) == casci.E_UNSUPPORTED
+    assert L.casci_rdm_spin_free(c._h, C.ctypes.data, casci.MEM_HOST, g1.ctypes.data, None) == casci.E_UNSUPPORTED
+    with pytest.raises(ValueError):
+        c.rdm(np.zeros(c.dims["Ndet"] + 1))

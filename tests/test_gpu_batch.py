@@ -54,7 +54,7 @@ def test_graph_replay_reproduces_eager_solve(torch, prec):
     assert np.array_equal(E0, E1)
 
 
-WIDTHS = (16, 32, 64, 128, 1602, 3202, 1604, 3204, 6404)
+WIDTHS = (16, 32, 64, 128, 1602, 3202, 1604, 3204, 6404, 99)
 
 
 @pytest.mark.parametrize("n", [8, 9])

@@ -173,7 +173,7 @@ def test_sigma_is_reproducible(torch):
         assert torch.equal(a, b), prec
     # and independent of the autotuned strip width of the same-spin gathers
     ref = c.sigma(Ct)
-    for lpe in (16, 32, 64, 128, 1602, 3202, 1604, 3204, 6404):
+    for lpe in (16, 32, 64, 128, 1602, 3202, 1604, 3204, 6404, 99):
         c.set_tuning(lpe, lpe)
         assert torch.equal(c.sigma(Ct), ref), lpe
     c.set_tuning(0, 0)
