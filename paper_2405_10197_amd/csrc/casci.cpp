@@ -113,7 +113,7 @@ struct casci_ctx {
     DBuf d_h, d_eri, d_fa_col, d_fa_val, d_fb_col, d_fb_val, d_jpq, d_diag;
     DBuf d_fa_c16, d_fa_v32, d_fb_c16, d_fb_v32;  // compact operator copies (< 65536 strings)
     struct Blocks {  // row-blocked form of one same-spin operator (SsBlk)
-        DBuf uni, binfo, pos, offs;
+        DBuf uni, binfo, goff, rbase, gs64, gs32;
         int64_t nblk = 0;
         bool have = false;
     } blk[2];        // [0]: alpha (and beta when nalpha = nbeta), [1]: beta
@@ -289,10 +289,7 @@ extern "C" void casci_destroy(casci_ctx* ctx)
                         &ctx->d_rdm_M, &ctx->d_rdm_G, &ctx->d_rdm_out};
         if (ctx->blas) (void)rocblas_destroy_handle(ctx->blas);
         for (auto& bl : ctx->blk) {
-            bl.uni.release();
-            bl.binfo.release();
-            bl.pos.release();
-            bl.offs.release();
+            for (DBuf* d : {&bl.uni, &bl.binfo, &bl.goff, &bl.rbase, &bl.gs64, &bl.gs32}) d->release();
         }
         for (auto& gr : ctx->graphs) (void)hipGraphExecDestroy(gr.exec);
         ctx->graphs.clear();
@@ -913,21 +910,25 @@ static SsOp ss_op(const casci_ctx* ctx, int spin)
     if (bl.have) {
         op.blk.uni = bl.uni.as<uint16_t>();
         op.blk.binfo = bl.binfo.as<int4>();
-        op.blk.pos = bl.pos.as<uint16_t>();
-        op.blk.offs = bl.offs.as<uint16_t>();
-        op.blk.ch = 64;
+        op.blk.goff = bl.goff.as<uint16_t>();
+        op.blk.rbase = bl.rbase.as<int32_t>();
+        op.blk.gs64 = bl.gs64.as<SsGroup>();
+        op.blk.gs32 = bl.gs32.as<SsGroup>();
+        op.blk.ch = SS_BLK_CH;
         op.blk.nblk = bl.nblk;
     }
     return op;
 }
 
 // Row-blocked form of a same-spin operator for the SS_BLOCKED gather: rows in
-// blocks of SS_BLK_R, the sorted union of the columns of each block, every
-// entry's column as its position in that union, and for each row the first
-// entry of every 64-row chunk of the union. The diagonal (entry 0) stays
-// outside: the kernel takes it from the row itself. Built on the host from
-// the operator's columns (ascending within each row past the diagonal);
-// needs fewer than 65536 strings.
+// blocks of SS_BLK_R, the sorted union of the columns of each block, and per
+// row its entries 1..r-1 (ascending columns) as groups of four aligned to the
+// entry index, split by chunks of SS_BLK_CH union rows: a group holds the LDS
+// offsets of its operands and the values of entries 4g..4g+3 (one stream for
+// FP64 input, one with FP32-rounded values for FP32 input), a slot outside
+// the chunk value 0 and the chunk's first union row. The diagonal (entry 0)
+// stays outside: the kernel takes it from the row itself. Built on the host
+// from the operator's rows; needs fewer than 65536 strings.
 static int ensure_ss_blocks(casci_ctx* ctx, int spin)
 {
     const bool b = spin == 1 && ctx->nb != ctx->na;
@@ -936,15 +937,21 @@ static int ensure_ss_blocks(casci_ctx* ctx, int spin)
     const int64_t N = b ? ctx->Nb : ctx->Na;
     const int r = b ? ctx->rb : ctx->ra;
     // not available: the other widths serve
-    if (!ctx->ops_sorted || N <= 0 || r <= 1 || N >= 65536 || r >= 65536) return CASCI_OK;
+    if (!ctx->ops_sorted || N <= 0 || r <= 1 || N >= 65536) return CASCI_OK;
     const DBuf& dcol = b ? ctx->d_fb_col : ctx->d_fa_col;
+    const DBuf& dval = b ? ctx->d_fb_val : ctx->d_fa_val;
     std::vector<int32_t> col((size_t)N * r);
+    std::vector<double> val((size_t)N * r);
     HIPC(hipMemcpyAsync(col.data(), dcol.p, col.size() * 4, hipMemcpyDeviceToHost, ctx->stream));
+    HIPC(hipMemcpyAsync(val.data(), dval.p, val.size() * 8, hipMemcpyDeviceToHost, ctx->stream));
     HIPC(hipStreamSynchronize(ctx->stream));
-    const int R = SS_BLK_R, CH = 64;
+    const int R = SS_BLK_R, CH = SS_BLK_CH;
     const int64_t nblk = (N + R - 1) / R;
-    std::vector<uint16_t> uni, pos((size_t)N * r), offs;
-    std::vector<int32_t> binfo((size_t)nblk * 4);
+    std::vector<uint16_t> uni, goff;
+    std::vector<int32_t> binfo((size_t)nblk * 4), rbase((size_t)N, 0);
+    std::vector<SsGroup> gs64, gs32;
+    gs64.reserve((size_t)N * (r / 4 + 16));
+    gs32.reserve((size_t)N * (r / 4 + 16));
     std::vector<int32_t> stamp((size_t)N, -1), where((size_t)N, 0);
     std::vector<int32_t> u;
     for (int64_t blk = 0; blk < nblk; ++blk) {
@@ -965,36 +972,68 @@ static int ensure_ss_blocks(casci_ctx* ctx, int spin)
         for (size_t k = 0; k < u.size(); ++k) where[u[k]] = (int32_t)k;
         const int nU = (int)u.size();
         const int nch = (nU + CH - 1) / CH;
+        if (nch > SS_BLK_MAXCH) return CASCI_OK;  // unions too wide: the other widths serve
         binfo[(size_t)blk * 4 + 0] = (int32_t)uni.size();
         binfo[(size_t)blk * 4 + 1] = nU;
-        binfo[(size_t)blk * 4 + 2] = (int32_t)offs.size();
+        binfo[(size_t)blk * 4 + 2] = (int32_t)goff.size();
         binfo[(size_t)blk * 4 + 3] = nch;
-        if (uni.size() + u.size() > 0x7fffffffu || offs.size() + (size_t)R * (nch + 1) > 0x7fffffffu)
+        if (uni.size() + u.size() > 0x7fffffffu || goff.size() + (size_t)R * (nch + 1) > 0x7fffffffu)
             return ctx->fail(CASCI_E_UNSUPPORTED, "same-spin operator too large for the row-blocked form");
         for (int32_t J : u) uni.push_back((uint16_t)J);
         for (int w = 0; w < R; ++w) {
             const int64_t I = I0 + w;
+            if (I >= I1) {
+                goff.insert(goff.end(), (size_t)nch + 1, 0);
+                continue;
+            }
+            if (gs64.size() > 0x7fffffffu) return ctx->fail(CASCI_E_UNSUPPORTED, "row-blocked form: too many groups");
+            rbase[(size_t)I] = (int32_t)gs64.size();
+            const int32_t* cI = col.data() + (size_t)I * r;
+            const double* vI = val.data() + (size_t)I * r;
             int e = 1;
-            for (int ch = 0; ch <= nch; ++ch) {
-                if (I < I1)
-                    while (e < r && where[col[(size_t)I * r + e]] < ch * CH) ++e;
-                offs.push_back((uint16_t)(I < I1 ? e : 1));
+            size_t ng = 0;
+            for (int ch = 0; ch < nch; ++ch) {
+                goff.push_back((uint16_t)ng);
+                int ez = e;
+                while (ez < r && where[cI[ez]] < (ch + 1) * CH) ++ez;
+                for (int g = e & ~3; g < ez; g += 4) {
+                    SsGroup a, b;
+                    for (int sl = 0; sl < 4; ++sl) {
+                        const int x = g + sl;
+                        const bool in = x >= e && x < ez;
+                        const uint32_t q = (uint32_t)(in ? where[cI[x]] : ch * CH);
+                        // row of the operand within the LDS chunk, times the row's bytes
+                        a.off[sl] = b.off[sl] = (q % CH) * (uint32_t)SS_BLK_ROWB;
+                        a.v[sl] = in ? vI[x] : 0.0;
+                        b.v[sl] = in ? (double)(float)vI[x] : 0.0;
+                    }
+                    gs64.push_back(a);
+                    gs32.push_back(b);
+                    ++ng;
+                }
+                e = ez;
             }
-            if (I < I1) {
-                pos[(size_t)I * r] = 0;  // the diagonal: not staged
-                for (int q = 1; q < r; ++q) pos[(size_t)I * r + q] = (uint16_t)where[col[(size_t)I * r + q]];
-            }
+            if (ng > 65535) return CASCI_OK;  // row too long for 16-bit group offsets
+            goff.push_back((uint16_t)ng);
         }
     }
     if (uni.empty()) uni.push_back(0);
+    if (gs64.empty()) {
+        gs64.push_back(SsGroup{});
+        gs32.push_back(SsGroup{});
+    }
     HIPC(bl.uni.ensure(uni.size() * 2));
     HIPC(bl.binfo.ensure(binfo.size() * 4));
-    HIPC(bl.pos.ensure(pos.size() * 2));
-    HIPC(bl.offs.ensure(offs.size() * 2));
+    HIPC(bl.goff.ensure(goff.size() * 2));
+    HIPC(bl.rbase.ensure(rbase.size() * 4));
+    HIPC(bl.gs64.ensure(gs64.size() * sizeof(SsGroup)));
+    HIPC(bl.gs32.ensure(gs32.size() * sizeof(SsGroup)));
     HIPC(hipMemcpyAsync(bl.uni.p, uni.data(), uni.size() * 2, hipMemcpyHostToDevice, ctx->stream));
     HIPC(hipMemcpyAsync(bl.binfo.p, binfo.data(), binfo.size() * 4, hipMemcpyHostToDevice, ctx->stream));
-    HIPC(hipMemcpyAsync(bl.pos.p, pos.data(), pos.size() * 2, hipMemcpyHostToDevice, ctx->stream));
-    HIPC(hipMemcpyAsync(bl.offs.p, offs.data(), offs.size() * 2, hipMemcpyHostToDevice, ctx->stream));
+    HIPC(hipMemcpyAsync(bl.goff.p, goff.data(), goff.size() * 2, hipMemcpyHostToDevice, ctx->stream));
+    HIPC(hipMemcpyAsync(bl.rbase.p, rbase.data(), rbase.size() * 4, hipMemcpyHostToDevice, ctx->stream));
+    HIPC(hipMemcpyAsync(bl.gs64.p, gs64.data(), gs64.size() * sizeof(SsGroup), hipMemcpyHostToDevice, ctx->stream));
+    HIPC(hipMemcpyAsync(bl.gs32.p, gs32.data(), gs32.size() * sizeof(SsGroup), hipMemcpyHostToDevice, ctx->stream));
     HIPC(hipStreamSynchronize(ctx->stream));  // pageable sources
     bl.nblk = nblk;
     bl.have = true;
@@ -1323,15 +1362,16 @@ static int sigma_dev_f32(casci_ctx* ctx, const float* C32, float* S32, int ab_pr
 // only while all of them are where they were at capture.
 static std::vector<void*> sigma_buffers(const casci_ctx* ctx)
 {
-    return {ctx->d_t1.p, ctx->d_t2.p, ctx->d_t3.p, ctx->d_c32.p, ctx->d_clp.p, ctx->d_fa_col.p,
+    std::vector<void*> v = {ctx->d_t1.p, ctx->d_t2.p, ctx->d_t3.p, ctx->d_c32.p, ctx->d_clp.p, ctx->d_fa_col.p,
             ctx->d_fa_val.p, ctx->d_fb_col.p, ctx->d_fb_val.p, ctx->d_vt_sym.p, ctx->d_vt_full.p,
             ctx->d_vt_sym_lp[0].p, ctx->d_vt_sym_lp[1].p, ctx->d_vt_full_lp[0].p, ctx->d_vt_full_lp[1].p,
             ctx->d_tg_sym.p, ctx->d_tg_full.p, ctx->red_sym.tab.p, ctx->red_sym.tinfo.p, ctx->red_full.tab.p,
             ctx->red_full.tinfo.p, ctx->d_la_j.p, ctx->d_la_pq.p, ctx->d_lb_j.p, ctx->d_bstr.p,
             ctx->d_pairs_sym.p, ctx->d_pairs_full.p, ctx->d_gin.p, ctx->d_gout.p, ctx->d_fa_c16.p,
-            ctx->d_fa_v32.p, ctx->d_fb_c16.p, ctx->d_fb_v32.p, ctx->d_rowmax.p, ctx->d_tg16.p, ctx->blk[0].uni.p,
-            ctx->blk[0].pos.p, ctx->blk[0].offs.p, ctx->blk[0].binfo.p, ctx->blk[1].uni.p, ctx->blk[1].pos.p,
-            ctx->blk[1].offs.p, ctx->blk[1].binfo.p};
+            ctx->d_fa_v32.p, ctx->d_fb_c16.p, ctx->d_fb_v32.p, ctx->d_rowmax.p, ctx->d_tg16.p};
+    for (const auto& bl : ctx->blk)
+        for (const DBuf* d : {&bl.uni, &bl.binfo, &bl.goff, &bl.rbase, &bl.gs64, &bl.gs32}) v.push_back(d->p);
+    return v;
 }
 
 // sigma_dev replayed from a captured HIP graph: one launch per build instead

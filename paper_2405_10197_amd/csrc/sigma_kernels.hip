@@ -71,6 +71,9 @@ __device__ inline float bcast_val(float v, int lane)
 }
 __device__ inline double bcast_val(double v, int lane) { return bcast_f64(v, lane); }
 
+#ifndef SS_GATHER_DEPTH
+#define SS_GATHER_DEPTH 4
+#endif
 template <typename TX, typename TY, int LPE, int VW, typename TC, typename TV>
 __global__ __launch_bounds__(256) void k_ss_gather(const TC* __restrict__ col,
                                                    const TV* __restrict__ val, int r,
@@ -101,12 +104,16 @@ __global__ __launch_bounds__(256) void k_ss_gather(const TC* __restrict__ col,
         const int64_t c = (strip * LPE + li) * VW;
         const bool full = c + VW <= ncols;
         const bool cok = c < ncols;
+        // one column per lane: lanes past the last column read column 0 (a valid
+        // address) and discard the result, so the loads need no branch and the
+        // compiler can keep D of them in flight
+        const int64_t cl = cok ? c : 0;
         const TC* colI = col + I * (int64_t)r;
         const TV* valI = val + I * (int64_t)r;
         auto load = [&](int J, double* out) {
             const TX* src = X + (int64_t)J * ldx + c;
             if constexpr (VW == 1) {
-                out[0] = (double)*src;
+                out[0] = (double)X[(int64_t)J * ldx + cl];
             } else {
                 if (full) {
                     const VX v = *reinterpret_cast<const VX*>(src);
@@ -124,7 +131,7 @@ __global__ __launch_bounds__(256) void k_ss_gather(const TC* __restrict__ col,
         // entries e = k mod 4 of the row in ascending order, and the row total is
         // (a_0 + a_1) + (a_2 + a_3). A lane of group g holds the accumulators of
         // its entries: all four (G = 1), k = g and g + 2 (G = 2), or k = g (G = 4).
-        constexpr int NACC = 4;  // loads in flight per lane
+        constexpr int NACC = VW == 1 ? SS_GATHER_DEPTH : 4;  // loads in flight per lane
         constexpr int NA = 4 / G;  // accumulators per lane
         double acc_[NA][VW] = {};
         for (int base = 0; base < r; base += 64) {
@@ -149,7 +156,7 @@ __global__ __launch_bounds__(256) void k_ss_gather(const TC* __restrict__ col,
                     }
                 }
                 // entries past r carry v = 0 and J = 0 (a valid row): no branch needed
-                if (cok) {
+                if (VW == 1 || cok) {
                     double x[NACC][VW];
 #pragma unroll
                     for (int h = 0; h < NACC; ++h) load(J[h], x[h]);
@@ -208,126 +215,159 @@ static hipError_t ss_gather(const TC* col, const TV* val, int r, int64_t nrows,
 // row-blocked same-spin gather (strip width code SS_BLOCKED)
 // ---------------------------------------------------------------------------
 // One workgroup of SS_BLK_R waves takes one block of SS_BLK_R consecutive rows
-// and one strip of 64 columns; wave w computes row b*R + w. The rows of X the
-// block needs (the sorted union of its rows' columns) are staged into LDS,
-// CH at a time in two buffers (the loads of the next chunk are in flight while
-// the current one is used), and each wave adds the entries of its row whose
-// column falls in the chunk, reading X from LDS. Neighbouring strings share
-// most of their neighbours (16 rows touch about 4000 distinct rows at n = 16
-// against 16 x 849 entries), so each row of X crosses the L2 once per block
-// instead of once per entry. The diagonal (entry 0, column I) comes from row
-// I of X directly; the entries 1..r-1 are stored in ascending column order,
-// so the ones of a chunk are contiguous. Summation order: that of the other
-// widths (accumulator k sums the entries e = k mod 4 in ascending order,
-// total (a0 + a1) + (a2 + a3)); entries are read in aligned groups of four,
-// and the ones outside the chunk enter as v = 0.
-template <typename TX, typename TY, typename TV, int CH>
-__global__ __launch_bounds__(64 * SS_BLK_R) void k_ss_gather_blk(SsBlk bk, const TV* __restrict__ val, int r,
+// and one strip of 64 x VW columns (VW adjacent columns per lane); wave w
+// computes row b*R + w. The rows of X the block needs (the sorted union of
+// its rows' columns) are staged into LDS, SS_BLK_CH at a time in two buffers
+// (the loads of the next chunk are in flight while the current one is used),
+// and each wave adds its row's entry groups of the chunk, reading X from LDS.
+// Neighbouring strings share most of their neighbours (16 rows touch about
+// 4000 distinct rows at n = 16 against 16 x 849 entries), so each row of X
+// crosses the L1 once per block instead of once per entry.
+//
+// A group (four LDS byte offsets and four FP64 values) is two wave-uniform
+// scalar loads that feed the LDS reads and FMAs directly (the FP32-operator
+// builds store (double)(float)v, the product the other widths form); the chunk
+// offsets of the row sit in two registers (loaded once) and the union indices
+// of a chunk are read one chunk ahead of its X rows, so the chunk loop waits
+// on nothing it has just issued. Staged rows are SS_BLK_ROWB bytes apart
+// whatever the element type and VW.
+//
+// The diagonal (entry 0, column I) comes from row I of X directly. Summation
+// order: that of the other widths (accumulator k sums the entries e = k mod 4
+// in ascending order, total (a0 + a1) + (a2 + a3)): the groups are aligned to
+// the entry index, chunks ascend with the columns, and padded slots add v = 0.
+template <typename TX, typename TY, typename TV, int VW>
+__global__ __launch_bounds__(64 * SS_BLK_R) void k_ss_gather_blk(SsBlk bk, const SsGroup* __restrict__ gs,
+                                                                 const TV* __restrict__ val, int r,
                                                                  int64_t nrows, int64_t ncols,
                                                                  const TX* __restrict__ X, int64_t ldx,
                                                                  TY* __restrict__ Y, double shift, int acc,
                                                                  int64_t nitems)
 {
-    constexpr int RPW = CH / SS_BLK_R;      // union rows a wave stages per chunk
-    constexpr int SUB = CH / 64;            // 64-row chunks of the offsets table per stage
-    extern __shared__ __align__(16) unsigned char smem[];
-    TX* stage = reinterpret_cast<TX*>(smem);  // [2][CH][64]
+    constexpr int CH = SS_BLK_CH;
+    constexpr int RPW = CH / SS_BLK_R;  // union rows a wave stages per chunk
+    using VX = typename Vec<TX, VW>::type;
+    static_assert(64 * VW * sizeof(TX) <= SS_BLK_ROWB, "a staged row holds 64 x VW elements");
+    extern __shared__ __align__(16) unsigned char smem[];  // [2][CH][SS_BLK_ROWB]
     const int64_t per_xcd = gridDim.x / 8;
     const int64_t t = (int64_t)(blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
     if (t >= nitems) return;
     const int64_t strip = t / bk.nblk, b = t - strip * bk.nblk;
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int64_t c = strip * 64 + lane;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+    const int64_t c = (strip * 64 + lane) * VW;
     const bool cok = c < ncols;
+    // lanes past the last column read column 0 and store nothing; with VW = 2 the
+    // row stride is even, so the pair (c, c + 1) lies inside the row
+    const int64_t cl = cok ? c : 0;
     const int4 bi = bk.binfo[b];
     const uint16_t* U = bk.uni + bi.x;
-    const int nU = bi.y, nch64 = bi.w;
-    const int nch = (nch64 + SUB - 1) / SUB;
-    const uint16_t* offs = bk.offs + bi.z + wave * (nch64 + 1);
+    const int nU = bi.y, nch = bi.w;
     const int64_t I = b * SS_BLK_R + wave;
     const bool rowok = I < nrows;
-    TX pf[RPW];
-    auto issue = [&](int ch) {
+
+    // the row's group offsets per chunk (lane l: offset l and 64 + l)
+    const uint16_t* goff = bk.goff + bi.z + (int64_t)wave * (nch + 1);
+    const int o0 = rowok && lane <= nch ? (int)goff[lane] : 0;
+    const int o1 = rowok && 64 + lane <= nch ? (int)goff[64 + lane] : 0;
+    auto off_at = [&](int i) { return i < 64 ? bcast_i32(o0, i) : bcast_i32(o1, i - 64); };
+    const SsGroup* grow = gs + (rowok ? (int64_t)bk.rbase[I] : 0);
+
+    // union indices of the chunk to stage next: lane i < RPW holds the wave's
+    // row i (-1: past the union), one vector load per chunk, read a chunk later
+    int un = -1;
+    VX pf[RPW];
+    auto load_u = [&](int ch) {
+        const int k = ch * CH + wave * RPW + lane;
+        un = lane < RPW && k < nU ? (int)U[k] : -1;
+    };
+    auto issue = [&]() {
 #pragma unroll
         for (int i = 0; i < RPW; ++i) {
-            const int k = ch * CH + wave * RPW + i;
-            TX v = (TX)0;
-            if (k < nU && cok) v = X[(int64_t)U[k] * ldx + c];
-            pf[i] = v;
+            const int row = bcast_i32(un, i);
+            pf[i] = row >= 0 ? *reinterpret_cast<const VX*>(X + (int64_t)row * ldx + cl) : VX{};
         }
     };
     auto commit = [&](int buf) {
 #pragma unroll
-        for (int i = 0; i < RPW; ++i) stage[((int64_t)buf * CH + wave * RPW + i) * 64 + lane] = pf[i];
+        for (int i = 0; i < RPW; ++i)
+            *reinterpret_cast<VX*>(smem + ((int64_t)buf * CH + wave * RPW + i) * SS_BLK_ROWB + lane * sizeof(VX)) =
+                pf[i];
     };
-    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-    // entry 0 (the diagonal, column I) is read from the row itself, the
-    // staged union holds the columns of entries 1..r-1
-    const double xI = rowok && cok ? (double)X[I * ldx + c] : 0.0;
-    if (rowok) a0 += (double)val[I * r] * xI;
-    issue(0);
+
+    double a[VW][4] = {};
+    double xI[VW];
+#pragma unroll
+    for (int u = 0; u < VW; ++u) {
+        xI[u] = rowok ? (double)X[I * ldx + cl + u] : 0.0;
+        if (rowok) a[u][0] += (double)val[I * r] * xI[u];
+    }
+    load_u(0);
+    issue();
+    if (nch > 1) load_u(1);
     commit(0);
     __syncthreads();
     for (int ch = 0; ch < nch; ++ch) {
-        if (ch + 1 < nch) issue(ch + 1);
+        if (ch + 1 < nch) {
+            issue();  // chunk ch + 1 (its union indices arrived during chunk ch - 1)
+            if (ch + 2 < nch) load_u(ch + 2);
+        }
         if (rowok) {
-            const int e0 = offs[ch * SUB], e1 = offs[min((ch + 1) * SUB, nch64)];
-            const TX* sb = stage + (int64_t)(ch & 1) * CH * 64;
-            const int p0 = ch * CH;
-            for (int base = e0 & ~3; base < e1; base += 64) {
-                const int e = base + lane;
-                const bool in = e >= e0 && e < e1;
-                const int pj = in ? (int)bk.pos[I * r + e] - p0 : 0;
-                const TV vj = in ? val[I * r + e] : (TV)0;
-                const int cnt = min(64, e1 - base);
-                for (int j = 0; j < cnt; j += 4) {
-                    // entries base + j + 0..3 go to accumulators 0..3 (base, j multiples of 4)
-                    const int q0 = bcast_i32(pj, j), q1 = bcast_i32(pj, j + 1);
-                    const int q2 = bcast_i32(pj, j + 2), q3 = bcast_i32(pj, j + 3);
-                    const double v0 = (double)bcast_val(vj, j), v1 = (double)bcast_val(vj, j + 1);
-                    const double v2 = (double)bcast_val(vj, j + 2), v3 = (double)bcast_val(vj, j + 3);
-                    const double x0 = (double)sb[q0 * 64 + lane], x1 = (double)sb[q1 * 64 + lane];
-                    const double x2 = (double)sb[q2 * 64 + lane], x3 = (double)sb[q3 * 64 + lane];
-                    a0 += v0 * x0;
-                    a1 += v1 * x1;
-                    a2 += v2 * x2;
-                    a3 += v3 * x3;
+            const unsigned char* sb = smem + (int64_t)(ch & 1) * CH * SS_BLK_ROWB + lane * sizeof(VX);
+            const int g1 = off_at(ch + 1);
+            for (int g = off_at(ch); g < g1; ++g) {
+                const SsGroup& G = grow[g];
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const VX xv = *reinterpret_cast<const VX*>(sb + G.off[k]);
+                    const TX* xe = reinterpret_cast<const TX*>(&xv);
+#pragma unroll
+                    for (int u = 0; u < VW; ++u) a[u][k] += G.v[k] * (double)xe[u];
                 }
             }
         }
         if (ch + 1 < nch) commit((ch + 1) & 1);
         __syncthreads();
     }
-    if (rowok && cok) {
-        const int64_t o = I * ncols + c;
-        double y = ((a0 + a1) + (a2 + a3)) + shift * xI;
-        if (acc) y += (double)Y[o];
-        Y[o] = (TY)y;
+    if (rowok) {
+#pragma unroll
+        for (int u = 0; u < VW; ++u) {
+            if (c + u >= ncols) continue;
+            const int64_t o = I * ncols + c + u;
+            double y = ((a[u][0] + a[u][1]) + (a[u][2] + a[u][3])) + shift * xI[u];
+            if (acc) y += (double)Y[o];
+            Y[o] = (TY)y;
+        }
     }
 }
 
 template <typename TX, typename TY, typename TV>
-static hipError_t ss_gather_blk(const SsBlk& bk, const TV* val, int r, int64_t nrows, int64_t ncols, const TX* X,
-                                int64_t ldx, TY* Y, double shift, int acc, hipStream_t st)
+static hipError_t ss_gather_blk(const SsBlk& bk, const SsGroup* gs, const TV* val, int r, int64_t nrows, int64_t ncols,
+                                const TX* X, int64_t ldx, TY* Y, double shift, int acc, hipStream_t st)
 {
     if (nrows <= 0 || ncols <= 0) return hipSuccess;
-    if (!bk.uni || bk.ch != 64) return invalid("same-spin gather: no row-blocked operator");
+    if (!bk.uni || !gs || bk.ch != SS_BLK_CH) return invalid("same-spin gather: no row-blocked operator");
     // a prefix of the rows (the autotuner times one) takes the blocks that cover it
     SsBlk b = bk;
     b.nblk = (nrows + SS_BLK_R - 1) / SS_BLK_R;
     if (b.nblk > bk.nblk) return invalid("same-spin gather: more rows than the row-blocked operator has");
-    constexpr int CH = sizeof(TX) == 4 ? 128 : 64;  // 32 KB per stage buffer either way
-    const int64_t nstrip = (ncols + 63) / 64;
+    // FP32 input: two adjacent columns per lane when the row stride allows aligned pairs
+    const bool pair = sizeof(TX) == 4 && ldx % 2 == 0;
+    const int64_t nstrip = (ncols + (pair ? 127 : 63)) / (pair ? 128 : 64);
     const int64_t nitems = nstrip * b.nblk;
     if (nitems > ((int64_t)1 << 31) - 8) return invalid("same-spin gather: too many row blocks x strips");
     const int64_t grid = (nitems + 7) / 8 * 8;
-    const size_t lds = (size_t)2 * CH * 64 * sizeof(TX);
-    auto kern = k_ss_gather_blk<TX, TY, TV, CH>;
-    hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return invalid("hipFuncSetAttribute(max dynamic LDS) failed");
-    hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(64 * SS_BLK_R), lds, st, b, val, r, nrows, ncols, X, ldx,
-                       Y, shift, acc, nitems);
-    return hipGetLastError();
+    const size_t lds = (size_t)2 * SS_BLK_CH * SS_BLK_ROWB;
+    auto launch = [&](auto kern) {
+        hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return invalid("hipFuncSetAttribute(max dynamic LDS) failed");
+        hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(64 * SS_BLK_R), lds, st, b, gs, val, r, nrows, ncols, X,
+                           ldx, Y, shift, acc, nitems);
+        return hipGetLastError();
+    };
+    if constexpr (sizeof(TX) == 4) {
+        if (pair) return launch(k_ss_gather_blk<TX, TY, TV, 2>);
+    }
+    return launch(k_ss_gather_blk<TX, TY, TV, 1>);
 }
 
 // strip width code: 16 / 32 / 64 lanes per entry with one column each, 128 =
@@ -374,7 +414,8 @@ hipError_t launch_ss_gather_f64(const SsOp& op, int64_t nrows, int64_t ncols, co
                                 double shift, int acc, hipStream_t st, int lpe)
 {
     if (lpe == SS_BLOCKED && op.blk.uni)
-        return ss_gather_blk<double, double>(op.blk, op.val, op.r, nrows, ncols, X, ncols, Y, shift, acc, st);
+        return ss_gather_blk<double, double>(op.blk, op.blk.gs64, op.val, op.r, nrows, ncols, X, ncols, Y, shift,
+                                             acc, st);
     if (lpe == SS_BLOCKED) lpe = 64;
     if (op.col16)
         return ss_gather_w<double, double>(op.col16, op.val, op.r, nrows, ncols, X, ncols, Y, shift, acc, st, lpe);
@@ -385,7 +426,8 @@ hipError_t launch_ss_gather_f32in(const SsOp& op, int64_t nrows, int64_t ncols, 
                                   double* Y, double shift, int acc, hipStream_t st, int lpe)
 {
     if (lpe == SS_BLOCKED && op.blk.uni && op.val32)
-        return ss_gather_blk<float, double>(op.blk, op.val32, op.r, nrows, ncols, X, ldx, Y, shift, acc, st);
+        return ss_gather_blk<float, double>(op.blk, op.blk.gs32, op.val32, op.r, nrows, ncols, X, ldx, Y, shift,
+                                            acc, st);
     if (lpe == SS_BLOCKED) lpe = 64;
     if (op.col16 && op.val32)
         return ss_gather_w<float, double>(op.col16, op.val32, op.r, nrows, ncols, X, ldx, Y, shift, acc, st, lpe);
@@ -396,7 +438,8 @@ hipError_t launch_ss_gather_f32(const SsOp& op, int64_t nrows, int64_t ncols, co
                                 double shift, int acc, hipStream_t st, int lpe)
 {
     if (lpe == SS_BLOCKED && op.blk.uni && op.val32)
-        return ss_gather_blk<float, float>(op.blk, op.val32, op.r, nrows, ncols, X, ncols, Y, shift, acc, st);
+        return ss_gather_blk<float, float>(op.blk, op.blk.gs32, op.val32, op.r, nrows, ncols, X, ncols, Y, shift,
+                                           acc, st);
     if (lpe == SS_BLOCKED) lpe = 64;
     if (op.col16 && op.val32)
         return ss_gather_w<float, float>(op.col16, op.val32, op.r, nrows, ncols, X, ncols, Y, shift, acc, st, lpe);
