@@ -237,7 +237,7 @@ static hipError_t ss_gather(const TC* col, const TV* val, int r, int64_t nrows,
 // in ascending order, total (a0 + a1) + (a2 + a3)): the groups are aligned to
 // the entry index, chunks ascend with the columns, and padded slots add v = 0.
 template <typename TX, typename TY, typename TV, int VW>
-__global__ __launch_bounds__(64 * SS_BLK_R) void k_ss_gather_blk(SsBlk bk, const SsGroup* __restrict__ gs,
+__global__ __launch_bounds__(64 * SS_BLK_R, 8) void k_ss_gather_blk(SsBlk bk, const SsGroup* __restrict__ gs,
                                                                  const TV* __restrict__ val, int r,
                                                                  int64_t nrows, int64_t ncols,
                                                                  const TX* __restrict__ X, int64_t ldx,
@@ -272,22 +272,25 @@ __global__ __launch_bounds__(64 * SS_BLK_R) void k_ss_gather_blk(SsBlk bk, const
     auto off_at = [&](int i) { return i < 64 ? bcast_i32(o0, i) : bcast_i32(o1, i - 64); };
     const SsGroup* grow = gs + (rowok ? (int64_t)bk.rbase[I] : 0);
 
-    // union indices of the chunk to stage next: lane i < RPW holds the wave's
-    // row i (-1: past the union), one vector load per chunk, read a chunk later
-    int un = -1;
-    VX pf[RPW];
+    // Staging runs two chunks ahead: while chunk ch is used, the X rows of
+    // chunk ch + 1 (registers of one set) and ch + 2 (the other set) are in
+    // flight, and the union indices of chunk ch + 3 (lane i < RPW: the wave's
+    // row i) are loaded before the X rows of ch + 2, so every wait leaves the
+    // newer loads outstanding. The loop is unrolled by two so that the
+    // register sets alternate statically.
+    // The loads are unconditional and their results used as loaded, so that
+    // the compiler's wait counts stay exact across the unrolled loop: slots
+    // past the union stage row U[0] again, which no group refers to.
     auto load_u = [&](int ch) {
         const int k = ch * CH + wave * RPW + lane;
-        un = lane < RPW && k < nU ? (int)U[k] : -1;
+        return (int)U[k < nU ? k : 0];
     };
-    auto issue = [&]() {
+    auto issue = [&](int un, VX (&pf)[RPW]) {
 #pragma unroll
-        for (int i = 0; i < RPW; ++i) {
-            const int row = bcast_i32(un, i);
-            pf[i] = row >= 0 ? *reinterpret_cast<const VX*>(X + (int64_t)row * ldx + cl) : VX{};
-        }
+        for (int i = 0; i < RPW; ++i)
+            pf[i] = *reinterpret_cast<const VX*>(X + (int64_t)bcast_i32(un, i) * ldx + cl);
     };
-    auto commit = [&](int buf) {
+    auto commit = [&](int buf, const VX (&pf)[RPW]) {
 #pragma unroll
         for (int i = 0; i < RPW; ++i)
             *reinterpret_cast<VX*>(smem + ((int64_t)buf * CH + wave * RPW + i) * SS_BLK_ROWB + lane * sizeof(VX)) =
@@ -301,32 +304,57 @@ __global__ __launch_bounds__(64 * SS_BLK_R) void k_ss_gather_blk(SsBlk bk, const
         xI[u] = rowok ? (double)X[I * ldx + cl + u] : 0.0;
         if (rowok) a[u][0] += (double)val[I * r] * xI[u];
     }
-    load_u(0);
-    issue();
-    if (nch > 1) load_u(1);
-    commit(0);
-    __syncthreads();
-    for (int ch = 0; ch < nch; ++ch) {
-        if (ch + 1 < nch) {
-            issue();  // chunk ch + 1 (its union indices arrived during chunk ch - 1)
-            if (ch + 2 < nch) load_u(ch + 2);
-        }
-        if (rowok) {
-            const unsigned char* sb = smem + (int64_t)(ch & 1) * CH * SS_BLK_ROWB + lane * sizeof(VX);
-            const int g1 = off_at(ch + 1);
-            for (int g = off_at(ch); g < g1; ++g) {
-                const SsGroup& G = grow[g];
+    auto compute = [&](int ch) {
+        if (!rowok) return;
+        const unsigned char* sb = smem + (int64_t)(ch & 1) * CH * SS_BLK_ROWB + lane * sizeof(VX);
+        auto add = [&](const SsGroup& G) {
 #pragma unroll
-                for (int k = 0; k < 4; ++k) {
-                    const VX xv = *reinterpret_cast<const VX*>(sb + G.off[k]);
-                    const TX* xe = reinterpret_cast<const TX*>(&xv);
+            for (int k = 0; k < 4; ++k) {
+                const VX xv = *reinterpret_cast<const VX*>(sb + G.off[k]);
+                const TX* xe = reinterpret_cast<const TX*>(&xv);
 #pragma unroll
-                    for (int u = 0; u < VW; ++u) a[u][k] += G.v[k] * (double)xe[u];
-                }
+                for (int u = 0; u < VW; ++u) a[u][k] += G.v[k] * (double)xe[u];
             }
+        };
+        const int g1 = off_at(ch + 1);
+        int g = off_at(ch);
+        // up to four groups per scalar round trip
+        for (; g + 4 <= g1; g += 4) {
+            const SsGroup G0 = grow[g], G1 = grow[g + 1], G2 = grow[g + 2], G3 = grow[g + 3];
+            add(G0);
+            add(G1);
+            add(G2);
+            add(G3);
         }
-        if (ch + 1 < nch) commit((ch + 1) & 1);
+        if (g + 2 <= g1) {
+            const SsGroup G0 = grow[g], G1 = grow[g + 1];
+            add(G0);
+            add(G1);
+            g += 2;
+        }
+        if (g < g1) add(grow[g]);
+    };
+    // one chunk: pn holds the X rows of chunk ch + 1 (in flight), pf receives
+    // those of chunk ch + 2 from the indices un; the indices of ch + 3 go to un2
+    auto step = [&](int ch, VX (&pn)[RPW], VX (&pf)[RPW], int& un, int& un2) {
+        un2 = load_u(ch + 3);
+        issue(un, pf);
+        compute(ch);
+        if (ch + 1 < nch) commit((ch + 1) & 1, pn);
         __syncthreads();
+    };
+    VX pa[RPW], pb[RPW];
+    int ua = load_u(0);
+    int ub = load_u(1);
+    issue(ua, pa);
+    issue(ub, pb);
+    ua = load_u(2);
+    commit(0, pa);
+    __syncthreads();
+    // chunk ch (even): next rows in pb, rows of ch + 2 into pa from ua, indices of ch + 3 into ub
+    for (int ch = 0; ch < nch; ch += 2) {
+        step(ch, pb, pa, ua, ub);
+        if (ch + 1 < nch) step(ch + 1, pa, pb, ub, ua);
     }
     if (rowok) {
 #pragma unroll
