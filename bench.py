@@ -424,6 +424,8 @@ def kernel_figures(P, dims, n, tag):
     # operator rows (16-bit columns and values in the input's type)
     gather_bytes = Nd * esz + Nd * 8.0 + dims["Na"] * dims["ra"] * (2.0 + esz)
     gathered = dims["ra"] * Nd * float(esz)
+    # one FP64 multiply-add per operator entry and column (the diagonal included)
+    gather_flops = 2.0 * dims["ra"] * Nd
     peak = PEAK["%s_TF" % ("f64" if tag == "f64" else HEADLINE["ab_prec"])]
     return {
         "sigma_builds": int(nb_sig),
@@ -437,6 +439,8 @@ def kernel_figures(P, dims, n, tag):
         "gather_GBps_algorithmic": gather_bytes / (aa_ms * 1e-3) / 1e9,
         "gather_GBps_gathered_operands": gathered / (aa_ms * 1e-3) / 1e9,
         "gather_bytes_algorithmic": gather_bytes,
+        "gather_flops": gather_flops,
+        "gather_TFLOPs": gather_flops / (aa_ms * 1e-3) / 1e12,
     }
 
 
@@ -605,6 +609,7 @@ def headline(args):
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         prof = ctx.profile_read()
+        tuning = ctx.tuning()
         del ctx
         est = max(est if (ran_w + ran_t) else 0.0, 1.05 * dt)
         t_hit, it_hit = time_to_threshold(info["hist_energy"], info["hist_time_ms"], Eref)
@@ -638,19 +643,34 @@ def headline(args):
     if part == "ab":
         lp = HEADLINE["ab_prec"]
         peak = PEAK["%s_TF" % lp] if tag == "lowp" else PEAK["f64_TF"]
-        kname = ("k_ab_lp<Mfma%s>" % lp.upper()) if tag == "lowp" else "k_ab<MfmaF64>"
+        # BF16: the fixed-point row kernel (the beta space fits its 16-bit targets here)
+        kname = {"bf16": "k_ab_bf16<double,3,3>", "f32": "k_ab_lp<MfmaF32>"}.get(lp, "k_ab<MfmaF64>") \
+            if tag == "lowp" else "k_ab<MfmaF64>"
         ach = fig["alpha_beta_TFLOPs"]
         traffic = read_traffic(os.path.join(ROOT, "profiles", "%s_%s_pmc.txt" % (
-            "ab_lp_" + lp if tag == "lowp" else "ab_f64", args.workload)))
+            {"bf16": "ab_bf16", "f32": "ab_lp_f32"}.get(lp, "ab_f64") if tag == "lowp" else "ab_f64",
+            args.workload)))
         roof = {"kernel": kname, "bound": "mfma", "achieved": ach, "peak": peak, "unit": "TFLOP/s",
                 "frac": ach / peak, "traffic": traffic}
     else:
-        kname = "k_ss_gather<float,double>" if tag == "lowp" else "k_ss_gather<double,double>"
-        ach = fig["gather_GBps_algorithmic"]
-        traffic = read_traffic(os.path.join(ROOT, "profiles", "%s_%s_pmc.txt" % (
-            "ss_gather_f32" if tag == "lowp" else "ss_gather_f64", args.workload)))
-        roof = {"kernel": kname, "bound": "hbm", "achieved": ach, "peak": PEAK["hbm_GBps"], "unit": "GB/s",
-                "frac": ach / PEAK["hbm_GBps"], "traffic": traffic}
+        # the width the autotuner chose for this space (99: row-blocked LDS form)
+        code = tuning.get("f32in" if tag == "lowp" else "f64", 0)
+        blocked = code == 99
+        if tag == "lowp":
+            kname = "k_ss_gather_blk<float,double,float,2>" if blocked else "k_ss_gather<float,double>"
+            pmc = "ss_gather_blk_f32" if blocked else "ss_gather_f32"
+        else:
+            kname = "k_ss_gather_blk<double,double,double,1>" if blocked else "k_ss_gather<double,double>"
+            pmc = "ss_gather_blk_f64" if blocked else "ss_gather_f64"
+        traffic = read_traffic(os.path.join(ROOT, "profiles", "%s_%s_pmc.txt" % (pmc, args.workload)))
+        # Roofline: the compulsory bytes (read C once, write sigma, read the
+        # operator) take a fraction of a millisecond at 8 TB/s, the FP64
+        # multiply-adds several: the binding roof is the FP64 vector rate
+        ach = fig["gather_TFLOPs"]
+        roof = {"kernel": kname, "width_code": code, "bound": "alu", "achieved": ach, "peak": PEAK["f64_TF"],
+                "unit": "TFLOP/s", "frac": ach / PEAK["f64_TF"], "traffic": traffic,
+                "hbm_view": {"achieved_GBps": fig["gather_GBps_algorithmic"], "peak_GBps": PEAK["hbm_GBps"],
+                             "frac": fig["gather_GBps_algorithmic"] / PEAK["hbm_GBps"]}}
     # the counters' HBM-side bytes over the same launch time (what the memory
     # side actually moved, against the algorithmic bytes of 'achieved')
     t_ms = fig["alpha_beta_ms"] if part == "ab" else fig["alpha_alpha_gather_ms"]

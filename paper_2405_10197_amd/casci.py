@@ -251,8 +251,9 @@ class Context:
         self._check(self._L.casci_set_tuning(self._h, int(f64), int(f32in)))
 
     def tuning(self):
-        """Autotuned lanes per gathered entry of the same-spin gathers:
-        {'f64': 16|32|64 or 0, 'f32in': ...} (0: not tuned yet)."""
+        """Autotuned strip width codes of the same-spin gathers, for FP64 and FP32
+        input: {'f64': code, 'f32in': code} (16/32/64 lanes per entry, 128,
+        1602, 3202, 1604, 3204, 6404 vector forms, 99 row-blocked; 0: not tuned yet)."""
         out = (ctypes.c_int * 2)()
         self._check(self._L.casci_get_tuning(self._h, out))
         return {"f64": out[0], "f32in": out[1]}
