@@ -51,6 +51,11 @@ WORKLOADS = {
     # name: (norb, nalpha, nbeta, nroots, seed, spin, description)
     "cas16": (16, 8, 8, 3, 4, "any", "CAS(16e,16o), 3 roots state-averaged (equal weights), "
               "165,636,900 determinants, seeded synthetic integrals (seed 4)"),
+    "dressed14": (14, 7, 7, 3, 4, "any", "CAS(14e,14o) on dressed integrals ((pq|rs) = (qp|sr) = (rs|pq) "
+                  "only: the model-space Hamiltonian of a reference relaxation), 3 roots, 11,778,624 "
+                  "determinants, seeded synthetic integrals (seed 4)"),
+    "dressed16": (16, 8, 8, 3, 4, "any", "CAS(16e,16o) on dressed integrals ((pq|rs) = (qp|sr) = (rs|pq) "
+                  "only), 3 roots, 165,636,900 determinants, seeded synthetic integrals (seed 4)"),
     "cas12": (12, 6, 6, 1, 2, "singlet", "CAS(12e,12o) singlet ground state, 853,776 determinants, "
               "seeded synthetic integrals (seed 2)"),
 }
@@ -129,17 +134,25 @@ def read_traffic(path):
     return b if now == m2.group(1) else None
 
 
-def make_ctx(casci, h, eri, n, na, nb):
+def workload_integrals(name, n, seed):
+    """(h, eri, e_core) of a workload: dressed (4-fold symmetric) or ordinary integrals."""
+    from paper_2405_10197_amd import synth
+    if name.startswith("dressed"):
+        return synth.dressed_integrals(n, seed)
+    return synth.integrals(n, seed)
+
+
+def make_ctx(casci, h, eri, n, na, nb, e_core=0.0):
     ctx = casci.Context(0)
-    ctx.set_integrals(h, eri)
+    ctx.set_integrals(h, eri, e_core)
     ctx.build_strings(na, nb, n)
     return ctx
 
 
-def sigma_only(args, casci, h, eri, n, na, nb):
+def sigma_only(args, casci, h, eri, n, na, nb, e_core=0.0):
     """Repeated sigma builds on a seeded normalised vector (for kernel profiling)."""
     import torch
-    ctx = make_ctx(casci, h, eri, n, na, nb)
+    ctx = make_ctx(casci, h, eri, n, na, nb, e_core)
     d = ctx.dims
     g = torch.Generator(device="cuda").manual_seed(50)
     C = torch.randn(d["Na"], d["Nb"], dtype=torch.float64, device="cuda", generator=g)
@@ -407,14 +420,15 @@ def mlp_mode(args):
                       "held_out_cas14": held, "cas16": out}), flush=True)
 
 
-def kernel_figures(P, dims, n, tag):
+def kernel_figures(P, dims, n, tag, full=False):
     """Per-launch averages and rates of the sigma kernels from HIP events recorded
-    on the library's stream (P = profile_read()[tag])."""
+    on the library's stream (P = profile_read()[tag]). full: the alpha-beta term
+    runs over all n^2 ordered pairs (dressed integrals, S^2 penalty)."""
     nb_sig = P["sigma_builds"]
     if nb_sig <= 0:
         return None
     Nd = dims["Ndet"]
-    M = n * (n + 1) // 2
+    M = n * n if full else n * (n + 1) // 2
     ab_flops = 2.0 * M * dims["sa"] * Nd
     ab_ms = P["ab_ms"] / nb_sig
     cv_ms = P.get("convert_ms", 0.0) / nb_sig
@@ -549,13 +563,13 @@ def headline(args):
     from paper_2405_10197_amd import casci, synth
 
     n, na, nb, k, seed, spin, desc = WORKLOADS[args.workload]
-    h, eri, _ = synth.integrals(n, seed)
+    h, eri, e_core = workload_integrals(args.workload, n, seed)
     common = dict(spin=spin, s2_penalty=1.0 if spin == "singlet" else 0.0)
     cpu = None if args.no_cpu_baseline else cpu_leg(args.cpu_seconds, full=args.cpu_full)
 
     # baseline and reference: plain FP64 sigma, diagonal preconditioner, residual < 1e-7
     log("[bench] FP64 diagonal-preconditioned solve of %s (reference energies, |r| < 1e-7)" % args.workload)
-    bctx = make_ctx(casci, h, eri, n, na, nb)
+    bctx = make_ctx(casci, h, eri, n, na, nb, e_core)
     dims = bctx.dims
     bctx.profile(True)
     t0 = time.perf_counter()
@@ -602,7 +616,7 @@ def headline(args):
         tag = "warmup%d" % ran_w if warm else "step%d" % ran_t
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        ctx = make_ctx(casci, h, eri, n, na, nb)
+        ctx = make_ctx(casci, h, eri, n, na, nb, e_core)
         ctx.profile(True)
         E, _, info = ctx.davidson(k, 1e-10, vectors=False, history=4000, max_iter=4000,
                                   progress=progress_printer(tag), **HEADLINE, **common)
@@ -627,9 +641,10 @@ def headline(args):
     E = Es[-1]
     info = infos[-1]
     P = profs[-1]
-    lowp = kernel_figures(P["lowp"], dims, n, "lowp")
-    f64 = kernel_figures(P["f64"], dims, n, "f64")
-    f64_base = kernel_figures(base_prof["f64"], dims, n, "f64")
+    full = args.workload.startswith("dressed") or spin == "singlet"
+    lowp = kernel_figures(P["lowp"], dims, n, "lowp", full)
+    f64 = kernel_figures(P["f64"], dims, n, "f64", full)
+    f64_base = kernel_figures(base_prof["f64"], dims, n, "f64", full)
     # dominant kernel of the timed step (total device time)
     cand = []
     for tag, fig in (("lowp", lowp), ("f64", f64)):
@@ -644,8 +659,9 @@ def headline(args):
         lp = HEADLINE["ab_prec"]
         peak = PEAK["%s_TF" % lp] if tag == "lowp" else PEAK["f64_TF"]
         # BF16: the fixed-point row kernel (the beta space fits its 16-bit targets here)
-        kname = {"bf16": "k_ab_bf16<double,3,3>", "f32": "k_ab_lp<MfmaF32>"}.get(lp, "k_ab<MfmaF64>") \
-            if tag == "lowp" else "k_ab<MfmaF64>"
+        # all ordered pairs (dressed integrals, S^2 penalty): the table-driven kernel
+        kname = {"bf16": "k_ab_lp<MfmaBF16>" if full else "k_ab_bf16<double,3,3>",
+                 "f32": "k_ab_lp<MfmaF32>"}.get(lp, "k_ab<MfmaF64>") if tag == "lowp" else "k_ab<MfmaF64>"
         ach = fig["alpha_beta_TFLOPs"]
         traffic = read_traffic(os.path.join(ROOT, "profiles", "%s_%s_pmc.txt" % (
             {"bf16": "ab_bf16", "f32": "ab_lp_f32"}.get(lp, "ab_f64") if tag == "lowp" else "ab_f64",
@@ -793,8 +809,8 @@ def main():
         return
     if args.sigma_only:
         n, na, nb, k, seed, spin, desc = WORKLOADS[args.workload]
-        h, eri, _ = synth.integrals(n, seed)
-        sigma_only(args, casci, h, eri, n, na, nb)
+        h, eri, e_core = workload_integrals(args.workload, n, seed)
+        sigma_only(args, casci, h, eri, n, na, nb, e_core)
         return
     headline(args)
 

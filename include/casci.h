@@ -100,13 +100,20 @@ const char* casci_last_error(const casci_ctx* ctx);
 
 /*
  * set_integrals: h (norb x norb, row-major, symmetric), eri (norb^4,
- * chemists' (pq|rs), 8-fold symmetric), e_core = the scalar V of
- * eq. (hamiltonian). mem = CASCI_MEM_HOST or CASCI_MEM_DEVICE for h and
- * eri. The arrays are copied. Checks: 1 <= norb <= 64, finiteness
- * (CASCI_E_NONFINITE), symmetry of h and the 8-fold symmetry of eri to
- * 1e-12 * max|value| (CASCI_E_ARG). If strings for a different norb exist
- * the call fails with CASCI_E_STATE. Invalidates all integral-dependent
- * device data (same-spin operators, diagonal, pair-integral matrices).
+ * chemists' (pq|rs)), e_core = the scalar V of eq. (hamiltonian). mem =
+ * CASCI_MEM_HOST or CASCI_MEM_DEVICE for h and eri. The arrays are copied.
+ * eri needs the symmetry of a Hermitian Hamiltonian, (pq|rs) = (qp|sr) =
+ * (rs|pq); the 8-fold symmetry of real-orbital integrals ((pq|rs) = (qp|rs)
+ * as well) is detected and lets the alpha-beta term fold its pair rows.
+ * Without it -- dressed integrals, such as the similarity-transformed
+ * Hamiltonian whose model-space diagonalisation is the reference relaxation
+ * of Sec. II.C -- the alpha-beta term runs over all ordered orbital pairs
+ * (the same sigma and Davidson otherwise). Checks: 1 <= norb <= 64,
+ * finiteness (CASCI_E_NONFINITE), symmetry of h and the 4-fold symmetry of
+ * eri to 1e-12 * max|value| (CASCI_E_ARG). If strings for a different norb
+ * exist the call fails with CASCI_E_STATE. Invalidates all
+ * integral-dependent device data (same-spin operators, diagonal,
+ * pair-integral matrices).
  */
 int casci_set_integrals(casci_ctx* ctx, int norb, const double* h, const double* eri,
                         double e_core, int mem);
@@ -250,7 +257,8 @@ typedef struct {
     double refine_rnorm;    /* > 0: every sigma in FP64 once max residual < this; also after 40
                                iterations without halving the best residual (<= 0: no threshold) */
     double r_tol;           /* residual threshold; <= 0 -> max(1e-6, sqrt(tol)/10) */
-    double s2_penalty;      /* lambda of H + lambda S^2 for CASCI_SPIN_SINGLET (< 0 -> 0) */
+    double s2_penalty;      /* lambda of H + lambda S^2 for CASCI_SPIN_SINGLET (0 -> 1 Eh); < 0: no
+                               penalty, the lowest roots of even transposition parity (S = 0, 2, ...) */
     const double* guess;    /* optional [nguess][Ndet] FP64 start vectors (host or device) */
     int nguess;
     int guess_mem;

@@ -128,6 +128,10 @@ struct casci_ctx {
     DBuf d_vt_sym_lp[2], d_vt_full_lp[2];  // FP32 and BF16 copies (round to nearest even)
     int M_sym = 0, Mp_sym = 0, M_full = 0, Mp_full = 0;
     bool have_full = false, have_s2 = false;
+    // (pq|rs) = (qp|rs) holds (8-fold symmetry): the alpha-beta term can fold
+    // the pair rows r <= s; without it (dressed integrals, 4-fold symmetry) it
+    // runs over all ordered pairs
+    bool eri8 = true;
     bool have_tg_sym = false, have_tg_full = false, have_tg16 = false;
 
     // workspaces
@@ -348,17 +352,23 @@ extern "C" int casci_set_integrals(casci_ctx* ctx, int norb, const double* h, co
             if (std::fabs(hh[p * n + q] - hh[q * n + p]) > th)
                 return ctx->fail(CASCI_E_ARG, "h is not symmetric");
     auto E = [&](size_t p, size_t q, size_t r, size_t s) { return ee[((p * n + q) * n + r) * n + s]; };
+    // A Hermitian Hamiltonian needs (pq|rs) = (qp|sr) and (pq|rs) = (rs|pq)
+    // (4-fold); ordinary integrals of real orbitals also have (pq|rs) = (qp|rs)
+    // (8-fold), dressed (similarity-transformed) ones need not
+    bool sym8 = true;
     for (size_t p = 0; p < n; ++p)
         for (size_t q = 0; q < n; ++q)
             for (size_t r = 0; r < n; ++r)
                 for (size_t s = 0; s < n; ++s) {
                     double v = E(p, q, r, s);
-                    if (std::fabs(v - E(q, p, r, s)) > te || std::fabs(v - E(p, q, s, r)) > te ||
-                        std::fabs(v - E(r, s, p, q)) > te)
-                        return ctx->fail(CASCI_E_ARG, "eri lacks the 8-fold (pq|rs) symmetry");
+                    if (std::fabs(v - E(q, p, s, r)) > te || std::fabs(v - E(r, s, p, q)) > te)
+                        return ctx->fail(CASCI_E_ARG,
+                                         "eri lacks the symmetry (pq|rs) = (qp|sr) = (rs|pq) of a Hermitian H");
+                    if (std::fabs(v - E(q, p, r, s)) > te) sym8 = false;
                 }
     ctx->h.swap(hh);
     ctx->eri.swap(ee);
+    ctx->eri8 = sym8;
     ctx->ecore = e_core;
     ctx->norb_ints = norb;
     ctx->has_ints = true;
@@ -683,7 +693,9 @@ static int ensure_prepared(casci_ctx* ctx, double lambda)
                              ctx->d_fa_val.as<double>(), ctx->ra,
                              (same ? ctx->d_fa_val : ctx->d_fb_val).as<double>(), ctx->rb,
                              ctx->d_jpq.as<double>(), ctx->ecore, lambda, ctx->d_diag.as<double>(), st));
-        if (lambda != 0.0) {
+        // all ordered pairs: with the S^2 penalty (not symmetric in rs) or
+        // integrals without the 8-fold symmetry
+        if (lambda != 0.0 || !ctx->eri8) {
             std::vector<uint16_t> pairs;
             std::vector<double> vt;
             pair_tables(n, true, pairs, ctx->M_full, ctx->Mp_full);
@@ -1212,7 +1224,7 @@ static int sigma_dev(casci_ctx* ctx, const double* C, double* S, int ab_prec, do
     // alpha-beta, overwriting t3
     if (has_ab) {
         CHECK_RC(mark(3, st));
-        const bool full = lambda != 0.0;
+        const bool full = lambda != 0.0 || !ctx->eri8;
         CHECK_RC(ensure_targets(ctx, full, alloc));
         AbParams p = ab_params(ctx, full);
         p.overwrite = 1;
@@ -1325,10 +1337,12 @@ static int sigma_dev_f32(casci_ctx* ctx, const float* C32, float* S32, int ab_pr
     CHECK_RC(mark(2));
     // alpha-beta, added into S32
     if (has_ab) {
-        AbParams p = ab_params(ctx, false);
+        const bool full = !ctx->eri8;
+        AbParams p = ab_params(ctx, full);
         p.overwrite = 0;
         AbReduce red;
-        CHECK_RC(ensure_reduce(ctx, false, &red));
+        CHECK_RC(ensure_targets(ctx, full));
+        CHECK_RC(ensure_reduce(ctx, full, &red));
         const int pr = ab_prec == CASCI_F32 ? 1 : 2;
         const int64_t ld = lowp_ld(pr, Nb);
         const void* Cs = C32;
@@ -1338,7 +1352,7 @@ static int sigma_dev_f32(casci_ctx* ctx, const float* C32, float* S32, int ab_pr
             HIPC(launch_convert_lowp_f32in(pr, C32, buf.p, Na, Nb, ld, st));
             Cs = buf.p;
         }
-        HIPC(launch_ab_lowp(p, red, pr, ctx->d_vt_sym_lp[pr - 1].p, Cs, ld, S32, st));
+        HIPC(launch_ab_lowp(p, red, pr, (full ? ctx->d_vt_full_lp : ctx->d_vt_sym_lp)[pr - 1].p, Cs, ld, S32, st));
     }
     CHECK_RC(mark(5));
     if (prof) {
@@ -2162,7 +2176,12 @@ static int davidson_impl(casci_ctx* ctx, int nroots, double tol, const casci_dav
     m_max = std::min<int64_t>(std::min(m_max, 64), Nd);
     m_max = std::max(m_max, (int)std::min<int64_t>(Nd, 2 * k));
     const double r_tol = o.r_tol > 0 ? o.r_tol : std::max(1e-6, std::sqrt(tol) / 10.0);
-    const double lambda = (o.spin == CASCI_SPIN_SINGLET && o.s2_penalty > 0) ? o.s2_penalty : 0.0;
+    // singlet: lambda S^2 lifts the S = 2, 4, ... states that share the even
+    // transposition parity (0 -> 1 Eh; < 0 -> parity only)
+    const double lambda = o.spin != CASCI_SPIN_SINGLET ? 0.0
+                          : o.s2_penalty > 0         ? o.s2_penalty
+                          : o.s2_penalty == 0        ? 1.0
+                                                     : 0.0;
     const bool singlet = o.spin == CASCI_SPIN_SINGLET;
     // Mixed precision (ab_prec F32/BF16): sigma of every new correction vector
     // uses the low-precision alpha-beta arithmetic, and at every collapse the

@@ -17,7 +17,18 @@ symmetry), drawn with ``numpy.random.default_rng(seed)`` in this order:
    (pq)x(rs) matrix, the factorised form of the integral classes in
    Sec. III.B of the paper.
 
-The scalar core energy is 0 for every synthetic workload.
+The scalar core energy is 0 for every synthetic workload except the dressed
+one below.
+
+Dressed integrals (``dressed_integrals``; the model-space Hamiltonian of a
+reference relaxation, Sec. II.C: a similarity-transformed Hamiltonian keeps
+the symmetry of a Hermitian operator, (pq|rs) = (qp|sr) = (rs|pq), but not
+(pq|rs) = (qp|rs)): the integrals above for ``seed``, then from
+``default_rng(seed + 1_000_003)`` in this order: a symmetric N(0, ``amp``)
+change of h (upper triangle with the diagonal, row-major, mirrored), a
+N(0, ``amp``) tensor X averaged over the four index maps of that symmetry,
+(X + X^(qpsr) + X^(rspq) + X^(srqp)) / 4, added to (pq|rs), and a scalar
+N(-1, 0.1).
 """
 from __future__ import annotations
 
@@ -50,6 +61,21 @@ def integrals(norb: int, seed: int, naux: int | None = None):
     eri = 0.5 * (eri + eri.transpose(0, 1, 3, 2))
     eri = 0.5 * (eri + eri.transpose(2, 3, 0, 1))
     return np.ascontiguousarray(h), np.ascontiguousarray(eri), 0.0
+
+
+def dressed_integrals(norb: int, seed: int, amp: float = 0.02):
+    """Return (h, eri, e_core) with the 4-fold symmetry only (see module doc)."""
+    h, eri, _ = integrals(norb, seed)
+    n = h.shape[0]
+    rng = np.random.default_rng(seed + 1_000_003)
+    iu = np.triu_indices(n)
+    dh = np.zeros((n, n))
+    dh[iu] = rng.normal(0.0, amp, size=iu[0].size)
+    dh[(iu[1], iu[0])] = dh[iu]
+    X = rng.normal(0.0, amp, size=(n, n, n, n))
+    dv = 0.25 * (X + X.transpose(1, 0, 3, 2) + X.transpose(2, 3, 0, 1) + X.transpose(3, 2, 1, 0))
+    e_core = float(rng.normal(-1.0, 0.1))
+    return np.ascontiguousarray(h + dh), np.ascontiguousarray(eri + dv), e_core
 
 
 def ci_vector(n_alpha_strings: int, n_beta_strings: int, seed: int, nvec: int = 1):

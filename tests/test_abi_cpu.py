@@ -86,6 +86,30 @@ def test_integral_validation():
     assert e.value.code == casci.E_NONFINITE
 
 
+def test_dressed_integrals_accepted_hermiticity_required():
+    # (pq|rs) = (qp|sr) = (rs|pq) is enough (dressed integrals); breaking either
+    # of those two relations is an error, breaking only (pq|rs) = (qp|rs) is not
+    h, eri, ec = synth.dressed_integrals(4, 2)
+    c = vctx()
+    c.set_integrals(h, eri, e_core=ec)
+    bad = eri.copy()
+    bad[0, 1, 2, 3] += 1e-3
+    bad[1, 0, 3, 2] += 1e-3            # keeps (pq|rs) = (qp|sr), breaks (rs|pq)
+    with pytest.raises(casci.CasciError) as e:
+        c.set_integrals(h, bad)
+    assert e.value.code == casci.E_ARG
+    bad = eri.copy()
+    bad[0, 1, 2, 3] += 1e-3
+    bad[2, 3, 0, 1] += 1e-3            # keeps (pq|rs) = (rs|pq), breaks (qp|sr)
+    with pytest.raises(casci.CasciError) as e:
+        c.set_integrals(h, bad)
+    assert e.value.code == casci.E_ARG
+    ok = eri.copy()
+    for idx in [(0, 1, 2, 3), (1, 0, 3, 2), (2, 3, 0, 1), (3, 2, 1, 0)]:
+        ok[idx] += 1e-3                # the whole 4-fold orbit moves together
+    c.set_integrals(h, ok)
+
+
 def test_call_order_and_norb_mismatch():
     h, eri, _ = synth.integrals(4, 1)
     c = vctx()

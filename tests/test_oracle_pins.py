@@ -301,6 +301,55 @@ def test_spectrum_invariant_under_orbital_rotation():
     assert np.abs(E3 - E1).max() > 1e-3
 
 
+# ---------------------------------------------------------------------------
+# dressed integrals: (pq|rs) = (qp|sr) = (rs|pq) only (reference relaxation,
+# Sec. II.C); the Slater-Condon rules need only particle exchange symmetry
+# ---------------------------------------------------------------------------
+def _random_ints4(n, seed):
+    # generic integrals with the 4-fold symmetry of a Hermitian H, not the 8-fold one
+    rng = np.random.default_rng(seed)
+    h = rng.normal(size=(n, n))
+    h = 0.5 * (h + h.T)
+    g = rng.normal(size=(n, n, n, n))
+    g = g + g.transpose(1, 0, 3, 2)
+    g = g + g.transpose(2, 3, 0, 1)
+    return h, 0.25 * g
+
+
+@pytest.mark.parametrize("n,na,nb", [(2, 1, 1), (3, 2, 1), (3, 1, 2), (4, 2, 2), (4, 3, 1), (4, 0, 2)])
+def test_dressed_hamiltonian_equals_second_quantised_definition(n, na, nb):
+    h, eri = _random_ints4(n, 400 + 10 * n + na)
+    assert np.abs(eri - eri.transpose(1, 0, 2, 3)).max() > 1e-3  # really not 8-fold
+    H = oracle.hamiltonian(h, eri, na, nb, ecore=-0.61)
+    Hb = _second_quantised_h(h, eri, na, nb, -0.61)
+    np.testing.assert_allclose(H, Hb, atol=1e-12, rtol=0)
+    np.testing.assert_allclose(H, H.T, atol=1e-12, rtol=0)       # still Hermitian
+
+
+def test_dressed_spectrum_invariant_under_orbital_rotation():
+    n = 5
+    h, eri, ec = synth.dressed_integrals(n, 23)
+    Q = synth.random_orthogonal(n, 24)
+    h2, eri2 = oracle.rotate_integrals(h, eri, Q)
+    E1 = np.linalg.eigvalsh(oracle.hamiltonian(h, eri, 3, 2, ec))
+    E2 = np.linalg.eigvalsh(oracle.hamiltonian(h2, eri2, 3, 2, ec))
+    np.testing.assert_allclose(E1, E2, atol=1e-11, rtol=0)
+    # folding the pair index (the 8-fold assumption) changes the spectrum
+    eri8 = 0.5 * (eri + eri.transpose(1, 0, 2, 3))
+    eri8 = 0.5 * (eri8 + eri8.transpose(0, 1, 3, 2))
+    E3 = np.linalg.eigvalsh(oracle.hamiltonian(h, eri8, 3, 2, ec))
+    assert np.abs(E3 - E1).max() > 1e-3
+
+
+def test_dressed_generator_symmetry():
+    h, eri, ec = synth.dressed_integrals(6, 5)
+    assert np.array_equal(h, h.T)
+    assert np.abs(eri - eri.transpose(1, 0, 3, 2)).max() < 1e-15
+    assert np.abs(eri - eri.transpose(2, 3, 0, 1)).max() < 1e-15
+    assert np.abs(eri - eri.transpose(1, 0, 2, 3)).max() > 1e-3
+    assert abs(ec + 1.0) < 0.5
+
+
 def test_singlet_selection_and_ground_state_parity():
     h, eri, _ = synth.integrals(6, 1)
     E, X, s2 = oracle.solve(h, eri, 3, 3, nroots=1, spin="singlet")
