@@ -363,6 +363,15 @@ int casci_abi_layout(int64_t* out, int n);
  */
 int casci_sym_eig(const double* A, int n, double* w, double* Z);
 
+/*
+ * Tile pairs of the S + p S^T combination of the transposition-parity sigma
+ * (host computation of the same mapping the kernel's workgroups use): for
+ * k = k0 .. k0+count-1, out[2(k-k0)] = bi and out[2(k-k0)+1] = bj of the k-th
+ * pair bi <= bj < nb in row-by-row order. Host memory only, no device.
+ * CASCI_E_ARG for nb < 1, count < 0, a null out or k outside [0, nb(nb+1)/2).
+ */
+int casci_tile_pairs(int64_t nb, int64_t k0, int64_t count, int64_t* out);
+
 /* ------------------------------------------------------------------------
  * Learned Davidson preconditioner (CASCI_PRECOND_MLP). A per-determinant
  * network 8 -> 64 -> 64 -> 1 (tanh, FP32) predicts the correction vector

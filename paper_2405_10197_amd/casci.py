@@ -141,6 +141,7 @@ def lib():
         "casci_profile_read": (I, [P, P]),
         "casci_abi_layout": (I, [P, I]),
         "casci_sym_eig": (I, [P, I, P, P]),
+        "casci_tile_pairs": (I, [I64, I64, I64, P]),
         "casci_batch_davidson": (I, [P, I, I, D, P, P, P, I]),
         "casci_get_tuning": (I, [P, P]),
         "casci_set_tuning": (I, [P, I, I]),
@@ -552,6 +553,18 @@ def batch_davidson(contexts, nroots: int = 1, tol: float = 1e-10, *, nthreads: i
         d["status"] = OK if infos[i].converged else NOCONV
         out.append(d)
     return E, out
+
+
+def tile_pairs(nb: int, k0: int = 0, count: int | None = None):
+    """Tile pairs (bi, bj) of the parity combination pass for workgroups
+    k0 .. k0+count-1 (casci_tile_pairs): int64 array [count, 2]."""
+    total = nb * (nb + 1) // 2
+    count = total - k0 if count is None else count
+    out = np.zeros((max(count, 0), 2), dtype=np.int64)
+    rc = lib().casci_tile_pairs(int(nb), int(k0), int(count), out.ctypes.data if count > 0 else None)
+    if rc < 0:
+        raise CasciError(rc, "casci_tile_pairs failed")
+    return out
 
 
 def sym_eig(A):

@@ -2102,6 +2102,20 @@ static bool ritz_eig(const double* G, int ldg, int m, const int* par, bool use_p
     return true;
 }
 
+extern "C" int casci_tile_pairs(int64_t nb, int64_t k0, int64_t count, int64_t* out)
+{
+    if (nb < 1 || nb > (int64_t)1 << 24 || count < 0 || (count > 0 && !out)) return CASCI_E_ARG;
+    const int64_t total = nb * (nb + 1) / 2;
+    if (k0 < 0 || k0 + count > total) return CASCI_E_ARG;
+    for (int64_t i = 0; i < count; ++i) {
+        int64_t bi, bj;
+        tile_pair_of(k0 + i, nb, bi, bj);
+        out[2 * i] = bi;
+        out[2 * i + 1] = bj;
+    }
+    return CASCI_OK;
+}
+
 extern "C" int casci_sym_eig(const double* A, int n, double* w, double* Z)
 {
     if (n < 0 || (n > 0 && (!A || !w || !Z))) return CASCI_E_ARG;

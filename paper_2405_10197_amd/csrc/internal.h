@@ -3,6 +3,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <math.h>
 #include <stdint.h>
 
 namespace casci {
@@ -15,6 +16,21 @@ namespace casci {
 __host__ __device__ inline int32_t l1_encode(int32_t J, int sign) { return sign > 0 ? J : ~J; }
 __host__ __device__ inline int32_t l1_index(int32_t v) { return v >= 0 ? v : ~v; }
 __host__ __device__ inline int l1_sign(int32_t v) { return v >= 0 ? 1 : -1; }
+
+// Tile pair (bi, bj), bi <= bj < nb, of index k in the row-by-row enumeration
+// of the upper triangle (the pairs of the S + p S^T pass): row bi starts at
+// s(bi) = bi nb - bi (bi - 1) / 2; the quadratic is inverted in floating point
+// and the rounding settled with integer checks.
+__host__ __device__ inline void tile_pair_of(int64_t k, int64_t nb, int64_t& bi, int64_t& bj)
+{
+    auto rs = [nb](int64_t b) { return b * nb - b * (b - 1) / 2; };
+    const double q = (double)(2 * nb + 1);
+    bi = (int64_t)((q - sqrt(q * q - 8.0 * (double)k)) * 0.5);
+    bi = bi < 0 ? 0 : (bi > nb - 1 ? nb - 1 : bi);
+    while (bi > 0 && rs(bi) > k) --bi;
+    while (bi + 1 < nb && rs(bi + 1) <= k) ++bi;
+    bj = bi + (k - rs(bi));
+}
 
 // bits strictly between orbitals a and b
 __host__ __device__ inline uint64_t between_mask(int a, int b)

@@ -503,17 +503,8 @@ __global__ __launch_bounds__(256) void k_sym_add(double* __restrict__ S, int64_t
 {
     __shared__ double A[32][33];
     __shared__ double B[32][33];
-    // blockIdx.x enumerates pairs bi <= bj row by row; row bi starts at
-    // s(bi) = bi nb - bi (bi - 1) / 2: invert the quadratic, then settle the
-    // rounding with integer checks
-    const int64_t k = blockIdx.x;
-    auto rs = [nb](int64_t b) { return b * nb - b * (b - 1) / 2; };
-    const double q = (double)(2 * nb + 1);
-    int64_t bi = (int64_t)((q - sqrt(q * q - 8.0 * (double)k)) * 0.5);
-    bi = bi < 0 ? 0 : (bi > nb - 1 ? nb - 1 : bi);
-    while (bi > 0 && rs(bi) > k) --bi;
-    while (bi + 1 < nb && rs(bi + 1) <= k) ++bi;
-    const int64_t bj = bi + (k - rs(bi));
+    int64_t bi, bj;
+    tile_pair_of(blockIdx.x, nb, bi, bj);
     const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
     const int64_t r0 = bi * 32, c0 = bj * 32;
     for (int i = ty; i < 32; i += 8) {

@@ -338,3 +338,21 @@ def test_rdm_argument_checks(L):
     assert L.casci_rdm_spin_free(c._h, C.ctypes.data, casci.MEM_HOST, g1.ctypes.data, None) == casci.E_UNSUPPORTED
     with pytest.raises(ValueError):
         c.rdm(np.zeros(c.dims["Ndet"] + 1))
+
+
+@pytest.mark.parametrize("nb", [1, 2, 3, 7, 64, 403, 1520])
+def test_tile_pairs_enumerate_the_upper_triangle(nb):
+    """The closed-form inversion the parity combination pass uses to find its
+    tile pair from the workgroup index: every pair bi <= bj < nb exactly once,
+    in row-by-row order (nb = 403: CAS(16,16), 1520: CAS(18,18) 32-row tiles)."""
+    got = casci.tile_pairs(nb)
+    bi, bj = np.triu_indices(nb)
+    assert np.array_equal(got[:, 0], bi) and np.array_equal(got[:, 1], bj)
+
+
+def test_tile_pairs_range_checks():
+    assert casci.tile_pairs(5, 14, 1).tolist() == [[4, 4]]
+    for args in [(0, 0, 1), (5, 15, 1), (5, -1, 1), (5, 10, 6)]:
+        with pytest.raises(casci.CasciError) as e:
+            casci.tile_pairs(*args)
+        assert e.value.code == casci.E_ARG
