@@ -92,8 +92,11 @@ __global__ __launch_bounds__(64 * ABF_WAVES) void k_ab_bf16(AbParams p, const __
     extern __shared__ __align__(16) unsigned char smem[];
     const int Kp = kb_count * MF::K;
     const int tsz = ((TileLayout<MF>::size(Kp) * 2 + 15) / 16) * 16;  // bytes of one D buffer
+    // sigma row, then one slot per lane that absorbs the (zero) contributions of
+    // entries without a target, so that every atomic add is unconditional
     unsigned* sig = reinterpret_cast<unsigned*>(smem);
-    unsigned char* dbase = smem + ((p.Nb * 4 + 15) / 16) * 16;
+    const int64_t nsig = ((p.Nb + 64) * 4 + 15) / 16 * 4;
+    unsigned char* dbase = smem + nsig * 4;
     int* sJ = reinterpret_cast<int*>(dbase + 2 * tsz);
 
     const int64_t per_xcd = gridDim.x / 8;
@@ -104,7 +107,7 @@ __global__ __launch_bounds__(64 * ABF_WAVES) void k_ab_bf16(AbParams p, const __
     const int ngrp = wave & 3, mgrp = wave >> 2;
     const int mtiles = p.Mp / 16;
 
-    for (int64_t i = tid; i < p.Nb; i += nth) sig[i] = 0u;
+    for (int64_t i = tid; i < p.Nb + 64; i += nth) sig[i] = 0u;
     for (int i = tid; i < Kp; i += nth) sJ[i] = i < p.sa ? l1_index(p.la_j[ia * p.sa + i]) : -1;
 
     // A fragments: row lane % 16 of M tile (mgrp * MT + mt), k = 32 kb + 8 (lane / 16) + q
@@ -117,16 +120,24 @@ __global__ __launch_bounds__(64 * ABF_WAVES) void k_ab_bf16(AbParams p, const __
 #pragma unroll
         for (int kb = 0; kb < KBMAX; ++kb) {
             typename MF::frag f;
+            // unconditional loads at clamped indices (then masked): the loads of
+            // a fragment are in flight together
+            int32_t enc[8];
+            int pqv[8];
 #pragma unroll
             for (int q = 0; q < 8; ++q) {
                 const int e = kb * MF::K + (lane >> 4) * 8 + q;
-                __bf16 v = (__bf16)0.0f;
-                if (kb < kb_count && e < p.sa && m < p.M) {
-                    const int32_t enc = p.la_j[ia * p.sa + e];
-                    const int pq = p.la_pq[ia * p.sa + e];
-                    v = Vt[(int64_t)((pq & 0xff) * p.n + (pq >> 8)) * p.Mp + m];
-                    if (l1_sign(enc) < 0) v = -v;
-                }
+                const int ec = e < p.sa ? e : p.sa - 1;
+                enc[q] = p.la_j[ia * p.sa + ec];
+                pqv[q] = p.la_pq[ia * p.sa + ec];
+            }
+            const int mc = m < p.M ? m : p.M - 1;
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const int e = kb * MF::K + (lane >> 4) * 8 + q;
+                __bf16 v = Vt[(int64_t)((pqv[q] & 0xff) * p.n + (pqv[q] >> 8)) * p.Mp + mc];
+                if (l1_sign(enc[q]) < 0) v = -v;
+                if (!(kb < kb_count && e < p.sa && m < p.M)) v = (__bf16)0.0f;
                 f[q] = v;
                 rs += fabs((double)(float)v);
             }
@@ -171,20 +182,32 @@ __global__ __launch_bounds__(64 * ABF_WAVES) void k_ab_bf16(AbParams p, const __
     const int nseg = Kp * SEGS;
     const int64_t ntiles = (p.Nb + AB_TN - 1) / AB_TN;
     constexpr int SPT = 2;  // segments per thread: Kp * 8 <= 2 * 768 for Kp <= 192
+    // A thread's segments are the same (list row, 8 columns) in every tile: their
+    // rows are read from LDS once. The loads are unconditional and their values
+    // used as loaded, so that the compiler's wait counts leave the next tile's
+    // loads in flight across the current tile's work: a padded list row (k >=
+    // s_alpha) reads row 0 and meets zero A fragments, columns past the row
+    // read its first columns and have no targets.
+    int64_t rowoff[SPT];
+    int segc[SPT];
+    bool segok[SPT];  // (sJ is complete: the barrier after the row maxima follows its writes)
+#pragma unroll
+    for (int q = 0; q < SPT; ++q) {
+        const int sidx = tid + q * nth;
+        const int k = sidx < nseg ? sidx / SEGS : 0;
+        const int J = sidx < nseg ? sJ[k] : -1;
+        segc[q] = (sidx - k * SEGS) * VEC;
+        segok[q] = sidx < nseg && J >= 0;
+        rowoff[q] = (int64_t)(J >= 0 ? J : 0) * ldc;
+    }
     vec_t pf[SPT];
     auto issue = [&](int64_t tile) {
         const int64_t j0 = tile * AB_TN;
 #pragma unroll
         for (int q = 0; q < SPT; ++q) {
-            const int sidx = tid + q * nth;
-            vec_t v = {0u, 0u, 0u, 0u};
-            if (sidx < nseg) {
-                const int k = sidx / SEGS, sg = sidx - k * SEGS;
-                const int64_t col = j0 + sg * VEC;
-                const int J = sJ[k];
-                if (J >= 0 && col < ldc) v = *reinterpret_cast<const vec_t*>(Cs + (int64_t)J * ldc + col);
-            }
-            pf[q] = v;
+            const int64_t col = j0 + segc[q];
+            const bool ok = segok[q] && col < ldc;
+            pf[q] = *reinterpret_cast<const vec_t*>(Cs + rowoff[q] + (ok ? col : 0));
         }
     };
     auto commit = [&](int buf) {
@@ -205,24 +228,23 @@ __global__ __launch_bounds__(64 * ABF_WAVES) void k_ab_bf16(AbParams p, const __
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt) {
             const int mtile = mgrp * MT + mt;
-            uint2 v = {0xffffffffu, 0xffffffffu};
-            if (mtile < mtiles)
-                v = *reinterpret_cast<const uint2*>(tg16 + (((tile * mtiles + mtile) * 4 + ngrp) * 256 + lane * 4));
-            dst[mt] = v;
+            // an M tile past the last computes nothing (zero accumulators): the
+            // targets of the last one are read and receive zeros
+            const int mtc = mtile < mtiles ? mtile : mtiles - 1;
+            dst[mt] = *reinterpret_cast<const uint2*>(tg16 + (((tile * mtiles + mtc) * 4 + ngrp) * 256 + lane * 4));
         }
     };
 
-    issue(0);
-    commit(0);
-    uint2 tgc[MT], tgn[MT];
-    load_tg(0, tgc);
-    __syncthreads();
-    for (int64_t t = 0; t < ntiles; ++t) {
+    // One tile: the loads of tile t + 1 (D rows into pf, targets into tn) are
+    // issued first and stay in flight through the MFMAs and the integer adds of
+    // tile t (targets tc, loaded one tile earlier); the loop is unrolled by two
+    // so that the two target register sets alternate without copies. Past the
+    // last tile the loads read the last tile again (unused).
+    auto step = [&](int64_t t, const uint2 (&tc)[MT], uint2 (&tn)[MT]) {
         const bool more = t + 1 < ntiles;
-        if (more) {
-            issue(t + 1);
-            load_tg(t + 1, tgn);
-        }
+        const int64_t tl = more ? t + 1 : t;
+        issue(tl);
+        load_tg(tl, tn);
         const __bf16* Dt = reinterpret_cast<const __bf16*>(dbase + (t & 1) * tsz);
         f4 acc[MT];
 #pragma unroll
@@ -246,24 +268,29 @@ __global__ __launch_bounds__(64 * ABF_WAVES) void k_ab_bf16(AbParams p, const __
         for (int mt = 0; mt < MT; ++mt) {
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                const unsigned w = v < 2 ? tgc[mt].x : tgc[mt].y;
+                const unsigned w = v < 2 ? tc[mt].x : tc[mt].y;
                 const unsigned e = (w >> (16 * (v & 1))) & 0xffffu;
-                tgt[mt][v] = e;
-                const int qi = __float2int_rn(acc[mt][v] * scale);
+                const bool none = e == TG16_NONE;
+                tgt[mt][v] = none ? (unsigned)p.Nb + lane : (e & 0x7fffu);
+                const int qi = none ? 0 : __float2int_rn(acc[mt][v] * scale);
                 q[mt][v] = (e & 0x8000u) ? -qi : qi;
             }
         }
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
-            for (int v = 0; v < 4; ++v)
-                if (tgt[mt][v] != TG16_NONE) atomicAdd(&sig[tgt[mt][v] & 0x7fffu], (unsigned)q[mt][v]);
-        if (more) {
-            commit((int)((t + 1) & 1));
-#pragma unroll
-            for (int mt = 0; mt < MT; ++mt) tgc[mt] = tgn[mt];
-        }
+            for (int v = 0; v < 4; ++v) atomicAdd(&sig[tgt[mt][v]], (unsigned)q[mt][v]);
+        if (more) commit((int)((t + 1) & 1));
         __syncthreads();
+    };
+    uint2 tga[MT], tgb[MT];
+    issue(0);
+    load_tg(0, tga);
+    commit(0);
+    __syncthreads();
+    for (int64_t t = 0; t < ntiles; t += 2) {
+        step(t, tga, tgb);
+        if (t + 1 < ntiles) step(t + 1, tgb, tga);
     }
     if (p.overwrite) {
         for (int64_t i = tid; i < p.Nb; i += nth) srow[i] = (TO)((double)(int)sig[i] * unit);
@@ -275,7 +302,7 @@ __global__ __launch_bounds__(64 * ABF_WAVES) void k_ab_bf16(AbParams p, const __
 static int64_t abf_lds_bytes(int kb_count, int64_t Nb)
 {
     const int Kp = kb_count * MfmaBF16::K;
-    int64_t b = (Nb * 4 + 15) / 16 * 16;
+    int64_t b = ((Nb + 64) * 4 + 15) / 16 * 16;
     b += 2 * (((int64_t)TileLayout<MfmaBF16>::size(Kp) * 2 + 15) / 16 * 16);
     b += (int64_t)Kp * 4 + 64;
     return b;
