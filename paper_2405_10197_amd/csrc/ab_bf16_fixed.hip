@@ -24,15 +24,17 @@
 // Targets: a 16-bit table in the order of the MFMA accumulator elements, one
 // 8-byte load per lane and 16x16 block: entry [lane][v] of block (tile, M
 // tile, sub-tile) is pair row 16 mt + 4 (lane / 16) + v and column
-// 64 t + 16 ns + lane % 16; bit 15 = negative sign, 0xffff = E_m Jb vanishes.
-// It needs fewer than 32767 beta strings; the sigma row needs Nb * 4 bytes of
-// LDS (Nb <= 15360).
+// 64 t + 16 ns + lane % 16; bits 0-14 = the target beta string, bit 15 =
+// negative sign. Where E_m Jb vanishes (or the column is past the last) the
+// entry names slot Nb + lane, one of 64 slots after the sigma row in LDS that
+// absorb such contributions and are never read, so the kernel adds every
+// element without a test. It needs Nb + 64 < 32768; the sigma row needs
+// (Nb + 64) * 4 bytes of LDS (Nb <= 15296).
 #include "ab_common.h"
 
 namespace casci {
 
 constexpr int ABF_WAVES = 12;  // 4 column groups x 3 pair-row groups
-constexpr uint16_t TG16_NONE = 0xffff;
 
 __global__ __launch_bounds__(256) void k_tg16(const int32_t* __restrict__ tg, int64_t Nb, int Mp, int64_t ntile,
                                               uint16_t* __restrict__ out)
@@ -50,7 +52,7 @@ __global__ __launch_bounds__(256) void k_tg16(const int32_t* __restrict__ tg, in
         const int64_t t = rest / mtiles;
         const int m = mt * 16 + 4 * (lane >> 4) + v;
         const int64_t jc = t * AB_TN + ns * 16 + (lane & 15);
-        uint16_t val = TG16_NONE;
+        uint16_t val = (uint16_t)(Nb + lane);  // absorbing slot of this lane
         if (jc < Nb) {
             const int32_t e = tg[jc * Mp + m];
             if (e != AB_NONE) val = (uint16_t)((l1_index(e) & 0x7fff) | (e < 0 ? 0x8000 : 0));
@@ -62,7 +64,7 @@ __global__ __launch_bounds__(256) void k_tg16(const int32_t* __restrict__ tg, in
 hipError_t launch_tg16(const int32_t* tg, int64_t Nb, int Mp, uint16_t* out, hipStream_t st)
 {
     if (Nb <= 0) return hipSuccess;
-    if (Nb >= 0x7fff) return ab_invalid("alpha-beta: 16-bit targets need fewer than 32767 beta strings");
+    if (Nb + 64 > 0x7fff) return ab_invalid("alpha-beta: 16-bit targets need Nb + 64 < 32768 beta strings");
     if (Mp % 16 != 0) return ab_invalid("alpha-beta: pair rows not padded to 16");
     const int64_t ntile = (Nb + AB_TN - 1) / AB_TN;
     const int64_t total = ntile * (Mp / 16) * 4 * 256;
@@ -261,7 +263,8 @@ __global__ __launch_bounds__(64 * ABF_WAVES) void k_ab_bf16(AbParams p, const __
                     if ((mgrp * MT + mt) < mtiles) acc[mt] = MF::mma(afr[mt][kb], b, acc[mt]);
             }
         }
-        // fixed-point scatter: all conversions first, then the integer adds
+        // fixed-point scatter: all conversions first, then the integer adds; the
+        // entry's sign bit flips the float's sign bit before the rounding
         int q[MT][4];
         unsigned tgt[MT][4];
 #pragma unroll
@@ -270,10 +273,9 @@ __global__ __launch_bounds__(64 * ABF_WAVES) void k_ab_bf16(AbParams p, const __
             for (int v = 0; v < 4; ++v) {
                 const unsigned w = v < 2 ? tc[mt].x : tc[mt].y;
                 const unsigned e = (w >> (16 * (v & 1))) & 0xffffu;
-                const bool none = e == TG16_NONE;
-                tgt[mt][v] = none ? (unsigned)p.Nb + lane : (e & 0x7fffu);
-                const int qi = none ? 0 : __float2int_rn(acc[mt][v] * scale);
-                q[mt][v] = (e & 0x8000u) ? -qi : qi;
+                tgt[mt][v] = e & 0x7fffu;
+                const float x = __uint_as_float(__float_as_uint(acc[mt][v]) ^ ((e & 0x8000u) << 16));
+                q[mt][v] = __float2int_rn(x * scale);
             }
         }
 #pragma unroll
@@ -312,7 +314,7 @@ bool ab_bf16_fixed_fits(int64_t Nb, int sa, int Mp)
 {
     const int kb_count = (sa + MfmaBF16::K - 1) / MfmaBF16::K;
     const int mtiles = Mp / 16;
-    return Nb < 0x7fff && kb_count <= 4 && (mtiles + 2) / 3 <= 4 && kb_count * MfmaBF16::K * 8 <= 2 * 64 * ABF_WAVES &&
+    return Nb + 64 < 0x8000 && kb_count <= 4 && (mtiles + 2) / 3 <= 4 && kb_count * MfmaBF16::K * 8 <= 2 * 64 * ABF_WAVES &&
            abf_lds_bytes(kb_count, Nb) <= 160 * 1024 - 512 - 2 * ABF_WAVES * 8;
 }
 

@@ -202,7 +202,7 @@ hipError_t launch_ab_lowp_bf16(const AbParams& p, const AbReduce& r, const void*
 hipError_t launch_ab_lowp_bf16(const AbParams& p, const AbReduce& r, const void* Vt, const void* Cs, int64_t ldc,
                                float* sigma, hipStream_t st);
 // BF16 contraction with the scatter from the accumulators into a 32-bit
-// fixed-point sigma row (ab_bf16_fixed.hip): symmetric pairs, Nb < 32767 and
+// fixed-point sigma row (ab_bf16_fixed.hip): symmetric pairs, Nb + 64 < 32768 and
 // the row in LDS; tg16 from launch_tg16 (tg16_entries(Nb, Mp) entries)
 bool ab_bf16_fixed_fits(int64_t Nb, int sa, int Mp);
 int64_t tg16_entries(int64_t Nb, int Mp);
