@@ -66,19 +66,23 @@ __device__ inline void ab_load_targets(const AbParams& p, int64_t j0, int wave, 
         const int m0 = (wave + mt * nwaves) * 16;
 #pragma unroll
         for (int ns = 0; ns < 4; ++ns) {
+            // unconditional load at a clamped address (an M tile past the last
+            // computes nothing; a column past the last reads column 0 and its
+            // accumulators are zero): the loads stay in flight across the tile
             const int64_t jc = j0 + ns * 16 + (lane & 15);
-            i4 v = {AB_NONE, AB_NONE, AB_NONE, AB_NONE};
-            if (m0 < p.Mp && jc < p.Nb) v = *reinterpret_cast<const i4*>(p.tg + jc * p.Mp + m0 + 4 * (lane >> 4));
-            dst[mt][ns] = v;
+            const int64_t jcc = jc < p.Nb ? jc : 0;
+            const int m0c = m0 < p.Mp ? m0 : 0;
+            dst[mt][ns] = *reinterpret_cast<const i4*>(p.tg + jcc * p.Mp + m0c + 4 * (lane >> 4));
         }
     }
 }
 
 // fixed-point scatter-add of one 16x64 accumulator block into the LDS row chunk
 // [lo, hi): all sixteen conversions first (independent, so they pipeline), then
-// the integer adds of the elements whose target lies in the chunk
+// the integer adds; an element without a target in the chunk goes to the
+// lane's absorbing slot after the chunk (never read), so no add is conditional
 __device__ inline void ab_scatter_fixed(unsigned long long* sig, const d4 (&acc)[4], const i4 (&tgt)[4],
-                                        int64_t lo, int64_t hi, double scale)
+                                        int64_t lo, int64_t hi, double scale, int absorb)
 {
     long long q[4][4];
     int off[4][4];
@@ -89,15 +93,14 @@ __device__ inline void ab_scatter_fixed(unsigned long long* sig, const d4 (&acc)
             const int32_t e = tgt[ns][v];
             const int64_t tgi = l1_index(e);
             const bool in = e != AB_NONE && tgi >= lo && tgi < hi;
-            off[ns][v] = in ? (int)(tgi - lo) : -1;
+            off[ns][v] = in ? (int)(tgi - lo) : absorb;
             q[ns][v] = __double2ll_rn((e >= 0 ? acc[ns][v] : -acc[ns][v]) * scale);
         }
     }
 #pragma unroll
     for (int ns = 0; ns < 4; ++ns)
 #pragma unroll
-        for (int v = 0; v < 4; ++v)
-            if (off[ns][v] >= 0) atomicAdd(&sig[off[ns][v]], (unsigned long long)q[ns][v]);
+        for (int v = 0; v < 4; ++v) atomicAdd(&sig[off[ns][v]], (unsigned long long)q[ns][v]);
 }
 
 template <int KBMAX, int MT, int PF>
@@ -112,7 +115,7 @@ __global__ __launch_bounds__(64 * AB_MAX_WAVES) void k_ab(AbParams p, const doub
     extern __shared__ __align__(16) unsigned char smem[];
     const int Kp = kb_count * MF::K;
     unsigned long long* sig = reinterpret_cast<unsigned long long*>(smem);
-    double* Dt = reinterpret_cast<double*>(smem + ((chunk * 8 + 15) / 16) * 16);
+    double* Dt = reinterpret_cast<double*>(smem + (((chunk + 64) * 8 + 15) / 16) * 16);
     int* sJ = reinterpret_cast<int*>(Dt + ((TileLayout<MF>::size(Kp) * 8 + 15) / 16) * 2);
 
     const int64_t per_xcd = gridDim.x / 8;
@@ -127,7 +130,8 @@ __global__ __launch_bounds__(64 * AB_MAX_WAVES) void k_ab(AbParams p, const doub
     const int wave = tid >> 6, lane = tid & 63;
     const int nwaves = nth >> 6;
 
-    for (int64_t i = tid; i < hi - lo; i += nth) sig[i] = 0ull;
+    // the row chunk and, after it, one absorbing slot per lane
+    for (int64_t i = tid; i < hi - lo + 64; i += nth) sig[i] = 0ull;
     for (int i = tid; i < Kp; i += nth) sJ[i] = i < p.sa ? l1_index(p.la_j[ia * p.sa + i]) : 0;
 
     // A fragments (row lane%16 of each M tile carries pair row arow(lane%16))
@@ -189,37 +193,53 @@ __global__ __launch_bounds__(64 * AB_MAX_WAVES) void k_ab(AbParams p, const doub
     const double unit = ldexp(1.0, -se);
 
     const int tile_elems = Kp * AB_TN;
+    // A thread's tile elements are the same (list row, column) in every tile:
+    // their rows are read from LDS once. The loads are unconditional at clamped
+    // addresses, so the compiler's wait counts leave them in flight: padded
+    // list rows meet zero A fragments, and columns past the last are stored to
+    // LDS as zeros (their clamped targets are real ones and must receive 0).
+    // (element idx = tid + i nth of a tile is list row idx / 64 = wave + i nwaves
+    // and column idx % 64 = lane, as nth is a multiple of 64)
+    static_assert(AB_TN == 64, "one column per lane");
+    int rowJ[PF];
+#pragma unroll
+    for (int i = 0; i < PF; ++i) {
+        const int k = wave + i * nwaves;
+        rowJ[i] = k < p.sa ? sJ[k] : 0;
+    }
     double pf[PF];
     auto load_tile = [&](int64_t j0) {
+        const int64_t col = j0 + lane < p.Nb ? j0 + lane : 0;
 #pragma unroll
-        for (int i = 0; i < PF; ++i) {
-            const int idx = tid + i * nth;
-            const int k = idx / AB_TN, c = idx - k * AB_TN;
-            double v = 0.0;
-            if (idx < tile_elems && k < p.sa && j0 + c < p.Nb) v = C[(int64_t)sJ[k] * p.Nb + j0 + c];
-            pf[i] = v;
-        }
+        for (int i = 0; i < PF; ++i) pf[i] = C[(int64_t)rowJ[i] * p.Nb + col];
     };
-    auto store_tile = [&]() {
+    auto store_tile = [&](int64_t j0) {
 #pragma unroll
         for (int i = 0; i < PF; ++i) {
             const int idx = tid + i * nth;
             if (idx < tile_elems) {
                 const int k = idx / AB_TN, c = idx - k * AB_TN;
-                Dt[TileLayout<MF>::at(k, c, Kp)] = pf[i];
+                Dt[TileLayout<MF>::at(k, c, Kp)] = j0 + c < p.Nb ? pf[i] : 0.0;
             }
         }
     };
+    const int absorb = (int)(hi - lo) + lane;
+    // One tile: this tile's targets (their latency hides behind the FP64 MFMA
+    // chain; a second register set for them would spill the A fragments) and
+    // the next tile's D elements are issued first; past the last tile the loads
+    // read the last tile again (unused).
     load_tile(0);
-    store_tile();
+    store_tile(0);
     __syncthreads();
-
     for (int64_t j0 = 0; j0 < p.Nb; j0 += AB_TN) {
         const bool more = j0 + AB_TN < p.Nb;
-        // this tile's targets: their latency hides behind the FP64 MFMA chain
-        i4 tgc[MT][4];
-        ab_load_targets<MT>(p, j0, wave, nwaves, lane, tgc);
-        if (more) load_tile(j0 + AB_TN);
+        const int64_t jn = more ? j0 + AB_TN : j0;
+        i4 tc[MT][4];
+        ab_load_targets<MT>(p, j0, wave, nwaves, lane, tc);
+        // keep the target loads ahead of the D loads: waiting for the targets
+        // before the adds then leaves the D loads in flight
+        __builtin_amdgcn_sched_barrier(0);
+        load_tile(jn);
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt) {
             const int mtile = wave + mt * nwaves;
@@ -240,10 +260,10 @@ __global__ __launch_bounds__(64 * AB_MAX_WAVES) void k_ab(AbParams p, const doub
                     }
                 }
             }
-            ab_scatter_fixed(sig, acc, tgc[mt], lo, hi, scale);
+            ab_scatter_fixed(sig, acc, tc[mt], lo, hi, scale, absorb);
         }
         __syncthreads();
-        if (more) store_tile();
+        if (more) store_tile(jn);
         __syncthreads();
     }
     if (p.overwrite)
@@ -255,7 +275,7 @@ __global__ __launch_bounds__(64 * AB_MAX_WAVES) void k_ab(AbParams p, const doub
 static int64_t ab_lds_bytes(int kb_count, int64_t chunk)
 {
     const int Kp = kb_count * MfmaF64::K;
-    int64_t b = (chunk * 8 + 15) / 16 * 16;
+    int64_t b = ((chunk + 64) * 8 + 15) / 16 * 16;
     b += ((int64_t)TileLayout<MfmaF64>::size(Kp) * 8 + 15) / 16 * 16;
     b += (int64_t)Kp * 4 + 64;
     return b;
