@@ -336,9 +336,25 @@ __global__ __launch_bounds__(64 * SS_BLK_R, 8) void k_ss_gather_blk(SsBlk bk, co
     };
     // one chunk: pn holds the X rows of chunk ch + 1 (in flight), pf receives
     // those of chunk ch + 2 from the indices un; the indices of ch + 3 go to un2
+    // L2 prefetch of the next chunk's group data: one coalesced dword per lane
+    // (256 bytes, about five groups) whose value is folded into a dummy one
+    // step later (and the dummy kept alive by an empty asm statement at the
+    // end), so the scalar loads of that chunk find their lines in the L2
+    // instead of the memory side: 44.6 -> 40.6 ms (FP64) and 24.7 -> 23.1 ms
+    // (FP32 input) at CAS(16,16); two chunks ahead was slower
+    const unsigned* g32 = reinterpret_cast<const unsigned*>(grow);
+    // last dword of the row's groups (rows past the last have none: index 0 of
+    // the stream, which exists)
+    const int gend = max(off_at(nch) * (int)(sizeof(SsGroup) / 4) - 1, 0);
+    unsigned pfx = 0u, pfx_acc = 0u;
     auto step = [&](int ch, VX (&pn)[RPW], VX (&pf)[RPW], int& un, int& un2) {
         un2 = load_u(ch + 3);
         issue(un, pf);
+        pfx_acc ^= pfx;
+        {
+            const int i = off_at(ch + 1 < nch ? ch + 1 : ch) * (int)(sizeof(SsGroup) / 4) + lane;
+            pfx = g32[i < gend ? i : gend];
+        }
         compute(ch);
         if (ch + 1 < nch) commit((ch + 1) & 1, pn);
         __syncthreads();
@@ -356,6 +372,7 @@ __global__ __launch_bounds__(64 * SS_BLK_R, 8) void k_ss_gather_blk(SsBlk bk, co
         step(ch, pb, pa, ua, ub);
         if (ch + 1 < nch) step(ch + 1, pa, pb, ub, ua);
     }
+    asm volatile("" ::"v"(pfx_acc ^ pfx));
     if (rowok) {
 #pragma unroll
         for (int u = 0; u < VW; ++u) {
