@@ -672,19 +672,25 @@ def headline(args):
         # the width the autotuner chose for this space (99: row-blocked LDS form)
         code = tuning.get("f32in" if tag == "lowp" else "f64", 0)
         blocked = code == 99
+        # the BF16 build's row-blocked gather sums in FP32 (FP32 vector roof),
+        # every other build in FP64
+        acc32 = tag == "lowp" and blocked and HEADLINE["ab_prec"] == "bf16"
         if tag == "lowp":
-            kname = "k_ss_gather_blk<float,double,float,2>" if blocked else "k_ss_gather<float,double>"
+            kname = ("k_ss_gather_blk<float,double,float,2,%s>" % ("float" if acc32 else "double")
+                     if blocked else "k_ss_gather<float,double>")
             pmc = "ss_gather_blk_f32" if blocked else "ss_gather_f32"
         else:
             kname = "k_ss_gather_blk<double,double,double,1>" if blocked else "k_ss_gather<double,double>"
             pmc = "ss_gather_blk_f64" if blocked else "ss_gather_f64"
         traffic = read_traffic(os.path.join(ROOT, "profiles", "%s_%s_pmc.txt" % (pmc, args.workload)))
         # Roofline: the compulsory bytes (read C once, write sigma, read the
-        # operator) take a fraction of a millisecond at 8 TB/s, the FP64
-        # multiply-adds several: the binding roof is the FP64 vector rate
+        # operator) take a fraction of a millisecond at 8 TB/s, the
+        # multiply-adds several: the binding roof is the vector rate of the
+        # accumulation type
         ach = fig["gather_TFLOPs"]
-        roof = {"kernel": kname, "width_code": code, "bound": "alu", "achieved": ach, "peak": PEAK["f64_TF"],
-                "unit": "TFLOP/s", "frac": ach / PEAK["f64_TF"], "traffic": traffic,
+        vpeak = PEAK["f32_TF"] if acc32 else PEAK["f64_TF"]
+        roof = {"kernel": kname, "width_code": code, "bound": "alu", "achieved": ach, "peak": vpeak,
+                "unit": "TFLOP/s", "frac": ach / vpeak, "traffic": traffic,
                 "hbm_view": {"achieved_GBps": fig["gather_GBps_algorithmic"], "peak_GBps": PEAK["hbm_GBps"],
                              "frac": fig["gather_GBps_algorithmic"] / PEAK["hbm_GBps"]}}
     # the counters' HBM-side bytes over the same launch time (what the memory

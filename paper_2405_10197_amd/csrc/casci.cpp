@@ -113,7 +113,7 @@ struct casci_ctx {
     DBuf d_h, d_eri, d_fa_col, d_fa_val, d_fb_col, d_fb_val, d_jpq, d_diag;
     DBuf d_fa_c16, d_fa_v32, d_fb_c16, d_fb_v32;  // compact operator copies (< 65536 strings)
     struct Blocks {  // row-blocked form of one same-spin operator (SsBlk)
-        DBuf uni, binfo, goff, rbase, gs64, gs32;
+        DBuf uni, binfo, goff, rbase, gs64, gs32, gsf;
         int64_t nblk = 0;
         bool have = false;
     } blk[2];        // [0]: alpha (and beta when nalpha = nbeta), [1]: beta
@@ -293,7 +293,7 @@ extern "C" void casci_destroy(casci_ctx* ctx)
                         &ctx->d_rdm_M, &ctx->d_rdm_G, &ctx->d_rdm_out};
         if (ctx->blas) (void)rocblas_destroy_handle(ctx->blas);
         for (auto& bl : ctx->blk) {
-            for (DBuf* d : {&bl.uni, &bl.binfo, &bl.goff, &bl.rbase, &bl.gs64, &bl.gs32}) d->release();
+            for (DBuf* d : {&bl.uni, &bl.binfo, &bl.goff, &bl.rbase, &bl.gs64, &bl.gs32, &bl.gsf}) d->release();
         }
         for (auto& gr : ctx->graphs) (void)hipGraphExecDestroy(gr.exec);
         ctx->graphs.clear();
@@ -898,15 +898,6 @@ static int ensure_reduce(casci_ctx* ctx, bool full, AbReduce* out, bool may_allo
     return CASCI_OK;
 }
 
-// sigma = (H + lambda S^2) C on device vectors (FP64 storage).
-// parity = +1 / -1 declares C = +-C^T (nalpha = nbeta only): transposition
-// commutes with H, so sigma_bb = parity * sigma_aa^T and one same-spin gather
-// serves both spins. parity = 0: general C. ab_prec != F64 also reads the
-// same-spin gather operand from an FP32 copy of C (accumulation stays FP64).
-// The alpha-beta contraction writes its own buffer, added in by the final pass
-// (with parity fused into the S + p S^T symmetrisation). Running it on a
-// second stream beside the gathers was measured not to help: each slows the
-// other by as much as the overlap gains.
 // The same-spin operator of one spin (1: beta; the alpha one when nalpha = nbeta)
 // with its compact copies when they exist.
 static SsOp ss_op(const casci_ctx* ctx, int spin)
@@ -926,6 +917,7 @@ static SsOp ss_op(const casci_ctx* ctx, int spin)
         op.blk.rbase = bl.rbase.as<int32_t>();
         op.blk.gs64 = bl.gs64.as<SsGroup>();
         op.blk.gs32 = bl.gs32.as<SsGroup>();
+        op.blk.gsf = bl.gsf.as<SsGroupF>();
         op.blk.ch = SS_BLK_CH;
         op.blk.nblk = bl.nblk;
     }
@@ -937,7 +929,8 @@ static SsOp ss_op(const casci_ctx* ctx, int spin)
 // row its entries 1..r-1 (ascending columns) as groups of four aligned to the
 // entry index, split by chunks of SS_BLK_CH union rows: a group holds the LDS
 // offsets of its operands and the values of entries 4g..4g+3 (one stream for
-// FP64 input, one with FP32-rounded values for FP32 input), a slot outside
+// FP64 input, one with FP32-rounded values for FP32 input, and the latter
+// with FP32 values for FP32 accumulation), a slot outside
 // the chunk value 0 and the chunk's first union row. The diagonal (entry 0)
 // stays outside: the kernel takes it from the row itself. Built on the host
 // from the operator's rows; needs fewer than 65536 strings.
@@ -962,8 +955,10 @@ static int ensure_ss_blocks(casci_ctx* ctx, int spin)
     std::vector<uint16_t> uni, goff;
     std::vector<int32_t> binfo((size_t)nblk * 4), rbase((size_t)N, 0);
     std::vector<SsGroup> gs64, gs32;
+    std::vector<SsGroupF> gsf;
     gs64.reserve((size_t)N * (r / 4 + 16));
     gs32.reserve((size_t)N * (r / 4 + 16));
+    gsf.reserve((size_t)N * (r / 4 + 16));
     std::vector<int32_t> stamp((size_t)N, -1), where((size_t)N, 0);
     std::vector<int32_t> u;
     for (int64_t blk = 0; blk < nblk; ++blk) {
@@ -1010,17 +1005,20 @@ static int ensure_ss_blocks(casci_ctx* ctx, int spin)
                 while (ez < r && where[cI[ez]] < (ch + 1) * CH) ++ez;
                 for (int g = e & ~3; g < ez; g += 4) {
                     SsGroup a, b;
+                    SsGroupF f;
                     for (int sl = 0; sl < 4; ++sl) {
                         const int x = g + sl;
                         const bool in = x >= e && x < ez;
                         const uint32_t q = (uint32_t)(in ? where[cI[x]] : ch * CH);
                         // row of the operand within the LDS chunk, times the row's bytes
-                        a.off[sl] = b.off[sl] = (q % CH) * (uint32_t)SS_BLK_ROWB;
+                        a.off[sl] = b.off[sl] = f.off[sl] = (q % CH) * (uint32_t)SS_BLK_ROWB;
                         a.v[sl] = in ? vI[x] : 0.0;
-                        b.v[sl] = in ? (double)(float)vI[x] : 0.0;
+                        f.v[sl] = in ? (float)vI[x] : 0.0f;
+                        b.v[sl] = (double)f.v[sl];
                     }
                     gs64.push_back(a);
                     gs32.push_back(b);
+                    gsf.push_back(f);
                     ++ng;
                 }
                 e = ez;
@@ -1033,6 +1031,7 @@ static int ensure_ss_blocks(casci_ctx* ctx, int spin)
     if (gs64.empty()) {
         gs64.push_back(SsGroup{});
         gs32.push_back(SsGroup{});
+        gsf.push_back(SsGroupF{});
     }
     HIPC(bl.uni.ensure(uni.size() * 2));
     HIPC(bl.binfo.ensure(binfo.size() * 4));
@@ -1040,12 +1039,14 @@ static int ensure_ss_blocks(casci_ctx* ctx, int spin)
     HIPC(bl.rbase.ensure(rbase.size() * 4));
     HIPC(bl.gs64.ensure(gs64.size() * sizeof(SsGroup)));
     HIPC(bl.gs32.ensure(gs32.size() * sizeof(SsGroup)));
+    HIPC(bl.gsf.ensure(gsf.size() * sizeof(SsGroupF)));
     HIPC(hipMemcpyAsync(bl.uni.p, uni.data(), uni.size() * 2, hipMemcpyHostToDevice, ctx->stream));
     HIPC(hipMemcpyAsync(bl.binfo.p, binfo.data(), binfo.size() * 4, hipMemcpyHostToDevice, ctx->stream));
     HIPC(hipMemcpyAsync(bl.goff.p, goff.data(), goff.size() * 2, hipMemcpyHostToDevice, ctx->stream));
     HIPC(hipMemcpyAsync(bl.rbase.p, rbase.data(), rbase.size() * 4, hipMemcpyHostToDevice, ctx->stream));
     HIPC(hipMemcpyAsync(bl.gs64.p, gs64.data(), gs64.size() * sizeof(SsGroup), hipMemcpyHostToDevice, ctx->stream));
     HIPC(hipMemcpyAsync(bl.gs32.p, gs32.data(), gs32.size() * sizeof(SsGroup), hipMemcpyHostToDevice, ctx->stream));
+    HIPC(hipMemcpyAsync(bl.gsf.p, gsf.data(), gsf.size() * sizeof(SsGroupF), hipMemcpyHostToDevice, ctx->stream));
     HIPC(hipStreamSynchronize(ctx->stream));  // pageable sources
     bl.nblk = nblk;
     bl.have = true;
@@ -1162,7 +1163,9 @@ static size_t sigma_work_layout(const casci_ctx* ctx, int ab_prec, int parity, u
 // parity = +1 / -1 declares C = +-C^T (nalpha = nbeta only): transposition
 // commutes with H, so sigma_bb = parity * sigma_aa^T and one same-spin gather
 // serves both spins. parity = 0: general C. ab_prec != F64 also reads the
-// same-spin gather operand from an FP32 copy of C (accumulation stays FP64).
+// same-spin gather operand from an FP32 copy of C; the accumulation stays
+// FP64, except in the row-blocked gather of a BF16 build, which sums in FP32
+// (relative error ~1e-6 against the ~1e-3 of the BF16 alpha-beta part).
 // The alpha-beta contraction writes its own buffer, added in by the final pass
 // (with parity fused into the S + p S^T symmetrisation). Running it on a
 // second stream beside the gathers was measured not to help: each slows the
@@ -1256,7 +1259,7 @@ static int sigma_dev(casci_ctx* ctx, const double* C, double* S, int ab_prec, do
     if (alloc && ctx->tune_lpe[lowp ? 1 : 0] == 0) CHECK_RC(autotune_gather(ctx, lowp, C, w.c32, ld32));
     const int lpe = ctx->tune_lpe[lowp ? 1 : 0];
     if (lowp)
-        HIPC(launch_ss_gather_f32in(ss_op(ctx, 0), Na, Nb, w.c32, ld32, S, s_aa, 0, st, lpe));
+        HIPC(launch_ss_gather_f32in(ss_op(ctx, 0), Na, Nb, w.c32, ld32, S, s_aa, 0, st, lpe, ab_prec == CASCI_BF16));
     else
         HIPC(launch_ss_gather_f64(ss_op(ctx, 0), Na, Nb, C, S, s_aa, 0, st, lpe));
     CHECK_RC(mark(1, st));
@@ -1384,7 +1387,7 @@ static std::vector<void*> sigma_buffers(const casci_ctx* ctx)
             ctx->d_pairs_sym.p, ctx->d_pairs_full.p, ctx->d_gin.p, ctx->d_gout.p, ctx->d_fa_c16.p,
             ctx->d_fa_v32.p, ctx->d_fb_c16.p, ctx->d_fb_v32.p, ctx->d_rowmax.p, ctx->d_tg16.p};
     for (const auto& bl : ctx->blk)
-        for (const DBuf* d : {&bl.uni, &bl.binfo, &bl.goff, &bl.rbase, &bl.gs64, &bl.gs32}) v.push_back(d->p);
+        for (const DBuf* d : {&bl.uni, &bl.binfo, &bl.goff, &bl.rbase, &bl.gs64, &bl.gs32, &bl.gsf}) v.push_back(d->p);
     return v;
 }
 
@@ -2236,8 +2239,14 @@ static int davidson_impl(casci_ctx* ctx, int nroots, double tol, const casci_dav
     double* SX = dSX.as<double>();
     auto vB = [&](int i) { return B + (size_t)i * Nd; };
     auto vS = [&](int i) { return S + (size_t)i * Nd; };
-    auto vX = [&](int i) { return X + (size_t)i * Nd; };
-    auto vSX = [&](int i) { return SX + (size_t)i * Nd; };
+    // X and SX hold two sets of k Ritz vectors: the current ones in half `cur`
+    // and the previous ones in the other half; a Rayleigh-Ritz step flips the
+    // halves instead of copying the previous set
+    int cur = 0;
+    auto vX = [&](int i) { return X + ((size_t)cur * k + i) * Nd; };
+    auto vSX = [&](int i) { return SX + ((size_t)cur * k + i) * Nd; };
+    auto vXp = [&](int i) { return X + ((size_t)(1 - cur) * k + i) * Nd; };
+    auto vSXp = [&](int i) { return SX + ((size_t)(1 - cur) * k + i) * Nd; };
     HIPC(ctx->d_small.ensure(64 * 1024 * 8));
     double* dsm = ctx->d_small.as<double>();
     // d_small layout (doubles): [8192, 8256) theta, [8320, 8320+4096)
@@ -2313,6 +2322,7 @@ static int davidson_impl(casci_ctx* ctx, int nroots, double tol, const casci_dav
             return CASCI_OK;
         };
         CHECK_RC(norms(before));
+        std::vector<double> cur = before;  // norms after the Gram-Schmidt against the basis
         if (m > 0) {
             // classical Gram-Schmidt against the basis; the second pass runs only
             // when the first removed most of a vector (norm ratio below 1/sqrt2),
@@ -2322,10 +2332,9 @@ static int davidson_impl(casci_ctx* ctx, int nroots, double tol, const casci_dav
                 for (double& x : c) x = -x;
                 CHECK_RC(combine(vB(0), m, c, cnt, 1.0, vB(m)));
                 if (pass == 0) {
-                    std::vector<double> after;
-                    CHECK_RC(norms(after));
+                    CHECK_RC(norms(cur));
                     bool again = false;
-                    for (int j = 0; j < cnt; ++j) again = again || !(after[j] > 0.7071 * before[j]);
+                    for (int j = 0; j < cnt; ++j) again = again || !(cur[j] > 0.7071 * before[j]);
                     if (!again) break;
                 }
             }
@@ -2333,11 +2342,29 @@ static int davidson_impl(casci_ctx* ctx, int nroots, double tol, const casci_dav
         kept = 0;
         for (int j = 0; j < cnt; ++j) {
             double* v = vB(m + j);
-            if (kept > 0) {
+            // Gram-Schmidt against the vectors kept so far. With parity, those of
+            // the other parity are orthogonal to v up to rounding: when they all
+            // come first (the corrections are generated grouped by parity) only
+            // the trailing run of v's parity is used. The second pass runs only
+            // when the first removed most of v (the same 1/sqrt2 rule as above,
+            // the removed part's norm taken from the coefficients).
+            int s0 = 0;
+            if (use_par && par[m + j] != 0) {
+                s0 = kept;
+                while (s0 > 0 && par[m + s0 - 1] == par[m + j]) --s0;
+                for (int i = 0; i < s0; ++i)
+                    if (par[m + i] == par[m + j] || par[m + i] == 0) s0 = 0;
+            }
+            if (kept > s0) {
                 for (int pass = 0; pass < 2; ++pass) {
-                    CHECK_RC(dots_dev(vB(m), kept, v, 1, c));
-                    for (double& x : c) x = -x;
-                    CHECK_RC(combine(vB(m), kept, c, 1, 1.0, v));
+                    CHECK_RC(dots_dev(vB(m + s0), kept - s0, v, 1, c));
+                    double removed = 0.0;
+                    for (double& x : c) {
+                        removed += x * x;
+                        x = -x;
+                    }
+                    CHECK_RC(combine(vB(m + s0), kept - s0, c, 1, 1.0, v));
+                    if (pass == 0 && !(removed > 0.5 * cur[j] * cur[j])) break;
                 }
             }
             // Re-project onto the vector's parity before normalising: what is left
@@ -2562,10 +2589,10 @@ static int davidson_impl(casci_ctx* ctx, int nroots, double tol, const casci_dav
         // G is held on the host: its small eigenproblem is solved there
         if (!ritz_eig(Gc.data(), m, m, par.data(), use_par, theta.data(), Y.data()))
             return ctx->fail(CASCI_E_UNSUPPORTED, "Rayleigh-Ritz: eigensolver did not converge");
-        // previous Ritz vectors move to slots [k, 2k)
+        // the current Ritz vectors become the previous ones (xpar[k, 2k) holds
+        // their parities)
         if (have_prev) {
-            HIPC(hipMemcpyAsync(vX(k), vX(0), vb * k, hipMemcpyDeviceToDevice, st));
-            HIPC(hipMemcpyAsync(vSX(k), vSX(0), vb * k, hipMemcpyDeviceToDevice, st));
+            cur = 1 - cur;
             for (int j = 0; j < k; ++j) xpar[k + j] = xpar[j];
         }
         // parity of each Ritz vector: the projected matrix is block diagonal in
@@ -2583,7 +2610,7 @@ static int davidson_impl(casci_ctx* ctx, int nroots, double tol, const casci_dav
         CHECK_RC(combine(vB(0), m, yk, k, 0.0, vX(0)));
         CHECK_RC(combine(vS(0), m, yk, k, 0.0, vSX(0)));
         HIPC(hipMemcpyAsync(dth, theta.data(), k * 8, hipMemcpyHostToDevice, st));
-        HIPC(launch_residual(X, SX, Nd, k, dth, ctx->d_diag.as<double>(), Nd, ctx->d_work.as<double>(),
+        HIPC(launch_residual(vX(0), vSX(0), Nd, k, dth, ctx->d_diag.as<double>(), Nd, ctx->d_work.as<double>(),
                              dres, st));
         std::vector<double> rs(4 * k);
         HIPC(hipMemcpyAsync(rs.data(), dres, 4 * k * 8, hipMemcpyDeviceToHost, st));
@@ -2607,14 +2634,18 @@ static int davidson_impl(casci_ctx* ctx, int nroots, double tol, const casci_dav
         if (info && info->hist_time_ms && it < info->hist_len) info->hist_time_ms[it] = wall.ms();
         for (int j = 0; j < k; ++j) theta_prev[j] = theta[j];
         if (o.progress) o.progress(o.progress_user, it, kreq, theta.data(), rn.data(), wall.ms());
-        if (col) CHECK_RC(collect_step(ctx, col, kreq, X, SX, theta, rn, dmin));
+        if (col) CHECK_RC(collect_step(ctx, col, kreq, vX(0), vSX(0), theta, rn, dmin));
         if (!std::isfinite(rmax)) return ctx->fail(CASCI_E_NONFINITE, "non-finite residual in Davidson");
         // collapse: keep current and previous Ritz vectors (room for ncorr new ones)
         auto collapse = [&](int ncorr) -> int {
             const int nkeep = (have_prev && 2 * k + ncorr <= m_max) ? 2 * k : k;
             const bool refine = prec != CASCI_F64;
-            HIPC(hipMemcpyAsync(vB(0), vX(0), vb * nkeep, hipMemcpyDeviceToDevice, st));
-            HIPC(hipMemcpyAsync(vS(0), vSX(0), vb * nkeep, hipMemcpyDeviceToDevice, st));
+            HIPC(hipMemcpyAsync(vB(0), vX(0), vb * k, hipMemcpyDeviceToDevice, st));
+            HIPC(hipMemcpyAsync(vS(0), vSX(0), vb * k, hipMemcpyDeviceToDevice, st));
+            if (nkeep > k) {
+                HIPC(hipMemcpyAsync(vB(k), vXp(0), vb * k, hipMemcpyDeviceToDevice, st));
+                HIPC(hipMemcpyAsync(vS(k), vSXp(0), vb * k, hipMemcpyDeviceToDevice, st));
+            }
             for (int j = 0; j < nkeep; ++j) par[j] = xpar[j];
             if (refine) {  // FP64 sigma of the current Ritz vectors, buffer roots included
                 // (refining those in low precision was measured to cost iterations)
@@ -2724,7 +2755,10 @@ static int davidson_impl(casci_ctx* ctx, int nroots, double tol, const casci_dav
             }
         }
         if (m + (int)todo.size() > m_max) CHECK_RC(collapse((int)todo.size()));
-        // corrections for unconverged roots
+        // corrections for unconverged roots, grouped by parity (Gram-Schmidt
+        // among the new vectors then skips the other parity)
+        if (use_par)
+            std::stable_sort(todo.begin(), todo.end(), [&](int a, int b) { return xpar[a] > xpar[b]; });
         const int cnt = (int)todo.size();
         for (int t = 0; t < cnt; ++t) {
             const int j = todo[t];
@@ -2783,7 +2817,7 @@ static int davidson_impl(casci_ctx* ctx, int nroots, double tol, const casci_dav
             if (info) CHECK_RC(spin_square_dev(ctx, vX(j), &s2v[j]));
         }
         if (vectors)
-            HIPC(hipMemcpyAsync(vectors, X, vb * kreq,
+            HIPC(hipMemcpyAsync(vectors, vX(0), vb * kreq,
                                 mem == CASCI_MEM_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice, st));
         HIPC(hipStreamSynchronize(st));
     }

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
+#include <type_traits>
 
 namespace casci {
 
@@ -99,6 +100,14 @@ struct SsGroup {
     uint32_t off[4];
     double v[4];
 };
+// the same group with FP32 values, for the FP32-accumulating gather of the
+// BF16 sigma build (32 bytes: one scalar load)
+struct SsGroupF {
+    uint32_t off[4];
+    float v[4];
+};
+template <typename TA>
+using SsGroupOf = typename std::conditional<std::is_same<TA, float>::value, SsGroupF, SsGroup>::type;
 struct SsBlk {
     const uint16_t* uni;   // unions of all blocks, concatenated (string indices < 65536)
     const int4* binfo;     // per block {union offset, union size, group offsets offset, chunks}
@@ -106,6 +115,7 @@ struct SsBlk {
     const int32_t* rbase;  // [N]: first group of each row
     const SsGroup* gs64;   // groups with FP64 values (FP64 input)
     const SsGroup* gs32;   // groups with values rounded to FP32 (FP32 input)
+    const SsGroupF* gsf;   // the gs32 groups with FP32 values (FP32 input, FP32 accumulation)
     int ch;                // union rows per chunk (SS_BLK_CH)
     int64_t nblk;
 };
@@ -115,16 +125,20 @@ struct SsOp {
     const uint16_t* col16;  // may be null
     const float* val32;     // may be null
     int r;
-    SsBlk blk = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, 0, 0};  // row-blocked form (blk.uni null: none)
+    SsBlk blk = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, 0, 0};  // row-blocked form (blk.uni null: none)
 };
 // Y(I,:) = [acc ? Y(I,:) : 0] + sum_e val[I*r+e] X(col[I*r+e], :) + shift * X(I,:)
 // (lpe: strip width code 16/32/64 lanes per entry, 128 = 64 lanes x 2 columns; 0 = 64).
 // FP64 X and Y: FP64 values (16-bit columns when present).
 hipError_t launch_ss_gather_f64(const SsOp& op, int64_t nrows, int64_t ncols, const double* X, double* Y,
                                 double shift, int acc, hipStream_t st, int lpe = 0);
-// FP32 copy of X with row stride ldx, FP64 Y (compact operator when present)
+// FP32 copy of X with row stride ldx, FP64 Y (compact operator when present).
+// acc32: the row-blocked width accumulates in FP32 (FP32 values, no
+// conversions per entry); the BF16 build uses it, whose alpha-beta part has a
+// rounding error far above that of FP32 sums. Other widths ignore it.
 hipError_t launch_ss_gather_f32in(const SsOp& op, int64_t nrows, int64_t ncols, const float* X, int64_t ldx,
-                                  double* Y, double shift, int acc, hipStream_t st, int lpe = 0);
+                                  double* Y, double shift, int acc, hipStream_t st, int lpe = 0,
+                                  bool acc32 = false);
 // FP32 X and Y (FP64 accumulation; compact operator when present)
 hipError_t launch_ss_gather_f32(const SsOp& op, int64_t nrows, int64_t ncols, const float* X, float* Y,
                                 double shift, int acc, hipStream_t st, int lpe = 0);

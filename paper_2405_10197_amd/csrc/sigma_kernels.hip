@@ -236,8 +236,13 @@ static hipError_t ss_gather(const TC* col, const TV* val, int r, int64_t nrows,
 // order: that of the other widths (accumulator k sums the entries e = k mod 4
 // in ascending order, total (a0 + a1) + (a2 + a3)): the groups are aligned to
 // the entry index, chunks ascend with the columns, and padded slots add v = 0.
-template <typename TX, typename TY, typename TV, int VW>
-__global__ __launch_bounds__(64 * SS_BLK_R, 8) void k_ss_gather_blk(SsBlk bk, const SsGroup* __restrict__ gs,
+//
+// TA is the accumulator type: double, or float for the BF16 build (groups
+// with FP32 values, one FMA per entry and column without conversions; the
+// same summation order in FP32).
+template <typename TX, typename TY, typename TV, int VW, typename TA>
+__global__ __launch_bounds__(64 * SS_BLK_R, 8) void k_ss_gather_blk(SsBlk bk,
+                                                                 const SsGroupOf<TA>* __restrict__ gs,
                                                                  const TV* __restrict__ val, int r,
                                                                  int64_t nrows, int64_t ncols,
                                                                  const TX* __restrict__ X, int64_t ldx,
@@ -270,7 +275,7 @@ __global__ __launch_bounds__(64 * SS_BLK_R, 8) void k_ss_gather_blk(SsBlk bk, co
     const int o0 = rowok && lane <= nch ? (int)goff[lane] : 0;
     const int o1 = rowok && 64 + lane <= nch ? (int)goff[64 + lane] : 0;
     auto off_at = [&](int i) { return i < 64 ? bcast_i32(o0, i) : bcast_i32(o1, i - 64); };
-    const SsGroup* grow = gs + (rowok ? (int64_t)bk.rbase[I] : 0);
+    const SsGroupOf<TA>* grow = gs + (rowok ? (int64_t)bk.rbase[I] : 0);
 
     // Staging runs two chunks ahead: while chunk ch is used, the X rows of
     // chunk ch + 1 (registers of one set) and ch + 2 (the other set) are in
@@ -297,37 +302,38 @@ __global__ __launch_bounds__(64 * SS_BLK_R, 8) void k_ss_gather_blk(SsBlk bk, co
                 pf[i];
     };
 
-    double a[VW][4] = {};
+    using TG = SsGroupOf<TA>;
+    TA a[VW][4] = {};
     double xI[VW];
 #pragma unroll
     for (int u = 0; u < VW; ++u) {
         xI[u] = rowok ? (double)X[I * ldx + cl + u] : 0.0;
-        if (rowok) a[u][0] += (double)val[I * r] * xI[u];
+        if (rowok) a[u][0] += (TA)val[I * r] * (TA)xI[u];
     }
     auto compute = [&](int ch) {
         if (!rowok) return;
         const unsigned char* sb = smem + (int64_t)(ch & 1) * CH * SS_BLK_ROWB + lane * sizeof(VX);
-        auto add = [&](const SsGroup& G) {
+        auto add = [&](const TG& G) {
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
                 const VX xv = *reinterpret_cast<const VX*>(sb + G.off[k]);
                 const TX* xe = reinterpret_cast<const TX*>(&xv);
 #pragma unroll
-                for (int u = 0; u < VW; ++u) a[u][k] += G.v[k] * (double)xe[u];
+                for (int u = 0; u < VW; ++u) a[u][k] += G.v[k] * (TA)xe[u];
             }
         };
         const int g1 = off_at(ch + 1);
         int g = off_at(ch);
         // up to four groups per scalar round trip
         for (; g + 4 <= g1; g += 4) {
-            const SsGroup G0 = grow[g], G1 = grow[g + 1], G2 = grow[g + 2], G3 = grow[g + 3];
+            const TG G0 = grow[g], G1 = grow[g + 1], G2 = grow[g + 2], G3 = grow[g + 3];
             add(G0);
             add(G1);
             add(G2);
             add(G3);
         }
         if (g + 2 <= g1) {
-            const SsGroup G0 = grow[g], G1 = grow[g + 1];
+            const TG G0 = grow[g], G1 = grow[g + 1];
             add(G0);
             add(G1);
             g += 2;
@@ -345,14 +351,14 @@ __global__ __launch_bounds__(64 * SS_BLK_R, 8) void k_ss_gather_blk(SsBlk bk, co
     const unsigned* g32 = reinterpret_cast<const unsigned*>(grow);
     // last dword of the row's groups (rows past the last have none: index 0 of
     // the stream, which exists)
-    const int gend = max(off_at(nch) * (int)(sizeof(SsGroup) / 4) - 1, 0);
+    const int gend = max(off_at(nch) * (int)(sizeof(TG) / 4) - 1, 0);
     unsigned pfx = 0u, pfx_acc = 0u;
     auto step = [&](int ch, VX (&pn)[RPW], VX (&pf)[RPW], int& un, int& un2) {
         un2 = load_u(ch + 3);
         issue(un, pf);
         pfx_acc ^= pfx;
         {
-            const int i = off_at(ch + 1 < nch ? ch + 1 : ch) * (int)(sizeof(SsGroup) / 4) + lane;
+            const int i = off_at(ch + 1 < nch ? ch + 1 : ch) * (int)(sizeof(TG) / 4) + lane;
             pfx = g32[i < gend ? i : gend];
         }
         compute(ch);
@@ -378,16 +384,16 @@ __global__ __launch_bounds__(64 * SS_BLK_R, 8) void k_ss_gather_blk(SsBlk bk, co
         for (int u = 0; u < VW; ++u) {
             if (c + u >= ncols) continue;
             const int64_t o = I * ncols + c + u;
-            double y = ((a[u][0] + a[u][1]) + (a[u][2] + a[u][3])) + shift * xI[u];
+            double y = (double)((a[u][0] + a[u][1]) + (a[u][2] + a[u][3])) + shift * xI[u];
             if (acc) y += (double)Y[o];
             Y[o] = (TY)y;
         }
     }
 }
 
-template <typename TX, typename TY, typename TV>
-static hipError_t ss_gather_blk(const SsBlk& bk, const SsGroup* gs, const TV* val, int r, int64_t nrows, int64_t ncols,
-                                const TX* X, int64_t ldx, TY* Y, double shift, int acc, hipStream_t st)
+template <typename TX, typename TY, typename TV, typename TA = double>
+static hipError_t ss_gather_blk(const SsBlk& bk, const SsGroupOf<TA>* gs, const TV* val, int r, int64_t nrows,
+                                int64_t ncols, const TX* X, int64_t ldx, TY* Y, double shift, int acc, hipStream_t st)
 {
     if (nrows <= 0 || ncols <= 0) return hipSuccess;
     if (!bk.uni || !gs || bk.ch != SS_BLK_CH) return invalid("same-spin gather: no row-blocked operator");
@@ -410,9 +416,9 @@ static hipError_t ss_gather_blk(const SsBlk& bk, const SsGroup* gs, const TV* va
         return hipGetLastError();
     };
     if constexpr (sizeof(TX) == 4) {
-        if (pair) return launch(k_ss_gather_blk<TX, TY, TV, 2>);
+        if (pair) return launch(k_ss_gather_blk<TX, TY, TV, 2, TA>);
     }
-    return launch(k_ss_gather_blk<TX, TY, TV, 1>);
+    return launch(k_ss_gather_blk<TX, TY, TV, 1, TA>);
 }
 
 // strip width code: 16 / 32 / 64 lanes per entry with one column each, 128 =
@@ -468,8 +474,11 @@ hipError_t launch_ss_gather_f64(const SsOp& op, int64_t nrows, int64_t ncols, co
 }
 
 hipError_t launch_ss_gather_f32in(const SsOp& op, int64_t nrows, int64_t ncols, const float* X, int64_t ldx,
-                                  double* Y, double shift, int acc, hipStream_t st, int lpe)
+                                  double* Y, double shift, int acc, hipStream_t st, int lpe, bool acc32)
 {
+    if (lpe == SS_BLOCKED && op.blk.uni && op.val32 && acc32 && op.blk.gsf)
+        return ss_gather_blk<float, double, float, float>(op.blk, op.blk.gsf, op.val32, op.r, nrows, ncols, X, ldx, Y,
+                                                          shift, acc, st);
     if (lpe == SS_BLOCKED && op.blk.uni && op.val32)
         return ss_gather_blk<float, double>(op.blk, op.blk.gs32, op.val32, op.r, nrows, ncols, X, ldx, Y, shift,
                                             acc, st);
