@@ -115,6 +115,7 @@ struct casci_ctx {
     struct Blocks {  // row-blocked form of one same-spin operator (SsBlk)
         DBuf uni, binfo, goff, rbase, gs64, gs32, gsf;
         int64_t nblk = 0;
+        int rows = 0;  // rows per block
         bool have = false;
     } blk[2];        // [0]: alpha (and beta when nalpha = nbeta), [1]: beta
     DBuf d_vt_sym, d_pairs_sym, d_vt_full, d_pairs_full, d_vt_s2;
@@ -920,20 +921,25 @@ static SsOp ss_op(const casci_ctx* ctx, int spin)
         op.blk.gsf = bl.gsf.as<SsGroupF>();
         op.blk.ch = SS_BLK_CH;
         op.blk.nblk = bl.nblk;
+        op.blk.rows = bl.rows;
     }
     return op;
 }
 
 // Row-blocked form of a same-spin operator for the SS_BLOCKED gather: rows in
-// blocks of SS_BLK_R, the sorted union of the columns of each block, and per
+// blocks of 32 (or 16), the sorted union of the columns of each block, and per
 // row its entries 1..r-1 (ascending columns) as groups of four aligned to the
 // entry index, split by chunks of SS_BLK_CH union rows: a group holds the LDS
 // offsets of its operands and the values of entries 4g..4g+3 (one stream for
 // FP64 input, one with FP32-rounded values for FP32 input, and the latter
-// with FP32 values for FP32 accumulation), a slot outside
-// the chunk value 0 and the chunk's first union row. The diagonal (entry 0)
-// stays outside: the kernel takes it from the row itself. Built on the host
-// from the operator's rows; needs fewer than 65536 strings.
+// with FP32 values for FP32 accumulation), a slot outside the chunk value 0
+// and the chunk's first union row. The diagonal (entry 0) stays outside: the
+// kernel takes it from the row itself. Built on the host from the
+// operator's rows; needs fewer than 65536 strings.
+static bool build_ss_blocks(int64_t N, int r, const std::vector<int32_t>& col, const std::vector<double>& val,
+                            int R, std::vector<uint16_t>& uni, std::vector<uint16_t>& goff,
+                            std::vector<int32_t>& binfo, std::vector<int32_t>& rbase, std::vector<SsGroup>& gs64,
+                            std::vector<SsGroup>& gs32, std::vector<SsGroupF>& gsf, int* rc);
 static int ensure_ss_blocks(casci_ctx* ctx, int spin)
 {
     const bool b = spin == 1 && ctx->nb != ctx->na;
@@ -950,12 +956,72 @@ static int ensure_ss_blocks(casci_ctx* ctx, int spin)
     HIPC(hipMemcpyAsync(col.data(), dcol.p, col.size() * 4, hipMemcpyDeviceToHost, ctx->stream));
     HIPC(hipMemcpyAsync(val.data(), dval.p, val.size() * 8, hipMemcpyDeviceToHost, ctx->stream));
     HIPC(hipStreamSynchronize(ctx->stream));
-    const int R = SS_BLK_R, CH = SS_BLK_CH;
-    const int64_t nblk = (N + R - 1) / R;
+    for (int64_t e0 = 0; e0 < N * (int64_t)r; e0 += r)
+        for (int e = 1; e < r; ++e) {
+            const int32_t J = col[(size_t)e0 + e];
+            if (J < 0 || J >= N) return ctx->fail(CASCI_E_DEVICE, "same-spin operator: column out of range");
+            if (e > 1 && J <= col[(size_t)e0 + e - 1])
+                return ctx->fail(CASCI_E_DEVICE, "same-spin operator: row not in ascending column order");
+        }
     std::vector<uint16_t> uni, goff;
-    std::vector<int32_t> binfo((size_t)nblk * 4), rbase((size_t)N, 0);
+    std::vector<int32_t> binfo, rbase;
     std::vector<SsGroup> gs64, gs32;
     std::vector<SsGroupF> gsf;
+    // 32-row blocks stage fewer union rows per row; where a union of 32 rows
+    // needs more than SS_BLK_MAXCH chunks, 16-row blocks; where those do too
+    // (or a row has more groups than 16-bit offsets hold), no blocked form
+    int R = 0;
+    int64_t nblk = 0;
+    for (int Rtry : {2 * SS_BLK_W, SS_BLK_W}) {
+        int rc = CASCI_OK;
+        if (build_ss_blocks(N, r, col, val, Rtry, uni, goff, binfo, rbase, gs64, gs32, gsf, &rc)) {
+            R = Rtry;
+            nblk = (N + R - 1) / R;
+            break;
+        }
+        if (rc != CASCI_OK) return ctx->fail(rc, "same-spin operator too large for the row-blocked form");
+    }
+    if (R == 0) return CASCI_OK;  // the other widths serve
+    HIPC(bl.uni.ensure(uni.size() * 2));
+    HIPC(bl.binfo.ensure(binfo.size() * 4));
+    HIPC(bl.goff.ensure(goff.size() * 2));
+    HIPC(bl.rbase.ensure(rbase.size() * 4));
+    HIPC(bl.gs64.ensure(gs64.size() * sizeof(SsGroup)));
+    HIPC(bl.gs32.ensure(gs32.size() * sizeof(SsGroup)));
+    HIPC(bl.gsf.ensure(gsf.size() * sizeof(SsGroupF)));
+    HIPC(hipMemcpyAsync(bl.uni.p, uni.data(), uni.size() * 2, hipMemcpyHostToDevice, ctx->stream));
+    HIPC(hipMemcpyAsync(bl.binfo.p, binfo.data(), binfo.size() * 4, hipMemcpyHostToDevice, ctx->stream));
+    HIPC(hipMemcpyAsync(bl.goff.p, goff.data(), goff.size() * 2, hipMemcpyHostToDevice, ctx->stream));
+    HIPC(hipMemcpyAsync(bl.rbase.p, rbase.data(), rbase.size() * 4, hipMemcpyHostToDevice, ctx->stream));
+    HIPC(hipMemcpyAsync(bl.gs64.p, gs64.data(), gs64.size() * sizeof(SsGroup), hipMemcpyHostToDevice, ctx->stream));
+    HIPC(hipMemcpyAsync(bl.gs32.p, gs32.data(), gs32.size() * sizeof(SsGroup), hipMemcpyHostToDevice, ctx->stream));
+    HIPC(hipMemcpyAsync(bl.gsf.p, gsf.data(), gsf.size() * sizeof(SsGroupF), hipMemcpyHostToDevice, ctx->stream));
+    HIPC(hipStreamSynchronize(ctx->stream));  // pageable sources
+    bl.nblk = nblk;
+    bl.rows = R;
+    bl.have = true;
+    ++ctx->gen;  // captured graphs hold the operator without the blocks
+    return CASCI_OK;
+}
+
+// The tables of the row-blocked form for blocks of R rows (the layout is
+// described above ensure_ss_blocks). Returns false when a block's union needs
+// more than SS_BLK_MAXCH chunks or a row more than 65535 groups (rc stays
+// CASCI_OK), or when a table outgrows its 32-bit offsets (rc set).
+static bool build_ss_blocks(int64_t N, int r, const std::vector<int32_t>& col, const std::vector<double>& val,
+                            int R, std::vector<uint16_t>& uni, std::vector<uint16_t>& goff,
+                            std::vector<int32_t>& binfo, std::vector<int32_t>& rbase, std::vector<SsGroup>& gs64,
+                            std::vector<SsGroup>& gs32, std::vector<SsGroupF>& gsf, int* rc)
+{
+    const int CH = SS_BLK_CH;
+    const int64_t nblk = (N + R - 1) / R;
+    uni.clear();
+    goff.clear();
+    gs64.clear();
+    gs32.clear();
+    gsf.clear();
+    binfo.assign((size_t)nblk * 4, 0);
+    rbase.assign((size_t)N, 0);
     gs64.reserve((size_t)N * (r / 4 + 16));
     gs32.reserve((size_t)N * (r / 4 + 16));
     gsf.reserve((size_t)N * (r / 4 + 16));
@@ -967,9 +1033,6 @@ static int ensure_ss_blocks(casci_ctx* ctx, int spin)
         for (int64_t I = I0; I < I1; ++I)
             for (int e = 1; e < r; ++e) {
                 const int32_t J = col[(size_t)I * r + e];
-                if (J < 0 || J >= N) return ctx->fail(CASCI_E_DEVICE, "same-spin operator: column out of range");
-                if (e > 1 && J <= col[(size_t)I * r + e - 1])
-                    return ctx->fail(CASCI_E_DEVICE, "same-spin operator: row not in ascending column order");
                 if (stamp[J] != (int32_t)blk) {
                     stamp[J] = (int32_t)blk;
                     u.push_back(J);
@@ -979,13 +1042,15 @@ static int ensure_ss_blocks(casci_ctx* ctx, int spin)
         for (size_t k = 0; k < u.size(); ++k) where[u[k]] = (int32_t)k;
         const int nU = (int)u.size();
         const int nch = (nU + CH - 1) / CH;
-        if (nch > SS_BLK_MAXCH) return CASCI_OK;  // unions too wide: the other widths serve
+        if (nch > SS_BLK_MAXCH) return false;  // union too wide
         binfo[(size_t)blk * 4 + 0] = (int32_t)uni.size();
         binfo[(size_t)blk * 4 + 1] = nU;
         binfo[(size_t)blk * 4 + 2] = (int32_t)goff.size();
         binfo[(size_t)blk * 4 + 3] = nch;
-        if (uni.size() + u.size() > 0x7fffffffu || goff.size() + (size_t)R * (nch + 1) > 0x7fffffffu)
-            return ctx->fail(CASCI_E_UNSUPPORTED, "same-spin operator too large for the row-blocked form");
+        if (uni.size() + u.size() > 0x7fffffffu || goff.size() + (size_t)R * (nch + 1) > 0x7fffffffu) {
+            *rc = CASCI_E_UNSUPPORTED;
+            return false;
+        }
         for (int32_t J : u) uni.push_back((uint16_t)J);
         for (int w = 0; w < R; ++w) {
             const int64_t I = I0 + w;
@@ -993,7 +1058,10 @@ static int ensure_ss_blocks(casci_ctx* ctx, int spin)
                 goff.insert(goff.end(), (size_t)nch + 1, 0);
                 continue;
             }
-            if (gs64.size() > 0x7fffffffu) return ctx->fail(CASCI_E_UNSUPPORTED, "row-blocked form: too many groups");
+            if (gs64.size() > 0x7fffffffu) {
+                *rc = CASCI_E_UNSUPPORTED;
+                return false;
+            }
             rbase[(size_t)I] = (int32_t)gs64.size();
             const int32_t* cI = col.data() + (size_t)I * r;
             const double* vI = val.data() + (size_t)I * r;
@@ -1023,7 +1091,7 @@ static int ensure_ss_blocks(casci_ctx* ctx, int spin)
                 }
                 e = ez;
             }
-            if (ng > 65535) return CASCI_OK;  // row too long for 16-bit group offsets
+            if (ng > 65535) return false;  // row too long for 16-bit group offsets
             goff.push_back((uint16_t)ng);
         }
     }
@@ -1033,25 +1101,7 @@ static int ensure_ss_blocks(casci_ctx* ctx, int spin)
         gs32.push_back(SsGroup{});
         gsf.push_back(SsGroupF{});
     }
-    HIPC(bl.uni.ensure(uni.size() * 2));
-    HIPC(bl.binfo.ensure(binfo.size() * 4));
-    HIPC(bl.goff.ensure(goff.size() * 2));
-    HIPC(bl.rbase.ensure(rbase.size() * 4));
-    HIPC(bl.gs64.ensure(gs64.size() * sizeof(SsGroup)));
-    HIPC(bl.gs32.ensure(gs32.size() * sizeof(SsGroup)));
-    HIPC(bl.gsf.ensure(gsf.size() * sizeof(SsGroupF)));
-    HIPC(hipMemcpyAsync(bl.uni.p, uni.data(), uni.size() * 2, hipMemcpyHostToDevice, ctx->stream));
-    HIPC(hipMemcpyAsync(bl.binfo.p, binfo.data(), binfo.size() * 4, hipMemcpyHostToDevice, ctx->stream));
-    HIPC(hipMemcpyAsync(bl.goff.p, goff.data(), goff.size() * 2, hipMemcpyHostToDevice, ctx->stream));
-    HIPC(hipMemcpyAsync(bl.rbase.p, rbase.data(), rbase.size() * 4, hipMemcpyHostToDevice, ctx->stream));
-    HIPC(hipMemcpyAsync(bl.gs64.p, gs64.data(), gs64.size() * sizeof(SsGroup), hipMemcpyHostToDevice, ctx->stream));
-    HIPC(hipMemcpyAsync(bl.gs32.p, gs32.data(), gs32.size() * sizeof(SsGroup), hipMemcpyHostToDevice, ctx->stream));
-    HIPC(hipMemcpyAsync(bl.gsf.p, gsf.data(), gsf.size() * sizeof(SsGroupF), hipMemcpyHostToDevice, ctx->stream));
-    HIPC(hipStreamSynchronize(ctx->stream));  // pageable sources
-    bl.nblk = nblk;
-    bl.have = true;
-    ++ctx->gen;  // captured graphs hold the operator without the blocks
-    return CASCI_OK;
+    return true;
 }
 
 // Autotuner of the same-spin gather: the strip width (lanes per gathered

@@ -80,8 +80,8 @@ hipError_t launch_scatter_values(const int64_t* idx, const double* v, int P, dou
 // FP64 values; optional compact copies (16-bit columns when there are fewer
 // than 65536 strings, FP32 values) that the gathers use when present.
 // Row-blocked form of a same-spin operator (strip width code SS_BLOCKED): rows
-// in blocks of SS_BLK_R; per block the sorted union of the columns its rows
-// touch. The gather stages the union rows of X in LDS, a chunk at a time, and
+// in blocks of 32 (16 where the unions of 32 rows are too wide); per block the
+// sorted union of the columns its rows touch. The gather stages the union rows of X in LDS, a chunk at a time, and
 // each row reads its operands there. Each row's entries 1..r-1 (ascending
 // columns) are split by chunks of the union and stored per chunk as groups of
 // four aligned to the entry index (group g holds entries 4g..4g+3): a slot
@@ -89,7 +89,7 @@ hipError_t launch_scatter_values(const int64_t* idx, const double* v, int P, dou
 // row, so every group is read and added whole (built by ensure_ss_blocks in
 // casci.cpp).
 constexpr int SS_BLOCKED = 99;
-constexpr int SS_BLK_R = 16;
+constexpr int SS_BLK_W = 16;  // waves per workgroup; a block has SS_BLK_W or 2 SS_BLK_W rows
 constexpr int SS_BLK_MAXCH = 127;  // union limit: SS_BLK_MAXCH chunks of SS_BLK_CH rows per block
 // union rows per LDS chunk, and bytes per staged row (64 FP64 columns or
 // 128 FP32 column pairs): 32 KB per chunk buffer
@@ -111,12 +111,13 @@ using SsGroupOf = typename std::conditional<std::is_same<TA, float>::value, SsGr
 struct SsBlk {
     const uint16_t* uni;   // unions of all blocks, concatenated (string indices < 65536)
     const int4* binfo;     // per block {union offset, union size, group offsets offset, chunks}
-    const uint16_t* goff;  // per block [SS_BLK_R][chunks + 1]: first group of each chunk, per row
+    const uint16_t* goff;  // per block [rows][chunks + 1]: first group of each chunk, per row
     const int32_t* rbase;  // [N]: first group of each row
     const SsGroup* gs64;   // groups with FP64 values (FP64 input)
     const SsGroup* gs32;   // groups with values rounded to FP32 (FP32 input)
     const SsGroupF* gsf;   // the gs32 groups with FP32 values (FP32 input, FP32 accumulation)
     int ch;                // union rows per chunk (SS_BLK_CH)
+    int rows;              // rows per block (SS_BLK_W or 2 SS_BLK_W)
     int64_t nblk;
 };
 struct SsOp {
@@ -125,7 +126,7 @@ struct SsOp {
     const uint16_t* col16;  // may be null
     const float* val32;     // may be null
     int r;
-    SsBlk blk = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, 0, 0};  // row-blocked form (blk.uni null: none)
+    SsBlk blk = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, 0, 0, 0};  // row-blocked form (blk.uni null: none)
 };
 // Y(I,:) = [acc ? Y(I,:) : 0] + sum_e val[I*r+e] X(col[I*r+e], :) + shift * X(I,:)
 // (lpe: strip width code 16/32/64 lanes per entry, 128 = 64 lanes x 2 columns; 0 = 64).

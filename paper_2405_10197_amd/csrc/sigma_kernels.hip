@@ -214,34 +214,43 @@ static hipError_t ss_gather(const TC* col, const TV* val, int r, int64_t nrows,
 // ---------------------------------------------------------------------------
 // row-blocked same-spin gather (strip width code SS_BLOCKED)
 // ---------------------------------------------------------------------------
-// One workgroup of SS_BLK_R waves takes one block of SS_BLK_R consecutive rows
-// and one strip of 64 x VW columns (VW adjacent columns per lane); wave w
-// computes row b*R + w. The rows of X the block needs (the sorted union of
-// its rows' columns) are staged into LDS, SS_BLK_CH at a time in two buffers
-// (the loads of the next chunk are in flight while the current one is used),
-// and each wave adds its row's entry groups of the chunk, reading X from LDS.
-// Neighbouring strings share most of their neighbours (16 rows touch about
-// 4000 distinct rows at n = 16 against 16 x 849 entries), so each row of X
-// crosses the L1 once per block instead of once per entry.
+// One workgroup of SS_BLK_W = 16 waves takes 16 RW consecutive rows (RW = 1
+// or 2 rows per wave) of a block of bk.rows = 16 or 32 and one strip of
+// 64 x VW columns (VW adjacent columns per lane); wave w computes rows
+// b*R + s*16*RW + w + 16q, q < RW, for part s of block b. The rows of X the block needs (the sorted union of its rows'
+// columns) are staged into LDS, SS_BLK_CH at a time in two buffers (the loads
+// of the next chunk are in flight while the current one is used), and each
+// wave adds its rows' entry groups of the chunk, reading X from LDS.
+// Neighbouring strings share most of their neighbours (at n = 16, 16 rows
+// touch about 4000 distinct rows and 32 rows about 5400, against 849 entries
+// per row), so each row of X crosses the L1 once per block instead of once per
+// entry, and 32-row blocks stage a third fewer rows per row than 16-row ones.
 //
-// A group (four LDS byte offsets and four FP64 values) is two wave-uniform
-// scalar loads that feed the LDS reads and FMAs directly (the FP32-operator
-// builds store (double)(float)v, the product the other widths form); the chunk
-// offsets of the row sit in two registers (loaded once) and the union indices
-// of a chunk are read one chunk ahead of its X rows, so the chunk loop waits
-// on nothing it has just issued. Staged rows are SS_BLK_ROWB bytes apart
-// whatever the element type and VW.
+// A group (four LDS byte offsets and four values) is wave-uniform scalar
+// loads that feed the LDS reads and FMAs directly (the FP32-operator builds
+// store (double)(float)v, the product the other widths form); the chunk
+// offsets of a row sit in two registers (loaded once) and the union indices
+// of a chunk are read ahead of its X rows, so the chunk loop waits on nothing
+// it has just issued. Staged rows are SS_BLK_ROWB bytes apart whatever the
+// element type and VW.
 //
 // The diagonal (entry 0, column I) comes from row I of X directly. Summation
 // order: that of the other widths (accumulator k sums the entries e = k mod 4
 // in ascending order, total (a0 + a1) + (a2 + a3)): the groups are aligned to
-// the entry index, chunks ascend with the columns, and padded slots add v = 0.
+// the entry index, chunks ascend with the columns, and padded slots add v = 0;
+// so the result does not depend on the block size either.
 //
 // TA is the accumulator type: double, or float for the BF16 build (groups
 // with FP32 values, one FMA per entry and column without conversions; the
 // same summation order in FP32).
-template <typename TX, typename TY, typename TV, int VW, typename TA>
-__global__ __launch_bounds__(64 * SS_BLK_R, 8) void k_ss_gather_blk(SsBlk bk,
+#ifndef SS_BLK_WPE
+#define SS_BLK_WPE 8
+#endif
+#ifndef SS_BLK_LDSB
+#define SS_BLK_LDSB 1
+#endif
+template <typename TX, typename TY, typename TV, int VW, typename TA, int RW>
+__global__ __launch_bounds__(64 * SS_BLK_W, SS_BLK_WPE) void k_ss_gather_blk(SsBlk bk,
                                                                  const SsGroupOf<TA>* __restrict__ gs,
                                                                  const TV* __restrict__ val, int r,
                                                                  int64_t nrows, int64_t ncols,
@@ -250,14 +259,21 @@ __global__ __launch_bounds__(64 * SS_BLK_R, 8) void k_ss_gather_blk(SsBlk bk,
                                                                  int64_t nitems)
 {
     constexpr int CH = SS_BLK_CH;
-    constexpr int RPW = CH / SS_BLK_R;  // union rows a wave stages per chunk
+    constexpr int RPW = CH / SS_BLK_W;  // union rows a wave stages per chunk
     using VX = typename Vec<TX, VW>::type;
+    using TG = SsGroupOf<TA>;
+    constexpr int GB = RW == 2 && sizeof(TA) == 8 ? 2 : 4;  // groups per scalar round trip
     static_assert(64 * VW * sizeof(TX) <= SS_BLK_ROWB, "a staged row holds 64 x VW elements");
     extern __shared__ __align__(16) unsigned char smem[];  // [2][CH][SS_BLK_ROWB]
     const int64_t per_xcd = gridDim.x / 8;
     const int64_t t = (int64_t)(blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
     if (t >= nitems) return;
-    const int64_t strip = t / bk.nblk, b = t - strip * bk.nblk;
+    // item t: strip, block, and the part of the block this workgroup takes
+    // (16 RW of its rows; a 32-row block is split in two when RW = 1)
+    const int nsub = bk.rows / (SS_BLK_W * RW);
+    const int64_t tb = t / nsub;
+    const int sub = (int)(t - tb * nsub);
+    const int64_t strip = tb / bk.nblk, b = tb - strip * bk.nblk;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
     const int64_t c = (strip * 64 + lane) * VW;
     const bool cok = c < ncols;
@@ -267,15 +283,24 @@ __global__ __launch_bounds__(64 * SS_BLK_R, 8) void k_ss_gather_blk(SsBlk bk,
     const int4 bi = bk.binfo[b];
     const uint16_t* U = bk.uni + bi.x;
     const int nU = bi.y, nch = bi.w;
-    const int64_t I = b * SS_BLK_R + wave;
-    const bool rowok = I < nrows;
 
-    // the row's group offsets per chunk (lane l: offset l and 64 + l)
-    const uint16_t* goff = bk.goff + bi.z + (int64_t)wave * (nch + 1);
-    const int o0 = rowok && lane <= nch ? (int)goff[lane] : 0;
-    const int o1 = rowok && 64 + lane <= nch ? (int)goff[64 + lane] : 0;
-    auto off_at = [&](int i) { return i < 64 ? bcast_i32(o0, i) : bcast_i32(o1, i - 64); };
-    const SsGroupOf<TA>* grow = gs + (rowok ? (int64_t)bk.rbase[I] : 0);
+    // per row of the wave: its index, the group offsets per chunk (lane l:
+    // offset l and 64 + l) and the start of its group stream
+    int64_t I[RW];
+    bool rowok[RW];
+    int o0[RW], o1[RW];
+    const TG* grow[RW];
+#pragma unroll
+    for (int q = 0; q < RW; ++q) {
+        const int w = sub * SS_BLK_W * RW + wave + SS_BLK_W * q;  // row of the block
+        I[q] = b * bk.rows + w;
+        rowok[q] = I[q] < nrows;
+        const uint16_t* goff = bk.goff + bi.z + (int64_t)w * (nch + 1);
+        o0[q] = rowok[q] && lane <= nch ? (int)goff[lane] : 0;
+        o1[q] = rowok[q] && 64 + lane <= nch ? (int)goff[64 + lane] : 0;
+        grow[q] = gs + (rowok[q] ? (int64_t)bk.rbase[I[q]] : 0);
+    }
+    auto off_at = [&](int q, int i) { return i < 64 ? bcast_i32(o0[q], i) : bcast_i32(o1[q], i - 64); };
 
     // Staging runs two chunks ahead: while chunk ch is used, the X rows of
     // chunk ch + 1 (registers of one set) and ch + 2 (the other set) are in
@@ -302,64 +327,110 @@ __global__ __launch_bounds__(64 * SS_BLK_R, 8) void k_ss_gather_blk(SsBlk bk,
                 pf[i];
     };
 
-    using TG = SsGroupOf<TA>;
-    TA a[VW][4] = {};
-    double xI[VW];
+    TA a[RW][VW][4] = {};
 #pragma unroll
-    for (int u = 0; u < VW; ++u) {
-        xI[u] = rowok ? (double)X[I * ldx + cl + u] : 0.0;
-        if (rowok) a[u][0] += (TA)val[I * r] * (TA)xI[u];
-    }
+    for (int q = 0; q < RW; ++q)
+#pragma unroll
+        for (int u = 0; u < VW; ++u)
+            if (rowok[q]) a[q][u][0] += (TA)val[I[q] * r] * (TA)X[I[q] * ldx + cl + u];
     auto compute = [&](int ch) {
-        if (!rowok) return;
         const unsigned char* sb = smem + (int64_t)(ch & 1) * CH * SS_BLK_ROWB + lane * sizeof(VX);
-        auto add = [&](const TG& G) {
 #pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                const VX xv = *reinterpret_cast<const VX*>(sb + G.off[k]);
-                const TX* xe = reinterpret_cast<const TX*>(&xv);
+        for (int q = 0; q < RW; ++q) {
+            if (!rowok[q]) continue;
+            auto add = [&](const TG& G) {
+#if SS_BLK_LDSB >= 1
+                VX xv[4];
 #pragma unroll
-                for (int u = 0; u < VW; ++u) a[u][k] += G.v[k] * (TA)xe[u];
+                for (int k = 0; k < 4; ++k) xv[k] = *reinterpret_cast<const VX*>(sb + G.off[k]);
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const TX* xe = reinterpret_cast<const TX*>(&xv[k]);
+#pragma unroll
+                    for (int u = 0; u < VW; ++u) a[q][u][k] += G.v[k] * (TA)xe[u];
+                }
+#else
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const VX xv = *reinterpret_cast<const VX*>(sb + G.off[k]);
+                    const TX* xe = reinterpret_cast<const TX*>(&xv);
+#pragma unroll
+                    for (int u = 0; u < VW; ++u) a[q][u][k] += G.v[k] * (TA)xe[u];
+                }
+#endif
+            };
+#if SS_BLK_LDSB == 4
+            auto add4 = [&](const TG& G0, const TG& G1, const TG& G2, const TG& G3) {
+                VX xv[4][4];
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    xv[0][k] = *reinterpret_cast<const VX*>(sb + G0.off[k]);
+                    xv[1][k] = *reinterpret_cast<const VX*>(sb + G1.off[k]);
+                    xv[2][k] = *reinterpret_cast<const VX*>(sb + G2.off[k]);
+                    xv[3][k] = *reinterpret_cast<const VX*>(sb + G3.off[k]);
+                }
+                const TG* GG[4] = {&G0, &G1, &G2, &G3};
+#pragma unroll
+                for (int h = 0; h < 4; ++h)
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) {
+                        const TX* xe = reinterpret_cast<const TX*>(&xv[h][k]);
+#pragma unroll
+                        for (int u = 0; u < VW; ++u) a[q][u][k] += GG[h]->v[k] * (TA)xe[u];
+                    }
+            };
+#endif
+            const TG* gr = grow[q];
+            const int g1 = off_at(q, ch + 1);
+            int g = off_at(q, ch);
+            // up to four groups per scalar round trip (two with two FP64 rows
+            // per wave, whose scalar registers would spill otherwise)
+            if constexpr (GB == 4) {
+                for (; g + 4 <= g1; g += 4) {
+                    const TG G0 = gr[g], G1 = gr[g + 1], G2 = gr[g + 2], G3 = gr[g + 3];
+#if SS_BLK_LDSB == 4
+                    add4(G0, G1, G2, G3);
+#else
+                    add(G0);
+                    add(G1);
+                    add(G2);
+                    add(G3);
+#endif
+                }
             }
-        };
-        const int g1 = off_at(ch + 1);
-        int g = off_at(ch);
-        // up to four groups per scalar round trip
-        for (; g + 4 <= g1; g += 4) {
-            const TG G0 = grow[g], G1 = grow[g + 1], G2 = grow[g + 2], G3 = grow[g + 3];
-            add(G0);
-            add(G1);
-            add(G2);
-            add(G3);
+            for (; g + 2 <= g1; g += 2) {
+                const TG G0 = gr[g], G1 = gr[g + 1];
+                add(G0);
+                add(G1);
+            }
+            if (g < g1) add(gr[g]);
         }
-        if (g + 2 <= g1) {
-            const TG G0 = grow[g], G1 = grow[g + 1];
-            add(G0);
-            add(G1);
-            g += 2;
-        }
-        if (g < g1) add(grow[g]);
     };
     // one chunk: pn holds the X rows of chunk ch + 1 (in flight), pf receives
     // those of chunk ch + 2 from the indices un; the indices of ch + 3 go to un2
     // L2 prefetch of the next chunk's group data: one coalesced dword per lane
-    // (256 bytes, about five groups) whose value is folded into a dummy one
-    // step later (and the dummy kept alive by an empty asm statement at the
-    // end), so the scalar loads of that chunk find their lines in the L2
-    // instead of the memory side: 44.6 -> 40.6 ms (FP64) and 24.7 -> 23.1 ms
-    // (FP32 input) at CAS(16,16); two chunks ahead was slower
-    const unsigned* g32 = reinterpret_cast<const unsigned*>(grow);
-    // last dword of the row's groups (rows past the last have none: index 0 of
-    // the stream, which exists)
-    const int gend = max(off_at(nch) * (int)(sizeof(TG) / 4) - 1, 0);
-    unsigned pfx = 0u, pfx_acc = 0u;
+    // and row (256 bytes) whose value is folded into a dummy one step later
+    // (and the dummy kept alive by an empty asm statement at the end), so the
+    // scalar loads of that chunk find their lines in the L2 instead of the
+    // memory side: 44.6 -> 40.6 ms (FP64) and 24.7 -> 23.1 ms (FP32 input,
+    // FP64 sums) at CAS(16,16) with 16-row blocks; two chunks ahead was slower
+    const int gw = (int)(sizeof(TG) / 4);  // dwords per group
+    // last dword of each row's groups (rows past the last have none: index 0
+    // of the stream, which exists)
+    int gend[RW];
+#pragma unroll
+    for (int q = 0; q < RW; ++q) gend[q] = max(off_at(q, nch) * gw - 1, 0);
+    unsigned pfx[RW], pfx_acc = 0u;
+#pragma unroll
+    for (int q = 0; q < RW; ++q) pfx[q] = 0u;
     auto step = [&](int ch, VX (&pn)[RPW], VX (&pf)[RPW], int& un, int& un2) {
         un2 = load_u(ch + 3);
         issue(un, pf);
-        pfx_acc ^= pfx;
-        {
-            const int i = off_at(ch + 1 < nch ? ch + 1 : ch) * (int)(sizeof(TG) / 4) + lane;
-            pfx = g32[i < gend ? i : gend];
+#pragma unroll
+        for (int q = 0; q < RW; ++q) {
+            pfx_acc ^= pfx[q];
+            const int i = off_at(q, ch + 1 < nch ? ch + 1 : ch) * gw + lane;
+            pfx[q] = reinterpret_cast<const unsigned*>(grow[q])[i < gend[q] ? i : gend[q]];
         }
         compute(ch);
         if (ch + 1 < nch) commit((ch + 1) & 1, pn);
@@ -378,13 +449,19 @@ __global__ __launch_bounds__(64 * SS_BLK_R, 8) void k_ss_gather_blk(SsBlk bk,
         step(ch, pb, pa, ua, ub);
         if (ch + 1 < nch) step(ch + 1, pa, pb, ub, ua);
     }
-    asm volatile("" ::"v"(pfx_acc ^ pfx));
-    if (rowok) {
+#pragma unroll
+    for (int q = 0; q < RW; ++q) pfx_acc ^= pfx[q];
+    asm volatile("" ::"v"(pfx_acc));
+#pragma unroll
+    for (int q = 0; q < RW; ++q) {
+        if (!rowok[q]) continue;
 #pragma unroll
         for (int u = 0; u < VW; ++u) {
             if (c + u >= ncols) continue;
-            const int64_t o = I * ncols + c + u;
-            double y = (double)((a[u][0] + a[u][1]) + (a[u][2] + a[u][3])) + shift * xI[u];
+            const int64_t o = I[q] * ncols + c + u;
+            // the diagonal element again (not held in registers through the loop)
+            const double xI = (double)X[I[q] * ldx + cl + u];
+            double y = (double)((a[q][u][0] + a[q][u][1]) + (a[q][u][2] + a[q][u][3])) + shift * xI;
             if (acc) y += (double)Y[o];
             Y[o] = (TY)y;
         }
@@ -397,28 +474,40 @@ static hipError_t ss_gather_blk(const SsBlk& bk, const SsGroupOf<TA>* gs, const 
 {
     if (nrows <= 0 || ncols <= 0) return hipSuccess;
     if (!bk.uni || !gs || bk.ch != SS_BLK_CH) return invalid("same-spin gather: no row-blocked operator");
+    if (bk.rows != SS_BLK_W && bk.rows != 2 * SS_BLK_W) return invalid("same-spin gather: unsupported block size");
     // a prefix of the rows (the autotuner times one) takes the blocks that cover it
     SsBlk b = bk;
-    b.nblk = (nrows + SS_BLK_R - 1) / SS_BLK_R;
+    b.nblk = (nrows + bk.rows - 1) / bk.rows;
     if (b.nblk > bk.nblk) return invalid("same-spin gather: more rows than the row-blocked operator has");
     // FP32 input: two adjacent columns per lane when the row stride allows aligned pairs
     const bool pair = sizeof(TX) == 4 && ldx % 2 == 0;
     const int64_t nstrip = (ncols + (pair ? 127 : 63)) / (pair ? 128 : 64);
-    const int64_t nitems = nstrip * b.nblk;
+    // two rows per wave on 32-row blocks, except where the FP64 sums of
+    // column pairs would not fit the registers of 8 waves per SIMD (then two
+    // workgroups share a block, each staging its union)
+    const bool two = bk.rows == 2 * SS_BLK_W && !(pair && sizeof(TA) == 8);
+    const int nsub = bk.rows / (SS_BLK_W * (two ? 2 : 1));
+    const int64_t nitems = nstrip * b.nblk * nsub;
     if (nitems > ((int64_t)1 << 31) - 8) return invalid("same-spin gather: too many row blocks x strips");
     const int64_t grid = (nitems + 7) / 8 * 8;
     const size_t lds = (size_t)2 * SS_BLK_CH * SS_BLK_ROWB;
     auto launch = [&](auto kern) {
         hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return invalid("hipFuncSetAttribute(max dynamic LDS) failed");
-        hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(64 * SS_BLK_R), lds, st, b, gs, val, r, nrows, ncols, X,
+        hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(64 * SS_BLK_W), lds, st, b, gs, val, r, nrows, ncols, X,
                            ldx, Y, shift, acc, nitems);
         return hipGetLastError();
     };
     if constexpr (sizeof(TX) == 4) {
-        if (pair) return launch(k_ss_gather_blk<TX, TY, TV, 2, TA>);
+        if (pair) {
+            if constexpr (sizeof(TA) == 8)
+                return launch(k_ss_gather_blk<TX, TY, TV, 2, TA, 1>);
+            else
+                return two ? launch(k_ss_gather_blk<TX, TY, TV, 2, TA, 2>)
+                           : launch(k_ss_gather_blk<TX, TY, TV, 2, TA, 1>);
+        }
     }
-    return launch(k_ss_gather_blk<TX, TY, TV, 1, TA>);
+    return two ? launch(k_ss_gather_blk<TX, TY, TV, 1, TA, 2>) : launch(k_ss_gather_blk<TX, TY, TV, 1, TA, 1>);
 }
 
 // strip width code: 16 / 32 / 64 lanes per entry with one column each, 128 =
