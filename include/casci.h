@@ -330,10 +330,12 @@ int casci_batch_davidson(casci_ctx* const* ctxs, int count, int nroots, double t
  * gather: 16, 32 or 64 lanes per gathered entry with one column each, 128
  * (64 lanes with two adjacent columns each), or L * 100 + V for L lanes per
  * entry with V adjacent columns each (1602, 3202; FP32 input also 1604, 3204,
- * 6404), or 99: row blocks of 16 strings whose union of neighbour rows is
- * staged in LDS (fewer than 65536 strings); 0 until the first sigma build in
- * that precision. The code changes only the speed: every width sums in the
- * same order, so sigma is bitwise the same whichever is chosen.
+ * 6404), or 99: row blocks of 32 (or 16) strings whose union of neighbour
+ * rows is staged in LDS (fewer than 65536 strings); 0 until the first sigma
+ * build in that precision. The code changes only the speed: every width sums
+ * in the same order, so sigma is bitwise the same whichever is chosen, with
+ * one exception: in BF16 builds width 99 sums in FP32 (relative difference
+ * ~1e-6, far below the BF16 alpha-beta error), the others in FP64.
  */
 int casci_get_tuning(casci_ctx* ctx, int* out);
 
@@ -342,6 +344,27 @@ int casci_get_tuning(casci_ctx* ctx, int* out);
  * for this context (a vector width the row stride does not allow falls back
  * to one column per lane). */
 int casci_set_tuning(casci_ctx* ctx, int f64_lpe, int f32in_lpe);
+
+/*
+ * Layout of the FP64 alpha-beta contraction (eq. (hamiltonian), the
+ * opposite-spin two-electron term), per pair set: out[0] for pair rows r <= s
+ * (integrals with 8-fold symmetry, no S^2 penalty), out[1] for all ordered
+ * pairs. Code 10 MT + split: MT = 1 or 2 sixteen-row M tiles per wave, the
+ * sigma row of an alpha string in split (1..4) times the fewest LDS chunks
+ * that fit; 0 until the first FP64 build with that pair set, whose autotuner
+ * times the layouts that have a kernel variant for the shape on the first
+ * eighth of the alpha strings and keeps the fastest for (device, norb,
+ * nalpha, nbeta, pair set) in this process. Every layout gives bitwise the
+ * same sigma (fixed-point sums).
+ */
+int casci_get_ab_layout(casci_ctx* ctx, int* out);
+
+/* Override the FP64 alpha-beta layout of pair set pairs (0 or 1, as above)
+ * for this context: code 0 (autotune at the next build) or 10 MT + split with
+ * MT 1..2 and split 1..4; CASCI_E_ARG otherwise. A layout with no kernel
+ * variant for the shape makes the next FP64 build fail (CASCI_E_DEVICE, the
+ * message names the missing variant). */
+int casci_set_ab_layout(casci_ctx* ctx, int pairs, int code);
 
 /*
  * Layout check for bindings: out[0..5] = sizeof(casci_davidson_opts),

@@ -145,6 +145,8 @@ def lib():
         "casci_batch_davidson": (I, [P, I, I, D, P, P, P, I]),
         "casci_get_tuning": (I, [P, P]),
         "casci_set_tuning": (I, [P, I, I]),
+        "casci_get_ab_layout": (I, [P, P]),
+        "casci_set_ab_layout": (I, [P, I, I]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -258,6 +260,17 @@ class Context:
         out = (ctypes.c_int * 2)()
         self._check(self._L.casci_get_tuning(self._h, out))
         return {"f64": out[0], "f32in": out[1]}
+
+    def set_ab_layout(self, pairs: int, code: int):
+        """Force the FP64 alpha-beta layout of pair set `pairs` (0: r <= s,
+        1: all ordered pairs): 0 = autotune, else 10 MT + split."""
+        self._check(self._L.casci_set_ab_layout(self._h, int(pairs), int(code)))
+
+    def ab_layout(self):
+        """Autotuned FP64 alpha-beta layouts {'sym': code, 'full': code} (0: not tuned yet)."""
+        out = (ctypes.c_int * 2)()
+        self._check(self._L.casci_get_ab_layout(self._h, out))
+        return {"sym": out[0], "full": out[1]}
 
     # -- problem definition -------------------------------------------------
     def set_integrals(self, h, eri, e_core: float = 0.0):

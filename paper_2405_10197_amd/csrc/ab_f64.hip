@@ -312,13 +312,20 @@ static hipError_t ab_launch_pf(const AbParams& p, const double* Vt, const double
 }
 
 hipError_t launch_ab_f64(const AbParams& p, const double* Vt, const double* C, const double* rowmax,
-                         double* sigma, hipStream_t st)
+                         double* sigma, hipStream_t st, int layout)
 {
     if (p.Na <= 0 || p.Nb <= 0 || p.sa <= 0 || p.M <= 0) return hipSuccess;
     if (!rowmax) return ab_invalid("alpha-beta: row maxima of C missing");
     const int kb_count = (p.sa + MfmaF64::K - 1) / MfmaF64::K;
     const int mtiles = p.Mp / 16;
-    const int MT = mtiles > AB_MAX_WAVES ? 2 : 1;
+    // layout: 0 = default (one M tile per wave, two above AB_MAX_WAVES tiles;
+    // the sigma row in as few LDS chunks as fit), else 10 MT + split with MT M
+    // tiles per wave and split times the fewest chunks. Every layout gives the
+    // same bits (integer sums), only the speed differs.
+    const int lmt = layout / 10, lsplit = layout % 10;
+    if (layout != 0 && (lmt < 1 || lmt > 2 || lsplit < 1 || lsplit > 4))
+        return ab_invalid("alpha-beta: FP64 layout code must be 0 or 10 MT + split, MT 1..2, split 1..4");
+    const int MT = layout != 0 ? lmt : (mtiles > AB_MAX_WAVES ? 2 : 1);
     const int nwaves = (mtiles + MT - 1) / MT;
     if (nwaves > AB_MAX_WAVES) return ab_invalid("alpha-beta: too many pair rows (norb too large)");
     // LDS: the static per-wave maxima plus the dynamic row chunk, D tile and row indices
@@ -326,7 +333,8 @@ hipError_t launch_ab_f64(const AbParams& p, const double* Vt, const double* C, c
     const int64_t fixed = ab_lds_bytes(kb_count, 0);
     int64_t chunk = (lds_cap - fixed) / 8;
     if (chunk < 256) return ab_invalid("alpha-beta: LDS too small for the sigma row chunk");
-    int nchunks = (int)((p.Nb + chunk - 1) / chunk);
+    int nchunks = (int)((p.Nb + chunk - 1) / chunk) * (layout != 0 ? lsplit : 1);
+    if (nchunks > p.Nb) nchunks = (int)p.Nb;
     chunk = (p.Nb + nchunks - 1) / nchunks;
     const int nth = 64 * nwaves;
     const int pf = (kb_count * MfmaF64::K * AB_TN + nth - 1) / nth;

@@ -166,6 +166,7 @@ struct casci_ctx {
     DBuf d_gin, d_gout;
     // lanes per entry chosen by the autotuner for the FP64 and FP32-input gathers (0: not yet)
     int tune_lpe[2] = {0, 0};
+    int tune_ab[2] = {0, 0};  // FP64 alpha-beta layout code per pair set ([0] r <= s, [1] all), 0: untuned
 
     int fail(int code, const std::string& msg)
     {
@@ -466,6 +467,7 @@ extern "C" int casci_build_strings(casci_ctx* ctx, int nalpha, int nbeta, int no
     ctx->rb = rb;
     ctx->has_strings = true;
     ctx->tune_lpe[0] = ctx->tune_lpe[1] = 0;
+    ctx->tune_ab[0] = ctx->tune_ab[1] = 0;
     ctx->prepared = false;
     ctx->have_full = ctx->have_s2 = false;
     ctx->have_tg_sym = ctx->have_tg_full = ctx->have_tg16 = false;
@@ -1171,6 +1173,66 @@ static int autotune_gather(casci_ctx* ctx, bool lowp, const double* C, const flo
     return CASCI_OK;
 }
 
+// Autotuner of the FP64 alpha-beta layout (M tiles per wave, sigma-row chunks
+// in LDS): the candidates with a kernel variant for this shape are timed on
+// the first eighth of the alpha strings (at least 256) of the build that
+// needs it, once per (device, norb, nalpha, nbeta, pair set) and cached for
+// the process. The fixed-point sums make every layout give the same bits.
+static std::map<std::array<int, 5>, int> g_tune_ab;
+
+static int autotune_ab_f64(casci_ctx* ctx, int full, const AbParams& p, const double* Vt, const double* C,
+                           const double* rowmax, double* out)
+{
+    const std::array<int, 5> key = {ctx->device, ctx->norb, ctx->na, ctx->nb, full};
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_tune_ab.find(key);
+        if (it != g_tune_ab.end()) {
+            ctx->tune_ab[full] = it->second;
+            return CASCI_OK;
+        }
+    }
+    hipStream_t st = ctx->stream;
+    hipEvent_t e0, e1;
+    HIPC(hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return ctx->fail(CASCI_E_DEVICE, "hipEventCreate failed");
+    }
+    AbParams q = p;
+    q.Na = std::min<int64_t>(p.Na, std::max<int64_t>(256, p.Na / 8));
+    int best = 0;
+    float best_ms = 0.f;
+    hipError_t err = hipSuccess;
+    static const int cand[] = {11, 21, 12, 22};
+    for (int code : cand) {
+        // a layout without a kernel variant for this shape is refused before
+        // any launch: skipped
+        if (launch_ab_f64(q, Vt, C, rowmax, out, st, code) != hipSuccess) {
+            set_launch_reason("");
+            continue;
+        }
+        if ((err = hipEventRecord(e0, st)) != hipSuccess) break;
+        for (int rep = 0; rep < 2 && err == hipSuccess; ++rep) err = launch_ab_f64(q, Vt, C, rowmax, out, st, code);
+        if (err != hipSuccess || (err = hipEventRecord(e1, st)) != hipSuccess) break;
+        if ((err = hipEventSynchronize(e1)) != hipSuccess) break;
+        float ms = 0.f;
+        if ((err = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess) break;
+        if (best == 0 || ms < best_ms) {
+            best = code;
+            best_ms = ms;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    HIPC(err);
+    if (best == 0) return ctx->fail(CASCI_E_UNSUPPORTED, "alpha-beta: no FP64 layout runs this shape");
+    ctx->tune_ab[full] = best;
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune_ab[key] = best;
+    return CASCI_OK;
+}
+
 // Vector-sized work buffers of one sigma build. sigma_dev fills them from the
 // context's own (growing) buffers, or takes them from the caller: the
 // allocation-free entry point passes slices of the library's static scratch.
@@ -1284,7 +1346,9 @@ static int sigma_dev(casci_ctx* ctx, const double* C, double* S, int ab_prec, do
         if (!lowp) {
             const DBuf& vt = full ? ctx->d_vt_full : ctx->d_vt_sym;
             HIPC(launch_row_absmax(C, Na, Nb, w.rowmax, st));
-            HIPC(launch_ab_f64(p, vt.as<double>(), C, w.rowmax, w.t3, st));
+            if (alloc && ctx->tune_ab[full] == 0)
+                CHECK_RC(autotune_ab_f64(ctx, full, p, vt.as<double>(), C, w.rowmax, w.t3));
+            HIPC(launch_ab_f64(p, vt.as<double>(), C, w.rowmax, w.t3, st, ctx->tune_ab[full]));
         } else {
             const DBuf* lp = full ? ctx->d_vt_full_lp : ctx->d_vt_sym_lp;
             if (ab_prec == CASCI_BF16 && !full && ab_bf16_fixed_fits(Nb, ctx->sa, p.Mp)) {
@@ -1519,6 +1583,26 @@ extern "C" int casci_get_tuning(casci_ctx* ctx, int* out)
     if (!ctx || !out) return CASCI_E_ARG;
     out[0] = ctx->tune_lpe[0];
     out[1] = ctx->tune_lpe[1];
+    return CASCI_OK;
+}
+
+extern "C" int casci_set_ab_layout(casci_ctx* ctx, int pairs, int code)
+{
+    if (!ctx) return CASCI_E_ARG;
+    if (pairs != 0 && pairs != 1) return ctx->fail(CASCI_E_ARG, "pairs must be 0 (r <= s) or 1 (all ordered pairs)");
+    const int mt = code / 10, split = code % 10;
+    if (code != 0 && (code < 0 || mt < 1 || mt > 2 || split < 1 || split > 4))
+        return ctx->fail(CASCI_E_ARG, "FP64 alpha-beta layout code must be 0 or 10 MT + split (MT 1..2, split 1..4)");
+    ctx->tune_ab[pairs] = code;
+    ++ctx->gen;  // captured graphs hold the old choice
+    return CASCI_OK;
+}
+
+extern "C" int casci_get_ab_layout(casci_ctx* ctx, int* out)
+{
+    if (!ctx || !out) return CASCI_E_ARG;
+    out[0] = ctx->tune_ab[0];
+    out[1] = ctx->tune_ab[1];
     return CASCI_OK;
 }
 

@@ -198,9 +198,12 @@ int abl_waves(int Mp);
 // sigma(Ia, :) += alpha-beta term; Vt[pq][Mp] in the arithmetic's type
 // (prec 1: float, FP32 MFMA; prec 2: bf16, BF16 MFMA; both accumulate in FP32)
 // FP64: fixed-point (order-independent) accumulation; rowmax[Na] = max_c |C(J, c)|
-// from launch_row_absmax bounds the partial sums
+// from launch_row_absmax bounds the partial sums. layout: 0 (default) or
+// 10 MT + split (MT = 1, 2 M tiles per wave; the sigma row in split times the
+// fewest LDS chunks, split 1..4); a layout without a kernel variant for this
+// shape returns hipErrorInvalidValue. All layouts give the same bits.
 hipError_t launch_ab_f64(const AbParams& p, const double* Vt, const double* C, const double* rowmax,
-                         double* sigma, hipStream_t st);
+                         double* sigma, hipStream_t st, int layout = 0);
 hipError_t launch_row_absmax(const double* C, int64_t rows, int64_t cols, double* out, hipStream_t st);
 hipError_t launch_ab_lowp(const AbParams& p, const AbReduce& r, int prec, const void* Vt, const void* Cs,
                           int64_t ldc, double* sigma, hipStream_t st);

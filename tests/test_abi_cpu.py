@@ -186,6 +186,23 @@ def test_batch_rejects_duplicate_contexts_and_bad_tuning(L):
         c.set_tuning(24, 0)
 
 
+def test_ab_layout_codes_checked(L):
+    """FP64 alpha-beta layout overrides: 0 or 10 MT + split (MT 1..2, split 1..4)
+    per pair set, anything else refused; the context reports what was set."""
+    c = casci.Context(-1)
+    assert c.ab_layout() == {"sym": 0, "full": 0}
+    c.set_ab_layout(0, 21)
+    c.set_ab_layout(1, 14)
+    assert c.ab_layout() == {"sym": 21, "full": 14}
+    c.set_ab_layout(0, 0)
+    assert c.ab_layout()["sym"] == 0
+    for pairs, code in ((2, 11), (-1, 11), (0, 31), (0, 15), (0, 10), (0, 5), (0, -11), (1, 100)):
+        with pytest.raises(casci.CasciError):
+            c.set_ab_layout(pairs, code)
+    assert c.ab_layout() == {"sym": 0, "full": 14}
+    assert L.casci_get_ab_layout(None, None) == casci.E_ARG
+
+
 def _sym_cases():
     rng = np.random.default_rng(11)
     for n in list(range(1, 41)) + [64, 100, 240]:

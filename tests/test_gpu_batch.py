@@ -87,6 +87,62 @@ def test_every_gather_width_matches_oracle(torch, n):
     assert t["f64"] in WIDTHS and t["f32in"] in WIDTHS
 
 
+def test_bf16_blocked_gather_sums_in_fp32(torch):
+    """In a BF16 build the row-blocked gather (width 99) sums in FP32 and the
+    other widths in FP64: the two sigmas differ at the FP32 rounding level,
+    far inside the BF16 error bound against the oracle."""
+    c, h, eri = make(10, 3020)
+    na, nb = electrons(10)
+    d = c.dims
+    x = synth.ci_vector(d["Na"], d["Nb"], 6)[0]
+    ref = oracle.sigma(h, eri, na, nb, x)
+    xt = torch.from_numpy(x).cuda()
+    c.set_tuning(0, 64)
+    s64 = c.sigma(xt, ab_prec="bf16").cpu().numpy()
+    c.set_tuning(0, 99)
+    s99 = c.sigma(xt, ab_prec="bf16").cpu().numpy()
+    c.set_tuning(0, 0)
+    scale = np.abs(ref).max()
+    assert np.abs(s99 - s64).max() < 1e-5 * scale
+    assert np.abs(s99 - ref).max() < 2e-2 * scale
+
+
+@pytest.mark.parametrize("n,dressed", [(10, False), (8, True)])
+def test_every_fp64_ab_layout_gives_the_same_bits(torch, n, dressed):
+    """FP64 alpha-beta layouts (M tiles per wave x sigma-row chunks in LDS):
+    every layout with a kernel variant for the shape gives bitwise the same
+    sigma (fixed-point sums), equal to the oracle's; one without a variant is
+    refused with an error; the autotuner picks one of those that run."""
+    na, nb = electrons(n)
+    if dressed:
+        h, eri, ec = synth.dressed_integrals(n, 3030 + n)
+    else:
+        (h, eri, _), ec = synth.integrals(n, 3030 + n), 0.0
+    c = casci.Context(0)
+    c.set_integrals(h, eri, ec)
+    c.build_strings(na, nb, n)
+    pairs = 1 if dressed else 0
+    d = c.dims
+    x = synth.ci_vector(d["Na"], d["Nb"], 7)[0]
+    ref = oracle.sigma(h, eri, na, nb, x, ecore=ec)
+    xt = torch.from_numpy(x).cuda()
+    first, ran = None, []
+    for code in (11, 21, 12, 22, 13, 14, 24):
+        c.set_ab_layout(pairs, code)
+        try:
+            s = c.sigma(xt).cpu().numpy()
+        except casci.CasciError:
+            continue
+        ran.append(code)
+        first = s if first is None else first
+        assert np.array_equal(s, first), code
+    assert len(ran) >= 4, ran
+    assert np.abs(first - ref).max() < 1e-12 * max(1.0, np.abs(ref).max())
+    c.set_ab_layout(pairs, 0)
+    assert np.array_equal(c.sigma(xt).cpu().numpy(), first)
+    assert c.ab_layout()["full" if dressed else "sym"] in ran
+
+
 def test_batch_matches_single_solves_and_oracle(torch):
     """Uneven active spaces CAS(8,8) .. CAS(10,10) (CAS(9,9) as a doublet), 4
     roots each, own integrals each, solved concurrently with graph-replayed
