@@ -300,7 +300,11 @@ __global__ __launch_bounds__(64 * SS_BLK_W, SS_BLK_WPE) void k_ss_gather_blk(SsB
         o1[q] = rowok[q] && 64 + lane <= nch ? (int)goff[64 + lane] : 0;
         grow[q] = gs + (rowok[q] ? (int64_t)bk.rbase[I[q]] : 0);
     }
-    auto off_at = [&](int q, int i) { return i < 64 ? bcast_i32(o0[q], i) : bcast_i32(o1[q], i - 64); };
+    // both halves read and one selected: no branch per lookup
+    auto off_at = [&](int q, int i) {
+        const int lo = bcast_i32(o0[q], i & 63), hi = bcast_i32(o1[q], i & 63);
+        return i < 64 ? lo : hi;
+    };
 
     // Staging runs two chunks ahead: while chunk ch is used, the X rows of
     // chunk ch + 1 (registers of one set) and ch + 2 (the other set) are in
@@ -315,10 +319,13 @@ __global__ __launch_bounds__(64 * SS_BLK_W, SS_BLK_WPE) void k_ss_gather_blk(SsB
         const int k = ch * CH + wave * RPW + lane;
         return (int)U[k < nU ? k : 0];
     };
+    // row offsets in 32 bits (the launch checks that every row of X is
+    // within 2^32 elements), one scalar multiply per staged row
+    const uint32_t ldx32 = (uint32_t)ldx;
     auto issue = [&](int un, VX (&pf)[RPW]) {
 #pragma unroll
         for (int i = 0; i < RPW; ++i)
-            pf[i] = *reinterpret_cast<const VX*>(X + (int64_t)bcast_i32(un, i) * ldx + cl);
+            pf[i] = *reinterpret_cast<const VX*>(X + (uint64_t)((uint32_t)bcast_i32(un, i) * ldx32) + cl);
     };
     auto commit = [&](int buf, const VX (&pf)[RPW]) {
 #pragma unroll
@@ -479,6 +486,9 @@ static hipError_t ss_gather_blk(const SsBlk& bk, const SsGroupOf<TA>* gs, const 
     SsBlk b = bk;
     b.nblk = (nrows + bk.rows - 1) / bk.rows;
     if (b.nblk > bk.nblk) return invalid("same-spin gather: more rows than the row-blocked operator has");
+    // staged rows are addressed with 32-bit element offsets
+    if ((uint64_t)bk.nblk * (uint64_t)bk.rows * (uint64_t)ldx >= ((uint64_t)1 << 32))
+        return invalid("same-spin gather: X too large for the row-blocked form's 32-bit row offsets");
     // FP32 input: two adjacent columns per lane when the row stride allows aligned pairs
     const bool pair = sizeof(TX) == 4 && ldx % 2 == 0;
     const int64_t nstrip = (ncols + (pair ? 127 : 63)) / (pair ? 128 : 64);
