@@ -675,12 +675,14 @@ def headline(args):
         # the BF16 build's row-blocked gather sums in FP32 (FP32 vector roof),
         # every other build in FP64
         acc32 = tag == "lowp" and blocked and HEADLINE["ab_prec"] == "bf16"
+        # (the last template argument: rows per wave, 2 with the 32-row blocks
+        # that CAS(16,16)'s unions fit; FP64 sums of column pairs take 1)
         if tag == "lowp":
-            kname = ("k_ss_gather_blk<float,double,float,2,%s>" % ("float" if acc32 else "double")
+            kname = ("k_ss_gather_blk<float,double,float,2,%s>" % ("float,2" if acc32 else "double,1")
                      if blocked else "k_ss_gather<float,double>")
             pmc = "ss_gather_blk_f32" if blocked else "ss_gather_f32"
         else:
-            kname = "k_ss_gather_blk<double,double,double,1>" if blocked else "k_ss_gather<double,double>"
+            kname = "k_ss_gather_blk<double,double,double,1,double,2>" if blocked else "k_ss_gather<double,double>"
             pmc = "ss_gather_blk_f64" if blocked else "ss_gather_f64"
         traffic = read_traffic(os.path.join(ROOT, "profiles", "%s_%s_pmc.txt" % (pmc, args.workload)))
         # Roofline: the compulsory bytes (read C once, write sigma, read the

@@ -164,12 +164,21 @@ int casci_get_same_spin_operator(casci_ctx* ctx, int spin, int32_t* col, double*
 int casci_get_diagonal(casci_ctx* ctx, double* out, int mem);
 
 /*
+ * Addresses (row-major into [Na][Nb]) of the `want` lowest diagonal elements
+ * H_II (eq. (hamiltonian)), ascending by value, ties by lower address: the
+ * determinants the Davidson start space is built from. out: host int64
+ * [want]; 0 <= want <= number of determinants, else CASCI_E_ARG.
+ */
+int casci_lowest_diagonal(casci_ctx* ctx, int64_t want, int64_t* out);
+
+/*
  * sigma: sigma = H C for one CI vector (the sigma build of Sec. II.A.1).
  * C and sigma are Na x Nb row-major arrays of `dtype` (CASCI_F64, or
  * CASCI_F32 for single-precision storage). ab_prec selects the arithmetic
  * of the alpha-beta contraction: CASCI_F64 (FP64 MFMA), CASCI_F32 (FP32
  * MFMA) or CASCI_BF16 (BF16 MFMA, FP32 accumulate); the alpha-alpha /
- * beta-beta terms accumulate in FP64. FP32 storage on the device with
+ * beta-beta terms accumulate in FP64 (in FP32 in the row-blocked gather of a
+ * BF16 build, see casci_get_tuning). FP32 storage on the device with
  * ab_prec F32/BF16 keeps every vector-sized buffer in FP32 (no FP64 copy:
  * the large-active-space path); other FP32 cases convert to FP64 inside.
  * sigma is overwritten, never accumulated. C and sigma must not overlap.

@@ -146,6 +146,7 @@ def lib():
         "casci_get_tuning": (I, [P, P]),
         "casci_set_tuning": (I, [P, I, I]),
         "casci_get_ab_layout": (I, [P, P]),
+        "casci_lowest_diagonal": (I, [P, ctypes.c_int64, P]),
         "casci_set_ab_layout": (I, [P, I, I]),
     }
     for name, (res, args) in sig.items():
@@ -330,6 +331,12 @@ class Context:
             out = np.zeros((d["Na"], d["Nb"]))
         p, mem = self._vec(out, d["Ndet"], "out")
         self._check(self._L.casci_get_diagonal(self._h, p, mem))
+        return out
+
+    def lowest_diagonal(self, want: int):
+        """Addresses of the `want` lowest diagonal elements, ascending (ties: lower address)."""
+        out = np.zeros(int(want), dtype=np.int64)
+        self._check(self._L.casci_lowest_diagonal(self._h, int(want), out.ctypes.data))
         return out
 
     # -- compute ------------------------------------------------------------

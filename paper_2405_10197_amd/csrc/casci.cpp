@@ -1685,6 +1685,23 @@ extern "C" int casci_get_diagonal(casci_ctx* ctx, double* out, int mem)
     return CASCI_OK;
 }
 
+static int lowest_diag(casci_ctx* ctx, int64_t want, std::vector<int64_t>& out);
+
+extern "C" int casci_lowest_diagonal(casci_ctx* ctx, int64_t want, int64_t* out)
+{
+    if (!ctx) return CASCI_E_ARG;
+    if (!out || want < 0) return ctx->fail(CASCI_E_ARG, "out is NULL or want < 0");
+    if (ctx->validate_only) return ctx->fail(CASCI_E_UNSUPPORTED, kValidateOnly);
+    if (!ctx->has_strings) return ctx->fail(CASCI_E_ARG, "build strings first");
+    if (want > ctx->Nd) return ctx->fail(CASCI_E_ARG, "want exceeds the number of determinants");
+    DeviceGuard g(ctx->device);
+    CHECK_RC(ensure_prepared(ctx, 0.0));
+    std::vector<int64_t> v;
+    CHECK_RC(lowest_diag(ctx, want, v));
+    std::copy(v.begin(), v.end(), out);
+    return CASCI_OK;
+}
+
 static int check_vec_args(casci_ctx* ctx, const void* C, const void* S, int dtype, int ab_prec, int mem)
 {
     if (!C || !S) return ctx->fail(CASCI_E_ARG, "C and sigma must not be NULL");
@@ -2283,6 +2300,94 @@ static std::vector<int64_t> lowest_entries(const std::vector<double>& d, int64_t
     return heap;
 }
 
+// Minimum and maximum of the diagonal (device reduction, fixed partition).
+static int diag_range(casci_ctx* ctx, double* lo, double* hi)
+{
+    DBuf part;
+    HIPC(part.ensure(2 * 512 * 8));
+    int nblk = 0;
+    HIPC(launch_minmax(ctx->d_diag.as<double>(), ctx->Nd, part.as<double>(), &nblk, ctx->stream));
+    std::vector<double> h((size_t)2 * nblk);
+    HIPC(hipMemcpyAsync(h.data(), part.p, h.size() * 8, hipMemcpyDeviceToHost, ctx->stream));
+    HIPC(hipStreamSynchronize(ctx->stream));
+    *lo = INFINITY;
+    *hi = -INFINITY;
+    for (int b = 0; b < nblk; ++b) {
+        *lo = std::fmin(*lo, h[b]);
+        *hi = std::fmax(*hi, h[nblk + b]);
+    }
+    return CASCI_OK;
+}
+
+// The `want` lowest diagonal elements (ties: lower address), ascending by
+// (value, address): a histogram of the diagonal over [min, max] and the
+// entries of the lowest bins that hold at least `want` are found on the
+// device; only those are sorted on the host. Bins are monotonic in the value,
+// so every entry left out is larger than every one collected and the result
+// is exactly that of a full selection. Where the lowest bins hold more than
+// 2^22 entries (massively degenerate diagonals) the whole diagonal is
+// selected on the host instead.
+static int lowest_diag(casci_ctx* ctx, int64_t want, std::vector<int64_t>& out)
+{
+    out.clear();
+    const int64_t Nd = ctx->Nd;
+    want = std::min<int64_t>(want, Nd);
+    if (want <= 0) return CASCI_OK;
+    hipStream_t st = ctx->stream;
+    const double* d = ctx->d_diag.as<double>();
+    double lo = 0.0, hi = 0.0;
+    CHECK_RC(diag_range(ctx, &lo, &hi));
+    constexpr int NBINS = 4096;
+    constexpr int64_t CAP = (int64_t)1 << 22;
+    const double inv_w = hi > lo ? NBINS / (hi - lo) : 0.0;
+    DBuf hist, cnt;
+    HIPC(hist.ensure(NBINS * 4));
+    HIPC(cnt.ensure(8));
+    HIPC(hipMemsetAsync(hist.p, 0, NBINS * 4, st));
+    HIPC(launch_value_hist(d, Nd, lo, inv_w, NBINS, hist.as<unsigned>(), st));
+    std::vector<unsigned> hh(NBINS);
+    HIPC(hipMemcpyAsync(hh.data(), hist.p, NBINS * 4, hipMemcpyDeviceToHost, st));
+    HIPC(hipStreamSynchronize(st));
+    int bmax = 0;
+    int64_t c = 0;
+    for (; bmax < NBINS; ++bmax) {
+        c += hh[bmax];
+        if (c >= want) break;
+    }
+    if (bmax == NBINS) return ctx->fail(CASCI_E_DEVICE, "diagonal selection: histogram lost entries");
+    auto by_value = [](const std::pair<double, int64_t>& a, const std::pair<double, int64_t>& b) {
+        return a.first < b.first || (a.first == b.first && a.second < b.second);
+    };
+    std::vector<std::pair<double, int64_t>> cand;
+    if (c <= CAP) {
+        DBuf bidx, bval;
+        HIPC(bidx.ensure((size_t)c * 8));
+        HIPC(bval.ensure((size_t)c * 8));
+        HIPC(hipMemsetAsync(cnt.p, 0, 8, st));
+        HIPC(launch_value_collect(d, Nd, lo, inv_w, NBINS, bmax, cnt.as<unsigned long long>(), bidx.as<int64_t>(),
+                                  bval.as<double>(), c, st));
+        unsigned long long found = 0;
+        std::vector<int64_t> h_idx((size_t)c);
+        std::vector<double> h_val((size_t)c);
+        HIPC(hipMemcpyAsync(&found, cnt.p, 8, hipMemcpyDeviceToHost, st));
+        HIPC(hipMemcpyAsync(h_idx.data(), bidx.p, (size_t)c * 8, hipMemcpyDeviceToHost, st));
+        HIPC(hipMemcpyAsync(h_val.data(), bval.p, (size_t)c * 8, hipMemcpyDeviceToHost, st));
+        HIPC(hipStreamSynchronize(st));
+        if ((int64_t)found != c) return ctx->fail(CASCI_E_DEVICE, "diagonal selection: histogram and collection disagree");
+        cand.resize((size_t)c);
+        for (int64_t i = 0; i < c; ++i) cand[(size_t)i] = {h_val[(size_t)i], h_idx[(size_t)i]};
+    } else {
+        std::vector<double> diag((size_t)Nd);
+        HIPC(hipMemcpyAsync(diag.data(), d, (size_t)Nd * 8, hipMemcpyDeviceToHost, st));
+        HIPC(hipStreamSynchronize(st));
+        for (int64_t i : lowest_entries(diag, want)) cand.push_back({diag[(size_t)i], i});
+    }
+    std::partial_sort(cand.begin(), cand.begin() + want, cand.end(), by_value);
+    out.resize((size_t)want);
+    for (int64_t i = 0; i < want; ++i) out[(size_t)i] = cand[(size_t)i].second;
+    return CASCI_OK;
+}
+
 static int davidson_impl(casci_ctx* ctx, int nroots, double tol, const casci_davidson_opts* opts,
                          double* energies, void* vectors, int mem, casci_davidson_info* info,
                          Collector* col)
@@ -2552,12 +2657,10 @@ static int davidson_impl(casci_ctx* ctx, int nroots, double tol, const casci_dav
         CHECK_RC(orthonormalize(0, ng, kept));
         m = kept;
     }
-    // host copy of the diagonal: start vectors and the lowest element (a
-    // feature of the learned preconditioner)
-    std::vector<double> diag(Nd);
-    HIPC(hipMemcpyAsync(diag.data(), ctx->d_diag.p, vb, hipMemcpyDeviceToHost, st));
-    HIPC(hipStreamSynchronize(st));
-    const double dmin = *std::min_element(diag.begin(), diag.end());
+    // the lowest diagonal element (a feature of the learned preconditioner);
+    // the start vectors' lowest elements are selected on the device too
+    double dmin = 0.0, dmax = 0.0;
+    CHECK_RC(diag_range(ctx, &dmin, &dmax));
     if (m < k && !singlet) {
         // Start space: eigenvectors of H in the P-space of the lowest-diagonal
         // determinants (with their transposition partners when nalpha == nbeta,
@@ -2566,7 +2669,8 @@ static int davidson_impl(casci_ctx* ctx, int nroots, double tol, const casci_dav
         // and never see a lower state of another.
         const int Pt = (int)std::min<int64_t>(Nd, 240);
         const int64_t want = std::min<int64_t>(Nd, 2 * (int64_t)Pt);
-        const std::vector<int64_t> idx = lowest_entries(diag, want);
+        std::vector<int64_t> idx;
+        CHECK_RC(lowest_diag(ctx, want, idx));
         const bool paired = ctx->na == ctx->nb;
         std::vector<int64_t> dets;
         auto has = [&](int64_t x) { return std::find(dets.begin(), dets.end(), x) != dets.end(); };
@@ -2634,7 +2738,8 @@ static int davidson_impl(casci_ctx* ctx, int nroots, double tol, const casci_dav
         // diagonal preconditioner, so a space without antisymmetric vectors
         // would never reach odd-S states. SINGLET keeps the + combinations.
         const int64_t want = std::min<int64_t>(Nd, 8 * k + 16);
-        const std::vector<int64_t> idx = lowest_entries(diag, want);
+        std::vector<int64_t> idx;
+        CHECK_RC(lowest_diag(ctx, want, idx));
 
         struct Pick {
             int64_t lo, hi;

@@ -443,4 +443,97 @@ hipError_t launch_absmax(const double* x, int64_t n, double* work, double* out, 
     return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// lowest entries of the diagonal (start vectors): min/max, a histogram over
+// [min, max], then the entries of the lowest bins, which the host sorts
+// ---------------------------------------------------------------------------
+// per-block minimum and maximum over a contiguous slice (fixed partition)
+__global__ __launch_bounds__(RED_THREADS) void k_minmax_partial(const double* __restrict__ x, int64_t n, int nblk,
+                                                                double* __restrict__ out)
+{
+    __shared__ double smin[RED_THREADS], smax[RED_THREADS];
+    const int64_t per = (n + nblk - 1) / nblk;
+    const int64_t lo = (int64_t)blockIdx.x * per, hi = min(n, lo + per);
+    double a = INFINITY, b = -INFINITY;
+    for (int64_t k = lo + threadIdx.x; k < hi; k += RED_THREADS) {
+        a = fmin(a, x[k]);
+        b = fmax(b, x[k]);
+    }
+    smin[threadIdx.x] = a;
+    smax[threadIdx.x] = b;
+    __syncthreads();
+    for (int st = RED_THREADS / 2; st > 0; st >>= 1) {
+        if ((int)threadIdx.x < st) {
+            smin[threadIdx.x] = fmin(smin[threadIdx.x], smin[threadIdx.x + st]);
+            smax[threadIdx.x] = fmax(smax[threadIdx.x], smax[threadIdx.x + st]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        out[blockIdx.x] = smin[0];
+        out[nblk + blockIdx.x] = smax[0];
+    }
+}
+
+// bin of a value: the same expression in the histogram and the collection
+__device__ inline int value_bin(double v, double lo, double inv_w, int nbins)
+{
+    const double t = (v - lo) * inv_w;
+    return t < (double)nbins ? (t > 0.0 ? (int)t : 0) : nbins - 1;
+}
+
+__global__ __launch_bounds__(256) void k_value_hist(const double* __restrict__ x, int64_t n, double lo,
+                                                    double inv_w, int nbins, unsigned* __restrict__ hist)
+{
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += stride)
+        atomicAdd(&hist[value_bin(x[k], lo, inv_w, nbins)], 1u);
+}
+
+// entries in bins <= bmax, in any order (the caller sorts them); at most cap
+__global__ __launch_bounds__(256) void k_value_collect(const double* __restrict__ x, int64_t n, double lo,
+                                                       double inv_w, int nbins, int bmax,
+                                                       unsigned long long* __restrict__ count,
+                                                       int64_t* __restrict__ idx, double* __restrict__ val,
+                                                       int64_t cap)
+{
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += stride) {
+        const double v = x[k];
+        if (value_bin(v, lo, inv_w, nbins) <= bmax) {
+            const unsigned long long s = atomicAdd(count, 1ull);
+            if ((int64_t)s < cap) {
+                idx[s] = k;
+                val[s] = v;
+            }
+        }
+    }
+}
+
+hipError_t launch_minmax(const double* x, int64_t n, double* out, int* nblk_out, hipStream_t st)
+{
+    const int nblk = red_blocks(n);
+    *nblk_out = nblk;
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_minmax_partial, dim3(nblk), dim3(RED_THREADS), 0, st, x, n, nblk, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_value_hist(const double* x, int64_t n, double lo, double inv_w, int nbins, unsigned* hist,
+                             hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_value_hist, dim3(ew_grid(n)), dim3(256), 0, st, x, n, lo, inv_w, nbins, hist);
+    return hipGetLastError();
+}
+
+hipError_t launch_value_collect(const double* x, int64_t n, double lo, double inv_w, int nbins, int bmax,
+                                unsigned long long* count, int64_t* idx, double* val, int64_t cap, hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_value_collect, dim3(ew_grid(n)), dim3(256), 0, st, x, n, lo, inv_w, nbins, bmax, count,
+                       idx, val, cap);
+    return hipGetLastError();
+}
+
 }  // namespace casci

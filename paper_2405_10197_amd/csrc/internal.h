@@ -258,6 +258,16 @@ hipError_t launch_scale(double* x, double a, int64_t n, hipStream_t st);
 // out[0] = x_i and out[1] = i for the largest |x_i| (ties: lowest i); work holds
 // 2 * 512 doubles of partials
 hipError_t launch_absmax(const double* x, int64_t n, double* work, double* out, hipStream_t st);
+// out[0..nblk) per-block minima and out[nblk..2 nblk) maxima of x[0..n)
+// (nblk <= 512, returned in *nblk_out)
+hipError_t launch_minmax(const double* x, int64_t n, double* out, int* nblk_out, hipStream_t st);
+// hist[b] += number of entries in bin b = clamp(floor((x - lo) inv_w), 0, nbins - 1)
+hipError_t launch_value_hist(const double* x, int64_t n, double lo, double inv_w, int nbins, unsigned* hist,
+                             hipStream_t st);
+// (index, value) of every entry in bins <= bmax, in any order, the first cap kept;
+// *count (zeroed by the caller) ends as the number found
+hipError_t launch_value_collect(const double* x, int64_t n, double lo, double inv_w, int nbins, int bmax,
+                                unsigned long long* count, int64_t* idx, double* val, int64_t cap, hipStream_t st);
 
 // rdm_kernels.hip (density matrices)
 // rows [D^alpha_pq ; D^beta_pq ; C] (row stride ldm) of the determinants of alpha strings [a0, a0 + nblk)
