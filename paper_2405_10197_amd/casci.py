@@ -147,6 +147,8 @@ def lib():
         "casci_set_tuning": (I, [P, I, I]),
         "casci_get_ab_layout": (I, [P, P]),
         "casci_lowest_diagonal": (I, [P, ctypes.c_int64, P]),
+        "casci_release_cache": (I, [I]),
+        "casci_cached_bytes": (ctypes.c_int64, [I]),
         "casci_set_ab_layout": (I, [P, I, I]),
     }
     for name, (res, args) in sig.items():
@@ -547,6 +549,17 @@ class Context:
             out["hist_energy"], out["hist_residual"], out["hist_time_ms"] = (
                 hist[0][:n], hist[1][:n], hist[2][:n])
         return E, vec, out
+
+
+def release_cache(device: int = -1):
+    """Return the library's cached device blocks (casci_release_cache) to the driver."""
+    if lib().casci_release_cache(int(device)) != OK:
+        raise CasciError("casci_release_cache failed")
+
+
+def cached_bytes(device: int = -1) -> int:
+    """Bytes of device memory the library's block cache holds (casci_cached_bytes)."""
+    return int(lib().casci_cached_bytes(int(device)))
 
 
 def batch_davidson(contexts, nroots: int = 1, tol: float = 1e-10, *, nthreads: int = 0, **kw):

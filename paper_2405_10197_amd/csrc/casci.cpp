@@ -27,15 +27,76 @@ using namespace casci;
 
 namespace {
 
+// Process-wide cache of large device blocks. A solve allocates ~160 GB of
+// basis vectors at CAS(16,16) and frees them at its end; allocating that much
+// again after a free cost 1.4-3.8 s per solve (growing with each solve in the
+// process), so blocks of at least BLOCK_CACHE_MIN bytes are kept on release
+// and handed to later requests of the same or a slightly smaller size. A
+// released block is cached only after the device has finished with it (the
+// synchronisation hipFree itself performs), at most half of the device's
+// memory is held, and an allocation that fails empties the cache of that
+// device and is retried. casci_release_cache frees the cached blocks.
+constexpr size_t BLOCK_CACHE_MIN = (size_t)64 << 20;
+struct BlockCache {
+    std::mutex mu;
+    std::map<int, std::multimap<size_t, void*>> free;  // device -> (bytes, block)
+    std::map<int, size_t> held;
+};
+BlockCache& block_cache()
+{
+    static BlockCache* c = new BlockCache;  // never destroyed: blocks may outlive static destructors
+    return *c;
+}
+void* cache_take(int dev, size_t b, size_t* got)
+{
+    BlockCache& c = block_cache();
+    std::lock_guard<std::mutex> lk(c.mu);
+    auto& m = c.free[dev];
+    auto it = m.lower_bound(b);
+    if (it == m.end() || it->first > b + b / 8) return nullptr;  // at most 12.5% larger
+    void* p = it->second;
+    *got = it->first;
+    c.held[dev] -= it->first;
+    m.erase(it);
+    return p;
+}
+void cache_flush(int dev)
+{
+    BlockCache& c = block_cache();
+    std::lock_guard<std::mutex> lk(c.mu);
+    auto& m = c.free[dev];
+    for (auto& kv : m) (void)hipFree(kv.second);
+    m.clear();
+    c.held[dev] = 0;
+}
+
 struct DBuf {
     void* p = nullptr;
     size_t bytes = 0;
+    int dev = -1;
     hipError_t ensure(size_t b)
     {
         if (b <= bytes && p) return hipSuccess;
         release();
         if (b == 0) b = 16;
-        hipError_t e = hipMalloc(&p, b);
+        int d = 0;
+        hipError_t e = hipGetDevice(&d);
+        if (e != hipSuccess) return e;
+        if (b >= BLOCK_CACHE_MIN) {
+            size_t got = 0;
+            if (void* q = cache_take(d, b, &got)) {
+                p = q;
+                bytes = got;
+                dev = d;
+                return hipSuccess;
+            }
+        }
+        e = hipMalloc(&p, b);
+        if (e != hipSuccess && b >= BLOCK_CACHE_MIN) {
+            (void)hipGetLastError();
+            cache_flush(d);
+            e = hipMalloc(&p, b);
+        }
         if (e != hipSuccess) {
             p = nullptr;
             bytes = 0;
@@ -43,11 +104,34 @@ struct DBuf {
             return e;
         }
         bytes = b;
+        dev = d;
         return hipSuccess;
     }
     void release()
     {
-        if (p) (void)hipFree(p);
+        if (p) {
+            bool cached = false;
+            if (bytes >= BLOCK_CACHE_MIN) {
+                int cur = -1;
+                (void)hipGetDevice(&cur);
+                if (cur != dev) (void)hipSetDevice(dev);
+                size_t fr = 0, tot = 0;
+                if (hipDeviceSynchronize() == hipSuccess && hipMemGetInfo(&fr, &tot) == hipSuccess) {
+                    BlockCache& c = block_cache();
+                    std::lock_guard<std::mutex> lk(c.mu);
+                    if (c.held[dev] + bytes <= tot / 2) {
+                        c.free[dev].emplace(bytes, p);
+                        c.held[dev] += bytes;
+                        cached = true;
+                    }
+                }
+                (void)hipGetLastError();
+                if (!cached) (void)hipFree(p);
+                if (cur >= 0 && cur != dev) (void)hipSetDevice(cur);
+            } else {
+                (void)hipFree(p);
+            }
+        }
         p = nullptr;
         bytes = 0;
     }
@@ -274,6 +358,32 @@ extern "C" int casci_create(casci_ctx** out, int device, void* hip_stream)
     }
     *out = ctx;
     return CASCI_OK;
+}
+
+extern "C" int casci_release_cache(int device)
+{
+    std::vector<int> devs;
+    {
+        BlockCache& c = block_cache();
+        std::lock_guard<std::mutex> lk(c.mu);
+        for (auto& kv : c.free)
+            if (device < 0 || kv.first == device) devs.push_back(kv.first);
+    }
+    for (int d : devs) {
+        DeviceGuard g(d);
+        cache_flush(d);
+    }
+    return CASCI_OK;
+}
+
+extern "C" int64_t casci_cached_bytes(int device)
+{
+    BlockCache& c = block_cache();
+    std::lock_guard<std::mutex> lk(c.mu);
+    int64_t n = 0;
+    for (auto& kv : c.held)
+        if (device < 0 || kv.first == device) n += (int64_t)kv.second;
+    return n;
 }
 
 extern "C" void casci_destroy(casci_ctx* ctx)

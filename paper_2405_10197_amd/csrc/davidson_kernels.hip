@@ -482,12 +482,22 @@ __device__ inline int value_bin(double v, double lo, double inv_w, int nbins)
     return t < (double)nbins ? (t > 0.0 ? (int)t : 0) : nbins - 1;
 }
 
+// one histogram per workgroup in LDS (the values crowd into few bins, so
+// global atomics per element would serialise), added to the global one at
+// the end; nbins <= VALUE_HIST_MAXBINS
+constexpr int VALUE_HIST_MAXBINS = 4096;
 __global__ __launch_bounds__(256) void k_value_hist(const double* __restrict__ x, int64_t n, double lo,
                                                     double inv_w, int nbins, unsigned* __restrict__ hist)
 {
+    __shared__ unsigned sh[VALUE_HIST_MAXBINS];
+    for (int b = threadIdx.x; b < nbins; b += blockDim.x) sh[b] = 0u;
+    __syncthreads();
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += stride)
-        atomicAdd(&hist[value_bin(x[k], lo, inv_w, nbins)], 1u);
+        atomicAdd(&sh[value_bin(x[k], lo, inv_w, nbins)], 1u);
+    __syncthreads();
+    for (int b = threadIdx.x; b < nbins; b += blockDim.x)
+        if (sh[b]) atomicAdd(&hist[b], sh[b]);
 }
 
 // entries in bins <= bmax, in any order (the caller sorts them); at most cap
@@ -523,7 +533,9 @@ hipError_t launch_value_hist(const double* x, int64_t n, double lo, double inv_w
                              hipStream_t st)
 {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_value_hist, dim3(ew_grid(n)), dim3(256), 0, st, x, n, lo, inv_w, nbins, hist);
+    if (nbins < 1 || nbins > VALUE_HIST_MAXBINS) return hipErrorInvalidValue;
+    const int64_t g = std::min<int64_t>(1024, (n + 255) / 256);
+    hipLaunchKernelGGL(k_value_hist, dim3((unsigned)g), dim3(256), 0, st, x, n, lo, inv_w, nbins, hist);
     return hipGetLastError();
 }
 

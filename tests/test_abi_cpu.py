@@ -186,6 +186,15 @@ def test_batch_rejects_duplicate_contexts_and_bad_tuning(L):
         c.set_tuning(24, 0)
 
 
+def test_block_cache_calls_without_a_device(L):
+    """The device-block cache is empty until something is released on a GPU;
+    its calls need no device."""
+    assert casci.cached_bytes() == 0
+    casci.release_cache()
+    casci.release_cache(3)
+    assert L.casci_cached_bytes(-1) == 0
+
+
 def test_ab_layout_codes_checked(L):
     """FP64 alpha-beta layout overrides: 0 or 10 MT + split (MT 1..2, split 1..4)
     per pair set, anything else refused; the context reports what was set."""

@@ -61,3 +61,26 @@ def test_lowest_diagonal_argument_checks(torch):
     with pytest.raises(casci.CasciError):
         c.lowest_diagonal(c.dims["Ndet"] + 1)
     assert c.lowest_diagonal(0).size == 0
+
+
+def test_block_cache_reuses_the_basis_of_a_previous_solve(torch):
+    """Two identical solves in one process: the second takes its basis blocks
+    from the library's cache (the first left them there) and gives bitwise
+    the same energies and iterations; releasing the cache empties it."""
+    h, eri, _ = synth.integrals(12, 905)
+    out = []
+    for rep in range(2):
+        c = casci.Context(0)
+        c.set_integrals(h, eri)
+        c.build_strings(6, 6, 12)
+        E, _, info = c.davidson(2, 1e-9, r_tol=1e-5, precond="olsen", vectors=False, history=400, max_iter=400)
+        assert info["converged"]
+        out.append((E, info["iterations"], info["hist_energy"]))
+        del c
+        # the basis B and its sigma vectors S (tens of vectors of 6.8 MB each)
+        # are kept
+        assert casci.cached_bytes(0) >= 2 * (64 << 20)
+    assert np.array_equal(out[0][0], out[1][0]) and out[0][1] == out[1][1]
+    assert np.array_equal(out[0][2], out[1][2])
+    casci.release_cache()
+    assert casci.cached_bytes() == 0
