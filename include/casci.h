@@ -96,8 +96,9 @@ int casci_create(casci_ctx** out, int device, void* hip_stream);
  * Device memory cache: blocks of 64 MiB and more that the library frees
  * (the Davidson basis, vector-sized work buffers) are kept for later
  * requests of about the same size instead of being returned to the driver,
- * at most half of a device's memory; an allocation that fails empties the
- * cache of its device and is retried. casci_release_cache returns the cached
+ * at most three quarters of a device's memory (the least recently released
+ * blocks go first); an allocation that fails empties the cache of its device
+ * and is retried. casci_release_cache returns the cached
  * blocks of `device` (-1: every device) to the driver, casci_cached_bytes
  * reports how many bytes are held. Not for use while another thread is in a
  * library call on that device.

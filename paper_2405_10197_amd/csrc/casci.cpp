@@ -8,6 +8,7 @@
 #include <algorithm>
 #include <array>
 #include <atomic>
+#include <list>
 #include <map>
 #include <mutex>
 #include <thread>
@@ -33,13 +34,15 @@ namespace {
 // process), so blocks of at least BLOCK_CACHE_MIN bytes are kept on release
 // and handed to later requests of the same or a slightly smaller size. A
 // released block is cached only after the device has finished with it (the
-// synchronisation hipFree itself performs), at most half of the device's
-// memory is held, and an allocation that fails empties the cache of that
-// device and is retried. casci_release_cache frees the cached blocks.
+// synchronisation hipFree itself performs). At most three quarters of the
+// device's memory is held: a block released into a full cache evicts the
+// least recently released ones (a later solve repeats the latest one's
+// sizes), and an allocation that fails empties the cache of that device and
+// is retried. casci_release_cache frees the cached blocks.
 constexpr size_t BLOCK_CACHE_MIN = (size_t)64 << 20;
 struct BlockCache {
     std::mutex mu;
-    std::map<int, std::multimap<size_t, void*>> free;  // device -> (bytes, block)
+    std::map<int, std::list<std::pair<size_t, void*>>> free;  // device -> blocks, oldest first
     std::map<int, size_t> held;
 };
 BlockCache& block_cache()
@@ -51,22 +54,41 @@ void* cache_take(int dev, size_t b, size_t* got)
 {
     BlockCache& c = block_cache();
     std::lock_guard<std::mutex> lk(c.mu);
-    auto& m = c.free[dev];
-    auto it = m.lower_bound(b);
-    if (it == m.end() || it->first > b + b / 8) return nullptr;  // at most 12.5% larger
-    void* p = it->second;
-    *got = it->first;
-    c.held[dev] -= it->first;
-    m.erase(it);
+    auto& l = c.free[dev];
+    auto best = l.end();
+    for (auto it = l.begin(); it != l.end(); ++it)  // smallest block that fits, at most 12.5% larger
+        if (it->first >= b && it->first <= b + b / 8 && (best == l.end() || it->first < best->first)) best = it;
+    if (best == l.end()) return nullptr;
+    void* p = best->second;
+    *got = best->first;
+    c.held[dev] -= best->first;
+    l.erase(best);
     return p;
+}
+// keeps block p of `bytes` on device dev (current) if it fits under cap after
+// evicting the oldest blocks; false: the caller frees it
+bool cache_put(int dev, void* p, size_t bytes, size_t cap)
+{
+    if (bytes > cap) return false;
+    BlockCache& c = block_cache();
+    std::lock_guard<std::mutex> lk(c.mu);
+    auto& l = c.free[dev];
+    while (!l.empty() && c.held[dev] + bytes > cap) {
+        (void)hipFree(l.front().second);
+        c.held[dev] -= l.front().first;
+        l.pop_front();
+    }
+    l.emplace_back(bytes, p);
+    c.held[dev] += bytes;
+    return true;
 }
 void cache_flush(int dev)
 {
     BlockCache& c = block_cache();
     std::lock_guard<std::mutex> lk(c.mu);
-    auto& m = c.free[dev];
-    for (auto& kv : m) (void)hipFree(kv.second);
-    m.clear();
+    auto& l = c.free[dev];
+    for (auto& kv : l) (void)hipFree(kv.second);
+    l.clear();
     c.held[dev] = 0;
 }
 
@@ -116,15 +138,8 @@ struct DBuf {
                 (void)hipGetDevice(&cur);
                 if (cur != dev) (void)hipSetDevice(dev);
                 size_t fr = 0, tot = 0;
-                if (hipDeviceSynchronize() == hipSuccess && hipMemGetInfo(&fr, &tot) == hipSuccess) {
-                    BlockCache& c = block_cache();
-                    std::lock_guard<std::mutex> lk(c.mu);
-                    if (c.held[dev] + bytes <= tot / 2) {
-                        c.free[dev].emplace(bytes, p);
-                        c.held[dev] += bytes;
-                        cached = true;
-                    }
-                }
+                if (hipDeviceSynchronize() == hipSuccess && hipMemGetInfo(&fr, &tot) == hipSuccess)
+                    cached = cache_put(dev, p, bytes, tot / 4 * 3);
                 (void)hipGetLastError();
                 if (!cached) (void)hipFree(p);
                 if (cur >= 0 && cur != dev) (void)hipSetDevice(cur);
