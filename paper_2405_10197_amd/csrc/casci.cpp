@@ -2670,6 +2670,18 @@ static int davidson_impl(casci_ctx* ctx, int nroots, double tol, const casci_dav
         HIPC(launch_sym_add(v, ctx->Na, p, 0.5, st));
         return CASCI_OK;
     };
+    // the same, with |v|^2 of the result summed in the same pass (per tile
+    // pair, then in a fixed order) instead of another pass over v
+    auto symmetrize_norm = [&](double* v, int p, double* nrm2) -> int {
+        const int64_t parts = sym_add_parts(ctx->Na);
+        if (parts > INT32_MAX) return ctx->fail(CASCI_E_UNSUPPORTED, "too many tile pairs for the norm");
+        CHECK_RC(ensure_work(ctx, (size_t)(parts + 511) / 512));
+        HIPC(launch_sym_add(v, ctx->Na, p, 0.5, st, nullptr, ctx->d_work.as<double>()));
+        HIPC(launch_reduce_partials(ctx->d_work.as<double>(), 1, (int)parts, dres, st));
+        HIPC(hipMemcpyAsync(nrm2, dres, 8, hipMemcpyDeviceToHost, st));
+        HIPC(hipStreamSynchronize(st));
+        return CASCI_OK;
+    };
 
     // ---- orthonormalise vectors [m, m+cnt) of B against [0, m) and each other;
     // returns the number kept (compacted to [m, m+kept))
@@ -2735,10 +2747,15 @@ static int davidson_impl(casci_ctx* ctx, int nroots, double tol, const casci_dav
             // after Gram-Schmidt can be small, and normalising it would amplify
             // rounding-level components of the other parity. The projection
             // keeps orthogonality to a basis of pure-parity vectors.
-            if (use_par && par[m + j] != 0) CHECK_RC(symmetrize(v, par[m + j]));
-            std::vector<double> nn;
-            CHECK_RC(dots_dev(v, 1, v, 1, nn));
-            const double nrm = std::sqrt(nn[0]);
+            double n2 = 0.0;
+            if (use_par && par[m + j] != 0) {
+                CHECK_RC(symmetrize_norm(v, par[m + j], &n2));
+            } else {
+                std::vector<double> nn;
+                CHECK_RC(dots_dev(v, 1, v, 1, nn));
+                n2 = nn[0];
+            }
+            const double nrm = std::sqrt(n2);
             if (!(nrm > 1e-8 * std::max(before[j], 1e-300)) || !(nrm > 1e-14)) continue;
             HIPC(launch_scale(v, 1.0 / nrm, Nd, st));
             if (kept != j) HIPC(hipMemcpyAsync(vB(m + kept), v, vb, hipMemcpyDeviceToDevice, st));

@@ -147,6 +147,13 @@ __global__ __launch_bounds__(256) void k_reduce_partials(const double* __restric
     if (lane == 0) out[o] = s;
 }
 
+hipError_t launch_reduce_partials(const double* work, int nout, int nparts, double* out, hipStream_t st)
+{
+    if (nout <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_reduce_partials, dim3((nout + 3) / 4), dim3(256), 0, st, work, nout, nparts, out);
+    return hipGetLastError();
+}
+
 hipError_t launch_block_dot(const double* A, int64_t lda, int na, const double* B, int64_t ldb,
                             int nb, int64_t len, double* work, double* out, hipStream_t st)
 {

@@ -145,9 +145,18 @@ hipError_t launch_ss_gather_f32(const SsOp& op, int64_t nrows, int64_t ncols, co
                                 double shift, int acc, hipStream_t st, int lpe = 0);
 hipError_t launch_compact_op(const int32_t* col, const double* val, int64_t n, uint16_t* col16, float* val32,
                              hipStream_t st);
-// S <- scale (S + p S^T) [+ T], S square n x n, in place (T may be null)
+// S <- scale (S + p S^T) [+ T], S square n x n, in place (T may be null).
+// nrm2 (may be null): per-workgroup sums of squares of the result, one per
+// tile pair (sym_add_parts(n) of them), for launch_reduce_partials
 hipError_t launch_sym_add(double* S, int64_t n, int p, double scale, hipStream_t st,
-                          const double* T = nullptr);
+                          const double* T = nullptr, double* nrm2 = nullptr);
+inline int64_t sym_add_parts(int64_t n)
+{
+    const int64_t nb = (n + 31) / 32;
+    return nb * (nb + 1) / 2;
+}
+// out[o] = sum over k of work[o * nparts + k] in a fixed order, o < nout
+hipError_t launch_reduce_partials(const double* work, int nout, int nparts, double* out, hipStream_t st);
 // out[j][i] (+)= in[i][j], in: rows x cols
 hipError_t launch_transpose_f64(const double* in, double* out, int64_t rows, int64_t cols, int acc,
                                 double scale, hipStream_t st);

@@ -623,8 +623,11 @@ hipError_t launch_compact_op(const int32_t* col, const double* val, int64_t n, u
 // pair (bi, bj) / (bj, bi) is read into LDS by one block before either is
 // written, so every output uses the original values.
 // ---------------------------------------------------------------------------
+// nrm2 (may be null): nrm2[block] = sum of the squares of the values the
+// block wrote (fixed order), for a norm of the result without another pass
 __global__ __launch_bounds__(256) void k_sym_add(double* __restrict__ S, int64_t n, double p,
-                                                 double scale, int64_t nb, const double* __restrict__ T)
+                                                 double scale, int64_t nb, const double* __restrict__ T,
+                                                 double* __restrict__ nrm2)
 {
     __shared__ double A[32][33];
     __shared__ double B[32][33];
@@ -639,25 +642,44 @@ __global__ __launch_bounds__(256) void k_sym_add(double* __restrict__ S, int64_t
         B[i][tx] = (rb < n && cb < n) ? S[rb * n + cb] : 0.0;
     }
     __syncthreads();
+    double ss = 0.0;
     for (int i = ty; i < 32; i += 8) {
         const int64_t ra = r0 + i, ca = c0 + tx;
-        if (ra < n && ca < n)
-            S[ra * n + ca] = scale * (A[i][tx] + p * B[tx][i]) + (T ? T[ra * n + ca] : 0.0);
+        if (ra < n && ca < n) {
+            const double y = scale * (A[i][tx] + p * B[tx][i]) + (T ? T[ra * n + ca] : 0.0);
+            S[ra * n + ca] = y;
+            ss += y * y;
+        }
         if (bi != bj) {
             const int64_t rb = c0 + i, cb = r0 + tx;
-            if (rb < n && cb < n)
-                S[rb * n + cb] = scale * (B[i][tx] + p * A[tx][i]) + (T ? T[rb * n + cb] : 0.0);
+            if (rb < n && cb < n) {
+                const double y = scale * (B[i][tx] + p * A[tx][i]) + (T ? T[rb * n + cb] : 0.0);
+                S[rb * n + cb] = y;
+                ss += y * y;
+            }
         }
+    }
+    if (nrm2) {  // uniform: the whole block takes this branch or none
+        __syncthreads();
+        double* red = &A[0][0];
+        red[threadIdx.x] = ss;
+        __syncthreads();
+        for (int st = 128; st > 0; st >>= 1) {
+            if ((int)threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) nrm2[blockIdx.x] = red[0];
     }
 }
 
-hipError_t launch_sym_add(double* S, int64_t n, int p, double scale, hipStream_t st, const double* T)
+hipError_t launch_sym_add(double* S, int64_t n, int p, double scale, hipStream_t st, const double* T,
+                          double* nrm2)
 {
     if (n <= 0) return hipSuccess;
     const int64_t nb = (n + 31) / 32;
     const int64_t pairs = nb * (nb + 1) / 2;
     if (pairs > 0x7fffffffLL) return invalid("sym_add: matrix too large");
-    hipLaunchKernelGGL(k_sym_add, dim3((unsigned)pairs), dim3(256), 0, st, S, n, (double)p, scale, nb, T);
+    hipLaunchKernelGGL(k_sym_add, dim3((unsigned)pairs), dim3(256), 0, st, S, n, (double)p, scale, nb, T, nrm2);
     return hipGetLastError();
 }
 
