@@ -103,16 +103,20 @@ __device__ inline void ab_scatter_fixed(unsigned long long* sig, const d4 (&acc)
         for (int v = 0; v < 4; ++v) atomicAdd(&sig[off[ns][v]], (unsigned long long)q[ns][v]);
 }
 
-template <int KBMAX, int MT, int PF>
+// EXACT: kb_count == KBMAX, known at compile time, so the K-block loop has
+// no run-time guard (with one, every K block was a branch that cost register
+// copies and an MFMA drain before the next)
+template <int KBMAX, int MT, int PF, bool EXACT>
 __global__ __launch_bounds__(64 * AB_MAX_WAVES) void k_ab(AbParams p, const double* __restrict__ Vt,
                                                           const double* __restrict__ C,
                                                           const double* __restrict__ rowmax,
-                                                          double* __restrict__ sigma, int kb_count, int64_t chunk,
-                                                          int nchunks)
+                                                          double* __restrict__ sigma, int kb_count_arg,
+                                                          int64_t chunk, int nchunks)
 {
     using MF = MfmaF64;
     __shared__ double s_amax[AB_MAX_WAVES], s_cmax[AB_MAX_WAVES];
     extern __shared__ __align__(16) unsigned char smem[];
+    const int kb_count = EXACT ? KBMAX : kb_count_arg;
     const int Kp = kb_count * MF::K;
     unsigned long long* sig = reinterpret_cast<unsigned long long*>(smem);
     double* Dt = reinterpret_cast<double*>(smem + (((chunk + 64) * 8 + 15) / 16) * 16);
@@ -292,7 +296,7 @@ static hipError_t ab_launch_pf(const AbParams& p, const double* Vt, const double
     dim3 blk(64 * nwaves);
 #define AB_PF(PFV)                                                                                  \
     if (pf <= PFV) {                                                                                \
-        auto kern = k_ab<KB, MTV, PFV>;                                                             \
+        auto kern = kb_count == KB ? k_ab<KB, MTV, PFV, true> : k_ab<KB, MTV, PFV, false>;          \
         hipError_t e = hipFuncSetAttribute((const void*)kern,                                       \
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);   \
         if (e != hipSuccess) {                                                                      \
