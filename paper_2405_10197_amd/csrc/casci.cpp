@@ -265,6 +265,7 @@ struct casci_ctx {
     DBuf d_gin, d_gout;
     // lanes per entry chosen by the autotuner for the FP64 and FP32-input gathers (0: not yet)
     int tune_lpe[2] = {0, 0};
+    bool tune_blk[2] = {false, false};  // the tuned width was chosen with the row-blocked form available (or set)
     int tune_ab[2] = {0, 0};  // FP64 alpha-beta layout code per pair set ([0] r <= s, [1] all), 0: untuned
 
     int fail(int code, const std::string& msg)
@@ -592,6 +593,7 @@ extern "C" int casci_build_strings(casci_ctx* ctx, int nalpha, int nbeta, int no
     ctx->rb = rb;
     ctx->has_strings = true;
     ctx->tune_lpe[0] = ctx->tune_lpe[1] = 0;
+    ctx->tune_blk[0] = ctx->tune_blk[1] = false;
     ctx->tune_ab[0] = ctx->tune_ab[1] = 0;
     ctx->prepared = false;
     ctx->have_full = ctx->have_s2 = false;
@@ -1241,17 +1243,24 @@ static std::map<std::array<int, 5>, int> g_tune;
 
 static int autotune_gather(casci_ctx* ctx, bool lowp, const double* C, const float* C32, int64_t ld32)
 {
-    const std::array<int, 5> key = {ctx->device, ctx->norb, ctx->na, ctx->nb, lowp ? 1 : 0};
+    // the choice depends on whether the row-blocked form is among the candidates
+    const bool blk = ctx->blk[0].have;
+    const std::array<int, 5> key = {ctx->device, ctx->norb, ctx->na, ctx->nb, (lowp ? 1 : 0) + (blk ? 2 : 0)};
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
         auto it = g_tune.find(key);
         if (it != g_tune.end()) {
             ctx->tune_lpe[lowp] = it->second;
+            ctx->tune_blk[lowp] = blk;
             return CASCI_OK;
         }
     }
     hipStream_t st = ctx->stream;
-    HIPC(ctx->d_t1.ensure((size_t)ctx->Nd * 8));
+    // timed on the first eighth of the rows (at least 2048): the same strips and
+    // operator rows, a fraction of the cost on large spaces; the FP64 output of
+    // those rows only (the FP32-storage build holds no full FP64 vector)
+    const int64_t nt = std::min<int64_t>(ctx->Na, std::max<int64_t>(2048, ctx->Na / 8));
+    HIPC(ctx->d_t1.ensure((size_t)nt * ctx->Nb * 8));
     hipEvent_t e0, e1;
     HIPC(hipEventCreate(&e0));
     if (hipEventCreate(&e1) != hipSuccess) {
@@ -1261,12 +1270,9 @@ static int autotune_gather(casci_ctx* ctx, bool lowp, const double* C, const flo
     int best = 0;
     float best_ms = 0.f;
     hipError_t err = hipSuccess;
-    // timed on the first eighth of the rows (at least 2048): the same strips and
-    // operator rows, a fraction of the cost on large spaces
-    const int64_t nt = std::min<int64_t>(ctx->Na, std::max<int64_t>(2048, ctx->Na / 8));
     static const int cand64[] = {SS_BLOCKED, 16, 32, 64, 128, 1602, 3202};
     static const int cand32[] = {SS_BLOCKED, 16, 32, 64, 128, 1602, 3202, 1604, 3204, 6404};
-    const bool blk = ctx->blk[0].have;  // the blocked width joins when its tables exist
+    // (the blocked width joins when its tables exist)
     const int* cand = (lowp ? cand32 : cand64) + (blk ? 0 : 1);
     const int ncand = (lowp ? 10 : 7) - (blk ? 0 : 1);
     for (int ci = 0; ci < ncand; ++ci) {
@@ -1293,6 +1299,7 @@ static int autotune_gather(casci_ctx* ctx, bool lowp, const double* C, const flo
     (void)hipEventDestroy(e1);
     HIPC(err);
     ctx->tune_lpe[lowp] = best;
+    ctx->tune_blk[lowp] = blk;
     std::lock_guard<std::mutex> lk(g_tune_mu);
     g_tune[key] = best;
     return CASCI_OK;
@@ -1495,7 +1502,10 @@ static int sigma_dev(casci_ctx* ctx, const double* C, double* S, int ab_prec, do
     const double s_aa = parity != 0 ? 0.5 * shift : shift;  // halved: S + p S^T doubles it
     // the strip width changes only the speed, not the sums (fixed summation order)
     if (alloc) CHECK_RC(ensure_ss_blocks(ctx, 0));
-    if (alloc && ctx->tune_lpe[lowp ? 1 : 0] == 0) CHECK_RC(autotune_gather(ctx, lowp, C, w.c32, ld32));
+    // tuned once, and again once the row-blocked form exists if an earlier
+    // build (the FP32-storage one) tuned without it
+    if (alloc && (ctx->tune_lpe[lowp ? 1 : 0] == 0 || (ctx->blk[0].have && !ctx->tune_blk[lowp ? 1 : 0])))
+        CHECK_RC(autotune_gather(ctx, lowp, C, w.c32, ld32));
     const int lpe = ctx->tune_lpe[lowp ? 1 : 0];
     if (lowp)
         HIPC(launch_ss_gather_f32in(ss_op(ctx, 0), Na, Nb, w.c32, ld32, S, s_aa, 0, st, lpe, ab_prec == CASCI_BF16));
@@ -1545,6 +1555,59 @@ static int sigma_dev(casci_ctx* ctx, const double* C, double* S, int ab_prec, do
 // same-spin gathers accumulate in FP64 registers and store FP32; the
 // alpha-beta term (FP32 or BF16 MFMA, FP32 accumulation) is added into S32.
 // Timed parts go to the low-precision profile slots.
+// Width of the FP32-storage build's gather (FP32 in and out), timed on the
+// whole space with the build's own kernel writing into S32 (overwritten by
+// the build afterwards): on the first eighth of the rows the FP64-output
+// launches the other tuner times ranked the widths differently at
+// CAS(18,18) (64 lanes there, 1.88 s in full, against 1.07 s for 3204).
+// Cached per (device, norb, nalpha, nbeta) for the process.
+static int autotune_gather_f32s(casci_ctx* ctx, const float* C32, float* S32)
+{
+    const bool blk = ctx->blk[0].have;
+    const std::array<int, 5> key = {ctx->device, ctx->norb, ctx->na, ctx->nb, 4 + (blk ? 2 : 0)};
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_tune.find(key);
+        if (it != g_tune.end()) {
+            ctx->tune_lpe[1] = it->second;
+            ctx->tune_blk[1] = blk;
+            return CASCI_OK;
+        }
+    }
+    hipStream_t st = ctx->stream;
+    hipEvent_t e0, e1;
+    HIPC(hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return ctx->fail(CASCI_E_DEVICE, "hipEventCreate failed");
+    }
+    static const int cand[] = {SS_BLOCKED, 64, 128, 1604, 3204, 6404};
+    int best = 0;
+    float best_ms = 0.f;
+    hipError_t err = hipSuccess;
+    for (int ci = blk ? 0 : 1; ci < 6; ++ci) {
+        const int lpe = cand[ci];
+        if ((err = hipEventRecord(e0, st)) != hipSuccess) break;
+        err = launch_ss_gather_f32(ss_op(ctx, 0), ctx->Na, ctx->Nb, C32, S32, 0.0, 0, st, lpe);
+        if (err != hipSuccess || (err = hipEventRecord(e1, st)) != hipSuccess) break;
+        if ((err = hipEventSynchronize(e1)) != hipSuccess) break;
+        float ms = 0.f;
+        if ((err = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess) break;
+        if (best == 0 || ms < best_ms) {
+            best = lpe;
+            best_ms = ms;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    HIPC(err);
+    ctx->tune_lpe[1] = best;
+    ctx->tune_blk[1] = blk;
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune[key] = best;
+    return CASCI_OK;
+}
+
 static int sigma_dev_f32(casci_ctx* ctx, const float* C32, float* S32, int ab_prec)
 {
     hipStream_t st = ctx->stream;
@@ -1561,6 +1624,9 @@ static int sigma_dev_f32(casci_ctx* ctx, const float* C32, float* S32, int ab_pr
     };
     CHECK_RC(mark(0));
     CHECK_RC(mark(3));
+    // the FP32-input width, tuned on this build's own kernel if no build has
+    // tuned it yet
+    if (ctx->tune_lpe[1] == 0) CHECK_RC(autotune_gather_f32s(ctx, C32, S32));
     const int lpe = ctx->tune_lpe[1];
     // alpha-alpha: S32 = F_a C + shift C
     HIPC(launch_ss_gather_f32(ss_op(ctx, 0), Na, Nb, C32, S32, shift, 0, st, lpe));
@@ -1699,6 +1765,7 @@ extern "C" int casci_set_tuning(casci_ctx* ctx, int f64_lpe, int f32in_lpe)
                              "strip width code must be 0, 16, 32, 64, 128, 1602, 3202, 1604, 3204, 6404 or 99");
     ctx->tune_lpe[0] = f64_lpe;
     ctx->tune_lpe[1] = f32in_lpe;
+    ctx->tune_blk[0] = ctx->tune_blk[1] = true;  // a width set by the caller is kept
     ++ctx->gen;  // captured graphs hold the old choice
     return CASCI_OK;
 }
