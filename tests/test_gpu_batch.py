@@ -87,6 +87,20 @@ def test_every_gather_width_matches_oracle(torch, n):
     assert t["f64"] in WIDTHS and t["f32in"] in WIDTHS
 
 
+def test_fp32_storage_build_tunes_its_gather(torch):
+    """The FP32-storage build (FP32 C and sigma) times its own FP32-output
+    gather on the whole space when no width is tuned yet: the choice is one
+    of its candidates and sigma matches the oracle to the FP32 bound."""
+    c, h, eri = make(10, 3040)
+    na, nb = electrons(10)
+    d = c.dims
+    x = synth.ci_vector(d["Na"], d["Nb"], 8)[0].astype(np.float32)
+    ref = oracle.sigma(h, eri, na, nb, x.astype(np.float64))
+    s = c.sigma(torch.from_numpy(x).cuda(), ab_prec="f32").cpu().numpy()
+    assert c.tuning()["f32in"] in (64, 128, 1604, 3204, 6404, 99)
+    assert np.abs(s - ref).max() < 1e-5 * np.abs(ref).max()
+
+
 def test_bf16_blocked_gather_sums_in_fp32(torch):
     """In a BF16 build the row-blocked gather (width 99) sums in FP32 and the
     other widths in FP64: the two sigmas differ at the FP32 rounding level,
