@@ -96,6 +96,15 @@ struct DBuf {
     void* p = nullptr;
     size_t bytes = 0;
     int dev = -1;
+    DBuf() = default;
+    DBuf(const DBuf&) = delete;  // one owner per block: a copy would release it twice
+    DBuf& operator=(const DBuf&) = delete;
+    void swap(DBuf& o)
+    {
+        std::swap(p, o.p);
+        std::swap(bytes, o.bytes);
+        std::swap(dev, o.dev);
+    }
     hipError_t ensure(size_t b)
     {
         if (b <= bytes && p) return hipSuccess;
@@ -569,13 +578,13 @@ extern "C" int casci_build_strings(casci_ctx* ctx, int nalpha, int nbeta, int no
         HIPC(launch_single_lists(norb, nbeta, Nb, tmp.d_bstr.as<uint64_t>(), tmp.d_binom.as<int64_t>(),
                                  sb, tmp.d_lb_j.as<int32_t>(), tmp.d_lb_pq.as<uint16_t>(), ctx->stream));
         HIPC(hipStreamSynchronize(ctx->stream));
-        std::swap(ctx->d_binom, tmp.d_binom);
-        std::swap(ctx->d_astr, tmp.d_astr);
-        std::swap(ctx->d_bstr, tmp.d_bstr);
-        std::swap(ctx->d_la_j, tmp.d_la_j);
-        std::swap(ctx->d_la_pq, tmp.d_la_pq);
-        std::swap(ctx->d_lb_j, tmp.d_lb_j);
-        std::swap(ctx->d_lb_pq, tmp.d_lb_pq);
+        ctx->d_binom.swap(tmp.d_binom);
+        ctx->d_astr.swap(tmp.d_astr);
+        ctx->d_bstr.swap(tmp.d_bstr);
+        ctx->d_la_j.swap(tmp.d_la_j);
+        ctx->d_la_pq.swap(tmp.d_la_pq);
+        ctx->d_lb_j.swap(tmp.d_lb_j);
+        ctx->d_lb_pq.swap(tmp.d_lb_pq);
         DBuf* old[] = {&tmp.d_binom, &tmp.d_astr, &tmp.d_bstr, &tmp.d_la_j,
                        &tmp.d_la_pq, &tmp.d_lb_j, &tmp.d_lb_pq};
         for (DBuf* b : old) b->release();
