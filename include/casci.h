@@ -418,6 +418,26 @@ int casci_sym_eig(const double* A, int n, double* w, double* Z);
  */
 int casci_tile_pairs(int64_t nb, int64_t k0, int64_t count, int64_t* out);
 
+/*
+ * Row-blocked tables of a same-spin operator (the form the SS_BLOCKED gather
+ * of the alpha-alpha / beta-beta terms of eq. (hamiltonian) reads), built on
+ * the host exactly as the library builds them, for checking without a
+ * device. Input: N < 65536 rows of r >= 2 entries, int32 columns (entry 0 the
+ * diagonal, then strictly ascending) and FP64 values; R = 16 or 32 rows per
+ * block. sizes[0..3] = union entries, groups, group-offset entries, blocks
+ * (all 0 when a union needs more than 127 chunks of 64 rows or a row more
+ * than 65535 groups). Outputs may be null (sizes only): uni[sizes[0]]
+ * (uint16, the sorted union of each block, concatenated), binfo[4 blocks]
+ * (union offset, union size, group-offset offset, chunks), goff[sizes[2]]
+ * (per block [R][chunks + 1] first group of each chunk relative to the row),
+ * rbase[N] (first group of each row), goffs / gvals [4 sizes[1]] (per group
+ * the LDS byte offsets (union position mod 64) x 512 and the FP64 values,
+ * slots outside the chunk 0). CASCI_E_ARG on bad sizes or columns.
+ */
+int casci_ss_block_tables(int64_t N, int r, const int32_t* col, const double* val, int R, int64_t* sizes,
+                          uint16_t* uni, int32_t* binfo, uint16_t* goff, int32_t* rbase, uint32_t* goffs,
+                          double* gvals);
+
 /* ------------------------------------------------------------------------
  * Learned Davidson preconditioner (CASCI_PRECOND_MLP). A per-determinant
  * network 8 -> 64 -> 64 -> 1 (tanh, FP32) predicts the correction vector

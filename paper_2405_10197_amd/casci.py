@@ -148,6 +148,7 @@ def lib():
         "casci_get_ab_layout": (I, [P, P]),
         "casci_lowest_diagonal": (I, [P, ctypes.c_int64, P]),
         "casci_release_cache": (I, [I]),
+        "casci_ss_block_tables": (I, [I64, I, P, P, I, P, P, P, P, P, P, P]),
         "casci_cached_bytes": (ctypes.c_int64, [I]),
         "casci_set_ab_layout": (I, [P, I, I]),
     }
@@ -551,10 +552,39 @@ class Context:
         return E, vec, out
 
 
+def ss_block_tables(col, val, R: int):
+    """Row-blocked tables of a same-spin operator in row form (casci_ss_block_tables,
+    host only): col int32 [N, r] (diagonal first, then ascending), val float64
+    [N, r]. Returns None when the form is not available, else a dict of arrays
+    uni, binfo [blocks, 4], goff, rbase, goffs [groups, 4], gvals [groups, 4]."""
+    col = np.ascontiguousarray(col, dtype=np.int32)
+    val = np.ascontiguousarray(val, dtype=np.float64)
+    N, r = col.shape
+    if val.shape != col.shape:
+        raise ValueError("col and val must have the same shape")
+    L = lib()
+    sizes = np.zeros(4, dtype=np.int64)
+    z = None
+    rc = L.casci_ss_block_tables(N, r, col.ctypes.data, val.ctypes.data, int(R), sizes.ctypes.data, z, z, z, z, z, z)
+    if rc != OK:
+        raise CasciError(rc, "casci_ss_block_tables failed")
+    if sizes[3] == 0:
+        return None
+    out = {"uni": np.zeros(sizes[0], np.uint16), "binfo": np.zeros((sizes[3], 4), np.int32),
+           "goff": np.zeros(sizes[2], np.uint16), "rbase": np.zeros(N, np.int32),
+           "goffs": np.zeros((sizes[1], 4), np.uint32), "gvals": np.zeros((sizes[1], 4), np.float64)}
+    rc = L.casci_ss_block_tables(N, r, col.ctypes.data, val.ctypes.data, int(R), sizes.ctypes.data,
+                                 *(out[k].ctypes.data for k in ("uni", "binfo", "goff", "rbase", "goffs", "gvals")))
+    if rc != OK:
+        raise CasciError(rc, "casci_ss_block_tables failed")
+    return out
+
+
 def release_cache(device: int = -1):
     """Return the library's cached device blocks (casci_release_cache) to the driver."""
-    if lib().casci_release_cache(int(device)) != OK:
-        raise CasciError("casci_release_cache failed")
+    rc = lib().casci_release_cache(int(device))
+    if rc != OK:
+        raise CasciError(rc, "casci_release_cache failed")
 
 
 def cached_bytes(device: int = -1) -> int:

@@ -2471,6 +2471,46 @@ extern "C" int casci_tile_pairs(int64_t nb, int64_t k0, int64_t count, int64_t* 
     return CASCI_OK;
 }
 
+extern "C" int casci_ss_block_tables(int64_t N, int r, const int32_t* col, const double* val, int R,
+                                     int64_t* sizes, uint16_t* uni, int32_t* binfo, uint16_t* goff,
+                                     int32_t* rbase, uint32_t* goffs, double* gvals)
+{
+    if (N < 1 || N >= 65536 || r < 2 || !col || !val || !sizes || (R != SS_BLK_W && R != 2 * SS_BLK_W))
+        return CASCI_E_ARG;
+    std::vector<int32_t> c(col, col + (size_t)N * r);
+    std::vector<double> v(val, val + (size_t)N * r);
+    for (int64_t e0 = 0; e0 < N * (int64_t)r; e0 += r)
+        for (int e = 1; e < r; ++e) {
+            const int32_t J = c[(size_t)e0 + e];
+            if (J < 0 || J >= N || (e > 1 && J <= c[(size_t)e0 + e - 1])) return CASCI_E_ARG;
+        }
+    std::vector<uint16_t> u, go;
+    std::vector<int32_t> bi, rb;
+    std::vector<SsGroup> g64, g32;
+    std::vector<SsGroupF> gf;
+    int rc = CASCI_OK;
+    const bool ok = build_ss_blocks(N, r, c, v, R, u, go, bi, rb, g64, g32, gf, &rc);
+    if (rc != CASCI_OK) return rc;
+    if (!ok) {
+        for (int i = 0; i < 4; ++i) sizes[i] = 0;
+        return CASCI_OK;
+    }
+    sizes[0] = (int64_t)u.size();
+    sizes[1] = (int64_t)g64.size();
+    sizes[2] = (int64_t)go.size();
+    sizes[3] = (int64_t)(bi.size() / 4);
+    if (uni) std::copy(u.begin(), u.end(), uni);
+    if (binfo) std::copy(bi.begin(), bi.end(), binfo);
+    if (goff) std::copy(go.begin(), go.end(), goff);
+    if (rbase) std::copy(rb.begin(), rb.end(), rbase);
+    for (size_t i = 0; i < g64.size(); ++i)
+        for (int k = 0; k < 4; ++k) {
+            if (goffs) goffs[4 * i + k] = g64[i].off[k];
+            if (gvals) gvals[4 * i + k] = g64[i].v[k];
+        }
+    return CASCI_OK;
+}
+
 extern "C" int casci_sym_eig(const double* A, int n, double* w, double* Z)
 {
     if (n < 0 || (n > 0 && (!A || !w || !Z))) return CASCI_E_ARG;
