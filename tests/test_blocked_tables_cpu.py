@@ -85,3 +85,39 @@ def test_blocked_tables_reject_bad_rows():
         casci.ss_block_tables(bad, val, 16)
     with pytest.raises(casci.CasciError):
         casci.ss_block_tables(col, val, 24)
+
+
+def test_fp32_sums_in_the_canonical_order_stay_near_fp32_rounding():
+    """The BF16 build's gather sums in FP32 from FP32 values and an FP32 copy
+    of C in the canonical order (accumulator k takes the entries e = k mod 4
+    of each row in ascending order, the diagonal first into accumulator 0,
+    total (a0 + a1) + (a2 + a3)). Emulated on the tables at CAS(10,10)-like
+    structure, the result stays within a few units of FP32 rounding of the
+    FP64 product, far below the ~1e-3 of the BF16 alpha-beta term."""
+    col, val = row_form(10, 5, 321)
+    t = casci.ss_block_tables(col, val, 32)
+    N, r = col.shape
+    X = np.random.default_rng(8).standard_normal((N, 4))
+    X32 = X.astype(np.float32)
+    v32 = val.astype(np.float32)
+    acc = np.zeros((N, 4, X.shape[1]), dtype=np.float32)
+    acc[:, 0] = v32[:, :1] * X32
+    for b, (ux, un, gz, nch) in enumerate(t["binfo"]):
+        U = t["uni"][ux:ux + un].astype(np.int64)
+        for w in range(32):
+            i = b * 32 + w
+            if i >= N:
+                continue
+            go = t["goff"][gz + w * (nch + 1): gz + (w + 1) * (nch + 1)].astype(np.int64)
+            base = t["rbase"][i]
+            for ch in range(nch):
+                for g in range(base + go[ch], base + go[ch + 1]):
+                    for k in range(4):
+                        j = U[ch * CH + int(t["goffs"][g, k]) // ROWB]
+                        acc[i, k] += np.float32(t["gvals"][g, k]) * X32[j]
+    y = (acc[:, 0] + acc[:, 1]) + (acc[:, 2] + acc[:, 3])
+    F = np.zeros((N, N))
+    F[np.repeat(np.arange(N), r), col.reshape(-1)] = val.reshape(-1)
+    ref = F @ X
+    rel = np.abs(y.astype(np.float64) - ref).max() / np.abs(ref).max()
+    assert 1e-9 < rel < 1e-5, rel
