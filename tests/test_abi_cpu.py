@@ -376,6 +376,21 @@ def test_tile_pairs_enumerate_the_upper_triangle(nb):
     assert np.array_equal(got[:, 0], bi) and np.array_equal(got[:, 1], bj)
 
 
+@pytest.mark.parametrize("n", [1, 31, 32, 33, 100, 252])
+def test_tile_pairs_write_every_element_once(n):
+    """The parity combination writes tile (bi, bj) and, for bi != bj, its mirror
+    (bj, bi), 32 x 32 elements each clipped to the n x n matrix: over all pairs
+    every element is written exactly once, so the squares summed per pair (the
+    norm the Gram-Schmidt reads from that pass) add up to the whole vector's."""
+    nb = (n + 31) // 32
+    count = np.zeros((n, n), dtype=np.int64)
+    for bi, bj in casci.tile_pairs(nb):
+        count[bi * 32:(bi + 1) * 32, bj * 32:(bj + 1) * 32] += 1
+        if bi != bj:
+            count[bj * 32:(bj + 1) * 32, bi * 32:(bi + 1) * 32] += 1
+    assert np.all(count == 1)
+
+
 def test_tile_pairs_range_checks():
     assert casci.tile_pairs(5, 14, 1).tolist() == [[4, 4]]
     for args in [(0, 0, 1), (5, 15, 1), (5, -1, 1), (5, 10, 6)]:
